@@ -1,0 +1,10 @@
+"""CPU FP64 oracle for RSAI(tol) -- test infrastructure only.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the benchmark's ``cpu_baseline``
+leg may import this package. The GPU product path never touches it.
+"""
+from .oracle import (DROP_ADAPTIVE, DROP_FIXED, DROP_NONE, backward, bicgstab, build_lib,
+                     fixed_pattern, rsai)
+
+__all__ = ["rsai", "fixed_pattern", "backward", "bicgstab", "build_lib", "DROP_NONE",
+           "DROP_FIXED", "DROP_ADAPTIVE"]
