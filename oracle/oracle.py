@@ -49,7 +49,7 @@ def _load():
     lib.oracle_threads.restype = _I32
     lib.oracle_threads.argtypes = [_P]
     lib.oracle_export.restype = None
-    lib.oracle_export.argtypes = [_P] * 14
+    lib.oracle_export.argtypes = [_P] * 16
     lib.oracle_free.restype = None
     lib.oracle_free.argtypes = [_P]
     lib.oracle_fixed_pattern.restype = _I64
@@ -77,8 +77,10 @@ def rsai(A, c: int = 3, lmax: int = 8, eps: float = 0.4, drop: int = DROP_FIXED,
 
     Returns a dict with the CSC of M (columns = the processed columns, ascending) and
     per-column statistics: loops, resnorm (||A m_k - e_k||), nI, nJ, status,
-    sel_margin / drop_margin (smallest decision gaps), flops, nsolve, and optionally
-    hist (residual norm after each solve).
+    sel_margin / drop_margin (smallest decision gaps), flops (the oracle's own
+    from-scratch count), mflops (the QR-update work model), nsolve (loop solves),
+    ndrop (re-solves after a drop), and optionally hist (residual norm after each
+    loop solve).
     """
     if not (1 <= c <= 64):
         raise ValueError("c must be in 1..64")
@@ -97,11 +99,13 @@ def rsai(A, c: int = 3, lmax: int = 8, eps: float = 0.4, drop: int = DROP_FIXED,
             colptr=np.zeros(ncols + 1, np.int64), rowidx=np.zeros(nnz, np.int32), val=np.zeros(nnz),
             loops=np.zeros(ncols, np.int32), resnorm=np.zeros(ncols), nI=np.zeros(ncols, np.int32),
             nJ=np.zeros(ncols, np.int32), status=np.zeros(ncols, np.int32), sel_margin=np.zeros(ncols),
-            drop_margin=np.zeros(ncols), flops=np.zeros(ncols), nsolve=np.zeros(ncols, np.int32))
+            drop_margin=np.zeros(ncols), flops=np.zeros(ncols), nsolve=np.zeros(ncols, np.int32),
+            ndrop=np.zeros(ncols, np.int32), mflops=np.zeros(ncols))
         hh = np.zeros(ncols * 2 * (lmax + 1)) if hist else None
         lib.oracle_export(h, *[_ptr(out[k]) for k in ("colptr", "rowidx", "val", "loops", "resnorm", "nI",
                                                       "nJ", "status", "sel_margin", "drop_margin", "flops",
-                                                      "nsolve")], _ptr(hh))
+                                                      "nsolve")], _ptr(hh), _ptr(out["ndrop"]),
+                           _ptr(out["mflops"]))
         if hist:
             out["hist"] = hh.reshape(ncols, 2 * (lmax + 1))
         out["seconds"] = lib.oracle_seconds(h)

@@ -253,9 +253,27 @@ typedef struct {
     double eps, tol;
 } oparams;
 
+/*
+ * Flop count of one LS solve done as a Householder QR *update*: the factor of the
+ * first qlo columns (m rows) is kept, the qn - qlo new columns are brought in by
+ * applying the qlo stored reflectors, then reflectors qlo..qn-1 are formed and
+ * applied to the trailing columns and to Q^T e; then back substitution and the
+ * residual norm ||(Q^T e)(qn:m)||. qlo = 0 is a from-scratch QR. This is the
+ * algorithmic work model of the method (Algorithm 1, step 7), not the oracle's own
+ * from-scratch arithmetic.
+ */
+static double model_solve_flops(int m, int qlo, int qn) {
+    double f = 0.0;
+    for (int j = 0; j < qlo; ++j) f += 4.0 * (double)(m - j) * (double)(qn - qlo);
+    for (int j = qlo; j < qn; ++j)
+        f += 2.0 * (double)(m - j) + 4.0 * (double)(m - j) * (double)(qn - j - 1) + 4.0 * (double)(m - j);
+    f += (double)qn * (double)qn + 2.0 * (double)(m - qn);
+    return f;
+}
+
 /* Dropping (Section 4): entries |m_j| <= t leave J; LS solved again if anything left. */
 static int drop_step(const omat *A, int32_t k, const oparams *p, work *w, double *resnorm,
-                     double *flops, double *drop_margin) {
+                     double *flops, double *drop_margin, int *ndrop, double *mflops) {
     if (p->drop == OR_DROP_NONE) return OR_OK;
     const int q = w->J.n;
     double t = (p->drop == OR_DROP_FIXED) ? p->tol : p->eps / ((double)q * A->norm1);
@@ -273,12 +291,14 @@ static int drop_step(const omat *A, int32_t k, const oparams *p, work *w, double
     if (w->keep.n == 0) { w->keep.a[0] = w->J.a[best]; w->keep.n = 1; }
     memcpy(w->J.a, w->keep.a, sizeof(int32_t) * (size_t)w->keep.n);
     w->J.n = w->keep.n;
+    *ndrop += 1;
+    *mflops += model_solve_flops(w->I.n, 0, w->J.n);
     return ls_solve(A, k, w, resnorm, flops);
 }
 
 typedef struct {
-    int32_t loops, nI, nJ, status, nsolve;
-    double resnorm, sel_margin, drop_margin, flops;
+    int32_t loops, nI, nJ, status, nsolve, ndrop;
+    double resnorm, sel_margin, drop_margin, flops, mflops;
 } colstat;
 
 /*
@@ -288,8 +308,8 @@ typedef struct {
  */
 static void rsai_column(const omat *A, int32_t k, const oparams *p, work *w, colstat *st,
                         double *hist, int hist_len) {
-    double rn = 0.0, flops = 0.0, sel_margin = INFINITY, drop_margin = INFINITY;
-    int nsolve = 0;
+    double rn = 0.0, flops = 0.0, sel_margin = INFINITY, drop_margin = INFINITY, mflops = 0.0;
+    int nsolve = 0, ndrop = 0;
     int status = OR_OK;
     /* step 1: J^(0) = {k}, R^(0) empty, l = 0 */
     w->J.n = 0; iv_push(&w->J, k);
@@ -299,7 +319,8 @@ static void rsai_column(const omat *A, int32_t k, const oparams *p, work *w, col
     for (int64_t e = A->colptr[k]; e < A->colptr[k + 1]; ++e) iv_push(&w->I, A->rowidx[e]);
     int l = 0;
     status = ls_solve(A, k, w, &rn, &flops);
-    if (status == OR_OK) status = drop_step(A, k, p, w, &rn, &flops, &drop_margin);
+    mflops += model_solve_flops(w->I.n, 0, 1);
+    if (status == OR_OK) status = drop_step(A, k, p, w, &rn, &flops, &drop_margin, &ndrop, &mflops);
     if (hist && nsolve < hist_len) hist[nsolve] = rn;
     ++nsolve;
     /* step 3 */
@@ -371,6 +392,7 @@ static void rsai_column(const omat *A, int32_t k, const oparams *p, work *w, col
         }
         iv_sort_unique(&w->tmp);
         set_minus(&w->tmp, &w->I, &w->Ihat);
+        int qprev = w->J.n;
         {
             ivec scratch = {0, 0, 0};
             set_union_into(&w->J, &w->Jhat, &scratch);
@@ -379,7 +401,8 @@ static void rsai_column(const omat *A, int32_t k, const oparams *p, work *w, col
         }
         /* step 7: new LS solution and residual on the augmented pattern */
         status = ls_solve(A, k, w, &rn, &flops);
-        if (status == OR_OK) status = drop_step(A, k, p, w, &rn, &flops, &drop_margin);
+        mflops += model_solve_flops(w->I.n, qprev, w->J.n);
+        if (status == OR_OK) status = drop_step(A, k, p, w, &rn, &flops, &drop_margin, &ndrop, &mflops);
         if (hist && nsolve < hist_len) hist[nsolve] = rn;
         ++nsolve;
     }
@@ -392,6 +415,8 @@ static void rsai_column(const omat *A, int32_t k, const oparams *p, work *w, col
     st->drop_margin = drop_margin;
     st->flops = flops;
     st->nsolve = nsolve;
+    st->ndrop = ndrop;
+    st->mflops = mflops;
 }
 
 /* ---------------- result handle ---------------- */
@@ -496,7 +521,8 @@ int32_t oracle_threads(void *h) { return ((oresult *)h)->threads; }
 /* Copy results out; any pointer may be NULL. Arrays are per processed column. */
 void oracle_export(void *h, int64_t *colptr, int32_t *rowidx, double *val, int32_t *loops,
                    double *resnorm, int32_t *nI, int32_t *nJ, int32_t *status, double *sel_margin,
-                   double *drop_margin, double *flops, int32_t *nsolve, double *hist) {
+                   double *drop_margin, double *flops, int32_t *nsolve, double *hist, int32_t *ndrop,
+                   double *mflops) {
     oresult *R = (oresult *)h;
     if (colptr) memcpy(colptr, R->colptr, sizeof(int64_t) * (size_t)(R->ncols + 1));
     if (rowidx) memcpy(rowidx, R->rowidx, sizeof(int32_t) * (size_t)R->nnz);
@@ -511,6 +537,8 @@ void oracle_export(void *h, int64_t *colptr, int32_t *rowidx, double *val, int32
         if (drop_margin) drop_margin[t] = R->st[t].drop_margin;
         if (flops) flops[t] = R->st[t].flops;
         if (nsolve) nsolve[t] = R->st[t].nsolve;
+        if (ndrop) ndrop[t] = R->st[t].ndrop;
+        if (mflops) mflops[t] = R->st[t].mflops;
     }
     if (hist && R->hist) memcpy(hist, R->hist, sizeof(double) * (size_t)R->ncols * (size_t)R->hist_len);
 }
