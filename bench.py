@@ -1,0 +1,177 @@
+"""Benchmark: RSAI(tol) construction throughput on one MI355X.
+
+Workload: the 2D 5-point upwind convection-diffusion matrix on a 512 x 512 grid
+(n = 262144, nnz = 1,308,672), per-cell convection uniform in [-50, 50]^2 * h from
+seed 0; RSAI parameters c = 3, lmax = 8, eps = 0.4, fixed drop tolerance 1e-3.
+A step is one complete rsai_build (CSC check, row pattern, the fused size-tiered
+RSAI kernels, assembly of M as CSC) on inputs already resident in HBM.
+
+Printed as one JSON line: columns/s of the batched schedule (the value), the
+plain schedule on the same GPU, fwd+bwd time of the loss
+sum_k ||A m_k - e_k||^2 + ||A M b - b||^2, the roofline of the dominant kernel
+(HIP events around it on its own stream), and the CPU oracle on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RSAI columns/sec (FP64, n=262k) batched vs plain; fwd+bwd time; % FP64 roofline"
+FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
+HBM_PEAK_GBS = 8000.0
+PARAMS = dict(c=3, lmax=8, eps=0.4, drop="fixed", tol=1e-3)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--grid", type=int, default=512)
+    ap.add_argument("--profile-steps", type=int, default=0,
+                    help="only run this many batched builds (for rocprofv3), print nothing else")
+    return ap.parse_args()
+
+
+def time_builds(rsai, A, sched, steps, warmup, torch):
+    for _ in range(warmup):
+        p = rsai.build(A, sched=sched, **PARAMS)
+        p.nnz()
+        p.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = None
+    for _ in range(steps):
+        if plan is not None:
+            plan.close()
+        plan = rsai.build(A, sched=sched, **PARAMS)
+        plan.nnz()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    plan.close()
+    return dt
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(columns are independent; the sharding design is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1503_04500_amd.rsai as rsai
+    from paper_1503_04500_amd import gen
+
+    H = gen.cd2d(args.grid, seed=0)
+    A = rsai.Matrix.from_host(H, "cuda:0")
+    torch.cuda.synchronize()
+
+    if args.profile_steps:
+        for _ in range(args.profile_steps):
+            p = rsai.build(A, sched="batched", **PARAMS)
+            p.nnz()
+            p.close()
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_steps": args.profile_steps}))
+        return
+
+    # ---- batched (the value)
+    dt_b = time_builds(rsai, A, "batched", args.steps, args.warmup, torch)
+    # ---- dominant kernel timing with HIP events on the build stream, plus stats
+    tier0_ms, build_ms = [], []
+    last = None
+    for _ in range(max(3, min(args.steps, 10))):
+        if last is not None:
+            last.close()
+        last = rsai.build(A, sched="batched", timing=True, **PARAMS)
+        t = last.timing()
+        tier0_ms.append(t["tier0"])
+        build_ms.append(t["build"])
+    st = {k: v.cpu().numpy() for k, v in last.stats().items()}
+    nnzM = last.nnz()
+    last.close()
+    flops = float(st["flops"].sum())
+    t0_ms = float(np.median(tier0_ms))
+    achieved_tf = flops / (t0_ms * 1e-3) / 1e12
+    # algorithmic HBM bytes of the tier kernel: read A (val, rowidx, colptr), the row
+    # pattern (colidx, rowptr) once; write the per-column results (J, values) and the
+    # per-column statistics
+    n, nnz = H.n, H.nnz
+    bytes_alg = (nnz * (8 + 4) + (n + 1) * 8) + (nnz * 4 + (n + 1) * 8) + nnzM * (4 + 8) + n * (8 + 4 * 4 + 8 * 3)
+    hbm_gbs = bytes_alg / (t0_ms * 1e-3) / 1e9
+
+    # ---- plain schedule
+    plain = None
+    if not args.no_plain:
+        dt_p = time_builds(rsai, A, "plain", max(3, args.steps // 4), 1, torch)
+        plain = {"value": n / dt_p, "ms_per_step": dt_p * 1e3, "unit": "columns/s"}
+
+    # ---- fwd + bwd of L = sum_k ||A m_k - e_k||^2 + ||A M b - b||^2
+    from paper_1503_04500_amd import autograd as ag
+    b = torch.from_numpy(np.random.default_rng(0).standard_normal(n)).to("cuda:0")
+    fb = []
+    for it in range(4):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        val = A.val.clone().requires_grad_(True)
+        L = ag.rsai_loss(A, val, b, **PARAMS)
+        L.backward()
+        torch.cuda.synchronize()
+        if it > 0:
+            fb.append(time.perf_counter() - t0)
+    fwd_bwd_ms = float(np.median(fb)) * 1e3
+
+    # ---- CPU oracle on the host cores (full matrix, repeated up to ~10 s)
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        reps, tot, thr = 0, 0.0, 0
+        while tot < 10.0 and reps < 200:
+            R = oracle.rsai(H, c=3, lmax=8, eps=0.4, drop=oracle.DROP_FIXED, tol=1e-3)
+            tot += R["seconds"]
+            thr = R["threads"]
+            reps += 1
+        cpu = {"value": reps * n / tot, "unit": "columns/s", "cores": int(thr), "kind": "oracle",
+               "sample": f"the full {args.grid}x{args.grid} matrix ({n} columns) built {reps} times"}
+
+    out = {
+        "metric": METRIC,
+        "value": n / dt_b,
+        "unit": "columns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt_b * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"cd2d {args.grid}x{args.grid} upwind convection-diffusion, convection U[-50,50]^2*h "
+                               "seed 0 (n=%d, nnz=%d); RSAI(tol) c=3 lmax=8 eps=0.4 tol=1e-3" % (n, nnz),
+                   "n": n, "nnz": nnz, "nnzM": int(nnzM), "schedule": "batched"},
+        "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tf / FP64_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "tier_kernel<8,3,12,4>", "kernel_ms": t0_ms, "alg_flops": flops,
+                     "hbm_alg_bytes": bytes_alg, "hbm_achieved_GBs": hbm_gbs, "hbm_frac": hbm_gbs / HBM_PEAK_GBS},
+        "plain": plain,
+        "speedup_vs_plain": (plain["ms_per_step"] / (dt_b * 1e3)) if plain else None,
+        "fwd_bwd_ms": fwd_bwd_ms,
+        "build_event_ms": float(np.median(build_ms)),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

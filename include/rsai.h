@@ -1,0 +1,166 @@
+/*
+ * rsai.h -- C ABI of the MI355X (gfx950) implementation of RSAI(tol), the residual
+ * based sparse approximate inverse of Jia & Kang (arXiv:1503.04500).
+ *
+ * What it computes. For a real nonsingular n x n sparse matrix A (Section 1, eq. (1.1))
+ * the library builds M = (m_1, ..., m_n) column by column (eqs. (2.1)-(2.2)): each
+ * m_k minimises ||A m_k - e_k||_2 over an adaptively grown pattern J_k, solved as the
+ * reduced LS problem (2.3) on the rows I_k = nonzero rows of A(:, J_k). The pattern
+ * grows by Algorithm 1 (Section 3): start from J_k = {k}; while ||r_k|| > eps and
+ * fewer than lmax loops were done, take the c largest |r_k(i)| among the rows not used
+ * before (ties: smaller row index), add the columns of those rows of A that are not
+ * yet in J_k, and re-solve. After every solve, entries with |m_jk| <= tol (fixed
+ * tolerance) or <= eps / (nnz(m_k) ||A||_1) (adaptive tolerance, eq. (4.3)) leave
+ * J_k and the LS problem is solved again on the kept pattern (Section 4). The
+ * result is used as a right preconditioner, A M y = b, x = M y (eq. (1.2)).
+ *
+ * Conventions.
+ *   - Every pointer named in a function is a DEVICE pointer unless stated otherwise.
+ *   - CSC: int64 colptr[n+1] (colptr[0] = 0, non-decreasing), int32 rowidx[nnz]
+ *     (strictly ascending inside each column, in [0, n)), float64 val[nnz]. Every
+ *     column must hold at least one entry. Explicitly stored zeros are structural
+ *     nonzeros.
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream). All device
+ *     work is ordered on that stream; only the functions marked "synchronises" wait
+ *     for it.
+ *   - Errors: every function returns an rsai_status (negative on failure) and never
+ *     throws; rsai_last_error() gives a thread-local message. On failure no output
+ *     handle is created and nothing leaks.
+ *   - A is borrowed: it must stay alive and unchanged until rsai_destroy when
+ *     rsai_backward will be called (the adjoint re-reads A).
+ */
+#ifndef RSAI_H
+#define RSAI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RSAI_OK = 0,
+    RSAI_E_ARG = -1,      /* bad argument or parameter */
+    RSAI_E_CSC = -2,      /* malformed CSC input */
+    RSAI_E_SINGULAR = -3, /* a column's LS problem (2.3) is rank deficient */
+    RSAI_E_NOMEM = -4,    /* allocation failed */
+    RSAI_E_HIP = -5,      /* HIP runtime error */
+    RSAI_E_CAP = -6,      /* a column outgrew the largest LS size the build supports */
+    RSAI_E_STATE = -7     /* call not valid in the plan's state */
+} rsai_status;
+
+/* Borrowed view of one square CSC matrix (device pointers). */
+typedef struct {
+    int64_t n;
+    int64_t nnz;
+    const int64_t *colptr;
+    const int32_t *rowidx;
+    const double *val;
+} rsai_csc;
+
+typedef enum {
+    RSAI_DROP_NONE = 0,     /* basic RSAI, Algorithm 1 */
+    RSAI_DROP_FIXED = 1,    /* drop |m_jk| <= tol */
+    RSAI_DROP_ADAPTIVE = 2  /* drop |m_jk| <= eps / (nnz(m_k) ||A||_1), eq. (4.3) */
+} rsai_drop_mode;
+
+typedef enum {
+    RSAI_SCHED_BATCHED = 0, /* size-bucketed persistent kernels, whole loop fused */
+    RSAI_SCHED_PLAIN = 1    /* one wave per column, one launch per loop, state in HBM */
+} rsai_sched;
+
+typedef struct {
+    int32_t c;        /* dominant rows taken per loop (Algorithm 1, step 4), 1..8 */
+    int32_t lmax;     /* maximum number of loops, 0..64 */
+    double eps;       /* stop when ||A m_k - e_k||_2 <= eps */
+    int32_t drop;     /* rsai_drop_mode */
+    double tol;       /* fixed drop tolerance (RSAI_DROP_FIXED) */
+    int32_t sched;    /* rsai_sched */
+    int32_t validate; /* 1: check the CSC contract before building (one host sync) */
+    int32_t tier0;    /* first size tier for the batched schedule: -1 = choose from the
+                         tuning table / defaults, else a tier index (rsai_tier_info) */
+    int32_t timing;   /* 1: record per-kernel HIP event times (rsai_plan_timing) */
+    int32_t keep_factors;        /* 1: keep R factors of the final solves for backward */
+    int64_t factor_budget_bytes; /* keep factors only if they fit; else recompute */
+} rsai_params;
+
+typedef struct rsai_plan rsai_plan; /* opaque host handle */
+
+typedef void *(*rsai_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*rsai_free_fn)(void *ptr, void *stream, void *ctx);
+
+/* Defaults: c = 3, lmax = 10, eps = 0.4, FIXED, tol = 1e-3, batched, validate = 1
+   (the parameter ranges the paper suggests, Section 3 and Section 5). */
+rsai_status rsai_params_default(rsai_params *p);
+
+/* Route every device allocation of the library through (alloc, dealloc, ctx).
+   Passing NULLs restores hipMalloc/hipFree. Process-wide; not thread-safe against
+   concurrent builds. */
+rsai_status rsai_set_allocator(rsai_alloc_fn alloc, rsai_free_fn dealloc, void *ctx);
+
+/* Build M for one matrix. Queues all work on stream; with p->validate = 1 it first
+   synchronises once to check the CSC contract (RSAI_E_CSC on violation). */
+rsai_status rsai_build(const rsai_csc *A, const rsai_params *p, void *stream, rsai_plan **out);
+
+/* Build M for count matrices in one pass: the columns of all matrices share the
+   same size-bucketed persistent kernels (the method treats every column
+   independently, eq. (2.2)). Matrix i of the plan is A[i] (A is a host array). */
+rsai_status rsai_build_batched(int32_t count, const rsai_csc *A, const rsai_params *p, void *stream,
+                               rsai_plan **out);
+
+/* Number of matrices in a plan. */
+rsai_status rsai_plan_count(const rsai_plan *P, int32_t *count);
+
+/* nnz(M) of matrix mat (host output). Synchronises the build stream. Returns
+   RSAI_E_SINGULAR / RSAI_E_CAP if any column of the plan failed. */
+rsai_status rsai_plan_nnz(const rsai_plan *P, int32_t mat, int64_t *nnzM);
+
+/* Write M of matrix mat as CSC (rows ascending per column) into caller buffers:
+   colptr[n+1], rowidx[nnzM], val[nnzM]. */
+rsai_status rsai_export_M(const rsai_plan *P, int32_t mat, int64_t *colptr, int32_t *rowidx, double *val,
+                          void *stream);
+
+/* Per-column statistics of matrix mat, each a device array of n entries (any may
+   be NULL): loops used, final ||A m_k - e_k||_2, |I_k|, |J_k|, the column's
+   algorithmic flop count (Householder update model), and a status code
+   (0 ok, RSAI_E_SINGULAR, RSAI_E_CAP). */
+rsai_status rsai_export_stats(const rsai_plan *P, int32_t mat, int32_t *loops, double *resnorm, int32_t *nI,
+                              int32_t *nJ, double *flops, int32_t *status, void *stream);
+
+/* y = M x for matrix mat (x, y device arrays of n doubles). */
+rsai_status rsai_apply(const rsai_plan *P, int32_t mat, const double *x, double *y, void *stream);
+
+/* Adjoint of the fixed-pattern LS map A -> M (pattern of M fixed, values from (2.3)):
+   dA_val += d/dA [ <dM_val, M> + w_frob * sum_k ||A m_k - e_k||^2 ] restricted to
+   the structural nonzeros of A. dM_val (nnzM entries, CSC order of rsai_export_M)
+   may be NULL. dA_val has nnz(A) entries and is accumulated into. */
+rsai_status rsai_backward(rsai_plan *P, int32_t mat, const double *dM_val, double w_frob, double *dA_val,
+                          void *stream);
+
+/* y = A x (transpose = 0) or y = A^T x (transpose = 1) for a CSC matrix. */
+rsai_status rsai_spmv(const rsai_csc *A, const double *x, double *y, int32_t transpose, void *stream);
+
+/* Gradient of y = A x with respect to the values of A: dval[e] += dy[i] * x[j] for
+   every stored entry e = (i, j) of A (dval has nnz entries). */
+rsai_status rsai_spmv_vjp(const rsai_csc *A, const double *dy, const double *x, double *dval, void *stream);
+
+/* Kernel times of the last build/backward when p->timing = 1 (host array of up to
+   n doubles, milliseconds): [0] preprocessing, [1] tier-0 kernel, [2] later tiers,
+   [3] assembly, [4] whole build, [5] backward. Synchronises. */
+rsai_status rsai_plan_timing(const rsai_plan *P, double *ms, int32_t n);
+
+/* Describe size tier t (host outputs): lanes per column, max |I|, max |J|.
+   Returns RSAI_E_ARG past the last tier. */
+rsai_status rsai_tier_info(int32_t t, int32_t *lanes, int32_t *max_rows, int32_t *max_cols);
+
+/* Destroy a plan (NULL is allowed). Synchronises the build stream. */
+rsai_status rsai_destroy(rsai_plan *P);
+
+/* Thread-local message for the last error (never NULL). */
+const char *rsai_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RSAI_H */

@@ -1,0 +1,331 @@
+// Adjoint of the fixed-pattern LS map A -> M (pattern of M fixed, each m_k the
+// solution of (2.3) on I_k = nonzero rows of A(:, J_k)).
+//
+// From the normal equations A_k^T (A_k m - e) = 0 of (2.3):
+//   dm = -(A_k^T A_k)^{-1} (dA_k^T r + A_k^T dA_k m),   r = A_k m - e_k(I_k),
+// so for an upstream gradient g = dL/dm and z = (A_k^T A_k)^{-1} g = R^{-1} R^{-T} g:
+//   dL/dA_k = -(r z^T + (A_k z) m^T).
+// The Frobenius term w * sum_k ||A m_k - e_k||^2 adds 2 w r m^T (its part through M
+// vanishes because A_k^T r = 0). Contributions land on the structural nonzeros of
+// A(I_k, J_k) and are accumulated with atomics into dA.
+//
+// One group of 16 lanes per column: the block A(I_k, J_k) is re-gathered and
+// factorised by Householder QR in registers (row i in lane i mod 16), then
+// A_k z = Q [R z; 0] = Q [u; 0] with R^T u = g, and r = -Q [0; (Q^T e)(q:m)].
+#include <climits>
+
+#include "rsai_kernels.h"
+
+namespace rsai {
+
+namespace {
+constexpr int BG = 16, BRPL = 4, BQMAX = 32, BSTAGE = 4;
+constexpr int BMMAX = BG * BRPL;
+constexpr int BGPW = 64 / BG;
+constexpr int BLOGHSI = ilog2ceil(2 * BMMAX);
+constexpr int BHSI = 1 << BLOGHSI;
+
+struct BLds {
+    double stage[BSTAGE * BMMAX];
+    double rdiag[BQMAX];
+    double beta[BQMAX];
+    double zS[BQMAX];
+    int Jl[BQMAX];
+    int Il[BMMAX];
+    int hI[BHSI];
+    int hIv[BHSI];
+    int newk[BMMAX];
+    int news[BMMAX];
+    int cnt;
+    int pad;
+};
+}  // namespace
+
+int backward_max_cols() { return BQMAX; }
+int backward_max_rows() { return BMMAX; }
+
+__global__ void k_max2(int64_t n, const int32_t *a, const int32_t *b, int32_t *out2) {
+    int ma = 0, mb = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        ma = max(ma, a[i]);
+        mb = max(mb, b[i]);
+    }
+    atomicMax(&out2[0], ma);
+    atomicMax(&out2[1], mb);
+}
+void launch_max2(int64_t n, const int32_t *a, const int32_t *b, int32_t *out2, hipStream_t s) {
+    hipLaunchKernelGGL(k_max2, dim3(256), dim3(256), 0, s, n, a, b, out2);
+}
+
+__global__ __launch_bounds__(64) void backward_kernel(BwdArgs a) {
+    constexpr int G = BG, RPL = BRPL, QMAX = BQMAX, MMAX = BMMAX;
+    __shared__ BLds lds[BGPW];
+    const int gl = threadIdx.x % G;
+    const int grp = threadIdx.x / G;
+    BLds &S = lds[grp];
+    const MatDev A = a.mats[a.mat];
+    const int64_t n = a.n;
+    const int64_t gstride = (int64_t)gridDim.x * BGPW;
+    // uniform trip count over the wave so every barrier is reached by all lanes
+    const int64_t iters = (n + gstride - 1) / gstride;
+
+    for (int64_t itk = 0; itk < iters; ++itk) {
+        const int64_t k = itk * gstride + (int64_t)blockIdx.x * BGPW + grp;
+        bool act = k < n;
+        int q = 0, m = 0;
+        int64_t mb = 0;
+        if (act) {
+            mb = a.Mcolptr[k];
+            q = (int)(a.Mcolptr[k + 1] - mb);
+            if (q > QMAX || q < 1) {
+                if (q > QMAX && gl == 0) atomicOr(a.err, 8);
+                act = false;
+            }
+        }
+        bool any_g = false;
+        if (act && a.gM)
+            for (int c = 0; c < q; ++c) any_g |= (a.gM[mb + c] != 0.0);
+        if (act && !any_g && a.w_frob == 0.0) act = false;
+        for (int t = gl; t < BHSI; t += G) S.hI[t] = HEMPTY;
+        if (act) {
+            for (int t = gl; t < q; t += G) S.Jl[t] = a.Mrowidx[mb + t];
+            if (gl == 0) S.cnt = 0;
+        }
+        __syncthreads();
+        // ---- I_k: rows of A(:, J_k)
+        bool ovf = false;
+        if (act) {
+            for (int c = 0; c < q; ++c) {
+                const int j = S.Jl[c];
+                for (int64_t e = A.colptr[j] + gl; e < A.colptr[j + 1]; e += G) {
+                    int sl;
+                    if (hinsert<BLOGHSI>(S.hI, A.rowidx[e], sl)) {
+                        int ps = atomicAdd(&S.cnt, 1);
+                        if (ps < MMAX) { S.newk[ps] = A.rowidx[e]; S.news[ps] = sl; }
+                    }
+                }
+                // keep the table below MMAX + one column: checked after each column
+                if (S.cnt > MMAX) { ovf = true; break; }
+            }
+        }
+        __syncthreads();
+        if (act) {
+            m = S.cnt;
+            if (m > MMAX || ovf) {
+                if (gl == 0) atomicOr(a.err, 8);
+                act = false;
+            }
+        }
+        int kidx = -1;
+        if (act) {
+            for (int s = 0; s < (MMAX + G - 1) / G; ++s) {
+                const int idx = s * G + gl;
+                if (idx < m) {
+                    const int key = S.newk[idx];
+                    int rank = 0;
+                    for (int t = 0; t < m; ++t) rank += (S.newk[t] < key) ? 1 : 0;
+                    S.Il[rank] = key;
+                    S.hIv[S.news[idx]] = rank;
+                    if (key == (int)k) kidx = rank;
+                }
+            }
+        }
+        kidx = gmax_i<G>(kidx);
+        __syncthreads();
+        // ---- gather A(I, J) into registers
+        double b[RPL][QMAX];
+        double y[RPL];
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            y[r] = (act && r * G + gl == kidx) ? 1.0 : 0.0;
+#pragma unroll
+            for (int c = 0; c < QMAX; ++c) b[r][c] = 0.0;
+        }
+        const int qmaxw = wave_max_i(act ? q : 0);
+        for (int c0 = 0; c0 < qmaxw; c0 += BSTAGE) {
+#pragma unroll
+            for (int s = 0; s < BSTAGE; ++s)
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) S.stage[s * MMAX + r * G + gl] = 0.0;
+            __syncthreads();
+            if (act) {
+#pragma unroll
+                for (int s = 0; s < BSTAGE; ++s) {
+                    const int c = c0 + s;
+                    if (c < q) {
+                        const int j = S.Jl[c];
+                        for (int64_t e = A.colptr[j] + gl; e < A.colptr[j + 1]; e += G) {
+                            const int sl = hfind<BLOGHSI>(S.hI, A.rowidx[e]);
+                            const int li = sl >= 0 ? S.hIv[sl] : -1;
+                            if (li >= 0 && li < MMAX) S.stage[s * MMAX + li] = A.val[e];
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            if (act) {
+#pragma unroll
+                for (int c = 0; c < QMAX; ++c) {
+                    const int s = c - c0;
+                    if (s >= 0 && s < BSTAGE && c < q)
+#pragma unroll
+                        for (int r = 0; r < RPL; ++r) b[r][c] = S.stage[s * MMAX + r * G + gl];
+                }
+            }
+            __syncthreads();
+        }
+        // ---- Householder QR of A(I, J) and Q^T e
+#pragma unroll
+        for (int j = 0; j < QMAX; ++j) {
+            if (j >= qmaxw) continue;
+            const bool ja = act && j < q;
+            double s2 = 0.0, x0p = 0.0;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int i = r * G + gl;
+                if (i >= j) s2 += b[r][j] * b[r][j];
+                if (i == j) x0p = b[r][j];
+            }
+            s2 = gsum<G>(s2);
+            const double x0 = gsum<G>(x0p);
+            const double nx = sqrt(s2);
+            const double alpha = (x0 >= 0.0) ? -nx : nx;
+            const double vj = x0 - alpha;
+            const double bj = (nx > 0.0) ? 1.0 / (nx * (nx + fabs(x0))) : 0.0;
+            if (ja) {
+#pragma unroll
+                for (int r = 0; r < RPL; ++r)
+                    if (r * G + gl == j) b[r][j] = vj;
+                if (gl == j % G) { S.rdiag[j] = alpha; S.beta[j] = bj; }
+            }
+#pragma unroll
+            for (int c = 0; c < QMAX; ++c) {
+                    if (c <= j) continue;
+                if (c >= qmaxw) continue;
+                double w = 0.0;
+#pragma unroll
+                for (int r = 0; r < RPL; ++r)
+                    if (r * G + gl >= j) w += b[r][j] * b[r][c];
+                w = gsum<G>(w);
+                if (ja && c < q) {
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r)
+                        if (r * G + gl >= j) b[r][c] -= bj * w * b[r][j];
+                }
+            }
+            double w = 0.0;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r)
+                if (r * G + gl >= j) w += b[r][j] * y[r];
+            w = gsum<G>(w);
+            if (ja) {
+#pragma unroll
+                for (int r = 0; r < RPL; ++r)
+                    if (r * G + gl >= j) y[r] -= bj * w * b[r][j];
+            }
+        }
+        __syncthreads();  // rdiag / beta visible to every lane of the group
+        // ---- u = R^{-T} g (forward substitution over the rows of R); lane keeps
+        // u_i for its own rows in ul
+        double ul[RPL];
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) ul[r] = 0.0;
+#pragma unroll
+        for (int j = 0; j < QMAX; ++j) {
+            if (j >= qmaxw) continue;
+            double part = 0.0;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r)
+                if (r * G + gl < j) part += b[r][j] * ul[r];
+            part = gsum<G>(part);
+            double uj = 0.0;
+            if (act && j < q) uj = ((a.gM ? a.gM[mb + j] : 0.0) - part) / S.rdiag[j];
+            if (gl == j % G) ul[j / G] = uj;
+        }
+        // ---- z = R^{-1} u (back substitution); z_j goes to LDS
+        {
+            double t[RPL];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) t[r] = ul[r];
+#pragma unroll
+            for (int j = QMAX - 1; j >= 0; --j) {
+                if (j >= qmaxw) continue;
+                double val = 0.0;
+                if (gl == j % G && act && j < q) val = t[j / G] / S.rdiag[j];
+                const double zj = gsum<G>(val);
+                if (act && j < q) {
+                    if (gl == 0) S.zS[j] = zj;
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r)
+                        if (r * G + gl < j) t[r] -= b[r][j] * zj;
+                }
+            }
+        }
+        // ---- A_k z = Q [u; 0] and r = -Q [0; (Q^T e)(q:m)]: reflectors in reverse
+        double az[RPL], rr[RPL];
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int i = r * G + gl;
+            az[r] = (i < q) ? ul[r] : 0.0;
+            rr[r] = (i >= q && i < m) ? y[r] : 0.0;
+        }
+#pragma unroll
+        for (int j = QMAX - 1; j >= 0; --j) {
+            if (j >= qmaxw) continue;
+            double w1 = 0.0, w2 = 0.0;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r)
+                if (r * G + gl >= j) {
+                    w1 += b[r][j] * az[r];
+                    w2 += b[r][j] * rr[r];
+                }
+            w1 = gsum<G>(w1);
+            w2 = gsum<G>(w2);
+            if (act && j < q) {
+                const double bj = S.beta[j];
+#pragma unroll
+                for (int r = 0; r < RPL; ++r)
+                    if (r * G + gl >= j) {
+                        az[r] -= bj * w1 * b[r][j];
+                        rr[r] -= bj * w2 * b[r][j];
+                    }
+            }
+        }
+        // stage r (negated: r = -z) and A_k z per local row
+        if (act) {
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int i = r * G + gl;
+                S.stage[i] = -rr[r];
+                S.stage[MMAX + i] = az[r];
+            }
+        }
+        __syncthreads();
+        // ---- scatter onto the nonzeros of A(:, J_k)
+        if (act) {
+            const double w2 = 2.0 * a.w_frob;
+#pragma unroll
+            for (int c = 0; c < QMAX; ++c) {
+                if (c < q) {
+                    const int j = S.Jl[c];
+                    const double zc = S.zS[c], mc = a.Mval[mb + c];
+                    for (int64_t e = A.colptr[j] + gl; e < A.colptr[j + 1]; e += G) {
+                        const int sl = hfind<BLOGHSI>(S.hI, A.rowidx[e]);
+                        const int li = sl >= 0 ? S.hIv[sl] : -1;
+                        if (li < 0) continue;
+                        const double ri = S.stage[li], azi = S.stage[MMAX + li];
+                        const double g = -(ri * zc + azi * mc) + w2 * ri * mc;
+                        atomicAdd(&a.dA[e], g);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+void launch_backward(const BwdArgs &a, int waves, hipStream_t s) {
+    hipLaunchKernelGGL(backward_kernel, dim3(waves), dim3(64), 0, s, a);
+}
+
+}  // namespace rsai

@@ -1,0 +1,196 @@
+// Device-side shared definitions of the RSAI(tol) kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rsai {
+
+// ----------------------------------------------------------------- per-build data
+
+struct MatDev {              // one matrix of a (possibly batched) build
+    int64_t n;
+    const int64_t *colptr;   // CSC of A (borrowed)
+    const int32_t *rowidx;
+    const double *val;
+    const int64_t *rowptr;   // row pattern of A (transpose), built by the library
+    const int32_t *colidx;
+    double norm1;            // ||A||_1, max column absolute sum (eq. (4.3))
+    int64_t col_base;        // global id of the matrix's first column in the batch
+};
+
+struct BuildParams {
+    int c, lmax, drop;
+    double eps, tol;
+};
+
+enum : int { DROP_NONE = 0, DROP_FIXED = 1, DROP_ADAPTIVE = 2 };
+enum : int { ST_OK = 0, ST_SINGULAR = 3, ST_CAP = 6, ST_INTERNAL = 7 };
+
+constexpr int CMAX = 8;      // largest c supported (dominant rows per loop)
+
+struct ColOut {              // per global column
+    int64_t *off;            // arena offset of the column's result
+    int32_t *nJ, *nI, *loops, *status;
+    double *resnorm, *flops;
+    int32_t *arenaJ;         // arena of J lists (global column ids, solve order)
+    double *arenaV;          // arena of values
+};
+
+// ----------------------------------------------------------------- DPP helpers
+// Data-parallel-primitive lane moves within a 16-lane row. Patterns used:
+//   0xB1 quad_perm [1,0,3,2] (xor 1), 0x4E quad_perm [2,3,0,1] (xor 2),
+//   0x141 row_half_mirror (i <-> 7-i in each 8), 0x140 row_mirror (i <-> 15-i).
+// Each pairs lane i with a lane of the other half of its aligned 2/4/8/16-group,
+// so applying them in order all-reduces over aligned groups of G <= 16 lanes, and
+// every lane of a group ends with the bitwise-identical result (a+b == b+a).
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int x) {
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    long long b = __double_as_longlong(x);
+    int lo = (int)(b & 0xffffffffLL);
+    int hi = (int)(b >> 32);
+    lo = dpp_i32<CTRL>(lo);
+    hi = dpp_i32<CTRL>(hi);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <int G>
+__device__ __forceinline__ double gsum(double x) {
+    static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "group size");
+    if constexpr (G >= 2) x = x + dpp_f64<0xB1>(x);
+    if constexpr (G >= 4) x = x + dpp_f64<0x4E>(x);
+    if constexpr (G >= 8) x = x + dpp_f64<0x141>(x);
+    if constexpr (G >= 16) x = x + dpp_f64<0x140>(x);
+    return x;
+}
+
+template <int G>
+__device__ __forceinline__ int gsum_i(int x) {
+    if constexpr (G >= 2) x = x + dpp_i32<0xB1>(x);
+    if constexpr (G >= 4) x = x + dpp_i32<0x4E>(x);
+    if constexpr (G >= 8) x = x + dpp_i32<0x141>(x);
+    if constexpr (G >= 16) x = x + dpp_i32<0x140>(x);
+    return x;
+}
+
+template <int G>
+__device__ __forceinline__ int gmax_i(int x) {
+    if constexpr (G >= 2) x = max(x, dpp_i32<0xB1>(x));
+    if constexpr (G >= 4) x = max(x, dpp_i32<0x4E>(x));
+    if constexpr (G >= 8) x = max(x, dpp_i32<0x141>(x));
+    if constexpr (G >= 16) x = max(x, dpp_i32<0x140>(x));
+    return x;
+}
+
+template <int CTRL>
+__device__ __forceinline__ void amax_step(double &a, int &g) {
+    double a2 = dpp_f64<CTRL>(a);
+    int g2 = dpp_i32<CTRL>(g);
+    bool take = (a2 > a) || (a2 == a && g2 < g);
+    a = take ? a2 : a;
+    g = take ? g2 : g;
+}
+
+// Group arg-max with key (a descending, g ascending): the dominant-row order with
+// ties going to the smaller global row index.
+template <int G>
+__device__ __forceinline__ void gargmax(double &a, int &g) {
+    if constexpr (G >= 2) amax_step<0xB1>(a, g);
+    if constexpr (G >= 4) amax_step<0x4E>(a, g);
+    if constexpr (G >= 8) amax_step<0x141>(a, g);
+    if constexpr (G >= 16) amax_step<0x140>(a, g);
+}
+
+// Value of x held by group lane `src` (others contribute exact zeros).
+template <int G>
+__device__ __forceinline__ double gbcast(double x, bool is_src) {
+    return gsum<G>(is_src ? x : 0.0);
+}
+template <int G>
+__device__ __forceinline__ int gbcast_i(int x, bool is_src) {
+    return gsum_i<G>(is_src ? x : 0);
+}
+
+// Wave-wide max of an int (all 64 lanes): row reduction then 4 lane reads.
+__device__ __forceinline__ int wave_max_i(int x) {
+    x = gmax_i<16>(x);
+    int a = __builtin_amdgcn_readlane(x, 0);
+    int b = __builtin_amdgcn_readlane(x, 16);
+    int c = __builtin_amdgcn_readlane(x, 32);
+    int d = __builtin_amdgcn_readlane(x, 48);
+    return max(max(a, b), max(c, d));
+}
+
+__device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0; }
+__device__ __forceinline__ bool wave_all(bool p) { return __ballot(!p) == 0; }
+
+// ----------------------------------------------------------------- LDS hash sets
+// Open addressing with linear probing, keys are global indices (>= 0), EMPTY = -1.
+// Callers keep the load below the table size so that probing always ends.
+
+constexpr int HEMPTY = -1;
+
+template <int LOGHS>
+__device__ __forceinline__ unsigned hslot(int key) {
+    return ((unsigned)key * 0x9E3779B1u) >> (32 - LOGHS);
+}
+
+// Insert key; returns true if it was not present. slot receives its position.
+template <int LOGHS>
+__device__ __forceinline__ bool hinsert(int *hk, int key, int &slot) {
+    constexpr unsigned MASK = (1u << LOGHS) - 1u;
+    unsigned h = hslot<LOGHS>(key);
+    for (int probe = 0; probe < (1 << LOGHS); ++probe) {
+        int old = atomicCAS(&hk[h], HEMPTY, key);
+        if (old == HEMPTY) { slot = (int)h; return true; }
+        if (old == key) { slot = (int)h; return false; }
+        h = (h + 1u) & MASK;
+    }
+    slot = -1;  // table full: callers size tables so this cannot happen
+    return false;
+}
+
+// Slot of key, or -1.
+template <int LOGHS>
+__device__ __forceinline__ int hfind(const int *hk, int key) {
+    constexpr unsigned MASK = (1u << LOGHS) - 1u;
+    unsigned h = hslot<LOGHS>(key);
+    for (int probe = 0; probe < (1 << LOGHS); ++probe) {
+        int v = hk[h];
+        if (v == key) return (int)h;
+        if (v == HEMPTY) return -1;
+        h = (h + 1u) & MASK;
+    }
+    return -1;
+}
+
+constexpr int ilog2ceil(int x) {
+    int l = 0;
+    while ((1 << l) < x) ++l;
+    return l;
+}
+
+// Algorithmic flops of one Householder-update LS solve: qlo kept columns, qn - qlo
+// new ones, m rows (update of the new columns by the stored reflectors, new
+// reflectors applied to the trailing columns and to Q^T e, back substitution and
+// the residual norm ||(Q^T e)(qn:m)||).
+__host__ __device__ inline double solve_flops(int m, int qlo, int qn) {
+    double f = 0.0;
+    double p = (double)(qn - qlo);
+    // sum_{j<qlo} 4 (m-j) p
+    f += 4.0 * p * ((double)qlo * m - 0.5 * (double)qlo * (qlo - 1));
+    for (int j = qlo; j < qn; ++j) {
+        double mj = (double)(m - j);
+        f += mj * (2.0 + 4.0 * (double)(qn - j - 1) + 4.0);
+    }
+    f += (double)qn * qn + 2.0 * (double)(m - qn);
+    return f;
+}
+
+}  // namespace rsai

@@ -1,0 +1,639 @@
+// C ABI of the RSAI(tol) library: plan object, device memory, launch sequence.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rsai.h"
+#include "rsai_kernels.h"
+
+using namespace rsai;
+
+namespace {
+
+thread_local std::string g_err = "";
+
+struct Alloc {
+    rsai_alloc_fn alloc = nullptr;
+    rsai_free_fn dealloc = nullptr;
+    void *ctx = nullptr;
+} g_alloc;
+
+rsai_status fail(rsai_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIPCHK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return fail(RSAI_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+void *dev_alloc(size_t bytes, hipStream_t s) {
+    if (bytes == 0) bytes = 8;
+    if (g_alloc.alloc) return g_alloc.alloc(bytes, (void *)s, g_alloc.ctx);
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+}
+void dev_free(void *p, hipStream_t s) {
+    if (!p) return;
+    if (g_alloc.dealloc) g_alloc.dealloc(p, (void *)s, g_alloc.ctx);
+    else (void)hipFree(p);
+}
+
+}  // namespace
+
+struct MatPlan {
+    rsai_csc A{};
+    int64_t col_base = 0;
+    int64_t *rowptr = nullptr;
+    int32_t *colidx = nullptr;
+    int32_t *rowcnt = nullptr;
+    double norm1 = 0.0;
+    int64_t g = 0;
+    int64_t *colptrM = nullptr;
+    int32_t *rowidxM = nullptr;
+    double *valM = nullptr;
+    int64_t capM = 0;
+    int64_t nnzM = -1;
+    int32_t maxq = -1, maxm = -1;  // largest final |J_k| and |I_k| (first backward)
+    // transpose of M (rows) for y = M x
+    int64_t *rowptrT = nullptr;
+    int32_t *colidxT = nullptr;
+    double *valT = nullptr;
+};
+
+struct rsai_plan {
+    rsai_params p{};
+    hipStream_t stream = nullptr;
+    std::vector<MatPlan> mats;
+    std::vector<MatDev> hmats;
+    std::vector<int64_t> hcolbase;
+    int64_t ncols = 0;
+    MatDev *d_mats = nullptr;
+    int64_t *d_colbase = nullptr;
+    ColOut out{};
+    int64_t arena_cap = 0;
+    int32_t *rec[8] = {};
+    int32_t *rec_count = nullptr;
+    int32_t *err = nullptr;
+    unsigned long long *stats = nullptr;
+    int64_t *scan_tmp = nullptr;
+    std::vector<void *> owned;
+    hipEvent_t ev[8] = {};
+    bool recorded[8] = {};
+    bool have_events = false;
+    void record(int i, hipStream_t s) {
+        if (have_events && hipEventRecord(ev[i], s) == hipSuccess) recorded[i] = true;
+    }
+    int ntiers_used = 0;
+
+    template <class T>
+    T *alloc(int64_t count, rsai_status &st) {
+        if (st != RSAI_OK) return nullptr;
+        void *q = dev_alloc(sizeof(T) * (size_t)std::max<int64_t>(count, 1), stream);
+        if (!q) {
+            st = fail(RSAI_E_NOMEM, "device allocation of %lld bytes failed", (long long)(sizeof(T) * count));
+            return nullptr;
+        }
+        owned.push_back(q);
+        return (T *)q;
+    }
+    void release() {
+        if (stream) (void)hipStreamSynchronize(stream);
+        else (void)hipDeviceSynchronize();
+        for (void *q : owned) dev_free(q, stream);
+        owned.clear();
+        if (have_events)
+            for (auto &e : ev) (void)hipEventDestroy(e);
+        have_events = false;
+    }
+};
+
+static rsai_status check_params(const rsai_params *p) {
+    if (!p) return fail(RSAI_E_ARG, "params is NULL");
+    if (p->c < 1 || p->c > CMAX) return fail(RSAI_E_ARG, "c must be in 1..%d", CMAX);
+    if (p->lmax < 0 || p->lmax > 64) return fail(RSAI_E_ARG, "lmax must be in 0..64");
+    if (!(p->eps >= 0.0)) return fail(RSAI_E_ARG, "eps must be >= 0");
+    if (p->drop < 0 || p->drop > 2) return fail(RSAI_E_ARG, "drop mode must be 0, 1 or 2");
+    if (p->drop == 1 && !(p->tol >= 0.0)) return fail(RSAI_E_ARG, "tol must be >= 0");
+    if (p->sched < 0 || p->sched > 1) return fail(RSAI_E_ARG, "sched must be 0 or 1");
+    if (p->tier0 < -1 || p->tier0 >= kNumTiers) return fail(RSAI_E_ARG, "tier0 out of range");
+    return RSAI_OK;
+}
+
+extern "C" {
+
+rsai_status rsai_params_default(rsai_params *p) {
+    if (!p) return fail(RSAI_E_ARG, "params is NULL");
+    std::memset(p, 0, sizeof(*p));
+    p->c = 3;
+    p->lmax = 10;
+    p->eps = 0.4;
+    p->drop = RSAI_DROP_FIXED;
+    p->tol = 1e-3;
+    p->sched = RSAI_SCHED_BATCHED;
+    p->validate = 1;
+    p->tier0 = -1;
+    p->timing = 0;
+    p->keep_factors = 0;
+    p->factor_budget_bytes = 0;
+    return RSAI_OK;
+}
+
+rsai_status rsai_set_allocator(rsai_alloc_fn alloc, rsai_free_fn dealloc, void *ctx) {
+    if ((alloc == nullptr) != (dealloc == nullptr)) return fail(RSAI_E_ARG, "alloc and dealloc must both be set");
+    g_alloc.alloc = alloc;
+    g_alloc.dealloc = dealloc;
+    g_alloc.ctx = ctx;
+    return RSAI_OK;
+}
+
+const char *rsai_last_error(void) { return g_err.c_str(); }
+
+rsai_status rsai_tier_info(int32_t t, int32_t *lanes, int32_t *max_rows, int32_t *max_cols) {
+    if (t < 0 || t >= kNumTiers) return fail(RSAI_E_ARG, "no tier %d", t);
+    if (lanes) *lanes = kTiers[t].G;
+    if (max_rows) *max_rows = kTiers[t].MMAX;
+    if (max_cols) *max_cols = kTiers[t].QMAX;
+    return RSAI_OK;
+}
+
+static int device_cus() {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+        if (cus <= 0) cus = 256;
+    }
+    return cus;
+}
+
+static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_params *prm, void *stream,
+                              rsai_plan **out) {
+    if (!out) return fail(RSAI_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || !As) return fail(RSAI_E_ARG, "need at least one matrix");
+    rsai_status st = check_params(prm);
+    if (st != RSAI_OK) return st;
+    for (int i = 0; i < count; ++i) {
+        const rsai_csc &A = As[i];
+        if (A.n < 1 || A.n > INT32_MAX - 1 || A.nnz < A.n || !A.colptr || !A.rowidx || !A.val)
+            return fail(RSAI_E_ARG, "matrix %d: bad sizes or NULL pointers", i);
+    }
+    (void)hipGetLastError();  // clear an error left by an unrelated earlier call
+    rsai_plan *P = new rsai_plan();
+    P->p = *prm;
+    P->stream = (hipStream_t)stream;
+    hipStream_t s = P->stream;
+    auto bail = [&](rsai_status code) {
+        P->release();
+        delete P;
+        return code;
+    };
+    if (P->p.timing) {
+        for (auto &e : P->ev)
+            if (hipEventCreate(&e) != hipSuccess) return bail(fail(RSAI_E_HIP, "hipEventCreate failed"));
+        P->have_events = true;
+        P->record(0, s);
+    }
+    P->mats.resize(count);
+    P->hcolbase.resize(count + 1);
+    int64_t ncols = 0;
+    for (int i = 0; i < count; ++i) {
+        P->mats[i].A = As[i];
+        P->mats[i].col_base = ncols;
+        P->hcolbase[i] = ncols;
+        ncols += As[i].n;
+    }
+    P->hcolbase[count] = ncols;
+    P->ncols = ncols;
+
+    // ---- preprocessing: contract check, row pattern, g, ||A||_1
+    P->err = P->alloc<int32_t>(4, st);
+    P->stats = P->alloc<unsigned long long>(2 * (int64_t)count, st);
+    int64_t maxn = 0;
+    for (int i = 0; i < count; ++i) maxn = std::max(maxn, As[i].n);
+    P->scan_tmp = P->alloc<int64_t>(scan_tmp_elems(std::max(maxn, ncols) + 1), st);
+    if (st != RSAI_OK) return bail(st);
+    launch_fill_i32(P->err, 0, 4, s);
+    launch_fill_i64((int64_t *)P->stats, 0, 2 * count, s);
+    if (P->p.validate) {
+        for (int i = 0; i < count; ++i) launch_validate(As[i].n, As[i].nnz, As[i].colptr, As[i].rowidx, P->err, s);
+        int32_t herr = 0;
+        if (hipMemcpyAsync(&herr, P->err, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return bail(fail(RSAI_E_HIP, "validation readback failed"));
+        if (herr) {
+            return bail(fail(RSAI_E_CSC, "malformed CSC (flags %d: 1 colptr, 2 row indices, 4 empty column)", herr));
+        }
+    }
+    for (int i = 0; i < count; ++i) {
+        MatPlan &M = P->mats[i];
+        const int64_t n = As[i].n, nnz = As[i].nnz;
+        M.rowptr = P->alloc<int64_t>(n + 1, st);
+        M.colidx = P->alloc<int32_t>(nnz, st);
+        M.rowcnt = P->alloc<int32_t>(n, st);
+        int32_t *fillpos = P->alloc<int32_t>(n, st);
+        if (st != RSAI_OK) return bail(st);
+        launch_fill_i32(M.rowcnt, 0, n, s);
+        launch_fill_i32(fillpos, 0, n, s);
+        launch_row_counts(nnz, As[i].rowidx, M.rowcnt, s);
+        launch_scan_i32(M.rowcnt, n, M.rowptr, P->scan_tmp, s);
+        launch_row_fill(n, As[i].colptr, As[i].rowidx, M.rowptr, fillpos, M.colidx, s);
+        launch_mat_stats(n, As[i].colptr, As[i].val, M.rowcnt, P->stats + 2 * i, s);
+    }
+    std::vector<unsigned long long> hstats(2 * count);
+    if (hipMemcpyAsync(hstats.data(), P->stats, sizeof(unsigned long long) * 2 * count, hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return bail(fail(RSAI_E_HIP, "preprocessing readback failed"));
+    P->hmats.resize(count);
+    for (int i = 0; i < count; ++i) {
+        MatPlan &M = P->mats[i];
+        M.g = (int64_t)hstats[2 * i];
+        unsigned long long bits = hstats[2 * i + 1];
+        std::memcpy(&M.norm1, &bits, sizeof(double));
+        MatDev &D = P->hmats[i];
+        D.n = As[i].n;
+        D.colptr = As[i].colptr;
+        D.rowidx = As[i].rowidx;
+        D.val = As[i].val;
+        D.rowptr = M.rowptr;
+        D.colidx = M.colidx;
+        D.norm1 = M.norm1;
+        D.col_base = M.col_base;
+    }
+    P->d_mats = P->alloc<MatDev>(count, st);
+    P->d_colbase = P->alloc<int64_t>(count + 1, st);
+    if (st != RSAI_OK) return bail(st);
+    if (hipMemcpyAsync(P->d_mats, P->hmats.data(), sizeof(MatDev) * count, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(P->d_colbase, P->hcolbase.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice, s) !=
+            hipSuccess)
+        return bail(fail(RSAI_E_HIP, "matrix table upload failed"));
+    P->record(1, s);
+
+    // ---- per-column outputs and the result arena: one slot of QMAX entries per
+    // column for every size class that may finish it
+    const bool plain = (P->p.sched == RSAI_SCHED_PLAIN);
+    const int t0 = plain ? kPlainTier : ((P->p.tier0 >= 0) ? P->p.tier0 : 0);
+    const int tlast = plain ? kPlainTier : kNumTiers - 1;
+    int64_t slot_base[8] = {};
+    int64_t acap = 0;
+    for (int t = t0; t <= tlast; ++t) {
+        slot_base[t] = acap;
+        acap += ncols * (int64_t)kTiers[t].QMAX;
+    }
+    P->arena_cap = acap;
+    P->out.off = P->alloc<int64_t>(ncols, st);
+    P->out.nJ = P->alloc<int32_t>(ncols, st);
+    P->out.nI = P->alloc<int32_t>(ncols, st);
+    P->out.loops = P->alloc<int32_t>(ncols, st);
+    P->out.status = P->alloc<int32_t>(ncols, st);
+    P->out.resnorm = P->alloc<double>(ncols, st);
+    P->out.flops = P->alloc<double>(ncols, st);
+    P->out.arenaJ = P->alloc<int32_t>(acap, st);
+    P->out.arenaV = P->alloc<double>(acap, st);
+    const int nlaunch = plain ? P->p.lmax + 1 : (tlast - t0 + 1);
+    P->rec_count = P->alloc<int32_t>(nlaunch + 1, st);
+    if (plain) {
+        P->rec[0] = P->alloc<int32_t>(ncols * (int64_t)kTiers[kPlainTier].REC, st);
+        P->rec[1] = P->alloc<int32_t>(ncols * (int64_t)kTiers[kPlainTier].REC, st);
+    } else {
+        for (int t = t0; t < tlast; ++t) P->rec[t] = P->alloc<int32_t>(ncols * (int64_t)kTiers[t].REC, st);
+    }
+    if (st != RSAI_OK) return bail(st);
+    launch_fill_i32(P->rec_count, 0, nlaunch + 1, s);
+    launch_fill_i32(P->out.status, ST_INTERNAL, ncols, s);  // every column must be written
+    launch_fill_i32(P->out.nJ, 0, ncols, s);
+
+    TierArgs base{};
+    base.mats = P->d_mats;
+    base.nmat = count;
+    base.col_base = P->d_colbase;
+    base.P.c = P->p.c;
+    base.P.lmax = P->p.lmax;
+    base.P.drop = P->p.drop;
+    base.P.eps = P->p.eps;
+    base.P.tol = P->p.tol;
+    base.out = P->out;
+    base.qlen = ncols;
+    base.err = P->err;
+    const int cus = device_cus();
+    if (plain) {
+        // ---- plain schedule: one size class, one launch per loop of Algorithm 1;
+        // the state of every unfinished column goes through HBM between launches
+        const int t = kPlainTier;
+        const int gpw = 64 / kTiers[t].G;
+        for (int L = 0; L < nlaunch; ++L) {
+            TierArgs a = base;
+            a.arena_base = slot_base[t];
+            a.one_loop = 1;
+            if (L == 0) {
+                a.rec_in = nullptr;
+            } else {
+                a.rec_in = P->rec[(L - 1) % 2];
+                a.rec_in_stride = kTiers[t].REC;
+                a.rec_in_count = P->rec_count + (L - 1);
+                a.rec_in_cap = ncols;
+            }
+            a.rec_out = P->rec[L % 2];
+            a.rec_out_stride = kTiers[t].REC;
+            a.rec_out_count = P->rec_count + L;
+            a.rec_out_cap = ncols;
+            int64_t want = (L == 0) ? (ncols + gpw - 1) / gpw : (int64_t)cus * 8;
+            int waves = (int)std::max<int64_t>(8, std::min<int64_t>(want, (int64_t)cus * 16));
+            waves = (waves + 7) / 8 * 8;
+            launch_tier_kernel(t, a, waves, s);
+        }
+        P->record(2, s);
+    } else {
+        for (int t = t0; t <= tlast; ++t) {
+            TierArgs a = base;
+            a.arena_base = slot_base[t];
+            a.one_loop = 0;
+            if (t == t0) {
+                a.rec_in = nullptr;
+            } else {
+                a.rec_in = P->rec[t - 1];
+                a.rec_in_stride = kTiers[t - 1].REC;
+                a.rec_in_count = P->rec_count + (t - t0 - 1);
+                a.rec_in_cap = ncols;
+            }
+            if (t < tlast) {
+                a.rec_out = P->rec[t];
+                a.rec_out_stride = kTiers[t].REC;
+                a.rec_out_count = P->rec_count + (t - t0);
+                a.rec_out_cap = ncols;
+            } else {
+                a.rec_out = nullptr;
+            }
+            const int gpw = 64 / kTiers[t].G;
+            int64_t want = (t == t0) ? (ncols + gpw - 1) / gpw : (int64_t)cus * 8;
+            int waves = (int)std::max<int64_t>(8, std::min<int64_t>(want, (int64_t)cus * 16));
+            waves = (waves + 7) / 8 * 8;
+            launch_tier_kernel(t, a, waves, s);
+            if (t == t0) P->record(2, s);
+        }
+    }
+    P->ntiers_used = tlast - t0 + 1;
+    P->record(3, s);
+
+    // ---- assembly of M per matrix: colptr = scan(nJ), then sort + copy
+    const int64_t qlast = kTiers[tlast].QMAX;
+    for (int i = 0; i < count; ++i) {
+        MatPlan &M = P->mats[i];
+        const int64_t n = As[i].n;
+        M.capM = n * qlast;
+        M.colptrM = P->alloc<int64_t>(n + 1, st);
+        M.rowidxM = P->alloc<int32_t>(M.capM, st);
+        M.valM = P->alloc<double>(M.capM, st);
+        if (st != RSAI_OK) return bail(st);
+        launch_scan_i32(P->out.nJ + M.col_base, n, M.colptrM, P->scan_tmp, s);
+        launch_assemble(n, P->out.off + M.col_base, P->out.nJ + M.col_base, M.colptrM, P->out.arenaJ, P->out.arenaV,
+                        M.rowidxM, M.valM, s);
+    }
+    P->record(4, s);
+    hipError_t le = hipGetLastError();
+    if (le != hipSuccess) return bail(fail(RSAI_E_HIP, "launch failed: %s", hipGetErrorString(le)));
+    *out = P;
+    return RSAI_OK;
+}
+
+rsai_status rsai_build(const rsai_csc *A, const rsai_params *p, void *stream, rsai_plan **out) {
+    return build_impl(1, A, p, stream, out);
+}
+
+rsai_status rsai_build_batched(int32_t count, const rsai_csc *A, const rsai_params *p, void *stream,
+                               rsai_plan **out) {
+    return build_impl(count, A, p, stream, out);
+}
+
+rsai_status rsai_plan_count(const rsai_plan *P, int32_t *count) {
+    if (!P || !count) return fail(RSAI_E_ARG, "NULL argument");
+    *count = (int32_t)P->mats.size();
+    return RSAI_OK;
+}
+
+static rsai_status check_mat(const rsai_plan *P, int32_t mat) {
+    if (!P) return fail(RSAI_E_ARG, "plan is NULL");
+    if (mat < 0 || mat >= (int32_t)P->mats.size()) return fail(RSAI_E_ARG, "matrix index %d out of range", mat);
+    return RSAI_OK;
+}
+
+rsai_status rsai_plan_nnz(const rsai_plan *Pc, int32_t mat, int64_t *nnzM) {
+    rsai_status st = check_mat(Pc, mat);
+    if (st != RSAI_OK) return st;
+    if (!nnzM) return fail(RSAI_E_ARG, "nnzM is NULL");
+    rsai_plan *P = const_cast<rsai_plan *>(Pc);
+    MatPlan &M = P->mats[mat];
+    if (M.nnzM < 0) {
+        const int64_t n = M.A.n;
+        int64_t nz = 0;
+        int32_t herr = 0;
+        HIPCHK(hipMemcpyAsync(&nz, M.colptrM + n, sizeof(int64_t), hipMemcpyDeviceToHost, P->stream));
+        HIPCHK(hipMemcpyAsync(&herr, P->err, sizeof(int32_t), hipMemcpyDeviceToHost, P->stream));
+        std::vector<int32_t> stv((size_t)n);
+        HIPCHK(hipMemcpyAsync(stv.data(), P->out.status + M.col_base, sizeof(int32_t) * n, hipMemcpyDeviceToHost,
+                              P->stream));
+        HIPCHK(hipStreamSynchronize(P->stream));
+        if (herr) return fail(RSAI_E_STATE, "internal index error (flags %d)", herr);
+        int64_t nsing = 0, ncap = 0, nbad = 0;
+        for (int64_t k = 0; k < n; ++k) {
+            if (stv[k] == ST_SINGULAR) ++nsing;
+            else if (stv[k] == ST_CAP) ++ncap;
+            else if (stv[k] != ST_OK) ++nbad;
+        }
+        if (nbad) return fail(RSAI_E_STATE, "%lld columns were not processed", (long long)nbad);
+        if (nsing) return fail(RSAI_E_SINGULAR, "%lld columns have a rank-deficient LS problem", (long long)nsing);
+        if (ncap) return fail(RSAI_E_CAP, "%lld columns outgrew the largest supported LS size", (long long)ncap);
+        M.nnzM = nz;
+    }
+    *nnzM = M.nnzM;
+    return RSAI_OK;
+}
+
+rsai_status rsai_export_M(const rsai_plan *P, int32_t mat, int64_t *colptr, int32_t *rowidx, double *val,
+                          void *stream) {
+    int64_t nz = 0;
+    rsai_status st = rsai_plan_nnz(P, mat, &nz);
+    if (st != RSAI_OK) return st;
+    const MatPlan &M = P->mats[mat];
+    hipStream_t s = (hipStream_t)stream;
+    if (colptr) HIPCHK(hipMemcpyAsync(colptr, M.colptrM, sizeof(int64_t) * (M.A.n + 1), hipMemcpyDeviceToDevice, s));
+    if (rowidx && nz) HIPCHK(hipMemcpyAsync(rowidx, M.rowidxM, sizeof(int32_t) * nz, hipMemcpyDeviceToDevice, s));
+    if (val && nz) HIPCHK(hipMemcpyAsync(val, M.valM, sizeof(double) * nz, hipMemcpyDeviceToDevice, s));
+    return RSAI_OK;
+}
+
+rsai_status rsai_export_stats(const rsai_plan *P, int32_t mat, int32_t *loops, double *resnorm, int32_t *nI,
+                              int32_t *nJ, double *flops, int32_t *status, void *stream) {
+    rsai_status st = check_mat(P, mat);
+    if (st != RSAI_OK) return st;
+    const MatPlan &M = P->mats[mat];
+    const int64_t n = M.A.n, b = M.col_base;
+    hipStream_t s = (hipStream_t)stream;
+    if (s != P->stream) HIPCHK(hipStreamSynchronize(P->stream));
+    if (loops) HIPCHK(hipMemcpyAsync(loops, P->out.loops + b, 4 * n, hipMemcpyDeviceToDevice, s));
+    if (resnorm) HIPCHK(hipMemcpyAsync(resnorm, P->out.resnorm + b, 8 * n, hipMemcpyDeviceToDevice, s));
+    if (nI) HIPCHK(hipMemcpyAsync(nI, P->out.nI + b, 4 * n, hipMemcpyDeviceToDevice, s));
+    if (nJ) HIPCHK(hipMemcpyAsync(nJ, P->out.nJ + b, 4 * n, hipMemcpyDeviceToDevice, s));
+    if (flops) HIPCHK(hipMemcpyAsync(flops, P->out.flops + b, 8 * n, hipMemcpyDeviceToDevice, s));
+    if (status) HIPCHK(hipMemcpyAsync(status, P->out.status + b, 4 * n, hipMemcpyDeviceToDevice, s));
+    return RSAI_OK;
+}
+
+rsai_status rsai_apply(const rsai_plan *Pc, int32_t mat, const double *x, double *y, void *stream) {
+    int64_t nz = 0;
+    rsai_status st = rsai_plan_nnz(Pc, mat, &nz);
+    if (st != RSAI_OK) return st;
+    if (!x || !y) return fail(RSAI_E_ARG, "NULL vector");
+    rsai_plan *P = const_cast<rsai_plan *>(Pc);
+    MatPlan &M = P->mats[mat];
+    const int64_t n = M.A.n;
+    hipStream_t s = (hipStream_t)stream;
+    if (!M.rowptrT) {
+        // rows of M once: counts, scan, fill, sort each row by column
+        int32_t *cnt = P->alloc<int32_t>(n, st);
+        int32_t *fill = P->alloc<int32_t>(n, st);
+        int64_t *rp = P->alloc<int64_t>(n + 1, st);
+        int32_t *ci = P->alloc<int32_t>(nz, st);
+        double *vv = P->alloc<double>(nz, st);
+        if (st != RSAI_OK) return st;
+        launch_fill_i32(cnt, 0, n, P->stream);
+        launch_fill_i32(fill, 0, n, P->stream);
+        launch_row_counts(nz, M.rowidxM, cnt, P->stream);
+        launch_scan_i32(cnt, n, rp, P->scan_tmp, P->stream);
+        launch_csc_transpose_fill(n, M.colptrM, M.rowidxM, M.valM, rp, fill, ci, vv, P->stream);
+        launch_sort_rows(n, rp, ci, vv, P->stream);
+        HIPCHK(hipStreamSynchronize(P->stream));
+        M.rowptrT = rp;
+        M.colidxT = ci;
+        M.valT = vv;
+    }
+    launch_csr_spmv(n, M.rowptrT, M.colidxT, M.valT, x, y, s);
+    HIPCHK(hipGetLastError());
+    return RSAI_OK;
+}
+
+rsai_status rsai_spmv(const rsai_csc *A, const double *x, double *y, int32_t transpose, void *stream) {
+    if (!A || !x || !y) return fail(RSAI_E_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    if (transpose) {
+        launch_csc_spmv_t(A->n, A->colptr, A->rowidx, A->val, x, y, s);
+        HIPCHK(hipGetLastError());
+        return RSAI_OK;
+    }
+    // y = A x through the rows of A (deterministic summation order)
+    rsai_status st = RSAI_OK;
+    const int64_t n = A->n, nnz = A->nnz;
+    std::vector<void *> tmp;
+    auto al = [&](size_t bytes) -> void * {
+        void *p = dev_alloc(bytes, s);
+        if (!p) st = fail(RSAI_E_NOMEM, "allocation failed");
+        tmp.push_back(p);
+        return p;
+    };
+    int32_t *cnt = (int32_t *)al(4 * n);
+    int32_t *fill = (int32_t *)al(4 * n);
+    int64_t *rp = (int64_t *)al(8 * (n + 1));
+    int32_t *ci = (int32_t *)al(4 * nnz);
+    double *vv = (double *)al(8 * nnz);
+    int64_t *stmp = (int64_t *)al(8 * scan_tmp_elems(n + 1));
+    if (st == RSAI_OK) {
+        launch_fill_i32(cnt, 0, n, s);
+        launch_fill_i32(fill, 0, n, s);
+        launch_row_counts(nnz, A->rowidx, cnt, s);
+        launch_scan_i32(cnt, n, rp, stmp, s);
+        launch_csc_transpose_fill(n, A->colptr, A->rowidx, A->val, rp, fill, ci, vv, s);
+        launch_sort_rows(n, rp, ci, vv, s);
+        launch_csr_spmv(n, rp, ci, vv, x, y, s);
+        if (hipStreamSynchronize(s) != hipSuccess) st = fail(RSAI_E_HIP, "spmv failed");
+    }
+    for (void *p : tmp) dev_free(p, s);
+    return st;
+}
+
+rsai_status rsai_spmv_vjp(const rsai_csc *A, const double *dy, const double *x, double *dval, void *stream) {
+    if (!A || !dy || !x || !dval) return fail(RSAI_E_ARG, "NULL argument");
+    launch_spmv_vjp(A->n, A->colptr, A->rowidx, dy, x, dval, (hipStream_t)stream);
+    HIPCHK(hipGetLastError());
+    return RSAI_OK;
+}
+
+rsai_status rsai_backward(rsai_plan *P, int32_t mat, const double *dM_val, double w_frob, double *dA_val,
+                          void *stream) {
+    int64_t nz = 0;
+    rsai_status st = rsai_plan_nnz(P, mat, &nz);
+    if (st != RSAI_OK) return st;
+    if (!dA_val) return fail(RSAI_E_ARG, "dA_val is NULL");
+    MatPlan &M = P->mats[mat];
+    hipStream_t s = (hipStream_t)stream;
+    if (M.maxq < 0) {
+        int32_t *d2 = P->alloc<int32_t>(2, st);
+        if (st != RSAI_OK) return st;
+        int32_t h2[2] = {0, 0};
+        launch_fill_i32(d2, 0, 2, P->stream);
+        launch_max2(M.A.n, P->out.nJ + M.col_base, P->out.nI + M.col_base, d2, P->stream);
+        HIPCHK(hipMemcpyAsync(h2, d2, sizeof(h2), hipMemcpyDeviceToHost, P->stream));
+        HIPCHK(hipStreamSynchronize(P->stream));
+        M.maxq = h2[0];
+        M.maxm = h2[1];
+    }
+    if (M.maxq > backward_max_cols() || M.maxm > backward_max_rows())
+        return fail(RSAI_E_CAP, "adjoint supports |J_k| <= %d and |I_k| <= %d; this M has %d and %d",
+                    backward_max_cols(), backward_max_rows(), M.maxq, M.maxm);
+    BwdArgs a{};
+    a.mats = P->d_mats;
+    a.mat = mat;
+    a.n = M.A.n;
+    a.Mcolptr = M.colptrM;
+    a.Mrowidx = M.rowidxM;
+    a.Mval = M.valM;
+    a.gM = dM_val;
+    a.w_frob = w_frob;
+    a.dA = dA_val;
+    a.err = P->err;
+    P->record(5, s);
+    launch_backward(a, device_cus() * 8, s);
+    P->record(6, s);
+    HIPCHK(hipGetLastError());
+    return RSAI_OK;
+}
+
+rsai_status rsai_plan_timing(const rsai_plan *P, double *ms, int32_t n) {
+    if (!P || !ms) return fail(RSAI_E_ARG, "NULL argument");
+    if (!P->have_events) return fail(RSAI_E_STATE, "plan was built without timing");
+    HIPCHK(hipStreamSynchronize(P->stream));
+    auto el = [&](int a, int b) {
+        float t = 0.f;
+        if (!P->recorded[a] || !P->recorded[b]) return -1.0;
+        if (hipEventElapsedTime(&t, P->ev[a], P->ev[b]) != hipSuccess) return -1.0;
+        return (double)t;
+    };
+    double v[6] = {el(0, 1), el(1, 2), el(2, 3), el(3, 4), el(0, 4), el(5, 6)};
+    for (int i = 0; i < n && i < 6; ++i) ms[i] = v[i];
+    return RSAI_OK;
+}
+
+rsai_status rsai_destroy(rsai_plan *P) {
+    if (!P) return RSAI_OK;
+    P->release();
+    delete P;
+    return RSAI_OK;
+}
+
+}  // extern "C"

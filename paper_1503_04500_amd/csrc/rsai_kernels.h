@@ -1,0 +1,75 @@
+// Internal launch interface between the kernel files and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rsai_tier.h"
+
+namespace rsai {
+
+struct TierInfo {
+    int G, MMAX, QMAX, REC;
+};
+extern const TierInfo kTiers[];
+extern const int kNumTiers;
+extern const int kPlainTier;  // the one size class of the plain schedule
+
+void launch_tier_kernel(int tier, const TierArgs &a, int waves, hipStream_t s);
+
+// ---- preprocessing (rsai_prep.hip)
+// err bits: 1 colptr, 2 rows out of range / unsorted / duplicate, 4 empty column
+void launch_validate(int64_t n, int64_t nnz, const int64_t *colptr, const int32_t *rowidx, int32_t *err,
+                     hipStream_t s);
+void launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t s);
+void launch_fill_i64(int64_t *p, int64_t v, int64_t count, hipStream_t s);
+void launch_fill_f64(double *p, double v, int64_t count, hipStream_t s);
+// row pattern of A: counts -> rowptr (exclusive scan) -> colidx (unordered inside a row);
+// g (max row count) and ||A||_1 as bit patterns in stats[0], stats[1]
+void launch_row_counts(int64_t nnz, const int32_t *rowidx, int32_t *cnt, hipStream_t s);
+void launch_row_fill(int64_t n, const int64_t *colptr, const int32_t *rowidx, const int64_t *rowptr,
+                     int32_t *fillpos, int32_t *colidx, hipStream_t s);
+void launch_mat_stats(int64_t n, const int64_t *colptr, const double *val, const int32_t *rowcnt,
+                      unsigned long long *stats, hipStream_t s);
+
+// exclusive scan of n int32 counts into out[0..n] (out[n] = total); tmp needs
+// scan_tmp_elems(n) int64 elements
+int64_t scan_tmp_elems(int64_t n);
+void launch_scan_i32(const int32_t *in, int64_t n, int64_t *out, int64_t *tmp, hipStream_t s);
+
+// ---- assembly: per-column results in the arena -> CSC (rows ascending)
+void launch_assemble(int64_t n, const int64_t *off, const int32_t *nJ, const int64_t *colptrM,
+                     int32_t *arenaJ, double *arenaV, int32_t *rowidxM, double *valM, hipStream_t s);
+
+// ---- SpMV
+void launch_csc_transpose_fill(int64_t n, const int64_t *colptr, const int32_t *rowidx, const double *val,
+                               const int64_t *rowptr, int32_t *fillpos, int32_t *colidxT, double *valT,
+                               hipStream_t s);
+void launch_sort_rows(int64_t n, const int64_t *rowptr, int32_t *colidx, double *val, hipStream_t s);
+void launch_csr_spmv(int64_t n, const int64_t *rowptr, const int32_t *colidx, const double *val, const double *x,
+                     double *y, hipStream_t s);
+void launch_csc_spmv_t(int64_t n, const int64_t *colptr, const int32_t *rowidx, const double *val,
+                       const double *x, double *y, hipStream_t s);
+
+void launch_spmv_vjp(int64_t n, const int64_t *colptr, const int32_t *rowidx, const double *dy, const double *x,
+                     double *dval, hipStream_t s);
+
+// ---- adjoint (rsai_backward.hip)
+struct BwdArgs {
+    const MatDev *mats;
+    int mat;
+    int64_t n;
+    const int64_t *Mcolptr;
+    const int32_t *Mrowidx;
+    const double *Mval;
+    const double *gM;   // nullable
+    double w_frob;
+    double *dA;
+    int32_t *err;
+};
+int backward_max_cols();
+int backward_max_rows();
+void launch_max2(int64_t n, const int32_t *a, const int32_t *b, int32_t *out2, hipStream_t s);
+void launch_backward(const BwdArgs &a, int waves, hipStream_t s);
+
+}  // namespace rsai

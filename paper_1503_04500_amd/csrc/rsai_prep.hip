@@ -1,0 +1,314 @@
+// Preprocessing, scan, assembly and SpMV kernels.
+//
+// These steps are bandwidth- and latency-bound index work: one thread per column or
+// per entry, coalesced over the CSC arrays.
+#include "rsai_kernels.h"
+
+namespace rsai {
+
+static inline int nblocks(int64_t work, int per_block) {
+    int64_t b = (work + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    if (b > 1048576) b = 1048576;
+    return (int)b;
+}
+
+// ---------------------------------------------------------------- fills
+
+template <class T>
+__global__ void k_fill(T *p, T v, int64_t count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+void launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t s) {
+    if (count > 0) hipLaunchKernelGGL(k_fill<int32_t>, dim3(nblocks(count, 1024)), dim3(256), 0, s, p, v, count);
+}
+void launch_fill_i64(int64_t *p, int64_t v, int64_t count, hipStream_t s) {
+    if (count > 0) hipLaunchKernelGGL(k_fill<int64_t>, dim3(nblocks(count, 1024)), dim3(256), 0, s, p, v, count);
+}
+void launch_fill_f64(double *p, double v, int64_t count, hipStream_t s) {
+    if (count > 0) hipLaunchKernelGGL(k_fill<double>, dim3(nblocks(count, 1024)), dim3(256), 0, s, p, v, count);
+}
+
+// ---------------------------------------------------------------- CSC contract
+
+__global__ void k_validate(int64_t n, int64_t nnz, const int64_t *colptr, const int32_t *rowidx, int32_t *err) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = colptr[j], e = colptr[j + 1];
+        if ((j == 0 && s != 0) || (j == n - 1 && e != nnz) || s < 0 || e > nnz || s > e) {
+            atomicOr(err, 1);
+            continue;
+        }
+        if (e == s) {
+            atomicOr(err, 4);
+            continue;
+        }
+        int prev = -1;
+        for (int64_t t = s; t < e; ++t) {
+            const int r = rowidx[t];
+            if (r <= prev || r >= n) {
+                atomicOr(err, 2);
+                break;
+            }
+            prev = r;
+        }
+    }
+}
+void launch_validate(int64_t n, int64_t nnz, const int64_t *colptr, const int32_t *rowidx, int32_t *err,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_validate, dim3(nblocks(n, 256)), dim3(256), 0, s, n, nnz, colptr, rowidx, err);
+}
+
+// ---------------------------------------------------------------- row pattern
+
+__global__ void k_row_counts(int64_t nnz, const int32_t *rowidx, int32_t *cnt) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&cnt[rowidx[e]], 1);
+}
+void launch_row_counts(int64_t nnz, const int32_t *rowidx, int32_t *cnt, hipStream_t s) {
+    if (nnz > 0) hipLaunchKernelGGL(k_row_counts, dim3(nblocks(nnz, 1024)), dim3(256), 0, s, nnz, rowidx, cnt);
+}
+
+__global__ void k_row_fill(int64_t n, const int64_t *colptr, const int32_t *rowidx, const int64_t *rowptr,
+                           int32_t *fillpos, int32_t *colidx) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        for (int64_t e = colptr[j]; e < colptr[j + 1]; ++e) {
+            const int r = rowidx[e];
+            const int p = atomicAdd(&fillpos[r], 1);
+            colidx[rowptr[r] + p] = (int32_t)j;
+        }
+    }
+}
+void launch_row_fill(int64_t n, const int64_t *colptr, const int32_t *rowidx, const int64_t *rowptr,
+                     int32_t *fillpos, int32_t *colidx, hipStream_t s) {
+    hipLaunchKernelGGL(k_row_fill, dim3(nblocks(n, 256)), dim3(256), 0, s, n, colptr, rowidx, rowptr, fillpos, colidx);
+}
+
+// stats[0] = max row count (g of Theorem 4.1), stats[1] = bits of ||A||_1
+__global__ void k_mat_stats(int64_t n, const int64_t *colptr, const double *val, const int32_t *rowcnt,
+                            unsigned long long *stats) {
+    unsigned long long gmax = 0, nmax = 0;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int64_t e = colptr[j]; e < colptr[j + 1]; ++e) s += fabs(val[e]);
+        unsigned long long bits = (unsigned long long)__double_as_longlong(s);  // s >= 0: order-preserving
+        nmax = bits > nmax ? bits : nmax;
+        unsigned long long g = (unsigned long long)rowcnt[j];
+        gmax = g > gmax ? g : gmax;
+    }
+    atomicMax(&stats[0], gmax);
+    atomicMax(&stats[1], nmax);
+}
+void launch_mat_stats(int64_t n, const int64_t *colptr, const double *val, const int32_t *rowcnt,
+                      unsigned long long *stats, hipStream_t s) {
+    hipLaunchKernelGGL(k_mat_stats, dim3(nblocks(n, 256)), dim3(256), 0, s, n, colptr, val, rowcnt, stats);
+}
+
+// ---------------------------------------------------------------- exclusive scan
+// Three passes: per-block sums, a single-block scan of the block sums, and the
+// per-block scan with its offset. 2048 items per block.
+
+constexpr int SCAN_T = 256, SCAN_PER = 8, SCAN_B = SCAN_T * SCAN_PER;
+
+int64_t scan_tmp_elems(int64_t n) { return (n + SCAN_B - 1) / SCAN_B + 1; }
+
+__global__ void k_scan_sums(const int32_t *in, int64_t n, int64_t *bsum) {
+    __shared__ int64_t red[SCAN_T];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_B;
+    int64_t s = 0;
+    for (int t = threadIdx.x; t < SCAN_B; t += SCAN_T) {
+        int64_t i = base + t;
+        if (i < n) s += in[i];
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = SCAN_T / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
+}
+
+__global__ void k_scan_top(int64_t *bsum, int64_t nb) {
+    // exclusive scan of nb block sums by one block, in chunks of SCAN_T
+    __shared__ int64_t sh[SCAN_T];
+    __shared__ int64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < nb; c0 += SCAN_T) {
+        int64_t i = c0 + threadIdx.x;
+        int64_t v = (i < nb) ? bsum[i] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < SCAN_T; off <<= 1) {
+            int64_t t = (threadIdx.x >= off) ? sh[threadIdx.x - off] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < nb) bsum[i] = carry + sh[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == SCAN_T - 1) carry += sh[SCAN_T - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bsum[nb] = carry;
+}
+
+__global__ void k_scan_final(const int32_t *in, int64_t n, const int64_t *bsum, int64_t *out) {
+    __shared__ int64_t sh[SCAN_T];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_B + (int64_t)threadIdx.x * SCAN_PER;
+    int64_t loc[SCAN_PER];
+    int64_t s = 0;
+#pragma unroll
+    for (int t = 0; t < SCAN_PER; ++t) {
+        int64_t i = base + t;
+        loc[t] = s;
+        s += (i < n) ? in[i] : 0;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < SCAN_T; off <<= 1) {
+        int64_t t = (threadIdx.x >= off) ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    const int64_t pre = bsum[blockIdx.x] + sh[threadIdx.x] - s;
+#pragma unroll
+    for (int t = 0; t < SCAN_PER; ++t) {
+        int64_t i = base + t;
+        if (i < n) out[i] = pre + loc[t];
+    }
+}
+
+__global__ void k_scan_total(int64_t n, int64_t nb, const int64_t *bsum, int64_t *out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) out[n] = bsum[nb];
+}
+
+void launch_scan_i32(const int32_t *in, int64_t n, int64_t *out, int64_t *tmp, hipStream_t s) {
+    const int64_t nb = (n + SCAN_B - 1) / SCAN_B;
+    if (nb > 0) hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_T), 0, s, tmp, nb);
+    if (nb > 0) hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, n, tmp, out);
+    hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(64), 0, s, n, nb, tmp, out);
+}
+
+// ---------------------------------------------------------------- assembly
+// One thread per column: insertion-sort the column's (row, value) pairs in the
+// arena by row index, then copy them to M at colptrM[k].
+
+__global__ void k_assemble(int64_t n, const int64_t *off, const int32_t *nJ, const int64_t *colptrM,
+                           int32_t *aJ, double *aV, int32_t *rowidxM, double *valM) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const int q = nJ[k];
+        if (q <= 0) continue;
+        int32_t *J = aJ + off[k];
+        double *V = aV + off[k];
+        for (int a = 1; a < q; ++a) {
+            int key = J[a];
+            double v = V[a];
+            int b = a - 1;
+            while (b >= 0 && J[b] > key) {
+                J[b + 1] = J[b];
+                V[b + 1] = V[b];
+                --b;
+            }
+            J[b + 1] = key;
+            V[b + 1] = v;
+        }
+        const int64_t dst = colptrM[k];
+        for (int a = 0; a < q; ++a) {
+            rowidxM[dst + a] = J[a];
+            valM[dst + a] = V[a];
+        }
+    }
+}
+void launch_assemble(int64_t n, const int64_t *off, const int32_t *nJ, const int64_t *colptrM, int32_t *arenaJ,
+                     double *arenaV, int32_t *rowidxM, double *valM, hipStream_t s) {
+    hipLaunchKernelGGL(k_assemble, dim3(nblocks(n, 256)), dim3(256), 0, s, n, off, nJ, colptrM, arenaJ, arenaV, rowidxM,
+                       valM);
+}
+
+// ---------------------------------------------------------------- SpMV
+
+__global__ void k_csc_transpose_fill(int64_t n, const int64_t *colptr, const int32_t *rowidx, const double *val,
+                                     const int64_t *rowptr, int32_t *fillpos, int32_t *colidxT, double *valT) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        for (int64_t e = colptr[j]; e < colptr[j + 1]; ++e) {
+            const int r = rowidx[e];
+            const int p = atomicAdd(&fillpos[r], 1);
+            colidxT[rowptr[r] + p] = (int32_t)j;
+            valT[rowptr[r] + p] = val[e];
+        }
+    }
+}
+void launch_csc_transpose_fill(int64_t n, const int64_t *colptr, const int32_t *rowidx, const double *val,
+                               const int64_t *rowptr, int32_t *fillpos, int32_t *colidxT, double *valT,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_csc_transpose_fill, dim3(nblocks(n, 256)), dim3(256), 0, s, n, colptr, rowidx, val, rowptr,
+                       fillpos, colidxT, valT);
+}
+
+// sort each row's (col, value) pairs by column so that row sums have a fixed order
+__global__ void k_sort_rows(int64_t n, const int64_t *rowptr, int32_t *colidx, double *val) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = rowptr[i], e = rowptr[i + 1];
+        for (int64_t a = s + 1; a < e; ++a) {
+            int key = colidx[a];
+            double v = val ? val[a] : 0.0;
+            int64_t b = a - 1;
+            while (b >= s && colidx[b] > key) {
+                colidx[b + 1] = colidx[b];
+                if (val) val[b + 1] = val[b];
+                --b;
+            }
+            colidx[b + 1] = key;
+            if (val) val[b + 1] = v;
+        }
+    }
+}
+void launch_sort_rows(int64_t n, const int64_t *rowptr, int32_t *colidx, double *val, hipStream_t s) {
+    hipLaunchKernelGGL(k_sort_rows, dim3(nblocks(n, 256)), dim3(256), 0, s, n, rowptr, colidx, val);
+}
+
+__global__ void k_csr_spmv(int64_t n, const int64_t *rowptr, const int32_t *colidx, const double *val,
+                           const double *x, double *y) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) s += val[e] * x[colidx[e]];
+        y[i] = s;
+    }
+}
+void launch_csr_spmv(int64_t n, const int64_t *rowptr, const int32_t *colidx, const double *val, const double *x,
+                     double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_csr_spmv, dim3(nblocks(n, 256)), dim3(256), 0, s, n, rowptr, colidx, val, x, y);
+}
+
+// y = A^T x for CSC A: y_j = sum_i a_ij x_i (a column dot product)
+__global__ void k_csc_spmv_t(int64_t n, const int64_t *colptr, const int32_t *rowidx, const double *val,
+                             const double *x, double *y) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int64_t e = colptr[j]; e < colptr[j + 1]; ++e) s += val[e] * x[rowidx[e]];
+        y[j] = s;
+    }
+}
+void launch_csc_spmv_t(int64_t n, const int64_t *colptr, const int32_t *rowidx, const double *val, const double *x,
+                       double *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_csc_spmv_t, dim3(nblocks(n, 256)), dim3(256), 0, s, n, colptr, rowidx, val, x, y);
+}
+
+// dval[e] += dy[row(e)] * x[col(e)]: one thread per column
+__global__ void k_spmv_vjp(int64_t n, const int64_t *colptr, const int32_t *rowidx, const double *dy,
+                           const double *x, double *dval) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        const double xj = x[j];
+        for (int64_t e = colptr[j]; e < colptr[j + 1]; ++e) dval[e] += dy[rowidx[e]] * xj;
+    }
+}
+void launch_spmv_vjp(int64_t n, const int64_t *colptr, const int32_t *rowidx, const double *dy, const double *x,
+                     double *dval, hipStream_t s) {
+    hipLaunchKernelGGL(k_spmv_vjp, dim3(nblocks(n, 256)), dim3(256), 0, s, n, colptr, rowidx, dy, x, dval);
+}
+
+}  // namespace rsai

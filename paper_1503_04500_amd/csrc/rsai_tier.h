@@ -1,0 +1,86 @@
+// Size-tiered fused RSAI(tol) column kernel (gfx950, one wave per workgroup).
+//
+// A wave holds 64/G columns; each column is owned by an aligned group of G lanes.
+// The dense LS block A(I_k, J_k) of eq. (2.3) lives in registers, row i of the block
+// in lane (i mod G), register slot (i / G): a column's block is at most
+// MMAX = G * RPL rows by QMAX columns. Index sets are LDS hash sets (global index ->
+// local position); rows and columns are numbered in insertion order, new ones in
+// ascending global order, so the block grows by appending rows at the bottom and
+// columns at the right and the Householder factor can be updated in place
+// (Algorithm 1, step 7): stored reflectors are applied to the new columns only,
+// then new reflectors are formed.
+//
+// Every loop of Algorithm 1 runs in one pass of the wave's loop; groups that finish
+// take the next column, so different groups of a wave may be at different loops.
+// A column that outgrows the tier's caps is written to a spill record and resumed
+// by the next larger tier.
+#pragma once
+
+#include "rsai_dev.h"
+
+namespace rsai {
+
+constexpr int RHDR = 11;  // spill record header ints
+
+template <int G_, int RPL_, int QMAX_, int STAGE_>
+struct TierCfg {
+    static constexpr int G = G_, RPL = RPL_, QMAX = QMAX_, STAGE = STAGE_;
+    static constexpr int MMAX = G * RPL;
+    static constexpr int GPW = 64 / G;
+    static constexpr int LOGHSI = ilog2ceil(2 * MMAX);
+    static constexpr int HSI = 1 << LOGHSI;
+    static constexpr int LOGHSJ = ilog2ceil(2 * QMAX);
+    static constexpr int HSJ = 1 << LOGHSJ;
+    static constexpr int NEWC = MMAX > QMAX ? MMAX : QMAX;
+    static constexpr int RIN = HSI - MMAX - 1;  // candidates inserted per round (I)
+    static constexpr int RJN = HSJ - QMAX - 1;  // (J)
+    static constexpr int PREF = (QMAX > CMAX ? QMAX : CMAX) + 1;
+    static constexpr int REC = RHDR + QMAX + MMAX + (MMAX + 1) + CMAX;  // spill record ints
+    static_assert(RPL <= 32 && QMAX <= 32, "bit masks");
+    static_assert(RIN >= 1 && RJN >= 1, "hash sizes");
+    static_assert(QMAX <= MMAX, "row j of the block must exist for every column j");
+};
+
+// Record layout (int32): [0] global column id, [1] matrix, [2] k, [3] l, [4] q, [5] m,
+// [6] |R| (rows used as dominant rows, incl. k), [7] |R-hat| pending, [8..9] the
+// column's flop count so far (double), [10] flags (bit 0: the loop counter is still
+// to be advanced for the pending R-hat), then J[q], I[m], R[|R|], R-hat[|R-hat|].
+// q = 0 and no pending R-hat means "start from scratch".
+struct TierArgs {
+    const MatDev *mats;
+    int nmat;
+    const int64_t *col_base;  // [nmat + 1]
+    BuildParams P;
+    ColOut out;
+    int64_t arena_base;       // first arena slot of this tier
+    int64_t qlen;             // tier 0: number of columns (all matrices)
+    const int32_t *rec_in;    // tier >= 1: input records
+    int rec_in_stride;
+    const int32_t *rec_in_count;
+    int64_t rec_in_cap;
+    int32_t *rec_out;         // spill records for the next tier (nullptr: last tier)
+    int rec_out_stride;
+    int32_t *rec_out_count;
+    int64_t rec_out_cap;
+    int32_t *err;             // global error flags (bit 0: internal)
+    int one_loop;             // 1: park every column after one loop (plain schedule)
+};
+
+template <class C>
+struct GLds {
+    double stage[C::STAGE * C::MMAX];
+    double rdiag[C::QMAX];
+    double beta[C::QMAX];
+    int Ilist[C::MMAX];
+    int Jlist[C::QMAX];
+    int hI[C::HSI];
+    int hIv[C::HSI];
+    int hJ[C::HSJ];
+    int newk[C::NEWC];
+    int news[C::NEWC];
+    int pref[C::PREF];
+    int cnt;
+    int pad;
+};
+
+}  // namespace rsai

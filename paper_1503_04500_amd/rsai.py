@@ -1,0 +1,278 @@
+"""Python binding of the RSAI(tol) C ABI (``include/rsai.h``).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+``librsai.so``. PyTorch supplies device memory (its caching allocator is plugged
+into the library) and streams. There is no CPU fallback: without the built library
+or without a GPU every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librsai.so")
+
+RSAI_OK = 0
+_STATUS = {-1: "RSAI_E_ARG", -2: "RSAI_E_CSC", -3: "RSAI_E_SINGULAR", -4: "RSAI_E_NOMEM", -5: "RSAI_E_HIP",
+           -6: "RSAI_E_CAP", -7: "RSAI_E_STATE"}
+DROP = {"none": 0, "fixed": 1, "adaptive": 2}
+SCHED = {"batched": 0, "plain": 1}
+
+
+class RSAIError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("c", ctypes.c_int32), ("lmax", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("drop", ctypes.c_int32), ("tol", ctypes.c_double), ("sched", ctypes.c_int32),
+                ("validate", ctypes.c_int32), ("tier0", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("keep_factors", ctypes.c_int32), ("factor_budget_bytes", ctypes.c_int64)]
+
+
+class CSCView(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("colptr", ctypes.c_void_p),
+                ("rowidx", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+_lib = None
+_ALLOC_T = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_T = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+_alloc_error = []
+
+
+def _torch_alloc(size, stream, ctx):
+    try:
+        return torch.cuda.caching_allocator_alloc(int(size), torch.cuda.current_device(), stream or 0)
+    except Exception as e:  # -> NULL; the library reports RSAI_E_NOMEM
+        _alloc_error.append(repr(e))
+        return None
+
+
+def _torch_free(ptr, stream, ctx):
+    if ptr:
+        torch.cuda.caching_allocator_delete(ptr)
+
+
+_alloc_cb = _ALLOC_T(_torch_alloc)
+_free_cb = _FREE_T(_torch_free)
+
+
+def load():
+    """Load ``librsai.so`` and route its device allocations through PyTorch."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sigs = {
+        "rsai_params_default": [P],
+        "rsai_set_allocator": [P, P, P],
+        "rsai_build": [P, P, P, P],
+        "rsai_build_batched": [I32, P, P, P, P],
+        "rsai_plan_count": [P, P],
+        "rsai_plan_nnz": [P, I32, P],
+        "rsai_export_M": [P, I32, P, P, P, P],
+        "rsai_export_stats": [P, I32, P, P, P, P, P, P, P],
+        "rsai_apply": [P, I32, P, P, P],
+        "rsai_backward": [P, I32, P, D, P, P],
+        "rsai_spmv": [P, P, P, I32, P],
+        "rsai_spmv_vjp": [P, P, P, P, P],
+        "rsai_plan_timing": [P, P, I32],
+        "rsai_tier_info": [I32, P, P, P],
+        "rsai_destroy": [P],
+    }
+    for name, args in sigs.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.rsai_last_error.argtypes = []
+    lib.rsai_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(code):
+    if code != RSAI_OK:
+        msg = load().rsai_last_error().decode()
+        if code == -4 and _alloc_error:
+            msg += f" (allocator: {_alloc_error[-1]})"
+        raise RSAIError(code, msg)
+
+
+def _use_torch_allocator():
+    lib = load()
+    _check(lib.rsai_set_allocator(ctypes.cast(_alloc_cb, ctypes.c_void_p), ctypes.cast(_free_cb, ctypes.c_void_p),
+                                  None))
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype, name):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor (no CPU path)")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    return t.contiguous()
+
+
+class Matrix:
+    """A CSC matrix resident on the GPU (int64 colptr, int32 rowidx, float64 val)."""
+
+    def __init__(self, colptr, rowidx, val):
+        self.colptr = _dev(colptr, torch.int64, "colptr")
+        self.rowidx = _dev(rowidx, torch.int32, "rowidx")
+        self.val = _dev(val, torch.float64, "val")
+        self.n = self.colptr.numel() - 1
+        self.nnz = self.rowidx.numel()
+
+    @classmethod
+    def from_host(cls, A, device="cuda"):
+        return cls(torch.as_tensor(A.colptr, dtype=torch.int64).to(device),
+                   torch.as_tensor(A.rowidx, dtype=torch.int32).to(device),
+                   torch.as_tensor(A.val, dtype=torch.float64).to(device))
+
+    def view(self, val=None):
+        v = self.val if val is None else val
+        return CSCView(self.n, self.nnz, self.colptr.data_ptr(), self.rowidx.data_ptr(), v.data_ptr())
+
+
+def params(c=3, lmax=10, eps=0.4, drop="fixed", tol=1e-3, sched="batched", validate=True, tier0=-1,
+           timing=False):
+    p = Params()
+    _check(load().rsai_params_default(ctypes.byref(p)))
+    p.c, p.lmax, p.eps, p.tol = int(c), int(lmax), float(eps), float(tol)
+    p.drop = DROP[drop] if isinstance(drop, str) else int(drop)
+    p.sched = SCHED[sched] if isinstance(sched, str) else int(sched)
+    p.validate = 1 if validate else 0
+    p.tier0 = int(tier0)
+    p.timing = 1 if timing else 0
+    return p
+
+
+class Plan:
+    """Result of rsai_build / rsai_build_batched (owns the library plan)."""
+
+    def __init__(self, handle, mats, prm, stream):
+        self._h = handle
+        self.mats = mats
+        self.params = prm
+        self.stream = stream
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.rsai_destroy(h)
+        self._h = None
+
+    def _hv(self):
+        if not self._h:
+            raise RSAIError(-7, "plan is closed")
+        return self._h
+
+    def nnz(self, mat=0):
+        out = ctypes.c_int64(0)
+        _check(load().rsai_plan_nnz(self._hv(), mat, ctypes.byref(out)))
+        return out.value
+
+    def export(self, mat=0):
+        """M of matrix mat as CSC tensors (colptr int64, rowidx int32, val float64)."""
+        n = self.mats[mat].n
+        nz = self.nnz(mat)
+        dev = self.mats[mat].colptr.device
+        cp = torch.empty(n + 1, dtype=torch.int64, device=dev)
+        ri = torch.empty(max(nz, 1), dtype=torch.int32, device=dev)
+        va = torch.empty(max(nz, 1), dtype=torch.float64, device=dev)
+        _check(load().rsai_export_M(self._hv(), mat, cp.data_ptr(), ri.data_ptr(), va.data_ptr(), _stream()))
+        return cp, ri[:nz], va[:nz]
+
+    def stats(self, mat=0):
+        n = self.mats[mat].n
+        dev = self.mats[mat].colptr.device
+        t = {k: torch.empty(n, dtype=torch.int32, device=dev) for k in ("loops", "nI", "nJ", "status")}
+        t["resnorm"] = torch.empty(n, dtype=torch.float64, device=dev)
+        t["flops"] = torch.empty(n, dtype=torch.float64, device=dev)
+        _check(load().rsai_export_stats(self._hv(), mat, t["loops"].data_ptr(), t["resnorm"].data_ptr(),
+                                        t["nI"].data_ptr(), t["nJ"].data_ptr(), t["flops"].data_ptr(),
+                                        t["status"].data_ptr(), _stream()))
+        return t
+
+    def apply(self, x, mat=0):
+        x = _dev(x, torch.float64, "x")
+        y = torch.empty_like(x)
+        _check(load().rsai_apply(self._hv(), mat, x.data_ptr(), y.data_ptr(), _stream()))
+        return y
+
+    def backward(self, dM_val, w_frob, dA_val, mat=0):
+        """dA_val += adjoint(dM_val) + w_frob * d(sum_k ||A m_k - e_k||^2)/dA (in place)."""
+        dA_val = _dev(dA_val, torch.float64, "dA_val")
+        ptr = None
+        if dM_val is not None:
+            dM_val = _dev(dM_val, torch.float64, "dM_val")
+            ptr = dM_val.data_ptr()
+        _check(load().rsai_backward(self._hv(), mat, ptr, float(w_frob), dA_val.data_ptr(), _stream()))
+        return dA_val
+
+    def timing(self):
+        ms = (ctypes.c_double * 6)()
+        _check(load().rsai_plan_timing(self._hv(), ms, 6))
+        return {"prep": ms[0], "tier0": ms[1], "tiers": ms[2], "assemble": ms[3], "build": ms[4], "backward": ms[5]}
+
+
+def build(A: Matrix, stream=None, **kw) -> Plan:
+    """Build the sparse approximate inverse M of one matrix (rsai_build)."""
+    return build_batched([A], stream=stream, **kw)
+
+
+def build_batched(mats, stream=None, **kw) -> Plan:
+    """Build M for several matrices in one pass (rsai_build_batched)."""
+    lib = load()
+    _use_torch_allocator()
+    prm = params(**kw)
+    views = (CSCView * len(mats))(*[m.view() for m in mats])
+    h = ctypes.c_void_p()
+    st = _stream(stream)
+    _check(lib.rsai_build_batched(len(mats), views, ctypes.byref(prm), st, ctypes.byref(h)))
+    return Plan(h, list(mats), prm, st)
+
+
+def spmv(A: Matrix, x, transpose=False, val=None):
+    """y = A x or A^T x (rsai_spmv)."""
+    x = _dev(x, torch.float64, "x")
+    y = torch.empty(A.n, dtype=torch.float64, device=x.device)
+    v = A.view(val)
+    _check(load().rsai_spmv(ctypes.byref(v), x.data_ptr(), y.data_ptr(), 1 if transpose else 0, _stream()))
+    return y
+
+
+def spmv_vjp(A: Matrix, dy, x, dval, val=None):
+    """dval[e] += dy[i] * x[j] for each stored entry (i, j) of A (rsai_spmv_vjp)."""
+    dy = _dev(dy, torch.float64, "dy")
+    x = _dev(x, torch.float64, "x")
+    dval = _dev(dval, torch.float64, "dval")
+    v = A.view(val)
+    _check(load().rsai_spmv_vjp(ctypes.byref(v), dy.data_ptr(), x.data_ptr(), dval.data_ptr(), _stream()))
+    return dval
+
+
+def tier_info(t):
+    g, mr, mc = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load().rsai_tier_info(t, ctypes.byref(g), ctypes.byref(mr), ctypes.byref(mc)))
+    return g.value, mr.value, mc.value
