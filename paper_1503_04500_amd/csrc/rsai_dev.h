@@ -128,6 +128,16 @@ __device__ __forceinline__ int wave_max_i(int x) {
 }
 
 __device__ __forceinline__ bool wave_any(bool p) { return __ballot(p) != 0; }
+
+// Synchronisation point of a single-wave workgroup. The LDS executes one wave's
+// instructions in order, so lanes see each other's earlier LDS writes; the fences
+// only stop the compiler from moving memory accesses across this point. Unlike
+// __syncthreads() it does not wait for outstanding global loads.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 __device__ __forceinline__ bool wave_all(bool p) { return __ballot(!p) == 0; }
 
 // ----------------------------------------------------------------- LDS hash sets

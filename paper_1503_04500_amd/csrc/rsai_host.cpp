@@ -382,7 +382,7 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
                 a.rec_out = nullptr;
             }
             const int gpw = 64 / kTiers[t].G;
-            int64_t want = (t == t0) ? (ncols + gpw - 1) / gpw : (int64_t)cus * 8;
+            int64_t want = (t == t0) ? (ncols + gpw - 1) / gpw : (int64_t)cus * 2;
             int waves = (int)std::max<int64_t>(8, std::min<int64_t>(want, (int64_t)cus * 16));
             waves = (waves + 7) / 8 * 8;
             launch_tier_kernel(t, a, waves, s);

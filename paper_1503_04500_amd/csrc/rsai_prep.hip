@@ -2,6 +2,8 @@
 //
 // These steps are bandwidth- and latency-bound index work: one thread per column or
 // per entry, coalesced over the CSC arrays.
+#include <algorithm>
+
 #include "rsai_kernels.h"
 
 namespace rsai {
@@ -85,8 +87,10 @@ void launch_row_fill(int64_t n, const int64_t *colptr, const int32_t *rowidx, co
 }
 
 // stats[0] = max row count (g of Theorem 4.1), stats[1] = bits of ||A||_1
+// (max column absolute sum); block reduction, one atomic per block
 __global__ void k_mat_stats(int64_t n, const int64_t *colptr, const double *val, const int32_t *rowcnt,
                             unsigned long long *stats) {
+    __shared__ unsigned long long sg[256], sn[256];
     unsigned long long gmax = 0, nmax = 0;
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
         double s = 0.0;
@@ -96,12 +100,24 @@ __global__ void k_mat_stats(int64_t n, const int64_t *colptr, const double *val,
         unsigned long long g = (unsigned long long)rowcnt[j];
         gmax = g > gmax ? g : gmax;
     }
-    atomicMax(&stats[0], gmax);
-    atomicMax(&stats[1], nmax);
+    sg[threadIdx.x] = gmax;
+    sn[threadIdx.x] = nmax;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            sg[threadIdx.x] = max(sg[threadIdx.x], sg[threadIdx.x + w]);
+            sn[threadIdx.x] = max(sn[threadIdx.x], sn[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        atomicMax(&stats[0], sg[0]);
+        atomicMax(&stats[1], sn[0]);
+    }
 }
 void launch_mat_stats(int64_t n, const int64_t *colptr, const double *val, const int32_t *rowcnt,
                       unsigned long long *stats, hipStream_t s) {
-    hipLaunchKernelGGL(k_mat_stats, dim3(nblocks(n, 256)), dim3(256), 0, s, n, colptr, val, rowcnt, stats);
+    hipLaunchKernelGGL(k_mat_stats, dim3(std::min(nblocks(n, 256), 1024)), dim3(256), 0, s, n, colptr, val, rowcnt, stats);
 }
 
 // ---------------------------------------------------------------- exclusive scan

@@ -69,8 +69,7 @@ struct TierArgs {
 template <class C>
 struct GLds {
     double stage[C::STAGE * C::MMAX];
-    double rdiag[C::QMAX];
-    double beta[C::QMAX];
+    double mt[C::QMAX];       // solution of the last LS solve, by column slot
     int Ilist[C::MMAX];
     int Jlist[C::QMAX];
     int hI[C::HSI];
@@ -79,6 +78,8 @@ struct GLds {
     int newk[C::NEWC];
     int news[C::NEWC];
     int pref[C::PREF];
+    int Rh[CMAX];             // pending dominant rows
+    int64_t segb[C::QMAX];
     int cnt;
     int pad;
 };

@@ -45,22 +45,17 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
     int kidx = -1;            // local row of k in I, or -1
     bool kR = false;          // k used as a dominant row while k is not in I
     int nRh = 0;
-    int Rh[CMAX];
     bool solve = false, dropok = false, linc = true;
     bool park = false;        // plain schedule: write the state out after this loop
     int status = ST_OK;
     double rn = 0.0, fl = 0.0;
-    double mt[QMAX];
     MatDev A{};
     // ---- per-lane block rows
     double b[RPL][QMAX];
     double y[RPL];
+    double rd[RPL], bt[RPL];  // R(i,i) and beta_i of the reflectors of this lane's rows
     unsigned rflag = 0u;      // bit r: local row r*G+gl is in R (used dominant rows)
 
-#pragma unroll
-    for (int t = 0; t < CMAX; ++t) Rh[t] = 0;
-#pragma unroll
-    for (int c = 0; c < QMAX; ++c) mt[c] = 0.0;
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
         y[r] = 0.0;
@@ -117,7 +112,7 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
                 for (int c = 0; c < QMAX; ++c) b[r][c] = 0.0;
             }
         }
-        __syncthreads();
+        wave_sync();
         bool resumed = false;
         if (start) {
             int rq = 0, rm = 0, rl = 0, rnR = 0, rnRh = 0;
@@ -155,11 +150,10 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
                 kidx = gmax_i<G>(kidx);
                 nRh = rnRh;
 #pragma unroll
-                for (int t = 0; t < CMAX; ++t)
-                    if (t < rnRh) Rh[t] = RI[rm + rnR + t];
+                for (int t = gl; t < rnRh; t += G) S.Rh[t] = RI[rm + rnR + t];
             }
         }
-        __syncthreads();
+        wave_sync();
         if (resumed) {
             // rows of R (the dominant rows used so far) -> flags of their local rows
             const int32_t *RR = rec + RHDR + q + m;
@@ -183,40 +177,54 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
         park = false;
         {
             const bool doK = busy && nRh > 0 && !spill;
-            if (doK && gl == 0) {
-                S.cnt = 0;
-                S.pref[0] = 0;
+            // start and prefix length of each pending row's pattern, held in registers
+            // by every lane of the group (the loads are independent)
+            int64_t sb[CMAX];
+            int sp[CMAX + 1];
+            sp[0] = 0;
 #pragma unroll
-                for (int t = 0; t < CMAX; ++t)
-                    if (t < nRh) S.pref[t + 1] = S.pref[t] + (int)(A.rowptr[Rh[t] + 1] - A.rowptr[Rh[t]]);
+            for (int t = 0; t < CMAX; ++t) {
+                int64_t b0 = 0, e0 = 0;
+                if (doK && t < nRh) {
+                    const int rt = S.Rh[t];
+                    b0 = A.rowptr[rt];
+                    e0 = A.rowptr[rt + 1];
+                }
+                sb[t] = b0;
+                sp[t + 1] = sp[t] + (int)(e0 - b0);
             }
-            __syncthreads();
-            const int total = doK ? S.pref[nRh] : 0;
+            const int total = doK ? sp[CMAX] : 0;
+            if (doK && gl == 0) S.cnt = 0;
+            wave_sync();
             bool ovf = false;
-            int seg = 0;
             for (int base = 0; wave_any(doK && !ovf && base < total); base += C::RJN) {
-                if (doK && !ovf) {
+                int cand[NRJ];
 #pragma unroll
-                    for (int s = 0; s < NRJ; ++s) {
-                        int uu = base + s * G + gl;
-                        if (uu < total && uu < base + C::RJN) {
-                            while (S.pref[seg + 1] <= uu) ++seg;
-                            int row = 0;
+                for (int s = 0; s < NRJ; ++s) {
+                    const int uu = base + s * G + gl;
+                    cand[s] = -1;
+                    if (doK && !ovf && uu < total && uu < base + C::RJN) {
+                        int64_t b0 = sb[0];
+                        int o0 = 0;
 #pragma unroll
-                            for (int t = 0; t < CMAX; ++t)
-                                if (t == seg) row = Rh[t];
-                            int col = A.colidx[A.rowptr[row] + (uu - S.pref[seg])];
-                            int sl;
-                            if (hinsert<C::LOGHSJ>(S.hJ, col, sl)) {
-                                int ps = atomicAdd(&S.cnt, 1);
-                                if (ps < C::NEWC) S.newk[ps] = col;
-                            }
+                        for (int t = 1; t < CMAX; ++t)
+                            if (uu >= sp[t]) { b0 = sb[t]; o0 = sp[t]; }
+                        cand[s] = A.colidx[b0 + (uu - o0)];
+                    }
+                }
+#pragma unroll
+                for (int s = 0; s < NRJ; ++s) {
+                    if (cand[s] >= 0) {
+                        int sl;
+                        if (hinsert<C::LOGHSJ>(S.hJ, cand[s], sl)) {
+                            int ps = atomicAdd(&S.cnt, 1);
+                            if (ps < C::NEWC) S.newk[ps] = cand[s];
                         }
                     }
                 }
-                __syncthreads();
+                wave_sync();
                 if (doK && !ovf && q + S.cnt > QMAX) ovf = true;
-                __syncthreads();
+                wave_sync();
             }
             const int nnew = (doK && !ovf) ? S.cnt : 0;
             if (doK) {
@@ -258,44 +266,57 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
                     }
                 }
             }
-            __syncthreads();
+            wave_sync();
         }
 
         // ================================ C. I-hat: rows of the new columns not in I
         {
             const bool doC = busy && !spill && p > 0;
-            if (doC && gl == 0) {
-                S.cnt = 0;
-                S.pref[0] = 0;
-                for (int t = 0; t < p; ++t) {
-                    int j = S.Jlist[q + t];
-                    S.pref[t + 1] = S.pref[t] + (int)(A.colptr[j + 1] - A.colptr[j]);
+            // pending columns in parallel: start -> LDS, length -> LDS, then every lane
+            // forms the prefix in registers
+            if (doC) {
+                for (int t = gl; t < p; t += G) {
+                    const int j = S.Jlist[q + t];
+                    const int64_t b0 = A.colptr[j];
+                    S.segb[t] = b0;
+                    S.pref[t] = (int)(A.colptr[j + 1] - b0);
                 }
+                if (gl == 0) S.cnt = 0;
             }
-            __syncthreads();
-            const int total = doC ? S.pref[p] : 0;
-            bool ovf = false;
-            int seg = 0;
-            for (int base = 0; wave_any(doC && !ovf && base < total); base += C::RIN) {
-                if (doC && !ovf) {
+            wave_sync();
+            int cpx[QMAX + 1];
+            cpx[0] = 0;
 #pragma unroll
-                    for (int s = 0; s < NRI; ++s) {
-                        int uu = base + s * G + gl;
-                        if (uu < total && uu < base + C::RIN) {
-                            while (S.pref[seg + 1] <= uu) ++seg;
-                            int j = S.Jlist[q + seg];
-                            int row = A.rowidx[A.colptr[j] + (uu - S.pref[seg])];
-                            int sl;
-                            if (hinsert<C::LOGHSI>(S.hI, row, sl)) {
-                                int ps = atomicAdd(&S.cnt, 1);
-                                if (ps < C::NEWC) { S.newk[ps] = row; S.news[ps] = sl; }
-                            }
+            for (int t = 0; t < QMAX; ++t) cpx[t + 1] = cpx[t] + ((doC && t < p) ? S.pref[t] : 0);
+            const int total = doC ? cpx[QMAX] : 0;
+            bool ovf = false;
+            for (int base = 0; wave_any(doC && !ovf && base < total); base += C::RIN) {
+                int cand[NRI];
+#pragma unroll
+                for (int s = 0; s < NRI; ++s) {
+                    const int uu = base + s * G + gl;
+                    cand[s] = -1;
+                    if (doC && !ovf && uu < total && uu < base + C::RIN) {
+                        int seg = 0, o0 = 0;
+#pragma unroll
+                        for (int t = 1; t < QMAX; ++t)
+                            if (uu >= cpx[t]) { seg = t; o0 = cpx[t]; }
+                        cand[s] = A.rowidx[S.segb[seg] + (uu - o0)];
+                    }
+                }
+#pragma unroll
+                for (int s = 0; s < NRI; ++s) {
+                    if (cand[s] >= 0) {
+                        int sl;
+                        if (hinsert<C::LOGHSI>(S.hI, cand[s], sl)) {
+                            int ps = atomicAdd(&S.cnt, 1);
+                            if (ps < C::NEWC) { S.newk[ps] = cand[s]; S.news[ps] = sl; }
                         }
                     }
                 }
-                __syncthreads();
+                wave_sync();
                 if (doC && !ovf && m + S.cnt > MMAX) ovf = true;
-                __syncthreads();
+                wave_sync();
             }
             if (doC && ovf) spill = true;
             // ============================ D. number the new rows (ascending order)
@@ -317,7 +338,7 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
                 }
             }
             kpos = gmax_i<G>(kpos);
-            __syncthreads();
+            wave_sync();
             if (doC && !ovf) {
                 if (kpos >= 0) {
                     kidx = kpos;
@@ -348,7 +369,7 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
             int nR = __popc(rflag);
             nR = gsum_i<G>(nR) + (kR ? 1 : 0);
             if (spill && gl == 0) S.cnt = 0;
-            __syncthreads();
+            wave_sync();
             if (ok) {
                 int32_t *R = args.rec_out + (int64_t)ps * args.rec_out_stride;
                 if (gl == 0) {
@@ -368,14 +389,14 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
                 if (kR && gl == 0) RR[atomicAdd(&S.cnt, 1)] = k;
 #pragma unroll
                 for (int t = 0; t < CMAX; ++t)
-                    if (t < nRh && gl == 0) RR[nR + t] = Rh[t];
+                    if (t < nRh && gl == 0) RR[nR + t] = S.Rh[t];
             }
             if (spill && !ok) {
                 // no larger tier can take the column
                 status = ST_CAP;
             }
             if (spill && ok) busy = false;
-            __syncthreads();
+            wave_sync();
         }
         if (busy && !spill) nRh = 0;  // pending rows consumed
 
@@ -408,24 +429,49 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
                 for (int s = 0; s < STAGE; ++s)
 #pragma unroll
                     for (int r = 0; r < RPL; ++r) S.stage[s * MMAX + r * G + gl] = 0.0;
-                __syncthreads();
-                if (ract) {
+                wave_sync();
+                // first G entries of each staged column: all loads issued together
+                int64_t ce1[STAGE], ce0[STAGE];
+                int rw[STAGE];
+                double vv[STAGE];
 #pragma unroll
-                    for (int s = 0; s < STAGE; ++s) {
-                        const int c = c0 + s;
-                        if (c < qn) {
-                            const int j = S.Jlist[c];
-                            const int64_t e1 = A.colptr[j + 1];
-                            for (int64_t e = A.colptr[j] + gl; e < e1; e += G) {
-                                int sl = hfind<C::LOGHSI>(S.hI, A.rowidx[e]);
-                                int li = sl >= 0 ? S.hIv[sl] : -1;
-                                if (li >= 0 && li < MMAX) S.stage[s * MMAX + li] = A.val[e];
-                                else lookup_fail = true;
-                            }
-                        }
+                for (int s = 0; s < STAGE; ++s) {
+                    const int c = c0 + s;
+                    ce0[s] = 0;
+                    ce1[s] = 0;
+                    if (ract && c < qn) {
+                        const int j = S.Jlist[c];
+                        ce0[s] = A.colptr[j];
+                        ce1[s] = A.colptr[j + 1];
                     }
                 }
-                __syncthreads();
+#pragma unroll
+                for (int s = 0; s < STAGE; ++s) {
+                    const int64_t e = ce0[s] + gl;
+                    rw[s] = -1;
+                    vv[s] = 0.0;
+                    if (e < ce1[s]) {
+                        rw[s] = A.rowidx[e];
+                        vv[s] = A.val[e];
+                    }
+                }
+#pragma unroll
+                for (int s = 0; s < STAGE; ++s) {
+                    if (rw[s] >= 0) {
+                        const int sl = hfind<C::LOGHSI>(S.hI, rw[s]);
+                        const int li = sl >= 0 ? S.hIv[sl] : -1;
+                        if (li >= 0 && li < MMAX) S.stage[s * MMAX + li] = vv[s];
+                        else lookup_fail = true;
+                    }
+                    // entries beyond the first G (long columns)
+                    for (int64_t e = ce0[s] + G + gl; e < ce1[s]; e += G) {
+                        const int sl = hfind<C::LOGHSI>(S.hI, A.rowidx[e]);
+                        const int li = sl >= 0 ? S.hIv[sl] : -1;
+                        if (li >= 0 && li < MMAX) S.stage[s * MMAX + li] = A.val[e];
+                        else lookup_fail = true;
+                    }
+                }
+                wave_sync();
                 if (ract) {
 #pragma unroll
                     for (int c = 0; c < QMAX; ++c) {
@@ -439,7 +485,7 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
                         }
                     }
                 }
-                __syncthreads();
+                wave_sync();
             }
             if (lookup_fail) atomicOr(args.err, 1);
 
@@ -470,12 +516,16 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
 #pragma unroll
                         for (int r = 0; r < RPL; ++r)
                             if (r * G + gl == j) b[r][j] = vj;
-                        if (gl == j % G) {
-                            S.rdiag[j] = alpha;
-                            S.beta[j] = bnew;
-                        }
+#pragma unroll
+                        for (int r = 0; r < RPL; ++r)
+                            if (r * G + gl == j) {
+                                rd[r] = alpha;
+                                bt[r] = bnew;
+                            }
                     }
-                    bj = newr ? bnew : S.beta[j];
+                    double bold = 0.0;
+                    if (wave_any(ja && !newr)) bold = gsum<G>((gl == j % G) ? bt[j / G] : 0.0);
+                    bj = newr ? bnew : bold;
                 }
 #pragma unroll
                 for (int c = 0; c < QMAX; ++c) {
@@ -521,10 +571,10 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
                     (void)dummy;
                     const bool own = (gl == j % G);
                     double val = 0.0;
-                    if (own && ja) val = z[j / G] / S.rdiag[j];
+                    if (own && ja) val = z[j / G] / rd[j / G];
                     const double mj = gsum<G>(val);
                     if (ja) {
-                        mt[j] = mj;
+                        if (gl == 0) S.mt[j] = mj;
 #pragma unroll
                         for (int r = 0; r < RPL; ++r)
                             if (r * G + gl < j) z[r] -= b[r][j] * mj;
@@ -556,7 +606,7 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
                     const double t = (P.drop == DROP_FIXED) ? P.tol : P.eps / ((double)q * A.norm1);
 #pragma unroll
                     for (int c = 0; c < QMAX; ++c)
-                        if (c < q && fabs(mt[c]) > t) keep |= 1u << c;
+                        if (c < q && fabs(S.mt[c]) > t) keep |= 1u << c;
                     if (__popc(keep) == q) dact = false;
                 }
                 if (wave_any(dact)) {
@@ -569,7 +619,7 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
 #pragma unroll
                             for (int c = 0; c < QMAX; ++c) {
                                 if (c < q) {
-                                    const double a = fabs(mt[c]);
+                                    const double a = fabs(S.mt[c]);
                                     const int gj = S.Jlist[c];
                                     if (a > bv || (a == bv && gj < bg)) { bv = a; bc = c; bg = gj; }
                                 }
@@ -582,7 +632,7 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
                             jv[s] = (c < q) ? S.Jlist[c] : 0;
                         }
                     }
-                    __syncthreads();
+                    wave_sync();
                     if (dact) {
 #pragma unroll
                         for (int s = 0; s < (QMAX + G - 1) / G; ++s) {
@@ -591,7 +641,7 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
                         }
                         for (int t = gl; t < C::HSJ; t += G) S.hJ[t] = HEMPTY;
                     }
-                    __syncthreads();
+                    wave_sync();
                     if (dact) {
                         const int nk = __popc(keep);
                         for (int t = gl; t < nk; t += G) {
@@ -604,7 +654,7 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
                         qmod = 0;
                         redo = true;
                     }
-                    __syncthreads();
+                    wave_sync();
                 }
             }
         }
@@ -620,7 +670,7 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
             // the columns taken in ascending global order. Rows whose coefficients tie
             // give bitwise-equal residuals, so exact ties reach the index tie-break.
             double *racc = S.stage;            // [MMAX] accumulator
-            double *mts = S.stage + MMAX;      // [QMAX] solution values by slot
+            const double *mts = S.mt;          // [QMAX] solution values by slot
             int *ord = S.newk;                 // [QMAX] slots in ascending column order
             if (sel) {
 #pragma unroll
@@ -634,15 +684,46 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
                     }
                 }
 #pragma unroll
-                for (int c = 0; c < QMAX; ++c)
-                    if (c < q && (c % G) == gl) mts[c] = mt[c];
-#pragma unroll
                 for (int r = 0; r < RPL; ++r) racc[r * G + gl] = 0.0;
             }
-            __syncthreads();
+            wave_sync();
             bool lookup_fail2 = false;
-            for (int t = 0; t < qmaxw; ++t) {
+            // Fast path: when no column of the group has more than G entries, each lane
+            // holds at most one entry per column, and the loads of all columns go out
+            // together; the accumulation below keeps the ascending column order.
+            bool shortcols = true;
+            int rw2[QMAX];
+            double vv2[QMAX];
+#pragma unroll
+            for (int t = 0; t < QMAX; ++t) {
+                rw2[t] = -1;
+                vv2[t] = 0.0;
                 if (sel && t < q) {
+                    const int j = S.Jlist[ord[t]];
+                    const int64_t e0 = A.colptr[j], e1 = A.colptr[j + 1];
+                    if (e1 - e0 > G) shortcols = false;
+                    const int64_t e = e0 + gl;
+                    if (e < e1) {
+                        rw2[t] = A.rowidx[e];
+                        vv2[t] = A.val[e];
+                    }
+                }
+            }
+            shortcols = gsum_i<G>(shortcols ? 0 : 1) == 0;
+            if (sel && shortcols) {
+#pragma unroll
+                for (int t = 0; t < QMAX; ++t) {
+                    if (rw2[t] >= 0) {
+                        const double mc = mts[ord[t]];
+                        const int sl = hfind<C::LOGHSI>(S.hI, rw2[t]);
+                        const int li = sl >= 0 ? S.hIv[sl] : -1;
+                        if (li >= 0 && li < MMAX) racc[li] = __fma_rn(vv2[t], mc, racc[li]);
+                        else lookup_fail2 = true;
+                    }
+                }
+            }
+            for (int t = 0; t < qmaxw; ++t) {
+                if (sel && !shortcols && t < q) {
                     const int c = ord[t];
                     const int j = S.Jlist[c];
                     const double mc = mts[c];
@@ -650,14 +731,14 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
                     for (int64_t e = A.colptr[j] + gl; e < e1; e += G) {
                         const int sl = hfind<C::LOGHSI>(S.hI, A.rowidx[e]);
                         const int li = sl >= 0 ? S.hIv[sl] : -1;
-                        if (li >= 0 && li < MMAX) racc[li] += A.val[e] * mc;
+                        if (li >= 0 && li < MMAX) racc[li] = __fma_rn(A.val[e], mc, racc[li]);
                         else lookup_fail2 = true;
                     }
                 }
                 // rows of one column are distinct; successive columns are ordered by
                 // the wave's in-order LDS execution
             }
-            __syncthreads();
+            wave_sync();
             if (lookup_fail2) atomicOr(args.err, 1);
             double ra[RPL];
             int gi[RPL];
@@ -687,7 +768,7 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
                 gargmax<G>(a, g);
                 if (kcand && (1.0 > a || (1.0 == a && k < g))) { a = 1.0; g = k; }
                 if (sel && a >= 0.0) {
-                    Rh[t] = g;
+                    if (gl == 0) S.Rh[t] = g;
                     nsel = t + 1;
                     if (kcand && g == k) {
                         kcand = false;
@@ -717,7 +798,7 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
             for (int c = 0; c < QMAX; ++c) {
                 if (c < qq && (c % G) == gl) {
                     args.out.arenaJ[slot + c] = S.Jlist[c];
-                    args.out.arenaV[slot + c] = mt[c];
+                    args.out.arenaV[slot + c] = S.mt[c];
                 }
             }
             if (gl == 0) {
@@ -731,7 +812,7 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
             }
             busy = false;
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 
