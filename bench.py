@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 METRIC = "RSAI columns/sec (FP64, n=262k) batched vs plain; fwd+bwd time; % FP64 roofline"
 FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk
 HBM_PEAK_GBS = 8000.0
-PARAMS = dict(c=3, lmax=8, eps=0.4, drop="fixed", tol=1e-3)
+PARAMS = dict(c=3, lmax=8, eps=0.4, drop="fixed", tol=1e-3, validate=2)
 
 
 def parse():
@@ -168,6 +168,7 @@ def main():
         "speedup_vs_plain": (plain["ms_per_step"] / (dt_b * 1e3)) if plain else None,
         "fwd_bwd_ms": fwd_bwd_ms,
         "build_event_ms": float(np.median(build_ms)),
+        "phase_ms": {k: float(v) for k, v in t.items()},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -77,10 +77,15 @@ typedef struct {
     int32_t drop;     /* rsai_drop_mode */
     double tol;       /* fixed drop tolerance (RSAI_DROP_FIXED) */
     int32_t sched;    /* rsai_sched */
-    int32_t validate; /* 1: check the CSC contract before building (one host sync) */
+    int32_t validate; /* CSC contract check: 0 none (input trusted), 1 checked before the
+                         build with one host synchronisation (RSAI_E_CSC from rsai_build),
+                         2 checked on the device without synchronising (the build's kernels
+                         then do nothing and rsai_plan_nnz reports RSAI_E_CSC) */
     int32_t tier0;    /* first size tier for the batched schedule: -1 = choose from the
                          tuning table / defaults, else a tier index (rsai_tier_info) */
     int32_t timing;   /* 1: record per-kernel HIP event times (rsai_plan_timing) */
+    int32_t refill;   /* first tier: -1 default, 0 a finished column's lanes take the next
+                         column at once, 1 the lanes of a wave take new columns together */
     int32_t keep_factors;        /* 1: keep R factors of the final solves for backward */
     int64_t factor_budget_bytes; /* keep factors only if they fit; else recompute */
 } rsai_params;
@@ -100,7 +105,8 @@ rsai_status rsai_params_default(rsai_params *p);
 rsai_status rsai_set_allocator(rsai_alloc_fn alloc, rsai_free_fn dealloc, void *ctx);
 
 /* Build M for one matrix. Queues all work on stream; with p->validate = 1 it first
-   synchronises once to check the CSC contract (RSAI_E_CSC on violation). */
+   synchronises once to check the CSC contract (RSAI_E_CSC on violation); with
+   p->validate = 0 or 2 it does not synchronise at all. */
 rsai_status rsai_build(const rsai_csc *A, const rsai_params *p, void *stream, rsai_plan **out);
 
 /* Build M for count matrices in one pass: the columns of all matrices share the

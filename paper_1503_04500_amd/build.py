@@ -32,14 +32,15 @@ def flags() -> list[str]:
             "-Wno-unused-command-line-argument", "-I", os.path.join(HERE, "..", "include")]
 
 
-def build(verbose: bool = False, extra: list[str] | None = None) -> str:
-    """Compile all sources and link ``librsai.so``. Returns the library path."""
-    os.makedirs(BUILD_DIR, exist_ok=True)
+def build(verbose: bool = False, extra: list[str] | None = None, out: str | None = None) -> str:
+    """Compile all sources and link ``librsai.so`` (or ``out``). Returns the library path."""
+    bdir = BUILD_DIR if out is None else BUILD_DIR + "_" + os.path.basename(out).replace(".so", "")
+    os.makedirs(bdir, exist_ok=True)
     hipcc = _hipcc()
     extra = list(extra or [])
 
     def compile_one(src):
-        obj = os.path.join(BUILD_DIR, src + ".o")
+        obj = os.path.join(bdir, src + ".o")
         cmd = [hipcc] + flags() + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
@@ -50,13 +51,14 @@ def build(verbose: bool = False, extra: list[str] | None = None) -> str:
 
     with cf.ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
         objs = list(ex.map(compile_one, SOURCES))
-    tmp = LIB + f".tmp{os.getpid()}"
+    target = LIB if out is None else out
+    tmp = target + f".tmp{os.getpid()}"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, target)
+    return target
 
 
 if __name__ == "__main__":

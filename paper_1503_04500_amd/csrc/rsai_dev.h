@@ -15,7 +15,7 @@ struct MatDev {              // one matrix of a (possibly batched) build
     const double *val;
     const int64_t *rowptr;   // row pattern of A (transpose), built by the library
     const int32_t *colidx;
-    double norm1;            // ||A||_1, max column absolute sum (eq. (4.3))
+    const unsigned long long *norm1_bits;  // ||A||_1 (max column absolute sum, eq. (4.3)) as bits
     int64_t col_base;        // global id of the matrix's first column in the batch
 };
 

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cstdarg>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -60,13 +61,12 @@ struct MatPlan {
     int64_t *rowptr = nullptr;
     int32_t *colidx = nullptr;
     int32_t *rowcnt = nullptr;
-    double norm1 = 0.0;
-    int64_t g = 0;
     int64_t *colptrM = nullptr;
     int32_t *rowidxM = nullptr;
     double *valM = nullptr;
     int64_t capM = 0;
     int64_t nnzM = -1;
+    int64_t *summary = nullptr;  // device: nnz(M), error flags, failed-column counts
     int32_t maxq = -1, maxm = -1;  // largest final |J_k| and |I_k| (first backward)
     // transpose of M (rows) for y = M x
     int64_t *rowptrT = nullptr;
@@ -129,9 +129,23 @@ static rsai_status check_params(const rsai_params *p) {
     if (p->drop < 0 || p->drop > 2) return fail(RSAI_E_ARG, "drop mode must be 0, 1 or 2");
     if (p->drop == 1 && !(p->tol >= 0.0)) return fail(RSAI_E_ARG, "tol must be >= 0");
     if (p->sched < 0 || p->sched > 1) return fail(RSAI_E_ARG, "sched must be 0 or 1");
+    if (p->validate < 0 || p->validate > 2) return fail(RSAI_E_ARG, "validate must be 0, 1 or 2");
     if (p->tier0 < -1 || p->tier0 >= kNumTiers) return fail(RSAI_E_ARG, "tier0 out of range");
+    if (p->refill < -1 || p->refill > 1) return fail(RSAI_E_ARG, "refill must be -1, 0 or 1");
     return RSAI_OK;
 }
+
+// Bump layout over one device allocation: a first pass measures, a second assigns.
+struct Layout {
+    char *base = nullptr;
+    size_t off = 0;
+    template <class T>
+    T *take(int64_t count) {
+        const size_t a = (off + 255) & ~(size_t)255;
+        off = a + sizeof(T) * (size_t)std::max<int64_t>(count, 1);
+        return base ? reinterpret_cast<T *>(base + a) : nullptr;
+    }
+};
 
 extern "C" {
 
@@ -147,6 +161,7 @@ rsai_status rsai_params_default(rsai_params *p) {
     p->validate = 1;
     p->tier0 = -1;
     p->timing = 0;
+    p->refill = -1;
     p->keep_factors = 0;
     p->factor_budget_bytes = 0;
     return RSAI_OK;
@@ -182,6 +197,13 @@ static int device_cus() {
     return cus;
 }
 
+static int sync_refill_default(int requested) {
+    if (requested == 0 || requested == 1) return requested;
+    const char *e = getenv("RSAI_SYNC_REFILL");
+    if (e && (e[0] == '0' || e[0] == '1')) return e[0] - '0';
+    return 1;
+}
+
 static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_params *prm, void *stream,
                               rsai_plan **out) {
     if (!out) return fail(RSAI_E_ARG, "out is NULL");
@@ -189,11 +211,14 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
     if (count < 1 || !As) return fail(RSAI_E_ARG, "need at least one matrix");
     rsai_status st = check_params(prm);
     if (st != RSAI_OK) return st;
+    int64_t ncols = 0;
     for (int i = 0; i < count; ++i) {
         const rsai_csc &A = As[i];
-        if (A.n < 1 || A.n > INT32_MAX - 1 || A.nnz < A.n || !A.colptr || !A.rowidx || !A.val)
+        if (A.n < 1 || A.n > INT32_MAX - 1 || A.nnz < A.n || A.nnz > INT32_MAX || !A.colptr || !A.rowidx || !A.val)
             return fail(RSAI_E_ARG, "matrix %d: bad sizes or NULL pointers", i);
+        ncols += A.n;
     }
+    if (ncols > INT32_MAX - 1) return fail(RSAI_E_ARG, "too many columns in one build");
     (void)hipGetLastError();  // clear an error left by an unrelated earlier call
     rsai_plan *P = new rsai_plan();
     P->p = *prm;
@@ -212,82 +237,19 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
     }
     P->mats.resize(count);
     P->hcolbase.resize(count + 1);
-    int64_t ncols = 0;
-    for (int i = 0; i < count; ++i) {
+    for (int i = 0, acc = 0; i < count; ++i) {
         P->mats[i].A = As[i];
-        P->mats[i].col_base = ncols;
-        P->hcolbase[i] = ncols;
-        ncols += As[i].n;
+        P->mats[i].col_base = acc;
+        P->hcolbase[i] = acc;
+        acc += (int)As[i].n;
     }
     P->hcolbase[count] = ncols;
     P->ncols = ncols;
-
-    // ---- preprocessing: contract check, row pattern, g, ||A||_1
-    P->err = P->alloc<int32_t>(4, st);
-    P->stats = P->alloc<unsigned long long>(2 * (int64_t)count, st);
     int64_t maxn = 0;
     for (int i = 0; i < count; ++i) maxn = std::max(maxn, As[i].n);
-    P->scan_tmp = P->alloc<int64_t>(scan_tmp_elems(std::max(maxn, ncols) + 1), st);
-    if (st != RSAI_OK) return bail(st);
-    launch_fill_i32(P->err, 0, 4, s);
-    launch_fill_i64((int64_t *)P->stats, 0, 2 * count, s);
-    if (P->p.validate) {
-        for (int i = 0; i < count; ++i) launch_validate(As[i].n, As[i].nnz, As[i].colptr, As[i].rowidx, P->err, s);
-        int32_t herr = 0;
-        if (hipMemcpyAsync(&herr, P->err, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
-            return bail(fail(RSAI_E_HIP, "validation readback failed"));
-        if (herr) {
-            return bail(fail(RSAI_E_CSC, "malformed CSC (flags %d: 1 colptr, 2 row indices, 4 empty column)", herr));
-        }
-    }
-    for (int i = 0; i < count; ++i) {
-        MatPlan &M = P->mats[i];
-        const int64_t n = As[i].n, nnz = As[i].nnz;
-        M.rowptr = P->alloc<int64_t>(n + 1, st);
-        M.colidx = P->alloc<int32_t>(nnz, st);
-        M.rowcnt = P->alloc<int32_t>(n, st);
-        int32_t *fillpos = P->alloc<int32_t>(n, st);
-        if (st != RSAI_OK) return bail(st);
-        launch_fill_i32(M.rowcnt, 0, n, s);
-        launch_fill_i32(fillpos, 0, n, s);
-        launch_row_counts(nnz, As[i].rowidx, M.rowcnt, s);
-        launch_scan_i32(M.rowcnt, n, M.rowptr, P->scan_tmp, s);
-        launch_row_fill(n, As[i].colptr, As[i].rowidx, M.rowptr, fillpos, M.colidx, s);
-        launch_mat_stats(n, As[i].colptr, As[i].val, M.rowcnt, P->stats + 2 * i, s);
-    }
-    std::vector<unsigned long long> hstats(2 * count);
-    if (hipMemcpyAsync(hstats.data(), P->stats, sizeof(unsigned long long) * 2 * count, hipMemcpyDeviceToHost, s) !=
-            hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-        return bail(fail(RSAI_E_HIP, "preprocessing readback failed"));
-    P->hmats.resize(count);
-    for (int i = 0; i < count; ++i) {
-        MatPlan &M = P->mats[i];
-        M.g = (int64_t)hstats[2 * i];
-        unsigned long long bits = hstats[2 * i + 1];
-        std::memcpy(&M.norm1, &bits, sizeof(double));
-        MatDev &D = P->hmats[i];
-        D.n = As[i].n;
-        D.colptr = As[i].colptr;
-        D.rowidx = As[i].rowidx;
-        D.val = As[i].val;
-        D.rowptr = M.rowptr;
-        D.colidx = M.colidx;
-        D.norm1 = M.norm1;
-        D.col_base = M.col_base;
-    }
-    P->d_mats = P->alloc<MatDev>(count, st);
-    P->d_colbase = P->alloc<int64_t>(count + 1, st);
-    if (st != RSAI_OK) return bail(st);
-    if (hipMemcpyAsync(P->d_mats, P->hmats.data(), sizeof(MatDev) * count, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(P->d_colbase, P->hcolbase.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice, s) !=
-            hipSuccess)
-        return bail(fail(RSAI_E_HIP, "matrix table upload failed"));
-    P->record(1, s);
 
-    // ---- per-column outputs and the result arena: one slot of QMAX entries per
-    // column for every size class that may finish it
+    // ---- size classes and the result arena: one slot of QMAX entries per column
+    // for every size class that may finish it
     const bool plain = (P->p.sched == RSAI_SCHED_PLAIN);
     const int t0 = plain ? kPlainTier : ((P->p.tier0 >= 0) ? P->p.tier0 : 0);
     const int tlast = plain ? kPlainTier : kNumTiers - 1;
@@ -298,27 +260,103 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
         acap += ncols * (int64_t)kTiers[t].QMAX;
     }
     P->arena_cap = acap;
-    P->out.off = P->alloc<int64_t>(ncols, st);
-    P->out.nJ = P->alloc<int32_t>(ncols, st);
-    P->out.nI = P->alloc<int32_t>(ncols, st);
-    P->out.loops = P->alloc<int32_t>(ncols, st);
-    P->out.status = P->alloc<int32_t>(ncols, st);
-    P->out.resnorm = P->alloc<double>(ncols, st);
-    P->out.flops = P->alloc<double>(ncols, st);
-    P->out.arenaJ = P->alloc<int32_t>(acap, st);
-    P->out.arenaV = P->alloc<double>(acap, st);
     const int nlaunch = plain ? P->p.lmax + 1 : (tlast - t0 + 1);
-    P->rec_count = P->alloc<int32_t>(nlaunch + 1, st);
-    if (plain) {
-        P->rec[0] = P->alloc<int32_t>(ncols * (int64_t)kTiers[kPlainTier].REC, st);
-        P->rec[1] = P->alloc<int32_t>(ncols * (int64_t)kTiers[kPlainTier].REC, st);
-    } else {
-        for (int t = t0; t < tlast; ++t) P->rec[t] = P->alloc<int32_t>(ncols * (int64_t)kTiers[t].REC, st);
-    }
+    const int64_t qlast = kTiers[tlast].QMAX;
+
+    // ---- every device buffer of the build, from one allocation
+    std::vector<int32_t *> fillpos(count);
+    auto layout = [&](Layout &L) {
+        P->err = L.take<int32_t>(4);
+        P->stats = L.take<unsigned long long>(2 * (int64_t)count);
+        P->scan_tmp = L.take<int64_t>(scan_tmp_elems(maxn + 1));
+        P->d_mats = L.take<MatDev>(count);
+        P->d_colbase = L.take<int64_t>(count + 1);
+        for (int i = 0; i < count; ++i) {
+            MatPlan &M = P->mats[i];
+            const int64_t n = As[i].n, nnz = As[i].nnz;
+            M.rowptr = L.take<int64_t>(n + 1);
+            M.colidx = L.take<int32_t>(nnz);
+            M.rowcnt = L.take<int32_t>(n);
+            fillpos[i] = L.take<int32_t>(n);
+            M.capM = n * qlast;
+            M.summary = L.take<int64_t>(8);
+            M.colptrM = L.take<int64_t>(n + 1);
+            M.rowidxM = L.take<int32_t>(M.capM);
+            M.valM = L.take<double>(M.capM);
+        }
+        P->out.off = L.take<int64_t>(ncols);
+        P->out.nJ = L.take<int32_t>(ncols);
+        P->out.nI = L.take<int32_t>(ncols);
+        P->out.loops = L.take<int32_t>(ncols);
+        P->out.status = L.take<int32_t>(ncols);
+        P->out.resnorm = L.take<double>(ncols);
+        P->out.flops = L.take<double>(ncols);
+        P->out.arenaJ = L.take<int32_t>(acap);
+        P->out.arenaV = L.take<double>(acap);
+        P->rec_count = L.take<int32_t>(nlaunch + 1);
+        for (int t = 0; t < 8; ++t) P->rec[t] = nullptr;
+        if (plain) {
+            P->rec[0] = L.take<int32_t>(ncols * (int64_t)kTiers[kPlainTier].REC);
+            P->rec[1] = L.take<int32_t>(ncols * (int64_t)kTiers[kPlainTier].REC);
+        } else {
+            for (int t = t0; t < tlast; ++t) P->rec[t] = L.take<int32_t>(ncols * (int64_t)kTiers[t].REC);
+        }
+    };
+    Layout L0;
+    layout(L0);
+    Layout L1;
+    L1.base = P->alloc<char>((int64_t)L0.off, st);
     if (st != RSAI_OK) return bail(st);
-    launch_fill_i32(P->rec_count, 0, nlaunch + 1, s);
-    launch_fill_i32(P->out.status, ST_INTERNAL, ncols, s);  // every column must be written
-    launch_fill_i32(P->out.nJ, 0, ncols, s);
+    layout(L1);
+
+    // ---- preprocessing: CSC contract, row pattern, ||A||_1 (all on the stream)
+    {
+        int32_t *fp[6] = {P->err, (int32_t *)P->stats, P->rec_count, P->out.status, P->out.nJ, nullptr};
+        int64_t fc[6] = {4, 4 * (int64_t)count, nlaunch + 1, ncols, ncols, 0};
+        int32_t fv[6] = {0, 0, 0, ST_INTERNAL, 0, 0};  // every column's status must be written
+        launch_fill_many(fp, fc, fv, 5, s);
+    }
+    if (P->p.validate)
+        for (int i = 0; i < count; ++i) launch_validate(As[i].n, As[i].nnz, As[i].colptr, As[i].rowidx, P->err, s);
+    if (P->p.validate == 1) {
+        // synchronous check: RSAI_E_CSC is returned here; with validate = 2 the later
+        // kernels skip their work and the error is reported by rsai_plan_nnz
+        int32_t herr = 0;
+        if (hipMemcpyAsync(&herr, P->err, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return bail(fail(RSAI_E_HIP, "validation readback failed"));
+        if (herr) return bail(fail(RSAI_E_CSC, "malformed CSC (flags %d: 1 colptr, 2 row indices, 4 empty column)", herr));
+    }
+    P->hmats.resize(count);
+    for (int i = 0; i < count; ++i) {
+        MatPlan &M = P->mats[i];
+        const int64_t n = As[i].n, nnz = As[i].nnz;
+        {
+            int32_t *fp[6] = {M.rowcnt, fillpos[i], nullptr, nullptr, nullptr, nullptr};
+            int64_t fc[6] = {n, n, 0, 0, 0, 0};
+            int32_t fv[6] = {0, 0, 0, 0, 0, 0};
+            launch_fill_many(fp, fc, fv, 2, s);
+        }
+        launch_row_counts(nnz, As[i].rowidx, M.rowcnt, P->err, s);
+        launch_scan_i32(M.rowcnt, n, M.rowptr, P->scan_tmp, s);
+        launch_row_fill(n, As[i].colptr, As[i].rowidx, M.rowptr, fillpos[i], M.colidx, P->err, s);
+        if (P->p.drop == RSAI_DROP_ADAPTIVE)
+            launch_mat_stats(n, As[i].colptr, As[i].val, M.rowcnt, P->stats + 2 * i, P->err, s);
+        MatDev &D = P->hmats[i];
+        D.n = n;
+        D.colptr = As[i].colptr;
+        D.rowidx = As[i].rowidx;
+        D.val = As[i].val;
+        D.rowptr = M.rowptr;
+        D.colidx = M.colidx;
+        D.norm1_bits = P->stats + 2 * i + 1;
+        D.col_base = M.col_base;
+    }
+    if (hipMemcpyAsync(P->d_mats, P->hmats.data(), sizeof(MatDev) * count, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(P->d_colbase, P->hcolbase.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice, s) !=
+            hipSuccess)
+        return bail(fail(RSAI_E_HIP, "matrix table upload failed"));
+    P->record(1, s);
 
     TierArgs base{};
     base.mats = P->d_mats;
@@ -332,6 +370,7 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
     base.out = P->out;
     base.qlen = ncols;
     base.err = P->err;
+    base.sync_refill = sync_refill_default(P->p.refill);
     const int cus = device_cus();
     if (plain) {
         // ---- plain schedule: one size class, one launch per loop of Algorithm 1;
@@ -342,6 +381,7 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
             TierArgs a = base;
             a.arena_base = slot_base[t];
             a.one_loop = 1;
+            a.sync_refill = 0;
             if (L == 0) {
                 a.rec_in = nullptr;
             } else {
@@ -365,6 +405,7 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
             TierArgs a = base;
             a.arena_base = slot_base[t];
             a.one_loop = 0;
+            if (t != t0) a.sync_refill = 0;
             if (t == t0) {
                 a.rec_in = nullptr;
             } else {
@@ -392,19 +433,13 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
     P->ntiers_used = tlast - t0 + 1;
     P->record(3, s);
 
-    // ---- assembly of M per matrix: colptr = scan(nJ), then sort + copy
-    const int64_t qlast = kTiers[tlast].QMAX;
+    // ---- assembly of M per matrix: colptr = scan(nJ), then compaction
     for (int i = 0; i < count; ++i) {
         MatPlan &M = P->mats[i];
         const int64_t n = As[i].n;
-        M.capM = n * qlast;
-        M.colptrM = P->alloc<int64_t>(n + 1, st);
-        M.rowidxM = P->alloc<int32_t>(M.capM, st);
-        M.valM = P->alloc<double>(M.capM, st);
-        if (st != RSAI_OK) return bail(st);
         launch_scan_i32(P->out.nJ + M.col_base, n, M.colptrM, P->scan_tmp, s);
-        launch_assemble(n, P->out.off + M.col_base, P->out.nJ + M.col_base, M.colptrM, P->out.arenaJ, P->out.arenaV,
-                        M.rowidxM, M.valM, s);
+        launch_assemble(n, (int)qlast, P->out.off + M.col_base, P->out.nJ + M.col_base, M.colptrM, P->out.arenaJ,
+                        P->out.arenaV, M.rowidxM, M.valM, s);
     }
     P->record(4, s);
     hipError_t le = hipGetLastError();
@@ -442,25 +477,19 @@ rsai_status rsai_plan_nnz(const rsai_plan *Pc, int32_t mat, int64_t *nnzM) {
     MatPlan &M = P->mats[mat];
     if (M.nnzM < 0) {
         const int64_t n = M.A.n;
-        int64_t nz = 0;
-        int32_t herr = 0;
-        HIPCHK(hipMemcpyAsync(&nz, M.colptrM + n, sizeof(int64_t), hipMemcpyDeviceToHost, P->stream));
-        HIPCHK(hipMemcpyAsync(&herr, P->err, sizeof(int32_t), hipMemcpyDeviceToHost, P->stream));
-        std::vector<int32_t> stv((size_t)n);
-        HIPCHK(hipMemcpyAsync(stv.data(), P->out.status + M.col_base, sizeof(int32_t) * n, hipMemcpyDeviceToHost,
-                              P->stream));
+        int64_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        launch_fill_i64(M.summary, 0, 8, P->stream);
+        launch_summary(n, M.colptrM, P->out.status + M.col_base, P->err, M.summary, P->stream);
+        HIPCHK(hipMemcpyAsync(h, M.summary, sizeof(h), hipMemcpyDeviceToHost, P->stream));
         HIPCHK(hipStreamSynchronize(P->stream));
-        if (herr) return fail(RSAI_E_STATE, "internal index error (flags %d)", herr);
-        int64_t nsing = 0, ncap = 0, nbad = 0;
-        for (int64_t k = 0; k < n; ++k) {
-            if (stv[k] == ST_SINGULAR) ++nsing;
-            else if (stv[k] == ST_CAP) ++ncap;
-            else if (stv[k] != ST_OK) ++nbad;
-        }
-        if (nbad) return fail(RSAI_E_STATE, "%lld columns were not processed", (long long)nbad);
-        if (nsing) return fail(RSAI_E_SINGULAR, "%lld columns have a rank-deficient LS problem", (long long)nsing);
-        if (ncap) return fail(RSAI_E_CAP, "%lld columns outgrew the largest supported LS size", (long long)ncap);
-        M.nnzM = nz;
+        const int64_t herr = h[1];
+        if (herr & 7) return fail(RSAI_E_CSC, "malformed CSC (flags %lld: 1 colptr, 2 row indices, 4 empty column)",
+                                  (long long)herr);
+        if (herr) return fail(RSAI_E_STATE, "internal index error (flags %lld)", (long long)herr);
+        if (h[4]) return fail(RSAI_E_STATE, "%lld columns were not processed", (long long)h[4]);
+        if (h[2]) return fail(RSAI_E_SINGULAR, "%lld columns have a rank-deficient LS problem", (long long)h[2]);
+        if (h[3]) return fail(RSAI_E_CAP, "%lld columns outgrew the largest supported LS size", (long long)h[3]);
+        M.nnzM = h[0];
     }
     *nnzM = M.nnzM;
     return RSAI_OK;
@@ -515,7 +544,7 @@ rsai_status rsai_apply(const rsai_plan *Pc, int32_t mat, const double *x, double
         if (st != RSAI_OK) return st;
         launch_fill_i32(cnt, 0, n, P->stream);
         launch_fill_i32(fill, 0, n, P->stream);
-        launch_row_counts(nz, M.rowidxM, cnt, P->stream);
+        launch_row_counts(nz, M.rowidxM, cnt, P->err, P->stream);
         launch_scan_i32(cnt, n, rp, P->scan_tmp, P->stream);
         launch_csc_transpose_fill(n, M.colptrM, M.rowidxM, M.valM, rp, fill, ci, vv, P->stream);
         launch_sort_rows(n, rp, ci, vv, P->stream);
@@ -553,10 +582,12 @@ rsai_status rsai_spmv(const rsai_csc *A, const double *x, double *y, int32_t tra
     int32_t *ci = (int32_t *)al(4 * nnz);
     double *vv = (double *)al(8 * nnz);
     int64_t *stmp = (int64_t *)al(8 * scan_tmp_elems(n + 1));
+    int32_t *zerr = (int32_t *)al(16);
     if (st == RSAI_OK) {
+        launch_fill_i32(zerr, 0, 4, s);
         launch_fill_i32(cnt, 0, n, s);
         launch_fill_i32(fill, 0, n, s);
-        launch_row_counts(nnz, A->rowidx, cnt, s);
+        launch_row_counts(nnz, A->rowidx, cnt, zerr, s);
         launch_scan_i32(cnt, n, rp, stmp, s);
         launch_csc_transpose_fill(n, A->colptr, A->rowidx, A->val, rp, fill, ci, vv, s);
         launch_sort_rows(n, rp, ci, vv, s);

@@ -26,11 +26,14 @@ void launch_fill_i64(int64_t *p, int64_t v, int64_t count, hipStream_t s);
 void launch_fill_f64(double *p, double v, int64_t count, hipStream_t s);
 // row pattern of A: counts -> rowptr (exclusive scan) -> colidx (unordered inside a row);
 // g (max row count) and ||A||_1 as bit patterns in stats[0], stats[1]
-void launch_row_counts(int64_t nnz, const int32_t *rowidx, int32_t *cnt, hipStream_t s);
+void launch_row_counts(int64_t nnz, const int32_t *rowidx, int32_t *cnt, const int32_t *err, hipStream_t s);
 void launch_row_fill(int64_t n, const int64_t *colptr, const int32_t *rowidx, const int64_t *rowptr,
-                     int32_t *fillpos, int32_t *colidx, hipStream_t s);
+                     int32_t *fillpos, int32_t *colidx, const int32_t *err, hipStream_t s);
 void launch_mat_stats(int64_t n, const int64_t *colptr, const double *val, const int32_t *rowcnt,
-                      unsigned long long *stats, hipStream_t s);
+                      unsigned long long *stats, const int32_t *err, hipStream_t s);
+void launch_fill_many(int32_t *const *p, const int64_t *count, const int32_t *v, int k, hipStream_t s);
+void launch_summary(int64_t n, const int64_t *colptrM, const int32_t *status, const int32_t *err, int64_t *out,
+                    hipStream_t s);
 
 // exclusive scan of n int32 counts into out[0..n] (out[n] = total); tmp needs
 // scan_tmp_elems(n) int64 elements
@@ -38,8 +41,8 @@ int64_t scan_tmp_elems(int64_t n);
 void launch_scan_i32(const int32_t *in, int64_t n, int64_t *out, int64_t *tmp, hipStream_t s);
 
 // ---- assembly: per-column results in the arena -> CSC (rows ascending)
-void launch_assemble(int64_t n, const int64_t *off, const int32_t *nJ, const int64_t *colptrM,
-                     int32_t *arenaJ, double *arenaV, int32_t *rowidxM, double *valM, hipStream_t s);
+void launch_assemble(int64_t n, int qcap, const int64_t *off, const int32_t *nJ, const int64_t *colptrM,
+                     const int32_t *arenaJ, const double *arenaV, int32_t *rowidxM, double *valM, hipStream_t s);
 
 // ---- SpMV
 void launch_csc_transpose_fill(int64_t n, const int64_t *colptr, const int32_t *rowidx, const double *val,

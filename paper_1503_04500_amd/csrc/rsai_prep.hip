@@ -32,6 +32,56 @@ void launch_fill_f64(double *p, double v, int64_t count, hipStream_t s) {
     if (count > 0) hipLaunchKernelGGL(k_fill<double>, dim3(nblocks(count, 1024)), dim3(256), 0, s, p, v, count);
 }
 
+// one launch for several int32 fills: p[i][0..count[i]) = v[i]
+struct Fill4 {
+    int32_t *p[6];
+    int64_t count[6];
+    int32_t v[6];
+};
+__global__ void k_fill_many(Fill4 f) {
+    for (int a = 0; a < 6; ++a) {
+        if (!f.p[a]) continue;
+        for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < f.count[a];
+             i += (int64_t)gridDim.x * blockDim.x)
+            f.p[a][i] = f.v[a];
+    }
+}
+void launch_fill_many(int32_t *const *p, const int64_t *count, const int32_t *v, int k, hipStream_t s) {
+    Fill4 f{};
+    int64_t mx = 1;
+    for (int a = 0; a < k && a < 6; ++a) {
+        f.p[a] = p[a];
+        f.count[a] = count[a];
+        f.v[a] = v[a];
+        mx = std::max(mx, count[a]);
+    }
+    hipLaunchKernelGGL(k_fill_many, dim3(nblocks(mx, 1024)), dim3(256), 0, s, f);
+}
+
+// summary for the host: out[0] = colptrM[n] (nnz of M), out[1] = error flags,
+// out[2..4] = columns with status singular / cap / anything else not ok
+__global__ void k_summary(int64_t n, const int64_t *colptrM, const int32_t *status, const int32_t *err,
+                          int64_t *out) {
+    int64_t a = 0, b = 0, c = 0;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const int st = status[k];
+        a += (st == 3);
+        b += (st == 6);
+        c += (st != 0 && st != 3 && st != 6);
+    }
+    if (a) atomicAdd((unsigned long long *)&out[2], (unsigned long long)a);
+    if (b) atomicAdd((unsigned long long *)&out[3], (unsigned long long)b);
+    if (c) atomicAdd((unsigned long long *)&out[4], (unsigned long long)c);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        out[0] = colptrM[n];
+        out[1] = *err;
+    }
+}
+void launch_summary(int64_t n, const int64_t *colptrM, const int32_t *status, const int32_t *err, int64_t *out,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_summary, dim3(std::min(nblocks(n, 256), 256)), dim3(256), 0, s, n, colptrM, status, err, out);
+}
+
 // ---------------------------------------------------------------- CSC contract
 
 __global__ void k_validate(int64_t n, int64_t nnz, const int64_t *colptr, const int32_t *rowidx, int32_t *err) {
@@ -63,16 +113,18 @@ void launch_validate(int64_t n, int64_t nnz, const int64_t *colptr, const int32_
 
 // ---------------------------------------------------------------- row pattern
 
-__global__ void k_row_counts(int64_t nnz, const int32_t *rowidx, int32_t *cnt) {
+__global__ void k_row_counts(int64_t nnz, const int32_t *rowidx, int32_t *cnt, const int32_t *err) {
+    if (*err) return;  // the CSC contract failed: touch nothing
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x)
         atomicAdd(&cnt[rowidx[e]], 1);
 }
-void launch_row_counts(int64_t nnz, const int32_t *rowidx, int32_t *cnt, hipStream_t s) {
-    if (nnz > 0) hipLaunchKernelGGL(k_row_counts, dim3(nblocks(nnz, 1024)), dim3(256), 0, s, nnz, rowidx, cnt);
+void launch_row_counts(int64_t nnz, const int32_t *rowidx, int32_t *cnt, const int32_t *err, hipStream_t s) {
+    if (nnz > 0) hipLaunchKernelGGL(k_row_counts, dim3(nblocks(nnz, 1024)), dim3(256), 0, s, nnz, rowidx, cnt, err);
 }
 
 __global__ void k_row_fill(int64_t n, const int64_t *colptr, const int32_t *rowidx, const int64_t *rowptr,
-                           int32_t *fillpos, int32_t *colidx) {
+                           int32_t *fillpos, int32_t *colidx, const int32_t *err) {
+    if (*err) return;
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
         for (int64_t e = colptr[j]; e < colptr[j + 1]; ++e) {
             const int r = rowidx[e];
@@ -82,14 +134,16 @@ __global__ void k_row_fill(int64_t n, const int64_t *colptr, const int32_t *rowi
     }
 }
 void launch_row_fill(int64_t n, const int64_t *colptr, const int32_t *rowidx, const int64_t *rowptr,
-                     int32_t *fillpos, int32_t *colidx, hipStream_t s) {
-    hipLaunchKernelGGL(k_row_fill, dim3(nblocks(n, 256)), dim3(256), 0, s, n, colptr, rowidx, rowptr, fillpos, colidx);
+                     int32_t *fillpos, int32_t *colidx, const int32_t *err, hipStream_t s) {
+    hipLaunchKernelGGL(k_row_fill, dim3(nblocks(n, 256)), dim3(256), 0, s, n, colptr, rowidx, rowptr, fillpos, colidx,
+                       err);
 }
 
 // stats[0] = max row count (g of Theorem 4.1), stats[1] = bits of ||A||_1
 // (max column absolute sum); block reduction, one atomic per block
 __global__ void k_mat_stats(int64_t n, const int64_t *colptr, const double *val, const int32_t *rowcnt,
-                            unsigned long long *stats) {
+                            unsigned long long *stats, const int32_t *err) {
+    if (*err) return;
     __shared__ unsigned long long sg[256], sn[256];
     unsigned long long gmax = 0, nmax = 0;
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
@@ -116,8 +170,8 @@ __global__ void k_mat_stats(int64_t n, const int64_t *colptr, const double *val,
     }
 }
 void launch_mat_stats(int64_t n, const int64_t *colptr, const double *val, const int32_t *rowcnt,
-                      unsigned long long *stats, hipStream_t s) {
-    hipLaunchKernelGGL(k_mat_stats, dim3(std::min(nblocks(n, 256), 1024)), dim3(256), 0, s, n, colptr, val, rowcnt, stats);
+                      unsigned long long *stats, const int32_t *err, hipStream_t s) {
+    hipLaunchKernelGGL(k_mat_stats, dim3(std::min(nblocks(n, 256), 1024)), dim3(256), 0, s, n, colptr, val, rowcnt, stats, err);
 }
 
 // ---------------------------------------------------------------- exclusive scan
@@ -145,33 +199,19 @@ __global__ void k_scan_sums(const int32_t *in, int64_t n, int64_t *bsum) {
     if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
 }
 
-__global__ void k_scan_top(int64_t *bsum, int64_t nb) {
-    // exclusive scan of nb block sums by one block, in chunks of SCAN_T
+__global__ void k_scan_final(const int32_t *in, int64_t n, int64_t nb, const int64_t *bsum, int64_t *out) {
     __shared__ int64_t sh[SCAN_T];
-    __shared__ int64_t carry;
-    if (threadIdx.x == 0) carry = 0;
+    // offset of this block: sum of the sums of all earlier blocks
+    int64_t pre = 0;
+    for (int64_t i = threadIdx.x; i < blockIdx.x; i += SCAN_T) pre += bsum[i];
+    sh[threadIdx.x] = pre;
     __syncthreads();
-    for (int64_t c0 = 0; c0 < nb; c0 += SCAN_T) {
-        int64_t i = c0 + threadIdx.x;
-        int64_t v = (i < nb) ? bsum[i] : 0;
-        sh[threadIdx.x] = v;
-        __syncthreads();
-        for (int off = 1; off < SCAN_T; off <<= 1) {
-            int64_t t = (threadIdx.x >= off) ? sh[threadIdx.x - off] : 0;
-            __syncthreads();
-            sh[threadIdx.x] += t;
-            __syncthreads();
-        }
-        if (i < nb) bsum[i] = carry + sh[threadIdx.x] - v;
-        __syncthreads();
-        if (threadIdx.x == SCAN_T - 1) carry += sh[SCAN_T - 1];
+    for (int w = SCAN_T / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) bsum[nb] = carry;
-}
-
-__global__ void k_scan_final(const int32_t *in, int64_t n, const int64_t *bsum, int64_t *out) {
-    __shared__ int64_t sh[SCAN_T];
+    const int64_t boff = sh[0];
+    __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * SCAN_B + (int64_t)threadIdx.x * SCAN_PER;
     int64_t loc[SCAN_PER];
     int64_t s = 0;
@@ -189,60 +229,45 @@ __global__ void k_scan_final(const int32_t *in, int64_t n, const int64_t *bsum, 
         sh[threadIdx.x] += t;
         __syncthreads();
     }
-    const int64_t pre = bsum[blockIdx.x] + sh[threadIdx.x] - s;
+    const int64_t pre2 = boff + sh[threadIdx.x] - s;
 #pragma unroll
     for (int t = 0; t < SCAN_PER; ++t) {
         int64_t i = base + t;
-        if (i < n) out[i] = pre + loc[t];
+        if (i < n) out[i] = pre2 + loc[t];
     }
+    if (blockIdx.x == nb - 1 && threadIdx.x == SCAN_T - 1) out[n] = boff + sh[SCAN_T - 1];
 }
 
-__global__ void k_scan_total(int64_t n, int64_t nb, const int64_t *bsum, int64_t *out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) out[n] = bsum[nb];
-}
-
+// exclusive scan with out[n] = total (n >= 1)
 void launch_scan_i32(const int32_t *in, int64_t n, int64_t *out, int64_t *tmp, hipStream_t s) {
     const int64_t nb = (n + SCAN_B - 1) / SCAN_B;
-    if (nb > 0) hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, n, tmp);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(SCAN_T), 0, s, tmp, nb);
-    if (nb > 0) hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, n, tmp, out);
-    hipLaunchKernelGGL(k_scan_total, dim3(1), dim3(64), 0, s, n, nb, tmp, out);
+    hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, n, nb, tmp, out);
 }
 
 // ---------------------------------------------------------------- assembly
-// One thread per column: insertion-sort the column's (row, value) pairs in the
-// arena by row index, then copy them to M at colptrM[k].
+// The tier kernels leave each column's (row, value) pairs in ascending row order in
+// its arena slot; assembly is a compaction: one thread per (column, position) pair
+// over n x QCAP, reading the padded slots and writing M at colptrM[k] + t.
 
-__global__ void k_assemble(int64_t n, const int64_t *off, const int32_t *nJ, const int64_t *colptrM,
-                           int32_t *aJ, double *aV, int32_t *rowidxM, double *valM) {
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
-        const int q = nJ[k];
-        if (q <= 0) continue;
-        int32_t *J = aJ + off[k];
-        double *V = aV + off[k];
-        for (int a = 1; a < q; ++a) {
-            int key = J[a];
-            double v = V[a];
-            int b = a - 1;
-            while (b >= 0 && J[b] > key) {
-                J[b + 1] = J[b];
-                V[b + 1] = V[b];
-                --b;
-            }
-            J[b + 1] = key;
-            V[b + 1] = v;
-        }
-        const int64_t dst = colptrM[k];
-        for (int a = 0; a < q; ++a) {
-            rowidxM[dst + a] = J[a];
-            valM[dst + a] = V[a];
+__global__ void k_assemble(int64_t n, int qcap, const int64_t *off, const int32_t *nJ, const int64_t *colptrM,
+                           const int32_t *aJ, const double *aV, int32_t *rowidxM, double *valM) {
+    const int64_t total = n * (int64_t)qcap;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t k = idx / qcap;
+        const int t = (int)(idx - k * qcap);
+        if (t < nJ[k]) {
+            const int64_t src = off[k] + t, dst = colptrM[k] + t;
+            rowidxM[dst] = aJ[src];
+            valM[dst] = aV[src];
         }
     }
 }
-void launch_assemble(int64_t n, const int64_t *off, const int32_t *nJ, const int64_t *colptrM, int32_t *arenaJ,
-                     double *arenaV, int32_t *rowidxM, double *valM, hipStream_t s) {
-    hipLaunchKernelGGL(k_assemble, dim3(nblocks(n, 256)), dim3(256), 0, s, n, off, nJ, colptrM, arenaJ, arenaV, rowidxM,
-                       valM);
+void launch_assemble(int64_t n, int qcap, const int64_t *off, const int32_t *nJ, const int64_t *colptrM,
+                     const int32_t *arenaJ, const double *arenaV, int32_t *rowidxM, double *valM, hipStream_t s) {
+    hipLaunchKernelGGL(k_assemble, dim3(nblocks(n * (int64_t)qcap, 1024)), dim3(256), 0, s, n, qcap, off, nJ, colptrM,
+                       arenaJ, arenaV, rowidxM, valM);
 }
 
 // ---------------------------------------------------------------- SpMV

@@ -22,12 +22,12 @@ namespace rsai {
 
 constexpr int RHDR = 11;  // spill record header ints
 
-template <int G_, int RPL_, int QMAX_, int STAGE_>
+template <int G_, int RPL_, int QMAX_, int STAGE_, int HSF_ = 2>
 struct TierCfg {
     static constexpr int G = G_, RPL = RPL_, QMAX = QMAX_, STAGE = STAGE_;
     static constexpr int MMAX = G * RPL;
     static constexpr int GPW = 64 / G;
-    static constexpr int LOGHSI = ilog2ceil(2 * MMAX);
+    static constexpr int LOGHSI = ilog2ceil(HSF_ * MMAX);  // row hash: HSF x MMAX slots
     static constexpr int HSI = 1 << LOGHSI;
     static constexpr int LOGHSJ = ilog2ceil(2 * QMAX);
     static constexpr int HSJ = 1 << LOGHSJ;
@@ -64,8 +64,12 @@ struct TierArgs {
     int64_t rec_out_cap;
     int32_t *err;             // global error flags (bit 0: internal)
     int one_loop;             // 1: park every column after one loop (plain schedule)
+    int sync_refill;          // 1: groups take new columns only when the whole wave is idle
 };
 
+// Per-group LDS. The staging tile doubles as scratch for the phase-local arrays:
+// the new-entry lists and segment tables of the augmentation phases, and the
+// residual accumulator and column order of the dominant-row phase.
 template <class C>
 struct GLds {
     double stage[C::STAGE * C::MMAX];
@@ -73,15 +77,24 @@ struct GLds {
     int Ilist[C::MMAX];
     int Jlist[C::QMAX];
     int hI[C::HSI];
-    int hIv[C::HSI];
     int hJ[C::HSJ];
-    int newk[C::NEWC];
-    int news[C::NEWC];
-    int pref[C::PREF];
     int Rh[CMAX];             // pending dominant rows
-    int64_t segb[C::QMAX];
     int cnt;
     int pad;
+    unsigned char hIv[C::HSI];  // local row of each key in hI
+
+    // augmentation phases (K, C, D)
+    __device__ int *newk() { return reinterpret_cast<int *>(stage); }
+    __device__ int *news() { return newk() + C::NEWC; }
+    __device__ int64_t *segb() { return reinterpret_cast<int64_t *>(stage + C::NEWC); }
+    __device__ int *pref() { return reinterpret_cast<int *>(segb() + C::QMAX); }
+    // dominant-row phase (J)
+    __device__ double *racc() { return stage; }
+    __device__ int *ord() { return reinterpret_cast<int *>(stage + C::MMAX); }
+
+    static_assert(C::NEWC * 8 + C::QMAX * 8 + C::PREF * 4 <= C::STAGE * C::MMAX * 8, "scratch fits the tile");
+    static_assert(C::MMAX * 8 + C::QMAX * 4 <= C::STAGE * C::MMAX * 8, "scratch fits the tile");
+    static_assert(C::MMAX < 256, "local rows fit a byte");
 };
 
 }  // namespace rsai

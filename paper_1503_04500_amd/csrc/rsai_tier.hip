@@ -7,8 +7,13 @@
 
 namespace rsai {
 
-template <class C>
-__global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
+#ifndef RSAI_TIER_WAVES_PER_SIMD
+#define RSAI_TIER_WAVES_PER_SIMD 2
+#endif
+
+// MULTI = false: one matrix, whose pointers stay in scalar registers.
+template <class C, bool MULTI>
+__global__ __launch_bounds__(64, RSAI_TIER_WAVES_PER_SIMD) void tier_kernel(TierArgs args) {
     constexpr int G = C::G, RPL = C::RPL, QMAX = C::QMAX, MMAX = C::MMAX, GPW = C::GPW;
     constexpr int STAGE = C::STAGE;
     constexpr int NRI = (C::RIN + G - 1) / G;   // per-lane candidates per I round
@@ -21,6 +26,7 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
     const int grp = lane / G;
     GLds<C> &S = lds[grp];
     const BuildParams P = args.P;
+    if (*args.err & 7) return;  // the CSC contract failed: process nothing
 
     // ---- static, XCD-aware schedule: each of the 8 XCDs takes a contiguous range
     const bool first_tier = (args.rec_in == nullptr);
@@ -50,6 +56,7 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
     int status = ST_OK;
     double rn = 0.0, fl = 0.0;
     MatDev A{};
+    if constexpr (!MULTI) A = args.mats[0];
     // ---- per-lane block rows
     double b[RPL][QMAX];
     double y[RPL];
@@ -66,7 +73,10 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
     while (true) {
         // ============================================================ A. refill
         bool start = false;
-        if (!busy && !fin) {
+        // with sync_refill, groups of a wave start their columns together, so they
+        // stay at the same loop and the wave's QR is only as wide as its work
+        const bool may_refill = args.sync_refill ? wave_all(!busy) : true;
+        if (!busy && !fin && may_refill) {
             if (u_next < qhi_range) {
                 pos = u_next;
                 u_next += gstride;
@@ -81,20 +91,25 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
         if (start) {
             if (first_tier) {
                 ucol = pos;
-                int lo = 0, hi = args.nmat - 1;  // matrix with col_base[mat] <= ucol
-                while (lo < hi) {
-                    int mid = (lo + hi + 1) / 2;
-                    if (args.col_base[mid] <= ucol) lo = mid; else hi = mid - 1;
+                if constexpr (MULTI) {
+                    int lo = 0, hi = args.nmat - 1;  // matrix with col_base[mat] <= ucol
+                    while (lo < hi) {
+                        int mid = (lo + hi + 1) / 2;
+                        if (args.col_base[mid] <= ucol) lo = mid; else hi = mid - 1;
+                    }
+                    mat = lo;
+                    k = (int)(ucol - args.col_base[mat]);
+                } else {
+                    mat = 0;
+                    k = (int)ucol;
                 }
-                mat = lo;
-                k = (int)(ucol - args.col_base[mat]);
             } else {
                 rec = args.rec_in + pos * (int64_t)args.rec_in_stride;
                 ucol = rec[0];
                 mat = rec[1];
                 k = rec[2];
             }
-            A = args.mats[mat];
+            if constexpr (MULTI) A = args.mats[mat];
             busy = true;
             status = ST_OK;
             fl = 0.0;
@@ -218,7 +233,7 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
                         int sl;
                         if (hinsert<C::LOGHSJ>(S.hJ, cand[s], sl)) {
                             int ps = atomicAdd(&S.cnt, 1);
-                            if (ps < C::NEWC) S.newk[ps] = cand[s];
+                            if (ps < C::NEWC) S.newk()[ps] = cand[s];
                         }
                     }
                 }
@@ -232,9 +247,9 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
                 for (int s = 0; s < NNEW; ++s) {
                     int idx = s * G + gl;
                     if (idx < nnew) {
-                        int key = S.newk[idx];
+                        int key = S.newk()[idx];
                         int rank = 0;
-                        for (int t = 0; t < nnew; ++t) rank += (S.newk[t] < key) ? 1 : 0;
+                        for (int t = 0; t < nnew; ++t) rank += (S.newk()[t] < key) ? 1 : 0;
                         S.Jlist[q + rank] = key;
                     }
                 }
@@ -278,8 +293,8 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
                 for (int t = gl; t < p; t += G) {
                     const int j = S.Jlist[q + t];
                     const int64_t b0 = A.colptr[j];
-                    S.segb[t] = b0;
-                    S.pref[t] = (int)(A.colptr[j + 1] - b0);
+                    S.segb()[t] = b0;
+                    S.pref()[t] = (int)(A.colptr[j + 1] - b0);
                 }
                 if (gl == 0) S.cnt = 0;
             }
@@ -287,7 +302,7 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
             int cpx[QMAX + 1];
             cpx[0] = 0;
 #pragma unroll
-            for (int t = 0; t < QMAX; ++t) cpx[t + 1] = cpx[t] + ((doC && t < p) ? S.pref[t] : 0);
+            for (int t = 0; t < QMAX; ++t) cpx[t + 1] = cpx[t] + ((doC && t < p) ? S.pref()[t] : 0);
             const int total = doC ? cpx[QMAX] : 0;
             bool ovf = false;
             for (int base = 0; wave_any(doC && !ovf && base < total); base += C::RIN) {
@@ -301,7 +316,7 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
 #pragma unroll
                         for (int t = 1; t < QMAX; ++t)
                             if (uu >= cpx[t]) { seg = t; o0 = cpx[t]; }
-                        cand[s] = A.rowidx[S.segb[seg] + (uu - o0)];
+                        cand[s] = A.rowidx[S.segb()[seg] + (uu - o0)];
                     }
                 }
 #pragma unroll
@@ -310,7 +325,7 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
                         int sl;
                         if (hinsert<C::LOGHSI>(S.hI, cand[s], sl)) {
                             int ps = atomicAdd(&S.cnt, 1);
-                            if (ps < C::NEWC) { S.newk[ps] = cand[s]; S.news[ps] = sl; }
+                            if (ps < C::NEWC) { S.newk()[ps] = cand[s]; S.news()[ps] = sl; }
                         }
                     }
                 }
@@ -327,12 +342,12 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
                 for (int s = 0; s < NNEW; ++s) {
                     int idx = s * G + gl;
                     if (idx < nnew) {
-                        int key = S.newk[idx];
+                        int key = S.newk()[idx];
                         int rank = 0;
-                        for (int t = 0; t < nnew; ++t) rank += (S.newk[t] < key) ? 1 : 0;
+                        for (int t = 0; t < nnew; ++t) rank += (S.newk()[t] < key) ? 1 : 0;
                         int li = m + rank;
                         S.Ilist[li] = key;
-                        S.hIv[S.news[idx]] = li;
+                        S.hIv[S.news()[idx]] = li;
                         if (key == k) kpos = li;
                     }
                 }
@@ -487,7 +502,7 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
                 }
                 wave_sync();
             }
-            if (lookup_fail) atomicOr(args.err, 1);
+            if (lookup_fail) atomicOr(args.err, 16);
 
             // ---- Householder QR update: stored reflectors j < qlo act on the new
             // columns only; reflectors qlo..qn-1 are formed and applied.
@@ -603,7 +618,9 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
                 bool dact = act && dropok && P.drop != DROP_NONE && status == ST_OK;
                 unsigned keep = 0u;
                 if (dact) {
-                    const double t = (P.drop == DROP_FIXED) ? P.tol : P.eps / ((double)q * A.norm1);
+                    const double t = (P.drop == DROP_FIXED)
+                                         ? P.tol
+                                         : P.eps / ((double)q * __longlong_as_double((long long)*A.norm1_bits));
 #pragma unroll
                     for (int c = 0; c < QMAX; ++c)
                         if (c < q && fabs(S.mt[c]) > t) keep |= 1u << c;
@@ -669,9 +686,9 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
             // r = A(I,J) m - e_k(I), eq. (2.4), formed from the sparse columns of A with
             // the columns taken in ascending global order. Rows whose coefficients tie
             // give bitwise-equal residuals, so exact ties reach the index tie-break.
-            double *racc = S.stage;            // [MMAX] accumulator
+            double *racc = S.racc();           // [MMAX] accumulator
             const double *mts = S.mt;          // [QMAX] solution values by slot
-            int *ord = S.newk;                 // [QMAX] slots in ascending column order
+            int *ord = S.ord();                // [QMAX] slots in ascending column order
             if (sel) {
 #pragma unroll
                 for (int s = 0; s < (QMAX + G - 1) / G; ++s) {
@@ -739,7 +756,7 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
                 // the wave's in-order LDS execution
             }
             wave_sync();
-            if (lookup_fail2) atomicOr(args.err, 1);
+            if (lookup_fail2) atomicOr(args.err, 16);
             double ra[RPL];
             int gi[RPL];
 #pragma unroll
@@ -794,11 +811,16 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
         if (finish) {
             const int64_t slot = args.arena_base + ucol * (int64_t)QMAX;
             const int qq = (status == ST_OK) ? q : 0;
+            // m_k with its rows in ascending order (rank of each entry in the group)
 #pragma unroll
-            for (int c = 0; c < QMAX; ++c) {
-                if (c < qq && (c % G) == gl) {
-                    args.out.arenaJ[slot + c] = S.Jlist[c];
-                    args.out.arenaV[slot + c] = S.mt[c];
+            for (int s = 0; s < (QMAX + G - 1) / G; ++s) {
+                const int c = s * G + gl;
+                if (c < qq) {
+                    const int jc = S.Jlist[c];
+                    int rank = 0;
+                    for (int t = 0; t < qq; ++t) rank += (S.Jlist[t] < jc) ? 1 : 0;
+                    args.out.arenaJ[slot + rank] = jc;
+                    args.out.arenaV[slot + rank] = S.mt[c];
                 }
             }
             if (gl == 0) {
@@ -820,13 +842,20 @@ __global__ __launch_bounds__(64) void tier_kernel(TierArgs args) {
 // t0: up to 24 x 12 blocks (2D 5-point stencils), 8 columns per wave
 // t1: up to 64 x 24 blocks (3D 7-point stencils), 4 columns per wave
 // t2: up to 128 x 32 blocks, 4 columns per wave
-using Tier0 = TierCfg<8, 3, 12, 4>;
+#ifndef RSAI_T0_STAGE
+#define RSAI_T0_STAGE 4
+#endif
+#ifndef RSAI_T0_HSF
+#define RSAI_T0_HSF 2
+#endif
+using Tier0 = TierCfg<8, 3, 12, RSAI_T0_STAGE, RSAI_T0_HSF>;
 using Tier1 = TierCfg<16, 4, 24, 4>;
 using Tier2 = TierCfg<16, 8, 32, 4>;
 
 template <class C>
 static void launch_tier(const TierArgs &a, int waves, hipStream_t s) {
-    hipLaunchKernelGGL(tier_kernel<C>, dim3(waves), dim3(64), 0, s, a);
+    if (a.nmat > 1) hipLaunchKernelGGL((tier_kernel<C, true>), dim3(waves), dim3(64), 0, s, a);
+    else hipLaunchKernelGGL((tier_kernel<C, false>), dim3(waves), dim3(64), 0, s, a);
 }
 
 const TierInfo kTiers[] = {

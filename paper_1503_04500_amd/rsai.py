@@ -13,7 +13,7 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librsai.so")
+LIB_PATH = os.environ.get("RSAI_LIB") or os.path.join(_HERE, "librsai.so")
 
 RSAI_OK = 0
 _STATUS = {-1: "RSAI_E_ARG", -2: "RSAI_E_CSC", -3: "RSAI_E_SINGULAR", -4: "RSAI_E_NOMEM", -5: "RSAI_E_HIP",
@@ -32,6 +32,7 @@ class Params(ctypes.Structure):
     _fields_ = [("c", ctypes.c_int32), ("lmax", ctypes.c_int32), ("eps", ctypes.c_double),
                 ("drop", ctypes.c_int32), ("tol", ctypes.c_double), ("sched", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("tier0", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("refill", ctypes.c_int32),
                 ("keep_factors", ctypes.c_int32), ("factor_budget_bytes", ctypes.c_int64)]
 
 
@@ -152,15 +153,16 @@ class Matrix:
 
 
 def params(c=3, lmax=10, eps=0.4, drop="fixed", tol=1e-3, sched="batched", validate=True, tier0=-1,
-           timing=False):
+           timing=False, refill=-1):
     p = Params()
     _check(load().rsai_params_default(ctypes.byref(p)))
     p.c, p.lmax, p.eps, p.tol = int(c), int(lmax), float(eps), float(tol)
     p.drop = DROP[drop] if isinstance(drop, str) else int(drop)
     p.sched = SCHED[sched] if isinstance(sched, str) else int(sched)
-    p.validate = 1 if validate else 0
+    p.validate = int(validate) if not isinstance(validate, bool) else (1 if validate else 0)
     p.tier0 = int(tier0)
     p.timing = 1 if timing else 0
+    p.refill = int(refill)
     return p
 
 

@@ -139,3 +139,41 @@ def test_plain_equals_batched_c2():
     assert np.array_equal(a["colptr"], b["colptr"]) and np.array_equal(a["rowidx"], b["rowidx"])
     assert np.allclose(a["val"], b["val"], rtol=1e-12, atol=1e-15)
     assert np.array_equal(a["flops"], b["flops"])
+
+
+# ---------------------------------------------------------------- CSC contract
+
+def _malformed(kind):
+    A = gen.cd2d(6, seed=1)
+    cp, ri, va = A.colptr.copy(), A.rowidx.copy(), A.val.copy()
+    if kind == "unsorted":
+        s = cp[10]
+        ri[s], ri[s + 1] = ri[s + 1], ri[s]
+    elif kind == "range":
+        ri[cp[7]] = A.n + 3
+    elif kind == "empty":
+        # move column 4's entries into column 5 (still n + 1 pointers, nnz >= n)
+        cp[5] = cp[4]
+    elif kind == "colptr":
+        cp[12], cp[13] = cp[13], cp[12]
+    return A.n, cp, ri, va
+
+
+@pytest.mark.parametrize("validate", [1, 2])
+@pytest.mark.parametrize("kind", ["unsorted", "range", "empty", "colptr"])
+def test_malformed_csc_reported(validate, kind):
+    import torch
+    import paper_1503_04500_amd.rsai as rsai
+    n, cp, ri, va = _malformed(kind)
+    M = rsai.Matrix(torch.from_numpy(cp).cuda(), torch.from_numpy(ri).cuda(), torch.from_numpy(va).cuda())
+    with pytest.raises(rsai.RSAIError) as ei:
+        plan = rsai.build(M, validate=validate, **C1)
+        plan.nnz()
+    assert ei.value.code == -2
+
+
+def test_async_validation_matches_sync_on_valid_input():
+    A = gen.c1()
+    a = run_gpu(A, validate=2, **C1)
+    b = run_gpu(A, validate=1, **C1)
+    assert np.array_equal(a["rowidx"], b["rowidx"]) and np.array_equal(a["val"], b["val"])
