@@ -66,7 +66,9 @@ typedef enum {
 } rsai_drop_mode;
 
 typedef enum {
-    RSAI_SCHED_BATCHED = 0, /* size-bucketed persistent kernels, whole loop fused */
+    RSAI_SCHED_BATCHED = 0, /* size-bucketed persistent kernels, whole loop fused; columns
+                               that outgrow the register tiers finish in a large class (one
+                               256-thread workgroup per column, |I_k| <= 8192, |J_k| <= 64) */
     RSAI_SCHED_PLAIN = 1    /* one wave per column, one launch per loop, state in HBM */
 } rsai_sched;
 
@@ -140,7 +142,9 @@ rsai_status rsai_apply(const rsai_plan *P, int32_t mat, const double *x, double 
 /* Adjoint of the fixed-pattern LS map A -> M (pattern of M fixed, values from (2.3)):
    dA_val += d/dA [ <dM_val, M> + w_frob * sum_k ||A m_k - e_k||^2 ] restricted to
    the structural nonzeros of A. dM_val (nnzM entries, CSC order of rsai_export_M)
-   may be NULL. dA_val has nnz(A) entries and is accumulated into. */
+   may be NULL. dA_val has nnz(A) entries and is accumulated into. Columns with
+   |J_k| > 32 or |I_k| > 64 are not supported: RSAI_E_CAP (checked before any
+   accumulation, one host synchronisation on the first call of a plan). */
 rsai_status rsai_backward(rsai_plan *P, int32_t mat, const double *dM_val, double w_frob, double *dA_val,
                           void *stream);
 
@@ -156,8 +160,9 @@ rsai_status rsai_spmv_vjp(const rsai_csc *A, const double *dy, const double *x, 
    [3] assembly, [4] whole build, [5] backward. Synchronises. */
 rsai_status rsai_plan_timing(const rsai_plan *P, double *ms, int32_t n);
 
-/* Describe size tier t (host outputs): lanes per column, max |I|, max |J|.
-   Returns RSAI_E_ARG past the last tier. */
+/* Describe size tier t (host outputs): lanes per column, max |I|, max |J|. The
+   register tiers come first; the index after them describes the large class of the
+   batched schedule. Returns RSAI_E_ARG past that. */
 rsai_status rsai_tier_info(int32_t t, int32_t *lanes, int32_t *max_rows, int32_t *max_cols);
 
 /* Destroy a plan (NULL is allowed). Synchronises the build stream. */

@@ -1,0 +1,539 @@
+// Large size class of the RSAI(tol) build: one 256-thread workgroup per column,
+// for the columns that outgrow the register tiers (tall LS blocks A(I_k, J_k) of up
+// to BMMAX rows and BQMAX columns, e.g. the power-law matrices whose long columns
+// bring hundreds to thousands of rows into I_k).
+//
+// Same steps as the register tiers (Algorithm 1 with the dropping of Section 4):
+//   * index sets are LDS hash sets; new rows are numbered in ascending global order
+//     (bitonic sort in LDS), so results do not depend on thread timing;
+//   * the dense block lives in a per-workgroup slab of global memory (column-major,
+//     leading dimension BMMAX); every solve refactors it by Householder QR with
+//     block-wide reductions (the work counted for the method is still the update
+//     model of the solve, as in the register tiers);
+//   * the residual for step 4 is A(I,J) m - e_k(I) accumulated from the sparse
+//     columns in ascending column order (eq. (2.4)), so exact ties reach the
+//     smaller-index rule.
+// Columns arrive only as spill records of the previous tier; a column that outgrows
+// this class ends with status RSAI_E_CAP.
+#include <climits>
+
+#include "rsai_kernels.h"
+
+namespace rsai {
+
+namespace {
+constexpr int NT = 256;                    // threads per workgroup
+constexpr int NW = NT / 64;                // waves
+constexpr int BLOGH = 14;                  // row hash: 16384 slots
+constexpr int BH = 1 << BLOGH;
+constexpr int BLOGHJ = 8;                  // column hash: 256 slots
+constexpr int BHJ = 1 << BLOGHJ;
+constexpr int SORTN = 8192;                // bitonic buffer for new rows
+
+struct BigLds {
+    int hI[BH];
+    unsigned short hIv[BH];
+    int hJ[BHJ];
+    int skey[SORTN];
+    int Jlist[BQMAX_BIG];
+    double mt[BQMAX_BIG];
+    double rd[BQMAX_BIG];
+    double bt[BQMAX_BIG];
+    double red[NW * 8];
+    int ired[NW * 2];
+    double dred[NW];
+    int Rh[CMAX];
+    int cnt, misc;
+};
+}  // namespace
+
+int big_max_rows() { return BMMAX_BIG; }
+int big_max_cols() { return BQMAX_BIG; }
+
+// block-wide sum (every thread gets the result)
+__device__ __forceinline__ double bsum(double x, BigLds &S) {
+    x = gsum<16>(x);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    x += __shfl_xor(x, 16);
+    x += __shfl_xor(x, 32);
+    __syncthreads();
+    if (lane == 0) S.dred[w] = x;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) t += S.dred[i];
+    __syncthreads();
+    return t;
+}
+__device__ __forceinline__ int bsum_i(int x, BigLds &S) {
+    x = gsum_i<16>(x);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    x += __shfl_xor(x, 16);
+    x += __shfl_xor(x, 32);
+    __syncthreads();
+    if (lane == 0) S.ired[w] = x;
+    __syncthreads();
+    int t = 0;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) t += S.ired[i];
+    __syncthreads();
+    return t;
+}
+// block arg-max of (a desc, g asc); every thread gets the winner
+__device__ __forceinline__ void bargmax(double &a, int &g, BigLds &S) {
+    gargmax<16>(a, g);
+#pragma unroll
+    for (int off = 16; off <= 32; off <<= 1) {
+        double a2 = __shfl_xor(a, off);
+        int g2 = __shfl_xor(g, off);
+        if (a2 > a || (a2 == a && g2 < g)) { a = a2; g = g2; }
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) { S.red[w] = a; S.ired[w] = g; }
+    __syncthreads();
+    a = S.red[0];
+    g = S.ired[0];
+#pragma unroll
+    for (int i = 1; i < NW; ++i)
+        if (S.red[i] > a || (S.red[i] == a && S.ired[i] < g)) { a = S.red[i]; g = S.ired[i]; }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
+    __shared__ BigLds S;
+    const int tid = threadIdx.x;
+    if (*args.err & 7) return;
+    const BuildParams P = args.P;
+    const int64_t Q = min((int64_t)(*args.rec_in_count), args.rec_in_cap);
+    double *B = args.scratch + (int64_t)blockIdx.x * args.scratch_stride;  // [BQMAX][BMMAX]
+    double *y = B + (int64_t)BQMAX_BIG * BMMAX_BIG;                         // Q^T e
+    double *racc = y + BMMAX_BIG;                                          // residual
+    int *Il = reinterpret_cast<int *>(racc + BMMAX_BIG);                   // rows of I
+    unsigned char *rfl = reinterpret_cast<unsigned char *>(Il + BMMAX_BIG);  // row in R
+
+    for (int64_t pos = blockIdx.x; pos < Q; pos += gridDim.x) {
+        const int32_t *rec = args.rec_in + pos * (int64_t)args.rec_in_stride;
+        const int ucol = rec[0], mat = rec[1], k = rec[2];
+        int l = rec[3], q = rec[4], m = rec[5];
+        const int nR = rec[6];
+        int nRh = rec[7];
+        double fl = __longlong_as_double(((long long)rec[9] << 32) | (long long)(unsigned)rec[8]);
+        const bool linc0 = (rec[10] & 1) != 0;
+        const MatDev A = args.mats[mat];
+        const int32_t *RJ = rec + RHDR, *RI = RJ + q, *RR = RI + m, *RHp = RR + nR;
+        int status = ST_OK;
+        double rn = 0.0;
+        bool kR = false;
+        int kidx = -1;
+
+        // ---- state from the record
+        for (int t = tid; t < BH; t += NT) S.hI[t] = HEMPTY;
+        for (int t = tid; t < BHJ; t += NT) S.hJ[t] = HEMPTY;
+        __syncthreads();
+        if (q > BQMAX_BIG || m > BMMAX_BIG) status = ST_CAP;
+        if (status == ST_OK) {
+            for (int t = tid; t < q; t += NT) {
+                S.Jlist[t] = RJ[t];
+                int sl;
+                hinsert<BLOGHJ>(S.hJ, RJ[t], sl);
+            }
+            for (int t = tid; t < m; t += NT) {
+                Il[t] = RI[t];
+                rfl[t] = 0;
+                int sl;
+                hinsert<BLOGH>(S.hI, RI[t], sl);
+                if (sl >= 0) S.hIv[sl] = (unsigned short)t;
+            }
+            if (tid < nRh) S.Rh[tid] = RHp[tid];
+        }
+        __syncthreads();
+        if (status == ST_OK) {
+            for (int t = tid; t < nR; t += NT) {
+                const int row = RR[t];
+                const int sl = hfind<BLOGH>(S.hI, row);
+                if (sl >= 0) rfl[S.hIv[sl]] = 1;
+            }
+            if (tid == 0) {
+                const int sl = hfind<BLOGH>(S.hI, k);
+                S.misc = sl >= 0 ? S.hIv[sl] : -1;
+                int kr = 0;
+                for (int t = 0; t < nR; ++t) kr |= (RR[t] == k);
+                S.cnt = kr;
+            }
+        }
+        __syncthreads();
+        kidx = S.misc;
+        kR = (kidx < 0) && S.cnt;
+        __syncthreads();
+
+        bool linc = linc0;       // advance l when J-hat is formed
+        bool first = true;       // the stored pattern has no factor here yet
+        bool need_solve = true;
+        bool dropok = false;
+        int qmod = -1;
+        int p_fresh = 0;
+        if (status == ST_OK && q == 0 && nRh == 0) {
+            // a column whose own rows exceed the register tiers: J = {k}, loop 0
+            if (tid == 0) {
+                S.Jlist[0] = k;
+                int sl;
+                hinsert<BLOGHJ>(S.hJ, k, sl);
+            }
+            __syncthreads();
+            p_fresh = 1;
+            linc = true;
+            dropok = true;
+            qmod = 0;
+        }
+        while (status == ST_OK) {
+            // ================= J-hat from the pending dominant rows (step 5)
+            int p = p_fresh;
+            p_fresh = 0;
+            if (nRh > 0) {
+                if (tid == 0) S.cnt = 0;
+                __syncthreads();
+                bool ovf = false;
+                for (int t = 0; t < nRh; ++t) {
+                    const int row = S.Rh[t];
+                    for (int64_t e = A.rowptr[row] + tid; e < A.rowptr[row + 1]; e += NT) {
+                        const int col = A.colidx[e];
+                        int sl;
+                        if (hinsert<BLOGHJ>(S.hJ, col, sl)) {
+                            const int ps = atomicAdd(&S.cnt, 1);
+                            if (q + ps < BQMAX_BIG) S.skey[ps] = col; else ovf = true;
+                        } else if (sl < 0) {
+                            ovf = true;  // table full
+                        }
+                    }
+                    if (__syncthreads_or(ovf)) { ovf = true; break; }
+                }
+                if (ovf) { status = ST_CAP; break; }
+                p = S.cnt;
+                // ascending order of the new columns (p < BQMAX_BIG: rank sort)
+                if (tid < p) {
+                    const int key = S.skey[tid];
+                    int rank = 0;
+                    for (int t = 0; t < p; ++t) rank += (S.skey[t] < key) ? 1 : 0;
+                    S.Jlist[q + rank] = key;
+                }
+                __syncthreads();
+                if (linc) ++l;
+                nRh = 0;
+                if (p == 0 && !first) need_solve = false;   // empty J-hat: no solve (step 6)
+                else need_solve = true;
+                dropok = (p > 0);
+                qmod = (p > 0) ? q : (first ? -1 : q);
+            }
+            // ================= I-hat: rows of the new columns (step 5)
+            if (need_solve && p > 0) {
+                if (tid == 0) S.cnt = 0;
+                __syncthreads();
+                bool ovf = false;
+                for (int t = 0; t < p; ++t) {
+                    const int j = S.Jlist[q + t];
+                    for (int64_t e = A.colptr[j] + tid; e < A.colptr[j + 1]; e += NT) {
+                        const int row = A.rowidx[e];
+                        int sl;
+                        if (hinsert<BLOGH>(S.hI, row, sl)) {
+                            const int ps = atomicAdd(&S.cnt, 1);
+                            if (m + ps < BMMAX_BIG && ps < SORTN) S.skey[ps] = row; else ovf = true;
+                        } else if (sl < 0) {
+                            ovf = true;  // table full
+                        }
+                    }
+                    if (__syncthreads_or(ovf)) { ovf = true; break; }
+                }
+                if (ovf) { status = ST_CAP; break; }
+                const int nn = S.cnt;
+                // bitonic sort of the new rows (ascending), padded with INT_MAX
+                int np2 = 1;
+                while (np2 < nn) np2 <<= 1;
+                for (int t = nn + tid; t < np2; t += NT) S.skey[t] = INT_MAX;
+                if (tid == 0) S.misc = -1;
+                __syncthreads();
+                for (int kk = 2; kk <= np2; kk <<= 1) {
+                    for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+                        for (int i = tid; i < np2; i += NT) {
+                            const int ixj = i ^ jj;
+                            if (ixj > i) {
+                                const int a = S.skey[i], b = S.skey[ixj];
+                                const bool up = (i & kk) == 0;
+                                if ((a > b) == up) { S.skey[i] = b; S.skey[ixj] = a; }
+                            }
+                        }
+                        __syncthreads();
+                    }
+                }
+                for (int t = tid; t < nn; t += NT) {
+                    const int row = S.skey[t];
+                    const int li = m + t;
+                    Il[li] = row;
+                    rfl[li] = 0;
+                    const int sl = hfind<BLOGH>(S.hI, row);
+                    if (sl >= 0) S.hIv[sl] = (unsigned short)li;
+                    if (row == k) {
+                        S.misc = li;
+                    }
+                }
+                __syncthreads();
+                if (S.misc >= 0) {
+                    kidx = S.misc;
+                    if (kR) {
+                        if (tid == 0) rfl[kidx] = 1;
+                        kR = false;
+                    }
+                }
+                m += nn;
+                q += p;
+                __syncthreads();
+            } else if (p > 0) {
+                q += p;
+            }
+            first = false;
+
+            // ================= LS solve(s) on (I, J): gather, QR, back substitution
+            int pass_drop = 0;
+            while (need_solve && status == ST_OK) {
+                const int qn = q;
+                // gather: zero the block, scatter the columns' entries, Q^T e = e_k
+                for (int c = 0; c < qn; ++c)
+                    for (int i = tid; i < m; i += NT) B[(int64_t)c * BMMAX_BIG + i] = 0.0;
+                for (int i = tid; i < m; i += NT) y[i] = (i == kidx) ? 1.0 : 0.0;
+                __syncthreads();
+                for (int c = 0; c < qn; ++c) {
+                    const int j = S.Jlist[c];
+                    for (int64_t e = A.colptr[j] + tid; e < A.colptr[j + 1]; e += NT) {
+                        const int sl = hfind<BLOGH>(S.hI, A.rowidx[e]);
+                        if (sl >= 0) B[(int64_t)c * BMMAX_BIG + S.hIv[sl]] = A.val[e];
+                    }
+                }
+                __syncthreads();
+                bool singular = false;
+                for (int j = 0; j < qn; ++j) {
+                    double *bj = B + (int64_t)j * BMMAX_BIG;
+                    double s2 = 0.0;
+                    for (int i = j + tid; i < m; i += NT) s2 += bj[i] * bj[i];
+                    s2 = bsum(s2, S);
+                    const double x0 = bj[j];
+                    const double nx = sqrt(s2);
+                    const double alpha = (x0 >= 0.0) ? -nx : nx;
+                    const double vj = x0 - alpha;
+                    const double be = (nx > 0.0) ? 1.0 / (nx * (nx + fabs(x0))) : 0.0;
+                    if (!(nx > 0.0)) singular = true;
+                    __syncthreads();
+                    if (tid == 0) {
+                        bj[j] = vj;
+                        S.rd[j] = alpha;
+                        S.bt[j] = be;
+                    }
+                    __syncthreads();
+                    // trailing columns and Q^T e, eight at a time
+                    for (int c0 = j + 1; c0 <= qn; c0 += 8) {
+                        double part[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) part[u] = 0.0;
+                        for (int i = j + tid; i < m; i += NT) {
+                            const double vi = bj[i];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                const int c = c0 + u;
+                                if (c < qn) part[u] += vi * B[(int64_t)c * BMMAX_BIG + i];
+                                else if (c == qn) part[u] += vi * y[i];
+                            }
+                        }
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) part[u] = gsum<16>(part[u]);
+                        const int lane = tid & 63, w = tid >> 6;
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            part[u] += __shfl_xor(part[u], 16);
+                            part[u] += __shfl_xor(part[u], 32);
+                        }
+                        if (lane == 0)
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) S.red[w * 8 + u] = part[u];
+                        __syncthreads();
+                        double wv[8];
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            double t = 0.0;
+#pragma unroll
+                            for (int ww = 0; ww < NW; ++ww) t += S.red[ww * 8 + u];
+                            wv[u] = t * be;
+                        }
+                        __syncthreads();
+                        for (int i = j + tid; i < m; i += NT) {
+                            const double vi = bj[i];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                const int c = c0 + u;
+                                if (c < qn) B[(int64_t)c * BMMAX_BIG + i] -= wv[u] * vi;
+                                else if (c == qn) y[i] -= wv[u] * vi;
+                            }
+                        }
+                        __syncthreads();
+                    }
+                }
+                if (singular) { status = ST_SINGULAR; break; }
+                // back substitution by wave 0: lane c holds m_c
+                if (tid < 64) {
+                    double mc_lane = 0.0;
+                    for (int j = qn - 1; j >= 0; --j) {
+                        double part = 0.0;
+                        for (int c = j + 1 + tid; c < qn; c += 64)
+                            part += B[(int64_t)c * BMMAX_BIG + j] * S.mt[c];
+                        part = gsum<16>(part);
+                        part += __shfl_xor(part, 16);
+                        part += __shfl_xor(part, 32);
+                        const double mj = (y[j] - part) / S.rd[j];
+                        if (tid == 0) S.mt[j] = mj;
+                        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                        (void)mc_lane;
+                    }
+                }
+                __syncthreads();
+                double s = 0.0;
+                for (int i = qn + tid; i < m; i += NT) s += y[i] * y[i];
+                s = bsum(s, S);
+                rn = sqrt(s + (kidx < 0 ? 1.0 : 0.0));
+                if (qmod >= 0) fl += solve_flops(m, qmod, qn);
+                // ---- dropping (Section 4), after the augment solve only
+                if (pass_drop == 0 && dropok && P.drop != DROP_NONE) {
+                    const double t = (P.drop == DROP_FIXED)
+                                         ? P.tol
+                                         : P.eps / ((double)qn * __longlong_as_double((long long)*A.norm1_bits));
+                    int nk = 0;
+                    for (int c = 0; c < qn; ++c) nk += (fabs(S.mt[c]) > t) ? 1 : 0;
+                    if (nk < qn) {
+                        __syncthreads();
+                        if (tid == 0) {
+                            if (nk == 0) {
+                                int bc = 0;
+                                for (int c = 1; c < qn; ++c) {
+                                    const double a = fabs(S.mt[c]), b = fabs(S.mt[bc]);
+                                    if (a > b || (a == b && S.Jlist[c] < S.Jlist[bc])) bc = c;
+                                }
+                                S.Jlist[0] = S.Jlist[bc];
+                                nk = 1;
+                            } else {
+                                int w = 0;
+                                for (int c = 0; c < qn; ++c)
+                                    if (fabs(S.mt[c]) > t) S.Jlist[w++] = S.Jlist[c];
+                            }
+                            S.cnt = nk;
+                        }
+                        for (int t2 = tid; t2 < BHJ; t2 += NT) S.hJ[t2] = HEMPTY;
+                        __syncthreads();
+                        nk = S.cnt;
+                        for (int c = tid; c < nk; c += NT) {
+                            int sl;
+                            hinsert<BLOGHJ>(S.hJ, S.Jlist[c], sl);
+                        }
+                        __syncthreads();
+                        q = nk;
+                        qmod = 0;
+                        pass_drop = 1;
+                        continue;  // solve on the kept pattern
+                    }
+                }
+                break;
+            }
+            if (status != ST_OK) break;
+            need_solve = false;
+
+            // ================= stop test (step 3)
+            if (rn <= P.eps || l >= P.lmax) break;
+
+            // ================= dominant rows of r (step 4), r from the sparse columns
+            if (tid == 0) {
+                // ascending column order, kept in skey
+                for (int c = 0; c < q; ++c) {
+                    int rank = 0;
+                    for (int t = 0; t < q; ++t) rank += (S.Jlist[t] < S.Jlist[c]) ? 1 : 0;
+                    S.skey[rank] = c;
+                }
+            }
+            for (int i = tid; i < m; i += NT) racc[i] = 0.0;
+            __syncthreads();
+            for (int t = 0; t < q; ++t) {
+                const int c = S.skey[t];
+                const int j = S.Jlist[c];
+                const double mc = S.mt[c];
+                for (int64_t e = A.colptr[j] + tid; e < A.colptr[j + 1]; e += NT) {
+                    const int sl = hfind<BLOGH>(S.hI, A.rowidx[e]);
+                    if (sl >= 0) {
+                        const int li = S.hIv[sl];
+                        racc[li] = __fma_rn(A.val[e], mc, racc[li]);
+                    }
+                }
+                __syncthreads();
+            }
+            bool kcand = (kidx < 0) && !kR;
+            int nsel = 0;
+            for (int t = 0; t < P.c; ++t) {
+                double a = -1.0;
+                int g = INT_MAX;
+                for (int i = tid; i < m; i += NT) {
+                    if (rfl[i]) continue;
+                    const double ri = racc[i] - ((i == kidx) ? 1.0 : 0.0);
+                    if (ri == 0.0) continue;
+                    const double ar = fabs(ri);
+                    const int gi = Il[i];
+                    if (ar > a || (ar == a && gi < g)) { a = ar; g = gi; }
+                }
+                bargmax(a, g, S);
+                if (kcand && (1.0 > a || (1.0 == a && k < g))) { a = 1.0; g = k; }
+                if (a < 0.0) break;
+                if (tid == 0) S.Rh[t] = g;
+                nsel = t + 1;
+                if (kcand && g == k) {
+                    kcand = false;
+                    kR = true;
+                } else {
+                    const int sl = hfind<BLOGH>(S.hI, g);
+                    if (tid == 0 && sl >= 0) rfl[S.hIv[sl]] = 1;
+                }
+                __syncthreads();
+            }
+            if (nsel == 0) break;  // no candidate row left: r = 0 (Section 3)
+            nRh = nsel;
+            linc = true;
+            __syncthreads();
+        }
+
+        // ================= output (rows of m_k ascending)
+        const int qq = (status == ST_OK) ? q : 0;
+        const int64_t slot = args.arena_base + (int64_t)ucol * BQMAX_BIG;
+        for (int c = tid; c < qq; c += NT) {
+            const int jc = S.Jlist[c];
+            int rank = 0;
+            for (int t = 0; t < qq; ++t) rank += (S.Jlist[t] < jc) ? 1 : 0;
+            args.out.arenaJ[slot + rank] = jc;
+            args.out.arenaV[slot + rank] = S.mt[c];
+        }
+        if (tid == 0) {
+            args.out.off[ucol] = slot;
+            args.out.nJ[ucol] = qq;
+            args.out.nI[ucol] = m;
+            args.out.loops[ucol] = l;
+            args.out.status[ucol] = status;
+            args.out.resnorm[ucol] = rn;
+            args.out.flops[ucol] = fl;
+        }
+        __syncthreads();
+    }
+}
+
+int64_t big_scratch_stride() {
+    // doubles per workgroup: block, Q^T e, residual, then rows (int) and flags (byte)
+    return (int64_t)BQMAX_BIG * BMMAX_BIG + 2 * (int64_t)BMMAX_BIG + (BMMAX_BIG * 5 + 7) / 8 + 8;
+}
+
+void launch_big_kernel(const BigArgs &a, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(big_kernel, dim3(blocks), dim3(NT), 0, s, a);
+}
+
+}  // namespace rsai

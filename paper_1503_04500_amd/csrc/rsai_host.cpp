@@ -86,6 +86,7 @@ struct rsai_plan {
     ColOut out{};
     int64_t arena_cap = 0;
     int32_t *rec[8] = {};
+    double *big_scratch = nullptr;   // per-workgroup slabs of the large size class
     int32_t *rec_count = nullptr;
     int32_t *err = nullptr;
     unsigned long long *stats = nullptr;
@@ -178,7 +179,13 @@ rsai_status rsai_set_allocator(rsai_alloc_fn alloc, rsai_free_fn dealloc, void *
 const char *rsai_last_error(void) { return g_err.c_str(); }
 
 rsai_status rsai_tier_info(int32_t t, int32_t *lanes, int32_t *max_rows, int32_t *max_cols) {
-    if (t < 0 || t >= kNumTiers) return fail(RSAI_E_ARG, "no tier %d", t);
+    if (t < 0 || t > kNumTiers) return fail(RSAI_E_ARG, "no tier %d", t);
+    if (t == kNumTiers) {  // the large size class: one 256-lane workgroup per column
+        if (lanes) *lanes = 256;
+        if (max_rows) *max_rows = big_max_rows();
+        if (max_cols) *max_cols = big_max_cols();
+        return RSAI_OK;
+    }
     if (lanes) *lanes = kTiers[t].G;
     if (max_rows) *max_rows = kTiers[t].MMAX;
     if (max_cols) *max_cols = kTiers[t].QMAX;
@@ -259,9 +266,14 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
         slot_base[t] = acap;
         acap += ncols * (int64_t)kTiers[t].QMAX;
     }
+    // the batched schedule ends with the large size class (one workgroup per column)
+    const bool big = !plain;
+    int64_t big_base = acap;
+    if (big) acap += ncols * (int64_t)BQMAX_BIG;
     P->arena_cap = acap;
-    const int nlaunch = plain ? P->p.lmax + 1 : (tlast - t0 + 1);
-    const int64_t qlast = kTiers[tlast].QMAX;
+    const int nlaunch = plain ? P->p.lmax + 1 : (tlast - t0 + 1 + (big ? 1 : 0));
+    const int64_t qlast = big ? std::max<int64_t>(kTiers[tlast].QMAX, BQMAX_BIG) : kTiers[tlast].QMAX;
+    const int big_blocks = device_cus();
 
     // ---- every device buffer of the build, from one allocation
     std::vector<int32_t *> fillpos(count);
@@ -299,8 +311,10 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
             P->rec[0] = L.take<int32_t>(ncols * (int64_t)kTiers[kPlainTier].REC);
             P->rec[1] = L.take<int32_t>(ncols * (int64_t)kTiers[kPlainTier].REC);
         } else {
-            for (int t = t0; t < tlast; ++t) P->rec[t] = L.take<int32_t>(ncols * (int64_t)kTiers[t].REC);
+            for (int t = t0; t < tlast + (big ? 1 : 0); ++t)
+                P->rec[t] = L.take<int32_t>(ncols * (int64_t)kTiers[t].REC);
         }
+        P->big_scratch = big ? L.take<double>((int64_t)big_blocks * big_scratch_stride()) : nullptr;
     };
     Layout L0;
     layout(L0);
@@ -414,7 +428,7 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
                 a.rec_in_count = P->rec_count + (t - t0 - 1);
                 a.rec_in_cap = ncols;
             }
-            if (t < tlast) {
+            if (t < tlast || big) {
                 a.rec_out = P->rec[t];
                 a.rec_out_stride = kTiers[t].REC;
                 a.rec_out_count = P->rec_count + (t - t0);
@@ -429,8 +443,24 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
             launch_tier_kernel(t, a, waves, s);
             if (t == t0) P->record(2, s);
         }
+        if (big) {
+            // columns that outgrew the last register tier: one workgroup per column
+            BigArgs b{};
+            b.mats = P->d_mats;
+            b.P = base.P;
+            b.out = P->out;
+            b.arena_base = big_base;
+            b.rec_in = P->rec[tlast];
+            b.rec_in_stride = kTiers[tlast].REC;
+            b.rec_in_count = P->rec_count + (tlast - t0);
+            b.rec_in_cap = ncols;
+            b.scratch = P->big_scratch;
+            b.scratch_stride = big_scratch_stride();
+            b.err = P->err;
+            launch_big_kernel(b, big_blocks, s);
+        }
     }
-    P->ntiers_used = tlast - t0 + 1;
+    P->ntiers_used = tlast - t0 + 1 + (big ? 1 : 0);
     P->record(3, s);
 
     // ---- assembly of M per matrix: colptr = scan(nJ), then compaction

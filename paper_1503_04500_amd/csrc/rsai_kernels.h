@@ -17,6 +17,27 @@ extern const int kPlainTier;  // the one size class of the plain schedule
 
 void launch_tier_kernel(int tier, const TierArgs &a, int waves, hipStream_t s);
 
+// ---- large size class (rsai_big.hip): one workgroup per column
+constexpr int BMMAX_BIG = 8192;  // rows of the LS block
+constexpr int BQMAX_BIG = 64;    // columns of the LS block
+struct BigArgs {
+    const MatDev *mats;
+    BuildParams P;
+    ColOut out;
+    int64_t arena_base;
+    const int32_t *rec_in;
+    int rec_in_stride;
+    const int32_t *rec_in_count;
+    int64_t rec_in_cap;
+    double *scratch;          // per-workgroup slabs
+    int64_t scratch_stride;   // doubles per slab
+    int32_t *err;
+};
+int big_max_rows();
+int big_max_cols();
+int64_t big_scratch_stride();
+void launch_big_kernel(const BigArgs &a, int blocks, hipStream_t s);
+
 // ---- preprocessing (rsai_prep.hip)
 // err bits: 1 colptr, 2 rows out of range / unsorted / duplicate, 4 empty column
 void launch_validate(int64_t n, int64_t nnz, const int64_t *colptr, const int32_t *rowidx, int32_t *err,

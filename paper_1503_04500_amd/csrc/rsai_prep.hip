@@ -250,23 +250,24 @@ void launch_scan_i32(const int32_t *in, int64_t n, int64_t *out, int64_t *tmp, h
 // its arena slot; assembly is a compaction: one thread per (column, position) pair
 // over n x QCAP, reading the padded slots and writing M at colptrM[k] + t.
 
+// 16 lanes per column copy its nJ[k] <= qcap entries from the arena slot into M
 __global__ void k_assemble(int64_t n, int qcap, const int64_t *off, const int32_t *nJ, const int64_t *colptrM,
                            const int32_t *aJ, const double *aV, int32_t *rowidxM, double *valM) {
-    const int64_t total = n * (int64_t)qcap;
+    const int64_t total = n * 16;
     for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t k = idx / qcap;
-        const int t = (int)(idx - k * qcap);
-        if (t < nJ[k]) {
-            const int64_t src = off[k] + t, dst = colptrM[k] + t;
-            rowidxM[dst] = aJ[src];
-            valM[dst] = aV[src];
+        const int64_t k = idx >> 4;
+        const int cnt = min(nJ[k], qcap);
+        const int64_t src0 = off[k], dst0 = colptrM[k];
+        for (int t = (int)(idx & 15); t < cnt; t += 16) {
+            rowidxM[dst0 + t] = aJ[src0 + t];
+            valM[dst0 + t] = aV[src0 + t];
         }
     }
 }
 void launch_assemble(int64_t n, int qcap, const int64_t *off, const int32_t *nJ, const int64_t *colptrM,
                      const int32_t *arenaJ, const double *arenaV, int32_t *rowidxM, double *valM, hipStream_t s) {
-    hipLaunchKernelGGL(k_assemble, dim3(nblocks(n * (int64_t)qcap, 1024)), dim3(256), 0, s, n, qcap, off, nJ, colptrM,
+    hipLaunchKernelGGL(k_assemble, dim3(nblocks(n * 16, 1024)), dim3(256), 0, s, n, qcap, off, nJ, colptrM,
                        arenaJ, arenaV, rowidxM, valM);
 }
 
