@@ -13,8 +13,8 @@
 //   * the residual for step 4 is A(I,J) m - e_k(I) accumulated from the sparse
 //     columns in ascending column order (eq. (2.4)), so exact ties reach the
 //     smaller-index rule.
-// Columns arrive only as spill records of the previous tier; a column that outgrows
-// this class ends with status RSAI_E_CAP.
+// Columns arrive as spill records of the previous class; a column that outgrows this
+// class ends with status RSAI_E_CAP.
 #include <climits>
 
 #include "rsai_kernels.h"
@@ -132,20 +132,41 @@ __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
         for (int t = tid; t < BHJ; t += NT) S.hJ[t] = HEMPTY;
         __syncthreads();
         if (q > BQMAX_BIG || m > BMMAX_BIG) status = ST_CAP;
+        int np2 = 1;
+        while (np2 < m) np2 <<= 1;
         if (status == ST_OK) {
             for (int t = tid; t < q; t += NT) {
                 S.Jlist[t] = RJ[t];
                 int sl;
                 hinsert<BLOGHJ>(S.hJ, RJ[t], sl);
             }
+            // rows of I numbered in ascending order (records may list them in any order)
+            for (int t = tid; t < np2; t += NT) S.skey[t] = (t < m) ? RI[t] : INT_MAX;
+            if (tid < nRh) S.Rh[tid] = RHp[tid];
+        }
+        __syncthreads();
+        if (status == ST_OK) {
+            for (int kk = 2; kk <= np2; kk <<= 1) {
+                for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+                    for (int i = tid; i < np2; i += NT) {
+                        const int ixj = i ^ jj;
+                        if (ixj > i) {
+                            const int a = S.skey[i], b = S.skey[ixj];
+                            const bool up = (i & kk) == 0;
+                            if ((a > b) == up) { S.skey[i] = b; S.skey[ixj] = a; }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
             for (int t = tid; t < m; t += NT) {
-                Il[t] = RI[t];
+                const int row = S.skey[t];
+                Il[t] = row;
                 rfl[t] = 0;
                 int sl;
-                hinsert<BLOGH>(S.hI, RI[t], sl);
+                hinsert<BLOGH>(S.hI, row, sl);
                 if (sl >= 0) S.hIv[sl] = (unsigned short)t;
             }
-            if (tid < nRh) S.Rh[tid] = RHp[tid];
         }
         __syncthreads();
         if (status == ST_OK) {
@@ -173,6 +194,11 @@ __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
         bool dropok = false;
         int qmod = -1;
         int p_fresh = 0;
+        if (rec[10] & 2) {
+            // augmented pattern handed over before its solve
+            dropok = (rec[10] & 4) != 0;
+            qmod = rec[11];
+        }
         if (status == ST_OK && q == 0 && nRh == 0) {
             // a column whose own rows exceed the register tiers: J = {k}, loop 0
             if (tid == 0) {

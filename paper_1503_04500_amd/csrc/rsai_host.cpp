@@ -179,8 +179,14 @@ rsai_status rsai_set_allocator(rsai_alloc_fn alloc, rsai_free_fn dealloc, void *
 const char *rsai_last_error(void) { return g_err.c_str(); }
 
 rsai_status rsai_tier_info(int32_t t, int32_t *lanes, int32_t *max_rows, int32_t *max_cols) {
-    if (t < 0 || t > kNumTiers) return fail(RSAI_E_ARG, "no tier %d", t);
-    if (t == kNumTiers) {  // the large size class: one 256-lane workgroup per column
+    if (t < 0 || t > kNumTiers + 1) return fail(RSAI_E_ARG, "no tier %d", t);
+    if (t == kNumTiers) {  // the sparse-block class: one 256-lane workgroup per column
+        if (lanes) *lanes = 256;
+        if (max_rows) *max_rows = WIDE_MMAX;
+        if (max_cols) *max_cols = WIDE_QMAX;
+        return RSAI_OK;
+    }
+    if (t == kNumTiers + 1) {  // the dense large class: one 256-lane workgroup per column
         if (lanes) *lanes = 256;
         if (max_rows) *max_rows = big_max_rows();
         if (max_cols) *max_cols = big_max_cols();
@@ -266,14 +272,19 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
         slot_base[t] = acap;
         acap += ncols * (int64_t)kTiers[t].QMAX;
     }
-    // the batched schedule ends with the large size class (one workgroup per column)
+    // the batched schedule ends with two workgroup-per-column classes: the sparse-block
+    // class, then the dense large class; they share one arena slot of 64 per column
     const bool big = !plain;
     int64_t big_base = acap;
     if (big) acap += ncols * (int64_t)BQMAX_BIG;
     P->arena_cap = acap;
-    const int nlaunch = plain ? P->p.lmax + 1 : (tlast - t0 + 1 + (big ? 1 : 0));
+    const int nlaunch = plain ? P->p.lmax + 1 : (tlast - t0 + 1 + (big ? 2 : 0));
     const int64_t qlast = big ? std::max<int64_t>(kTiers[tlast].QMAX, BQMAX_BIG) : kTiers[tlast].QMAX;
     const int big_blocks = device_cus();
+    const int wide_blocks = device_cus() * wide_blocks_per_cu();
+    // records into the dense class: few columns need it; more than this many end
+    // with RSAI_E_CAP
+    const int64_t wide_rec_cap = std::min<int64_t>(ncols, std::max<int64_t>(4096, ncols / 64));
 
     // ---- every device buffer of the build, from one allocation
     std::vector<int32_t *> fillpos(count);
@@ -313,6 +324,7 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
         } else {
             for (int t = t0; t < tlast + (big ? 1 : 0); ++t)
                 P->rec[t] = L.take<int32_t>(ncols * (int64_t)kTiers[t].REC);
+            if (big) P->rec[tlast + 1] = L.take<int32_t>(wide_rec_cap * (int64_t)wide_rec_stride());
         }
         P->big_scratch = big ? L.take<double>((int64_t)big_blocks * big_scratch_stride()) : nullptr;
     };
@@ -444,23 +456,39 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
             if (t == t0) P->record(2, s);
         }
         if (big) {
-            // columns that outgrew the last register tier: one workgroup per column
+            // columns that outgrew the last register tier: one workgroup per column,
+            // first on the compressed block, then (rarely) on the dense block
+            WideArgs w{};
+            w.mats = P->d_mats;
+            w.P = base.P;
+            w.out = P->out;
+            w.arena_base = big_base;
+            w.rec_in = P->rec[tlast];
+            w.rec_in_stride = kTiers[tlast].REC;
+            w.rec_in_count = P->rec_count + (tlast - t0);
+            w.rec_in_cap = ncols;
+            w.rec_out = P->rec[tlast + 1];
+            w.rec_out_stride = wide_rec_stride();
+            w.rec_out_count = P->rec_count + (tlast - t0 + 1);
+            w.rec_out_cap = wide_rec_cap;
+            w.err = P->err;
+            launch_wide_kernel(w, wide_blocks, s);
             BigArgs b{};
             b.mats = P->d_mats;
             b.P = base.P;
             b.out = P->out;
             b.arena_base = big_base;
-            b.rec_in = P->rec[tlast];
-            b.rec_in_stride = kTiers[tlast].REC;
-            b.rec_in_count = P->rec_count + (tlast - t0);
-            b.rec_in_cap = ncols;
+            b.rec_in = P->rec[tlast + 1];
+            b.rec_in_stride = wide_rec_stride();
+            b.rec_in_count = P->rec_count + (tlast - t0 + 1);
+            b.rec_in_cap = wide_rec_cap;
             b.scratch = P->big_scratch;
             b.scratch_stride = big_scratch_stride();
             b.err = P->err;
             launch_big_kernel(b, big_blocks, s);
         }
     }
-    P->ntiers_used = tlast - t0 + 1 + (big ? 1 : 0);
+    P->ntiers_used = tlast - t0 + 1 + (big ? 2 : 0);
     P->record(3, s);
 
     // ---- assembly of M per matrix: colptr = scan(nJ), then compaction

@@ -17,6 +17,30 @@ extern const int kPlainTier;  // the one size class of the plain schedule
 
 void launch_tier_kernel(int tier, const TierArgs &a, int waves, hipStream_t s);
 
+// ---- sparse-block size class (rsai_wide.hip): one workgroup per column, LS solved
+// on the compressed block (shared rows + one row per column)
+constexpr int WIDE_MMAX = 2048;  // rows of I
+constexpr int WIDE_QMAX = 63;    // columns of J
+constexpr int WIDE_RCAP = 8 * 64 + 1;  // dominant rows in a record: c * lmax + 1
+struct WideArgs {
+    const MatDev *mats;
+    BuildParams P;
+    ColOut out;
+    int64_t arena_base;       // slot of a column: arena_base + ucol * 64
+    const int32_t *rec_in;
+    int rec_in_stride;
+    const int32_t *rec_in_count;
+    int64_t rec_in_cap;
+    int32_t *rec_out;         // records for the dense large class
+    int rec_out_stride;
+    int32_t *rec_out_count;
+    int64_t rec_out_cap;
+    int32_t *err;
+};
+int wide_rec_stride();
+void launch_wide_kernel(const WideArgs &a, int blocks, hipStream_t s);
+int wide_blocks_per_cu();
+
 // ---- large size class (rsai_big.hip): one workgroup per column
 constexpr int BMMAX_BIG = 8192;  // rows of the LS block
 constexpr int BQMAX_BIG = 64;    // columns of the LS block

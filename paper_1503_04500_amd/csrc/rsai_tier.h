@@ -20,7 +20,13 @@
 
 namespace rsai {
 
-constexpr int RHDR = 11;  // spill record header ints
+// Spill record: header of RHDR ints, then J (q), I (m), R (nR: dominant rows used so
+// far), pending dominant rows (nRh). Header: [0] global column id, [1] matrix, [2] k,
+// [3] l, [4] q, [5] m, [6] nR, [7] nRh, [8..9] flop count (double bits), [10] flags:
+// bit 0 l is still to be advanced when the pending rows form J-hat, bit 1 the stored
+// pattern is augmented but not yet solved, bit 2 dropping applies to that solve;
+// [11] kept columns of the flop model of that solve.
+constexpr int RHDR = 12;
 
 template <int G_, int RPL_, int QMAX_, int STAGE_, int HSF_ = 2>
 struct TierCfg {

@@ -1,0 +1,642 @@
+// Sparse-block size class of the RSAI(tol) build: one 256-thread workgroup per
+// column, for LS blocks A(I_k, J_k) that outgrow the register tiers but are mostly
+// structurally empty (long sparse columns with few rows in common, as in matrices
+// with power-law column lengths). Up to WIDE_MMAX rows and WIDE_QMAX columns.
+//
+// The LS problem (2.3) is solved on an orthogonally equivalent compressed block.
+// A row of I_k met by exactly one column j of J_k (a private row of j) adds to
+// column j only; an orthogonal transformation of the private rows of j turns them
+// into one row holding their 2-norm s_j, and the part of e_k on them into
+// a_kj / s_j on that row (when k is one of them) plus a constant part
+// (s_j^2 - a_kj^2) / s_j^2 of ||r||^2 that no choice of m_k can reduce. The rows
+// met by two or more columns (shared rows) stay as they are. Householder QR of the
+// (shared + |J_k|) x |J_k| block then gives m_k and ||A m_k - e_k||.
+//
+// Everything else follows the register tiers step for step (Algorithm 1 with the
+// dropping of Section 4): I_k is an LDS hash set whose entries carry the number of
+// columns of J_k that hold the row and a flag for rows already used as dominant
+// rows; the residual for step 4 is formed from the sparse columns with the columns
+// taken in ascending global order, so exact ties reach the smaller-index rule.
+// Columns arrive as spill records of the last register tier. A column whose |I_k|
+// or compressed block outgrows this class moves on to the dense large class.
+#include <climits>
+
+#include "rsai_kernels.h"
+
+namespace rsai {
+
+namespace {
+constexpr int NT = 256;                 // threads per column
+constexpr int NW = NT / 64;             // waves
+constexpr int LOGH = 12;                // row hash: 4096 slots for |I| <= 2048
+constexpr int HS = 1 << LOGH;
+constexpr int MM = WIDE_MMAX;
+constexpr int QM = WIDE_QMAX;
+constexpr int LOGHJ = 8;                // column hash: 256 slots
+constexpr int HJ = 1 << LOGHJ;
+constexpr int BLK = 2048;               // compressed block, (S + q) x (q + 1), row-major
+constexpr int SHV = 768;                // values of the shared rows, S x q
+constexpr int SMAX = 128;               // shared rows
+constexpr int WBLOCKS_PER_CU = 3;       // LDS-limited residency
+static_assert(HS >= 2 * MM, "row hash load above one half");
+
+struct WLds {
+    int hk[HS];             // row keys
+    unsigned hv[HS / 4];    // one byte per slot: bits 0-6 columns of J holding the row, bit 7 row in R
+    int hJ[HJ];             // J as a set
+    double blk[BLK];
+    double shv[SHV];
+    double s2[64], s2x[64]; // private rows of each column: sum of squares (all / without row k)
+    double mt[64], rd[64];  // solution by slot, diagonal of R
+    double racc[SMAX];      // residual of the shared rows
+    int64_t cb[64];         // first entry of each column of J
+    int clen[64];
+    int Jl[64];             // J, slot order
+    int ord[64];            // slots in ascending column order
+    int srow[SMAX];         // shared rows, ascending
+    int stmp[SMAX];
+    int newc[64];           // columns of J-hat
+    int Rh[CMAX];           // pending dominant rows
+    double cva[NW];
+    int cvg[NW];
+    double dred[NW];
+    double akv;             // a_kj when k is a private row of column slot kcol
+    int kcol;
+    int cnt, nsh, flag;
+    double rn;
+};
+
+__device__ __forceinline__ unsigned hget(const WLds &S, int sl) {
+    return (S.hv[sl >> 2] >> ((sl & 3) * 8)) & 0xFFu;
+}
+__device__ __forceinline__ void hinc(WLds &S, int sl) { atomicAdd(&S.hv[sl >> 2], 1u << ((sl & 3) * 8)); }
+__device__ __forceinline__ void hdec(WLds &S, int sl) { atomicSub(&S.hv[sl >> 2], 1u << ((sl & 3) * 8)); }
+__device__ __forceinline__ void hsetR(WLds &S, int sl) { atomicOr(&S.hv[sl >> 2], 0x80u << ((sl & 3) * 8)); }
+
+// wave-wide sum; every lane gets the bitwise-same value
+__device__ __forceinline__ double wsum(double x) {
+    x = gsum<16>(x);
+    x += __shfl_xor(x, 16);
+    x += __shfl_xor(x, 32);
+    return x;
+}
+
+// (a desc, g asc) order of dominant-row candidates
+__device__ __forceinline__ bool better(double a, int g, double b, int h) { return a > b || (a == b && g < h); }
+
+// index of row in the ascending shared-row list, or -1
+__device__ __forceinline__ int sfind(const int *srow, int nsh, int row) {
+    int lo = 0, hi = nsh - 1;
+    while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int v = srow[mid];
+        if (v == row) return mid;
+        if (v < row) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
+}
+}  // namespace
+
+int wide_rec_stride() { return RHDR + 64 + WIDE_MMAX + WIDE_RCAP + CMAX; }
+int wide_blocks_per_cu() { return WBLOCKS_PER_CU; }
+
+__global__ __launch_bounds__(NT) void wide_kernel(WideArgs args) {
+    __shared__ WLds S;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if (*args.err & 7) return;
+    const BuildParams P = args.P;
+    const int64_t Q = min((int64_t)(*args.rec_in_count), args.rec_in_cap);
+
+    for (int64_t pos = blockIdx.x; pos < Q; pos += gridDim.x) {
+        const int32_t *rec = args.rec_in + pos * (int64_t)args.rec_in_stride;
+        const int ucol = rec[0], mat = rec[1], k = rec[2];
+        int l = rec[3], q = rec[4], m = rec[5];
+        const int nR0 = rec[6];
+        int nRh = rec[7];
+        double fl = __longlong_as_double(((long long)rec[9] << 32) | (long long)(unsigned)rec[8]);
+        bool linc = (rec[10] & 1) != 0;
+        const MatDev A = args.mats[mat];
+        const int32_t *RJ = rec + RHDR, *RI = RJ + q, *RR = RI + m, *RHp = RR + nR0;
+        int status = ST_OK;
+        bool spill = false, pend = false, pend_drop = false;
+        int pend_qmod = -1;
+        bool lookup_fail = false;
+        double rn = 0.0;
+
+        // ---------------------------------------------------------- state from the record
+        for (int t = tid; t < HS; t += NT) S.hk[t] = HEMPTY;
+        for (int t = tid; t < HS / 4; t += NT) S.hv[t] = 0u;
+        for (int t = tid; t < HJ; t += NT) S.hJ[t] = HEMPTY;
+        if (tid == 0) S.flag = 0;
+        __syncthreads();
+        if (q > QM || m > MM || nRh > CMAX) status = ST_CAP;  // larger than any register tier
+        if (status == ST_OK) {
+            for (int t = tid; t < q; t += NT) {
+                const int col = RJ[t];
+                S.Jl[t] = col;
+                S.cb[t] = A.colptr[col];
+                S.clen[t] = (int)(A.colptr[col + 1] - S.cb[t]);
+                int sl;
+                hinsert<LOGHJ>(S.hJ, col, sl);
+            }
+            for (int t = tid; t < m; t += NT) {
+                int sl;
+                hinsert<LOGH>(S.hk, RI[t], sl);
+            }
+            if (tid < nRh) S.Rh[tid] = RHp[tid];
+        }
+        __syncthreads();
+        if (status == ST_OK) {
+            // how many columns of J hold each row (every row of a column of J is in I)
+            for (int c = wid; c < q; c += NW) {
+                const int64_t e0 = S.cb[c];
+                for (int t = lane; t < S.clen[c]; t += 64) {
+                    const int sl = hfind<LOGH>(S.hk, A.rowidx[e0 + t]);
+                    if (sl >= 0) hinc(S, sl); else lookup_fail = true;
+                }
+            }
+            for (int t = tid; t < nR0; t += NT) {
+                const int row = RR[t];
+                const int sl = hfind<LOGH>(S.hk, row);
+                if (sl >= 0) hsetR(S, sl);
+                else if (row == k) S.flag = 1;  // k used as a dominant row while k is not in I
+            }
+        }
+        __syncthreads();
+        bool kR = S.flag != 0;
+        __syncthreads();
+
+        bool first = true, need_solve = true, dropok = false;
+        int qmod = -1;
+        int p = 0;
+        if (status == ST_OK && q == 0 && nRh == 0) {
+            // a column whose own rows exceed the register tiers: J = {k}, loop 0
+            if (tid == 0) {
+                S.Jl[0] = k;
+                S.cb[0] = A.colptr[k];
+                S.clen[0] = (int)(A.colptr[k + 1] - A.colptr[k]);
+                int sl;
+                hinsert<LOGHJ>(S.hJ, k, sl);
+            }
+            __syncthreads();
+            p = 1;
+            dropok = true;
+            qmod = 0;
+        }
+
+        while (status == ST_OK && !spill) {
+            // ================= J-hat: columns of the pending dominant rows not in J (step 5)
+            if (nRh > 0) {
+                if (linc) ++l;  // step 6
+                linc = false;
+                int64_t sb[CMAX];
+                int sp[CMAX + 1];
+                sp[0] = 0;
+#pragma unroll
+                for (int t = 0; t < CMAX; ++t) {
+                    int64_t b0 = 0, e0 = 0;
+                    if (t < nRh) {
+                        const int rt = S.Rh[t];
+                        b0 = A.rowptr[rt];
+                        e0 = A.rowptr[rt + 1];
+                    }
+                    sb[t] = b0;
+                    sp[t + 1] = sp[t] + (int)(e0 - b0);
+                }
+                if (tid == 0) S.cnt = 0;
+                __syncthreads();
+                bool ovf = false;
+                for (int u = tid; u < sp[CMAX]; u += NT) {
+                    int64_t b0 = sb[0];
+                    int o0 = 0;
+#pragma unroll
+                    for (int t = 1; t < CMAX; ++t)
+                        if (u >= sp[t]) { b0 = sb[t]; o0 = sp[t]; }
+                    const int col = A.colidx[b0 + (u - o0)];
+                    int sl;
+                    if (hinsert<LOGHJ>(S.hJ, col, sl)) {
+                        const int ps = atomicAdd(&S.cnt, 1);
+                        if (q + ps < QM) S.newc[ps] = col; else ovf = true;
+                    } else if (sl < 0) {
+                        ovf = true;  // table full
+                    }
+                }
+                if (__syncthreads_or(ovf)) { spill = true; break; }
+                p = S.cnt;
+                if (tid < p) {
+                    const int key = S.newc[tid];
+                    int rank = 0;
+                    for (int t = 0; t < p; ++t) rank += (S.newc[t] < key) ? 1 : 0;
+                    S.Jl[q + rank] = key;
+                    S.cb[q + rank] = A.colptr[key];
+                    S.clen[q + rank] = (int)(A.colptr[key + 1] - A.colptr[key]);
+                }
+                need_solve = !(p == 0 && !first);  // empty J-hat: the loop ends without a solve
+                dropok = (p > 0);
+                qmod = (p > 0) ? q : (first ? -1 : q);
+                __syncthreads();
+            }
+            // ================= I-hat: rows of the new columns not in I (step 5)
+            if (need_solve && p > 0) {
+                int total = 0;
+                for (int t = 0; t < p; ++t) total += S.clen[q + t];
+                if (m + total > MM) { spill = true; break; }  // may outgrow the row hash
+                if (tid == 0) S.cnt = 0;
+                __syncthreads();
+                int added = 0;
+                for (int c = q + wid; c < q + p; c += NW) {
+                    const int64_t e0 = S.cb[c];
+                    for (int t = lane; t < S.clen[c]; t += 64) {
+                        int sl;
+                        if (hinsert<LOGH>(S.hk, A.rowidx[e0 + t], sl)) ++added;
+                        if (sl >= 0) hinc(S, sl); else lookup_fail = true;
+                    }
+                }
+                if (added) atomicAdd(&S.cnt, added);
+                __syncthreads();
+                m += S.cnt;
+                if (kR) {
+                    // k entered I: its flag moves into the hash entry
+                    const int sl = hfind<LOGH>(S.hk, k);
+                    if (sl >= 0) {
+                        if (tid == 0) hsetR(S, sl);
+                        kR = false;
+                    }
+                }
+                q += p;
+                p = 0;
+            }
+            nRh = 0;  // pending rows consumed
+            first = false;
+
+            // ================= LS solve(s) on (I, J) (2.3): pass 0 the augmented pattern,
+            // pass 1 the pattern kept after dropping (Section 4)
+            for (int pass = 0; pass < 2 && need_solve && status == ST_OK; ++pass) {
+                // ---- shared rows (held by two or more columns of J), ascending
+                if (tid == 0) { S.nsh = 0; S.kcol = -1; S.akv = 0.0; S.flag = 0; }
+                __syncthreads();
+                for (int t = tid; t < HS; t += NT) {
+                    const int key = S.hk[t];
+                    if (key != HEMPTY && (hget(S, t) & 0x7Fu) >= 2u) {
+                        const int ps = atomicAdd(&S.nsh, 1);
+                        if (ps < SMAX) S.stmp[ps] = key;
+                    }
+                }
+                __syncthreads();
+                const int nsh = S.nsh;
+                const int ld = q + 1, mp = nsh + q;
+                if (nsh > SMAX || nsh * q > SHV || mp * ld > BLK) {
+                    // the compressed block does not fit: hand the unsolved pattern over
+                    spill = true;
+                    pend = true;
+                    pend_drop = dropok && pass == 0;
+                    pend_qmod = qmod;
+                    break;
+                }
+                if (tid < nsh) {
+                    const int key = S.stmp[tid];
+                    int rank = 0;
+                    for (int t = 0; t < nsh; ++t) rank += (S.stmp[t] < key) ? 1 : 0;
+                    S.srow[rank] = key;
+                }
+                for (int t = tid; t < mp * ld; t += NT) S.blk[t] = 0.0;
+                for (int t = tid; t < nsh * q; t += NT) S.shv[t] = 0.0;
+                __syncthreads();
+                // ---- gather: shared entries into the block, private rows into column sums
+                for (int c = wid; c < q; c += NW) {
+                    const int64_t e0 = S.cb[c];
+                    double a2 = 0.0, a2x = 0.0;
+                    for (int t = lane; t < S.clen[c]; t += 64) {
+                        const int row = A.rowidx[e0 + t];
+                        const double v = A.val[e0 + t];
+                        const int sl = hfind<LOGH>(S.hk, row);
+                        const unsigned cn = sl >= 0 ? (hget(S, sl) & 0x7Fu) : 0u;
+                        if (cn == 1u) {
+                            a2 += v * v;
+                            if (row != k) a2x += v * v;
+                            else { S.kcol = c; S.akv = v; }
+                        } else if (cn >= 2u) {
+                            const int si = sfind(S.srow, nsh, row);
+                            if (si >= 0) {
+                                S.blk[si * ld + c] = v;
+                                S.shv[si * q + c] = v;
+                            } else {
+                                lookup_fail = true;
+                            }
+                        } else {
+                            lookup_fail = true;
+                        }
+                    }
+                    a2 = wsum(a2);
+                    a2x = wsum(a2x);
+                    if (lane == 0) { S.s2[c] = a2; S.s2x[c] = a2x; }
+                }
+                __syncthreads();
+                // ---- the row of row k: shared (right-hand side 1), private (compressed), or
+                // outside the pattern (a constant 1 in ||r||^2)
+                const int ksl = hfind<LOGH>(S.hk, k);
+                const int kcn = ksl >= 0 ? (int)(hget(S, ksl) & 0x7Fu) : -1;
+                double kconst = 0.0;
+                if (kcn <= 0) kconst = 1.0;
+                if (kcn == 1 && S.kcol >= 0) {
+                    const double s2k = S.s2[S.kcol];
+                    kconst = s2k > 0.0 ? S.s2x[S.kcol] / s2k : 1.0;
+                }
+                if (tid < q) {
+                    const double sj = sqrt(S.s2[tid]);
+                    S.blk[(nsh + tid) * ld + tid] = sj;
+                    if (kcn == 1 && S.kcol == tid && sj > 0.0) S.blk[(nsh + tid) * ld + q] = S.akv / sj;
+                }
+                if (kcn >= 2 && tid == 0) {
+                    const int si = sfind(S.srow, nsh, k);
+                    if (si >= 0) S.blk[si * ld + q] = 1.0;
+                }
+                __syncthreads();
+                // ---- Householder QR of the compressed block and Q^T e (wave 0: lane c
+                // holds column c, lane q the right-hand side), back substitution
+                if (wid == 0) {
+                    bool singular = false;
+                    for (int j = 0; j < q; ++j) {
+                        double s = 0.0;
+                        for (int i = j + lane; i < mp; i += 64) {
+                            const double x = S.blk[i * ld + j];
+                            s += x * x;
+                        }
+                        s = wsum(s);
+                        const double x0 = S.blk[j * ld + j];
+                        const double nx = sqrt(s);
+                        const double alpha = (x0 >= 0.0) ? -nx : nx;
+                        const double be = (nx > 0.0) ? 1.0 / (nx * (nx + fabs(x0))) : 0.0;
+                        if (!(nx > 0.0)) singular = true;
+                        wave_sync();
+                        if (lane == 0) {
+                            S.blk[j * ld + j] = x0 - alpha;
+                            S.rd[j] = alpha;
+                        }
+                        wave_sync();
+                        if (lane > j && lane <= q) {
+                            double w = 0.0;
+                            for (int i = j; i < mp; ++i) w += S.blk[i * ld + j] * S.blk[i * ld + lane];
+                            w *= be;
+                            for (int i = j; i < mp; ++i) S.blk[i * ld + lane] -= w * S.blk[i * ld + j];
+                        }
+                        wave_sync();
+                    }
+                    if (!singular) {
+                        double y = (lane < q) ? S.blk[lane * ld + q] : 0.0;
+                        for (int j = q - 1; j >= 0; --j) {
+                            const double mj = __shfl(y, j) / S.rd[j];
+                            if (lane == 0) S.mt[j] = mj;
+                            if (lane < j) y -= S.blk[lane * ld + j] * mj;
+                        }
+                        double s = 0.0;
+                        for (int i = q + lane; i < mp; i += 64) {
+                            const double x = S.blk[i * ld + q];
+                            s += x * x;
+                        }
+                        s = wsum(s);
+                        if (lane == 0) S.rn = sqrt(s + kconst);
+                    } else if (lane == 0) {
+                        S.flag = 1;
+                    }
+                }
+                __syncthreads();
+                if (S.flag) { status = ST_SINGULAR; break; }
+                rn = S.rn;
+                if (qmod >= 0) fl += solve_flops(m, qmod, q);
+                // ---- dropping (Section 4), after the augment solve only
+                if (pass == 0 && dropok && P.drop != DROP_NONE) {
+                    const double th = (P.drop == DROP_FIXED)
+                                          ? P.tol
+                                          : P.eps / ((double)q * __longlong_as_double((long long)*A.norm1_bits));
+                    int nk = 0, bc = 0;
+                    for (int c = 0; c < q; ++c) {
+                        nk += (fabs(S.mt[c]) > th) ? 1 : 0;
+                        const double a = fabs(S.mt[c]), b = fabs(S.mt[bc]);
+                        if (a > b || (a == b && S.Jl[c] < S.Jl[bc])) bc = c;
+                    }
+                    if (nk < q) {
+                        // rows of the dropped columns lose one holder
+                        for (int c = wid; c < q; c += NW) {
+                            const bool keep = (nk == 0) ? (c == bc) : (fabs(S.mt[c]) > th);
+                            if (keep) continue;
+                            const int64_t e0 = S.cb[c];
+                            for (int t = lane; t < S.clen[c]; t += 64) {
+                                const int sl = hfind<LOGH>(S.hk, A.rowidx[e0 + t]);
+                                if (sl >= 0) hdec(S, sl); else lookup_fail = true;
+                            }
+                        }
+                        __syncthreads();
+                        if (tid == 0) {
+                            int w = 0;
+                            for (int c = 0; c < q; ++c) {
+                                const bool keep = (nk == 0) ? (c == bc) : (fabs(S.mt[c]) > th);
+                                if (keep) {
+                                    S.Jl[w] = S.Jl[c];
+                                    S.cb[w] = S.cb[c];
+                                    S.clen[w] = S.clen[c];
+                                    ++w;
+                                }
+                            }
+                            S.cnt = w;
+                        }
+                        for (int t = tid; t < HJ; t += NT) S.hJ[t] = HEMPTY;
+                        __syncthreads();
+                        q = S.cnt;
+                        for (int c = tid; c < q; c += NT) {
+                            int sl;
+                            hinsert<LOGHJ>(S.hJ, S.Jl[c], sl);
+                        }
+                        qmod = 0;
+                        __syncthreads();
+                        continue;  // solve on the kept pattern
+                    }
+                }
+                break;
+            }
+            if (status != ST_OK || spill) break;
+            need_solve = false;
+
+            // ================= stop test (step 3)
+            if (rn <= P.eps || l >= P.lmax) break;
+
+            // ================= dominant rows of r = A(I,J) m - e_k (step 4)
+            const int nsh = S.nsh;
+            if (tid < q) {
+                const int jc = S.Jl[tid];
+                int rank = 0;
+                for (int t = 0; t < q; ++t) rank += (S.Jl[t] < jc) ? 1 : 0;
+                S.ord[rank] = tid;
+            }
+            __syncthreads();
+            double ta[CMAX];
+            int tg[CMAX];
+#pragma unroll
+            for (int s = 0; s < CMAX; ++s) { ta[s] = -1.0; tg[s] = INT_MAX; }
+            auto offer = [&](double a, int g) {
+#pragma unroll
+                for (int s = 0; s < CMAX; ++s) {
+                    if (better(a, g, ta[s], tg[s])) {
+                        const double a1 = ta[s];
+                        const int g1 = tg[s];
+                        ta[s] = a;
+                        tg[s] = g;
+                        a = a1;
+                        g = g1;
+                    }
+                }
+            };
+            // shared rows: the columns in ascending global order, fused multiply-adds
+            if (tid < nsh) {
+                double acc = 0.0;
+                for (int t = 0; t < q; ++t) {
+                    const int c = S.ord[t];
+                    const double a = S.shv[tid * q + c];
+                    if (a != 0.0) acc = __fma_rn(a, S.mt[c], acc);
+                }
+                const int row = S.srow[tid];
+                const double ri = acc - ((row == k) ? 1.0 : 0.0);
+                const int sl = hfind<LOGH>(S.hk, row);
+                if (ri != 0.0 && sl >= 0 && !(hget(S, sl) & 0x80u)) offer(fabs(ri), row);
+            }
+            // private rows: one product each
+            for (int c = wid; c < q; c += NW) {
+                const int64_t e0 = S.cb[c];
+                const double mc = S.mt[c];
+                for (int t = lane; t < S.clen[c]; t += 64) {
+                    const int row = A.rowidx[e0 + t];
+                    const int sl = hfind<LOGH>(S.hk, row);
+                    const unsigned hvv = sl >= 0 ? hget(S, sl) : 0u;
+                    if ((hvv & 0x7Fu) == 1u && !(hvv & 0x80u)) {
+                        const double ri = __fma_rn(A.val[e0 + t], mc, 0.0) - ((row == k) ? 1.0 : 0.0);
+                        if (ri != 0.0) offer(fabs(ri), row);
+                    }
+                }
+            }
+            // row k outside the columns of J: r(k) = -1
+            if (tid == 0) {
+                const int ksl = hfind<LOGH>(S.hk, k);
+                if (ksl >= 0) {
+                    const unsigned hvv = hget(S, ksl);
+                    if ((hvv & 0x7Fu) == 0u && !(hvv & 0x80u)) offer(1.0, k);
+                } else if (!kR) {
+                    offer(1.0, k);
+                }
+            }
+            int nsel = 0;
+            for (int t = 0; t < P.c; ++t) {
+                double a = ta[0];
+                int g = tg[0];
+                gargmax<16>(a, g);
+#pragma unroll
+                for (int off = 16; off <= 32; off <<= 1) {
+                    const double a2 = __shfl_xor(a, off);
+                    const int g2 = __shfl_xor(g, off);
+                    if (better(a2, g2, a, g)) { a = a2; g = g2; }
+                }
+                if (lane == 0) { S.cva[wid] = a; S.cvg[wid] = g; }
+                __syncthreads();
+                a = S.cva[0];
+                g = S.cvg[0];
+#pragma unroll
+                for (int w = 1; w < NW; ++w)
+                    if (better(S.cva[w], S.cvg[w], a, g)) { a = S.cva[w]; g = S.cvg[w]; }
+                __syncthreads();
+                if (a < 0.0) break;
+                // the holder of the winner drops it from its list
+                if (tg[0] == g && ta[0] == a) {
+#pragma unroll
+                    for (int s = 0; s < CMAX - 1; ++s) { ta[s] = ta[s + 1]; tg[s] = tg[s + 1]; }
+                    ta[CMAX - 1] = -1.0;
+                    tg[CMAX - 1] = INT_MAX;
+                }
+                if (tid == 0) {
+                    S.Rh[t] = g;
+                    const int sl = hfind<LOGH>(S.hk, g);
+                    if (sl >= 0) hsetR(S, sl);
+                }
+                if (g == k && hfind<LOGH>(S.hk, k) < 0) kR = true;
+                nsel = t + 1;
+            }
+            __syncthreads();
+            if (nsel == 0) break;  // no candidate row left: r = 0 (Section 3)
+            nRh = nsel;
+            linc = true;
+        }
+        if (lookup_fail) atomicOr(args.err, 16);
+
+        if (spill) {
+            // ---- hand the column over to the dense large class
+            if (tid == 0) {
+                int ps = INT_MAX;
+                if (args.rec_out) ps = atomicAdd(args.rec_out_count, 1);
+                S.cnt = ps;
+                S.nsh = 0;  // R rows written
+                S.flag = 0; // I rows written
+            }
+            __syncthreads();
+            const int ps = S.cnt;
+            if (args.rec_out != nullptr && (int64_t)ps < args.rec_out_cap) {
+                int32_t *R = args.rec_out + (int64_t)ps * args.rec_out_stride;
+                int32_t *RJo = R + RHDR, *RIo = RJo + q, *RRo = RIo + m;
+                for (int t = tid; t < q; t += NT) RJo[t] = S.Jl[t];
+                // I (hash order; the receiver numbers its rows in ascending order) and R
+                for (int t = tid; t < HS; t += NT) {
+                    const int key = S.hk[t];
+                    if (key != HEMPTY) {
+                        RIo[atomicAdd(&S.flag, 1)] = key;
+                        if (hget(S, t) & 0x80u) {
+                            const int r = atomicAdd(&S.nsh, 1);
+                            if (r < WIDE_RCAP) RRo[r] = key;
+                        }
+                    }
+                }
+                __syncthreads();
+                int nR = S.nsh;
+                if (tid == 0 && kR && nR < WIDE_RCAP) RRo[nR] = k;
+                nR += kR ? 1 : 0;
+                nR = min(nR, WIDE_RCAP);
+                if (tid < nRh) RRo[nR + tid] = S.Rh[tid];
+                if (tid == 0) {
+                    R[0] = ucol; R[1] = mat; R[2] = k; R[3] = l;
+                    R[4] = q; R[5] = m; R[6] = nR; R[7] = nRh;
+                    const long long fb = __double_as_longlong(fl);
+                    R[8] = (int32_t)(fb & 0xffffffffLL);
+                    R[9] = (int32_t)(fb >> 32);
+                    R[10] = (linc ? 1 : 0) | (pend ? 2 : 0) | (pend_drop ? 4 : 0);
+                    R[11] = pend_qmod;
+                }
+                __syncthreads();
+                continue;
+            }
+            status = ST_CAP;  // no room in the next class
+        }
+
+        // ---------------------------------------------------------- output (rows ascending)
+        const int qq = (status == ST_OK) ? q : 0;
+        const int64_t slot = args.arena_base + (int64_t)ucol * 64;
+        for (int c = tid; c < qq; c += NT) {
+            const int jc = S.Jl[c];
+            int rank = 0;
+            for (int t = 0; t < qq; ++t) rank += (S.Jl[t] < jc) ? 1 : 0;
+            args.out.arenaJ[slot + rank] = jc;
+            args.out.arenaV[slot + rank] = S.mt[c];
+        }
+        if (tid == 0) {
+            args.out.off[ucol] = slot;
+            args.out.nJ[ucol] = qq;
+            args.out.nI[ucol] = m;
+            args.out.loops[ucol] = l;
+            args.out.status[ucol] = status;
+            args.out.resnorm[ucol] = rn;
+            args.out.flops[ucol] = fl;
+        }
+        __syncthreads();
+    }
+}
+
+void launch_wide_kernel(const WideArgs &a, int blocks, hipStream_t s) {
+    hipLaunchKernelGGL(wide_kernel, dim3(blocks), dim3(NT), 0, s, a);
+}
+
+}  // namespace rsai

@@ -121,6 +121,17 @@ def test_large_class_c3_shape():
     print("powerlaw n=20000", s)
 
 
+def test_dense_blocks_beyond_register_tiers():
+    """3D stencil with a small eps: |J_k| grows past the register tiers while most
+    rows of I_k are shared by several columns, so the compressed block does not fit
+    the sparse-block class and the dense large class solves it."""
+    A = gen.cd3d(12, seed=3)
+    ref = _ref(A, c=3, lmax=5, eps=0.1, drop=1, tol=1e-3)
+    assert (ref["nJ"] > 32).sum() > 300
+    gpu = run_gpu(A, c=3, lmax=5, eps=0.1, drop="fixed", tol=1e-3)
+    compare(A, gpu, ref, label="cd3d12-dense")
+
+
 def test_c3_sampled_columns():
     """C3 at full size (n = 10^6, power-law) built on the GPU in the benchmark's
     configuration; 3000 seeded random columns plus the 200 longest ones recomputed by
