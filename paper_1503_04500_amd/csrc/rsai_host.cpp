@@ -179,14 +179,14 @@ rsai_status rsai_set_allocator(rsai_alloc_fn alloc, rsai_free_fn dealloc, void *
 const char *rsai_last_error(void) { return g_err.c_str(); }
 
 rsai_status rsai_tier_info(int32_t t, int32_t *lanes, int32_t *max_rows, int32_t *max_cols) {
-    if (t < 0 || t > kNumTiers + 1) return fail(RSAI_E_ARG, "no tier %d", t);
-    if (t == kNumTiers) {  // the sparse-block class: one 256-lane workgroup per column
+    if (t < 0 || t > kNumTiers + WIDE_LEVELS) return fail(RSAI_E_ARG, "no tier %d", t);
+    if (t >= kNumTiers && t < kNumTiers + WIDE_LEVELS) {  // sparse-block classes: 256 lanes per column
         if (lanes) *lanes = 256;
-        if (max_rows) *max_rows = WIDE_MMAX;
+        if (max_rows) *max_rows = wide_max_rows(t - kNumTiers);
         if (max_cols) *max_cols = WIDE_QMAX;
         return RSAI_OK;
     }
-    if (t == kNumTiers + 1) {  // the dense large class: one 256-lane workgroup per column
+    if (t == kNumTiers + WIDE_LEVELS) {  // the dense large class: one 256-lane workgroup per column
         if (lanes) *lanes = 256;
         if (max_rows) *max_rows = big_max_rows();
         if (max_cols) *max_cols = big_max_cols();
@@ -213,6 +213,14 @@ static int device_cus() {
 static int sync_refill_default(int requested) {
     if (requested == 0 || requested == 1) return requested;
     const char *e = getenv("RSAI_SYNC_REFILL");
+    if (e && (e[0] == '0' || e[0] == '1')) return e[0] - '0';
+    return 1;
+}
+
+// spill routing by size estimate (1, default) or always to the next class (0);
+// RSAI_ROUTE overrides
+static int route_default() {
+    const char *e = getenv("RSAI_ROUTE");
     if (e && (e[0] == '0' || e[0] == '1')) return e[0] - '0';
     return 1;
 }
@@ -278,13 +286,14 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
     int64_t big_base = acap;
     if (big) acap += ncols * (int64_t)BQMAX_BIG;
     P->arena_cap = acap;
-    const int nlaunch = plain ? P->p.lmax + 1 : (tlast - t0 + 1 + (big ? 2 : 0));
+    const int nlaunch = plain ? P->p.lmax + 1 : (tlast - t0 + 1 + (big ? 1 + WIDE_LEVELS : 0));
     const int64_t qlast = big ? std::max<int64_t>(kTiers[tlast].QMAX, BQMAX_BIG) : kTiers[tlast].QMAX;
     const int big_blocks = device_cus();
-    const int wide_blocks = device_cus() * wide_blocks_per_cu();
-    // records into the dense class: few columns need it; more than this many end
-    // with RSAI_E_CAP
-    const int64_t wide_rec_cap = std::min<int64_t>(ncols, std::max<int64_t>(4096, ncols / 64));
+    // records out of each sparse-block instance: few columns need the next class;
+    // more than this many end with RSAI_E_CAP
+    int64_t wide_rec_cap[WIDE_LEVELS];
+    wide_rec_cap[0] = std::min<int64_t>(ncols, std::max<int64_t>(4096, ncols / 64));
+    wide_rec_cap[1] = std::min<int64_t>(ncols, std::max<int64_t>(4096, ncols / 256));
 
     // ---- every device buffer of the build, from one allocation
     std::vector<int32_t *> fillpos(count);
@@ -324,7 +333,9 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
         } else {
             for (int t = t0; t < tlast + (big ? 1 : 0); ++t)
                 P->rec[t] = L.take<int32_t>(ncols * (int64_t)kTiers[t].REC);
-            if (big) P->rec[tlast + 1] = L.take<int32_t>(wide_rec_cap * (int64_t)wide_rec_stride());
+            if (big)
+                for (int w = 0; w < WIDE_LEVELS; ++w)
+                    P->rec[tlast + 1 + w] = L.take<int32_t>(wide_rec_cap[w] * (int64_t)wide_rec_stride(w));
         }
         P->big_scratch = big ? L.take<double>((int64_t)big_blocks * big_scratch_stride()) : nullptr;
     };
@@ -416,10 +427,11 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
                 a.rec_in_count = P->rec_count + (L - 1);
                 a.rec_in_cap = ncols;
             }
-            a.rec_out = P->rec[L % 2];
-            a.rec_out_stride = kTiers[t].REC;
-            a.rec_out_count = P->rec_count + L;
-            a.rec_out_cap = ncols;
+            a.nq = 1;
+            a.q_rec[0] = P->rec[L % 2];
+            a.q_stride[0] = kTiers[t].REC;
+            a.q_count[0] = P->rec_count + L;
+            a.q_cap[0] = ncols;
             int64_t want = (L == 0) ? (ncols + gpw - 1) / gpw : (int64_t)cus * 8;
             int waves = (int)std::max<int64_t>(8, std::min<int64_t>(want, (int64_t)cus * 16));
             waves = (waves + 7) / 8 * 8;
@@ -440,13 +452,18 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
                 a.rec_in_count = P->rec_count + (t - t0 - 1);
                 a.rec_in_cap = ncols;
             }
-            if (t < tlast || big) {
-                a.rec_out = P->rec[t];
-                a.rec_out_stride = kTiers[t].REC;
-                a.rec_out_count = P->rec_count + (t - t0);
-                a.rec_out_cap = ncols;
-            } else {
-                a.rec_out = nullptr;
+            // queues of the later classes: queue i feeds class t + 1 + i (the register
+            // tiers, then the sparse-block class); records use the stride its reader expects
+            a.nq = 0;
+            const int nq_max = route_default() ? TierArgs::MAXQ : 1;
+            for (int c = t + 1; c <= tlast + (big ? 1 : 0) && a.nq < nq_max; ++c) {
+                const int i = a.nq++;
+                a.q_rec[i] = P->rec[c - 1];
+                a.q_stride[i] = kTiers[c - 1].REC;
+                a.q_count[i] = P->rec_count + (c - 1 - t0);
+                a.q_cap[i] = ncols;
+                a.q_mmax[i] = c <= tlast ? kTiers[c].MMAX : wide_max_rows(0);
+                a.q_qmax[i] = c <= tlast ? kTiers[c].QMAX : WIDE_QMAX;
             }
             const int gpw = 64 / kTiers[t].G;
             int64_t want = (t == t0) ? (ncols + gpw - 1) / gpw : (int64_t)cus * 2;
@@ -458,37 +475,39 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
         if (big) {
             // columns that outgrew the last register tier: one workgroup per column,
             // first on the compressed block, then (rarely) on the dense block
-            WideArgs w{};
-            w.mats = P->d_mats;
-            w.P = base.P;
-            w.out = P->out;
-            w.arena_base = big_base;
-            w.rec_in = P->rec[tlast];
-            w.rec_in_stride = kTiers[tlast].REC;
-            w.rec_in_count = P->rec_count + (tlast - t0);
-            w.rec_in_cap = ncols;
-            w.rec_out = P->rec[tlast + 1];
-            w.rec_out_stride = wide_rec_stride();
-            w.rec_out_count = P->rec_count + (tlast - t0 + 1);
-            w.rec_out_cap = wide_rec_cap;
-            w.err = P->err;
-            launch_wide_kernel(w, wide_blocks, s);
+            for (int lv = 0; lv < WIDE_LEVELS; ++lv) {
+                WideArgs w{};
+                w.mats = P->d_mats;
+                w.P = base.P;
+                w.out = P->out;
+                w.arena_base = big_base;
+                w.rec_in = P->rec[tlast + lv];
+                w.rec_in_stride = lv == 0 ? kTiers[tlast].REC : wide_rec_stride(lv - 1);
+                w.rec_in_count = P->rec_count + (tlast - t0 + lv);
+                w.rec_in_cap = lv == 0 ? ncols : wide_rec_cap[lv - 1];
+                w.rec_out = P->rec[tlast + 1 + lv];
+                w.rec_out_stride = wide_rec_stride(lv);
+                w.rec_out_count = P->rec_count + (tlast - t0 + 1 + lv);
+                w.rec_out_cap = wide_rec_cap[lv];
+                w.err = P->err;
+                launch_wide_kernel(lv, w, device_cus() * wide_blocks_per_cu(lv), s);
+            }
             BigArgs b{};
             b.mats = P->d_mats;
             b.P = base.P;
             b.out = P->out;
             b.arena_base = big_base;
-            b.rec_in = P->rec[tlast + 1];
-            b.rec_in_stride = wide_rec_stride();
-            b.rec_in_count = P->rec_count + (tlast - t0 + 1);
-            b.rec_in_cap = wide_rec_cap;
+            b.rec_in = P->rec[tlast + WIDE_LEVELS];
+            b.rec_in_stride = wide_rec_stride(WIDE_LEVELS - 1);
+            b.rec_in_count = P->rec_count + (tlast - t0 + WIDE_LEVELS);
+            b.rec_in_cap = wide_rec_cap[WIDE_LEVELS - 1];
             b.scratch = P->big_scratch;
             b.scratch_stride = big_scratch_stride();
             b.err = P->err;
             launch_big_kernel(b, big_blocks, s);
         }
     }
-    P->ntiers_used = tlast - t0 + 1 + (big ? 2 : 0);
+    P->ntiers_used = tlast - t0 + 1 + (big ? 1 + WIDE_LEVELS : 0);
     P->record(3, s);
 
     // ---- assembly of M per matrix: colptr = scan(nJ), then compaction

@@ -19,7 +19,7 @@ void launch_tier_kernel(int tier, const TierArgs &a, int waves, hipStream_t s);
 
 // ---- sparse-block size class (rsai_wide.hip): one workgroup per column, LS solved
 // on the compressed block (shared rows + one row per column)
-constexpr int WIDE_MMAX = 2048;  // rows of I
+constexpr int WIDE_LEVELS = 2;   // instances: |I| <= 2048, |I| <= 8192
 constexpr int WIDE_QMAX = 63;    // columns of J
 constexpr int WIDE_RCAP = 8 * 64 + 1;  // dominant rows in a record: c * lmax + 1
 struct WideArgs {
@@ -37,9 +37,10 @@ struct WideArgs {
     int64_t rec_out_cap;
     int32_t *err;
 };
-int wide_rec_stride();
-void launch_wide_kernel(const WideArgs &a, int blocks, hipStream_t s);
-int wide_blocks_per_cu();
+int wide_max_rows(int level);
+int wide_rec_stride(int level);  // ints per record written by that instance
+int wide_blocks_per_cu(int level);
+void launch_wide_kernel(int level, const WideArgs &a, int blocks, hipStream_t s);
 
 // ---- large size class (rsai_big.hip): one workgroup per column
 constexpr int BMMAX_BIG = 8192;  // rows of the LS block

@@ -64,10 +64,17 @@ struct TierArgs {
     int rec_in_stride;
     const int32_t *rec_in_count;
     int64_t rec_in_cap;
-    int32_t *rec_out;         // spill records for the next tier (nullptr: last tier)
-    int rec_out_stride;
-    int32_t *rec_out_count;
-    int64_t rec_out_cap;
+    // Record queues of the later classes a spilled column may go to (index 0: the
+    // next class). A column goes to the first class whose limits hold the estimated
+    // |I_k| and |J_k| of its next augmentation, else to the last queue; nq = 0 means
+    // no later class (a spill is then a cap error).
+    static constexpr int MAXQ = 4;
+    int nq;
+    int32_t *q_rec[MAXQ];
+    int q_stride[MAXQ];
+    int32_t *q_count[MAXQ];
+    int64_t q_cap[MAXQ];
+    int q_mmax[MAXQ], q_qmax[MAXQ];
     int32_t *err;             // global error flags (bit 0: internal)
     int one_loop;             // 1: park every column after one loop (plain schedule)
     int sync_refill;          // 1: groups take new columns only when the whole wave is idle

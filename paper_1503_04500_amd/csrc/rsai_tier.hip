@@ -188,6 +188,7 @@ __global__ __launch_bounds__(64, RSAI_TIER_WAVES_PER_SIMD) void tier_kernel(Tier
         // ====================================== K. J-hat from pending dominant rows
         // (Algorithm 1, step 5: columns of A(R-hat, :) not in J)
         bool spill = park;          // parked by the plain schedule: hand over as is
+        int est_m = m, est_q = q;   // size estimate of a spilled column (routing)
         const bool parked = park;
         park = false;
         {
@@ -209,6 +210,7 @@ __global__ __launch_bounds__(64, RSAI_TIER_WAVES_PER_SIMD) void tier_kernel(Tier
                 sp[t + 1] = sp[t] + (int)(e0 - b0);
             }
             const int total = doK ? sp[CMAX] : 0;
+            est_m = m;
             if (doK && gl == 0) S.cnt = 0;
             wave_sync();
             bool ovf = false;
@@ -238,7 +240,11 @@ __global__ __launch_bounds__(64, RSAI_TIER_WAVES_PER_SIMD) void tier_kernel(Tier
                     }
                 }
                 wave_sync();
-                if (doK && !ovf && q + S.cnt > QMAX) ovf = true;
+                if (doK && !ovf && q + S.cnt > QMAX) {
+                    // |J-hat| extrapolated from the share of new columns seen so far
+                    ovf = true;
+                    est_q = q + (int)ceilf((float)S.cnt * (float)total / (float)min(base + C::RJN, total));
+                }
                 wave_sync();
             }
             const int nnew = (doK && !ovf) ? S.cnt : 0;
@@ -330,7 +336,12 @@ __global__ __launch_bounds__(64, RSAI_TIER_WAVES_PER_SIMD) void tier_kernel(Tier
                     }
                 }
                 wave_sync();
-                if (doC && !ovf && m + S.cnt > MMAX) ovf = true;
+                if (doC && !ovf && m + S.cnt > MMAX) {
+                    // |I-hat| extrapolated from the share of new rows seen so far
+                    ovf = true;
+                    est_m = m + (int)ceilf((float)S.cnt * (float)total / (float)min(base + C::RIN, total));
+                    est_q = q + p;
+                }
                 wave_sync();
             }
             if (doC && ovf) spill = true;
@@ -376,17 +387,33 @@ __global__ __launch_bounds__(64, RSAI_TIER_WAVES_PER_SIMD) void tier_kernel(Tier
         // ================================================ spill to the next tier
         if (wave_any(spill)) {
             int ps = 0;
-            if (spill && gl == 0) ps = args.rec_out ? atomicAdd(args.rec_out_count, 1) : INT_MAX;
+            // destination class: the first whose limits hold the estimate
+            int d = args.nq - 1;
+#pragma unroll
+            for (int i = TierArgs::MAXQ - 2; i >= 0; --i)
+                if (i < args.nq - 1 && est_m <= args.q_mmax[i] && est_q <= args.q_qmax[i]) d = i;
+            int32_t *qrec = args.q_rec[0];
+            int qstr = args.q_stride[0];
+            int64_t qcap = args.q_cap[0];
+            if (spill && gl == 0) ps = INT_MAX;
+#pragma unroll
+            for (int i = 0; i < TierArgs::MAXQ; ++i) {
+                if (i > 0 && d == i) { qrec = args.q_rec[i]; qstr = args.q_stride[i]; qcap = args.q_cap[i]; }
+                // one counter address per pass, so that the lanes' increments combine
+                const bool mine = spill && gl == 0 && d == i && i < args.nq;
+                if (wave_any(mine) && mine) ps = atomicAdd(args.q_count[i], 1);
+            }
+            if (args.nq <= 0) qrec = nullptr;
             ps = gbcast_i<G>(ps, gl == 0);
             // the plain schedule has one size class: outgrowing it is a cap error
-            const bool ok = spill && args.rec_out != nullptr && (int64_t)ps < args.rec_out_cap &&
+            const bool ok = spill && qrec != nullptr && (int64_t)ps < qcap &&
                             (parked || !args.one_loop);
             int nR = __popc(rflag);
             nR = gsum_i<G>(nR) + (kR ? 1 : 0);
             if (spill && gl == 0) S.cnt = 0;
             wave_sync();
             if (ok) {
-                int32_t *R = args.rec_out + (int64_t)ps * args.rec_out_stride;
+                int32_t *R = qrec + (int64_t)ps * qstr;
                 if (gl == 0) {
                     R[0] = (int32_t)ucol; R[1] = mat; R[2] = k; R[3] = l;
                     R[4] = q; R[5] = m; R[6] = nR; R[7] = nRh;

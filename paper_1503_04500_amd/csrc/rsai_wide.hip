@@ -1,7 +1,7 @@
 // Sparse-block size class of the RSAI(tol) build: one 256-thread workgroup per
 // column, for LS blocks A(I_k, J_k) that outgrow the register tiers but are mostly
 // structurally empty (long sparse columns with few rows in common, as in matrices
-// with power-law column lengths). Up to WIDE_MMAX rows and WIDE_QMAX columns.
+// with power-law column lengths). Up to 8192 rows and WIDE_QMAX columns.
 //
 // The LS problem (2.3) is solved on an orthogonally equivalent compressed block.
 // A row of I_k met by exactly one column j of J_k (a private row of j) adds to
@@ -17,8 +17,8 @@
 // columns of J_k that hold the row and a flag for rows already used as dominant
 // rows; the residual for step 4 is formed from the sparse columns with the columns
 // taken in ascending global order, so exact ties reach the smaller-index rule.
-// Columns arrive as spill records of the last register tier. A column whose |I_k|
-// or compressed block outgrows this class moves on to the dense large class.
+// Columns arrive as spill records of the previous class. A column whose |I_k| or
+// compressed block outgrows this class moves on to the next one.
 #include <climits>
 
 #include "rsai_kernels.h"
@@ -28,19 +28,18 @@ namespace rsai {
 namespace {
 constexpr int NT = 256;                 // threads per column
 constexpr int NW = NT / 64;             // waves
-constexpr int LOGH = 12;                // row hash: 4096 slots for |I| <= 2048
-constexpr int HS = 1 << LOGH;
-constexpr int MM = WIDE_MMAX;
 constexpr int QM = WIDE_QMAX;
 constexpr int LOGHJ = 8;                // column hash: 256 slots
 constexpr int HJ = 1 << LOGHJ;
-constexpr int BLK = 2048;               // compressed block, (S + q) x (q + 1), row-major
-constexpr int SHV = 768;                // values of the shared rows, S x q
-constexpr int SMAX = 128;               // shared rows
-constexpr int WBLOCKS_PER_CU = 3;       // LDS-limited residency
-static_assert(HS >= 2 * MM, "row hash load above one half");
 
+// Two instances: rows of I up to 2048 (4096-slot row hash, three workgroups per CU)
+// and up to 8192 (16384 slots, one workgroup per CU, larger compressed blocks).
+//   BLK  doubles of the compressed block, (S + q) x (q + 1), row-major
+//   SHV  doubles of the shared rows' values, S x q
+//   SMAX shared rows
+template <int LOGH, int BLK, int SHV, int SMAX>
 struct WLds {
+    static constexpr int HS = 1 << LOGH;
     int hk[HS];             // row keys
     unsigned hv[HS / 4];    // one byte per slot: bits 0-6 columns of J holding the row, bit 7 row in R
     int hJ[HJ];             // J as a set
@@ -48,7 +47,6 @@ struct WLds {
     double shv[SHV];
     double s2[64], s2x[64]; // private rows of each column: sum of squares (all / without row k)
     double mt[64], rd[64];  // solution by slot, diagonal of R
-    double racc[SMAX];      // residual of the shared rows
     int64_t cb[64];         // first entry of each column of J
     int clen[64];
     int Jl[64];             // J, slot order
@@ -59,19 +57,22 @@ struct WLds {
     int Rh[CMAX];           // pending dominant rows
     double cva[NW];
     int cvg[NW];
-    double dred[NW];
     double akv;             // a_kj when k is a private row of column slot kcol
     int kcol;
     int cnt, nsh, flag;
     double rn;
 };
 
-__device__ __forceinline__ unsigned hget(const WLds &S, int sl) {
+template <class L>
+__device__ __forceinline__ unsigned hget(const L &S, int sl) {
     return (S.hv[sl >> 2] >> ((sl & 3) * 8)) & 0xFFu;
 }
-__device__ __forceinline__ void hinc(WLds &S, int sl) { atomicAdd(&S.hv[sl >> 2], 1u << ((sl & 3) * 8)); }
-__device__ __forceinline__ void hdec(WLds &S, int sl) { atomicSub(&S.hv[sl >> 2], 1u << ((sl & 3) * 8)); }
-__device__ __forceinline__ void hsetR(WLds &S, int sl) { atomicOr(&S.hv[sl >> 2], 0x80u << ((sl & 3) * 8)); }
+template <class L>
+__device__ __forceinline__ void hinc(L &S, int sl) { atomicAdd(&S.hv[sl >> 2], 1u << ((sl & 3) * 8)); }
+template <class L>
+__device__ __forceinline__ void hdec(L &S, int sl) { atomicSub(&S.hv[sl >> 2], 1u << ((sl & 3) * 8)); }
+template <class L>
+__device__ __forceinline__ void hsetR(L &S, int sl) { atomicOr(&S.hv[sl >> 2], 0x80u << ((sl & 3) * 8)); }
 
 // wave-wide sum; every lane gets the bitwise-same value
 __device__ __forceinline__ double wsum(double x) {
@@ -95,13 +96,51 @@ __device__ __forceinline__ int sfind(const int *srow, int nsh, int row) {
     }
     return -1;
 }
+constexpr int NCW = (64 + NW - 1) / NW;  // columns of J per wave
+
+// Visit every entry of the columns c0 + wid + NW*s (s < NCW, below c1) of J with the
+// lanes of one wave: the first 64 entries of all of the wave's columns are loaded
+// together, then the entries beyond 64 of long columns. f(s, c, row, val) is called
+// with s a compile-time constant after unrolling.
+template <bool VAL, class L, class F>
+__device__ __forceinline__ void wave_cols(const L &S, const MatDev &A, int c0, int c1, int wid, int lane, F &&f) {
+    constexpr int HB = NCW / 2;  // columns per batch of loads
+#pragma unroll
+    for (int h = 0; h < NCW; h += HB) {
+        if (c0 + wid + NW * h >= c1) break;
+        int rr[HB];
+        double vv[HB];
+#pragma unroll
+        for (int s = 0; s < HB; ++s) {
+            const int c = c0 + wid + NW * (h + s);
+            rr[s] = -1;
+            vv[s] = 0.0;
+            if (c < c1 && lane < S.clen[c]) {
+                const int64_t e = S.cb[c] + lane;
+                rr[s] = A.rowidx[e];
+                if (VAL) vv[s] = A.val[e];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < HB; ++s)
+            if (rr[s] >= 0) f(h + s, c0 + wid + NW * (h + s), rr[s], vv[s]);
+    }
+#pragma unroll
+    for (int s = 0; s < NCW; ++s) {
+        const int c = c0 + wid + NW * s;
+        if (c < c1 && S.clen[c] > 64) {
+            const int64_t e0 = S.cb[c];
+            for (int t = 64 + lane; t < S.clen[c]; t += 64) f(s, c, A.rowidx[e0 + t], VAL ? A.val[e0 + t] : 0.0);
+        }
+    }
+}
 }  // namespace
 
-int wide_rec_stride() { return RHDR + 64 + WIDE_MMAX + WIDE_RCAP + CMAX; }
-int wide_blocks_per_cu() { return WBLOCKS_PER_CU; }
-
-__global__ __launch_bounds__(NT) void wide_kernel(WideArgs args) {
-    __shared__ WLds S;
+template <int LOGH, int BLK, int SHV, int SMAX, int WPC>
+__global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
+    constexpr int HS = 1 << LOGH;
+    constexpr int MM = HS / 2;  // row hash load at most one half
+    __shared__ WLds<LOGH, BLK, SHV, SMAX> S;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     if (*args.err & 7) return;
     const BuildParams P = args.P;
@@ -148,13 +187,10 @@ __global__ __launch_bounds__(NT) void wide_kernel(WideArgs args) {
         __syncthreads();
         if (status == ST_OK) {
             // how many columns of J hold each row (every row of a column of J is in I)
-            for (int c = wid; c < q; c += NW) {
-                const int64_t e0 = S.cb[c];
-                for (int t = lane; t < S.clen[c]; t += 64) {
-                    const int sl = hfind<LOGH>(S.hk, A.rowidx[e0 + t]);
-                    if (sl >= 0) hinc(S, sl); else lookup_fail = true;
-                }
-            }
+            wave_cols<false>(S, A, 0, q, wid, lane, [&](int, int, int row, double) {
+                const int sl = hfind<LOGH>(S.hk, row);
+                if (sl >= 0) hinc(S, sl); else lookup_fail = true;
+            });
             for (int t = tid; t < nR0; t += NT) {
                 const int row = RR[t];
                 const int sl = hfind<LOGH>(S.hk, row);
@@ -169,6 +205,11 @@ __global__ __launch_bounds__(NT) void wide_kernel(WideArgs args) {
         bool first = true, need_solve = true, dropok = false;
         int qmod = -1;
         int p = 0;
+        if (rec[10] & 2) {
+            // augmented pattern handed over before its solve
+            dropok = (rec[10] & 4) != 0;
+            qmod = rec[11];
+        }
         if (status == ST_OK && q == 0 && nRh == 0) {
             // a column whose own rows exceed the register tiers: J = {k}, loop 0
             if (tid == 0) {
@@ -244,14 +285,11 @@ __global__ __launch_bounds__(NT) void wide_kernel(WideArgs args) {
                 if (tid == 0) S.cnt = 0;
                 __syncthreads();
                 int added = 0;
-                for (int c = q + wid; c < q + p; c += NW) {
-                    const int64_t e0 = S.cb[c];
-                    for (int t = lane; t < S.clen[c]; t += 64) {
-                        int sl;
-                        if (hinsert<LOGH>(S.hk, A.rowidx[e0 + t], sl)) ++added;
-                        if (sl >= 0) hinc(S, sl); else lookup_fail = true;
-                    }
-                }
+                wave_cols<false>(S, A, q, q + p, wid, lane, [&](int, int, int row, double) {
+                    int sl;
+                    if (hinsert<LOGH>(S.hk, row, sl)) ++added;
+                    if (sl >= 0) hinc(S, sl); else lookup_fail = true;
+                });
                 if (added) atomicAdd(&S.cnt, added);
                 __syncthreads();
                 m += S.cnt;
@@ -303,18 +341,16 @@ __global__ __launch_bounds__(NT) void wide_kernel(WideArgs args) {
                 for (int t = tid; t < nsh * q; t += NT) S.shv[t] = 0.0;
                 __syncthreads();
                 // ---- gather: shared entries into the block, private rows into column sums
-                for (int c = wid; c < q; c += NW) {
-                    const int64_t e0 = S.cb[c];
-                    double a2 = 0.0, a2x = 0.0;
-                    for (int t = lane; t < S.clen[c]; t += 64) {
-                        const int row = A.rowidx[e0 + t];
-                        const double v = A.val[e0 + t];
+                {
+                    double a2[NCW];
+#pragma unroll
+                    for (int t = 0; t < NCW; ++t) a2[t] = 0.0;
+                    wave_cols<true>(S, A, 0, q, wid, lane, [&](int sI, int c, int row, double v) {
                         const int sl = hfind<LOGH>(S.hk, row);
                         const unsigned cn = sl >= 0 ? (hget(S, sl) & 0x7Fu) : 0u;
                         if (cn == 1u) {
-                            a2 += v * v;
-                            if (row != k) a2x += v * v;
-                            else { S.kcol = c; S.akv = v; }
+                            a2[sI] += v * v;
+                            if (row == k) { S.kcol = c; S.akv = v; }
                         } else if (cn >= 2u) {
                             const int si = sfind(S.srow, nsh, row);
                             if (si >= 0) {
@@ -326,10 +362,30 @@ __global__ __launch_bounds__(NT) void wide_kernel(WideArgs args) {
                         } else {
                             lookup_fail = true;
                         }
+                    });
+#pragma unroll
+                    for (int t = 0; t < NCW; ++t) {
+                        const int c = wid + NW * t;
+                        if (c < q) {
+                            const double x = wsum(a2[t]);
+                            if (lane == 0) S.s2[c] = x;
+                        }
                     }
-                    a2 = wsum(a2);
-                    a2x = wsum(a2x);
-                    if (lane == 0) { S.s2[c] = a2; S.s2x[c] = a2x; }
+                }
+                __syncthreads();
+                // the column holding row k as a private row: its private sum without row k
+                if (S.kcol >= 0 && wid == (S.kcol % NW)) {
+                    const int c = S.kcol;
+                    const int64_t e0 = S.cb[c];
+                    double x = 0.0;
+                    for (int t = lane; t < S.clen[c]; t += 64) {
+                        const int row = A.rowidx[e0 + t];
+                        const double v = A.val[e0 + t];
+                        const int sl = hfind<LOGH>(S.hk, row);
+                        if (row != k && sl >= 0 && (hget(S, sl) & 0x7Fu) == 1u) x += v * v;
+                    }
+                    x = wsum(x);
+                    if (lane == 0) S.s2x[c] = x;
                 }
                 __syncthreads();
                 // ---- the row of row k: shared (right-hand side 1), private (compressed), or
@@ -375,10 +431,33 @@ __global__ __launch_bounds__(NT) void wide_kernel(WideArgs args) {
                         }
                         wave_sync();
                         if (lane > j && lane <= q) {
-                            double w = 0.0;
-                            for (int i = j; i < mp; ++i) w += S.blk[i * ld + j] * S.blk[i * ld + lane];
-                            w *= be;
-                            for (int i = j; i < mp; ++i) S.blk[i * ld + lane] -= w * S.blk[i * ld + j];
+                            // four independent partial sums, loads grouped ahead of use
+                            double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
+                            int i = j;
+                            for (; i + 3 < mp; i += 4) {
+                                const double v0 = S.blk[i * ld + j], v1 = S.blk[(i + 1) * ld + j];
+                                const double v2 = S.blk[(i + 2) * ld + j], v3 = S.blk[(i + 3) * ld + j];
+                                const double b0 = S.blk[i * ld + lane], b1 = S.blk[(i + 1) * ld + lane];
+                                const double b2 = S.blk[(i + 2) * ld + lane], b3 = S.blk[(i + 3) * ld + lane];
+                                w0 += v0 * b0;
+                                w1 += v1 * b1;
+                                w2 += v2 * b2;
+                                w3 += v3 * b3;
+                            }
+                            for (; i < mp; ++i) w0 += S.blk[i * ld + j] * S.blk[i * ld + lane];
+                            const double w = ((w0 + w1) + (w2 + w3)) * be;
+                            i = j;
+                            for (; i + 3 < mp; i += 4) {
+                                const double v0 = S.blk[i * ld + j], v1 = S.blk[(i + 1) * ld + j];
+                                const double v2 = S.blk[(i + 2) * ld + j], v3 = S.blk[(i + 3) * ld + j];
+                                const double b0 = S.blk[i * ld + lane], b1 = S.blk[(i + 1) * ld + lane];
+                                const double b2 = S.blk[(i + 2) * ld + lane], b3 = S.blk[(i + 3) * ld + lane];
+                                S.blk[i * ld + lane] = b0 - w * v0;
+                                S.blk[(i + 1) * ld + lane] = b1 - w * v1;
+                                S.blk[(i + 2) * ld + lane] = b2 - w * v2;
+                                S.blk[(i + 3) * ld + lane] = b3 - w * v3;
+                            }
+                            for (; i < mp; ++i) S.blk[i * ld + lane] -= w * S.blk[i * ld + j];
                         }
                         wave_sync();
                     }
@@ -417,15 +496,12 @@ __global__ __launch_bounds__(NT) void wide_kernel(WideArgs args) {
                     }
                     if (nk < q) {
                         // rows of the dropped columns lose one holder
-                        for (int c = wid; c < q; c += NW) {
+                        wave_cols<false>(S, A, 0, q, wid, lane, [&](int, int c, int row, double) {
                             const bool keep = (nk == 0) ? (c == bc) : (fabs(S.mt[c]) > th);
-                            if (keep) continue;
-                            const int64_t e0 = S.cb[c];
-                            for (int t = lane; t < S.clen[c]; t += 64) {
-                                const int sl = hfind<LOGH>(S.hk, A.rowidx[e0 + t]);
-                                if (sl >= 0) hdec(S, sl); else lookup_fail = true;
-                            }
-                        }
+                            if (keep) return;
+                            const int sl = hfind<LOGH>(S.hk, row);
+                            if (sl >= 0) hdec(S, sl); else lookup_fail = true;
+                        });
                         __syncthreads();
                         if (tid == 0) {
                             int w = 0;
@@ -500,19 +576,14 @@ __global__ __launch_bounds__(NT) void wide_kernel(WideArgs args) {
                 if (ri != 0.0 && sl >= 0 && !(hget(S, sl) & 0x80u)) offer(fabs(ri), row);
             }
             // private rows: one product each
-            for (int c = wid; c < q; c += NW) {
-                const int64_t e0 = S.cb[c];
-                const double mc = S.mt[c];
-                for (int t = lane; t < S.clen[c]; t += 64) {
-                    const int row = A.rowidx[e0 + t];
-                    const int sl = hfind<LOGH>(S.hk, row);
-                    const unsigned hvv = sl >= 0 ? hget(S, sl) : 0u;
-                    if ((hvv & 0x7Fu) == 1u && !(hvv & 0x80u)) {
-                        const double ri = __fma_rn(A.val[e0 + t], mc, 0.0) - ((row == k) ? 1.0 : 0.0);
-                        if (ri != 0.0) offer(fabs(ri), row);
-                    }
+            wave_cols<true>(S, A, 0, q, wid, lane, [&](int, int c, int row, double v) {
+                const int sl = hfind<LOGH>(S.hk, row);
+                const unsigned hvv = sl >= 0 ? hget(S, sl) : 0u;
+                if ((hvv & 0x7Fu) == 1u && !(hvv & 0x80u)) {
+                    const double ri = __fma_rn(v, S.mt[c], 0.0) - ((row == k) ? 1.0 : 0.0);
+                    if (ri != 0.0) offer(fabs(ri), row);
                 }
-            }
+            });
             // row k outside the columns of J: r(k) = -1
             if (tid == 0) {
                 const int ksl = hfind<LOGH>(S.hk, k);
@@ -635,8 +706,22 @@ __global__ __launch_bounds__(NT) void wide_kernel(WideArgs args) {
     }
 }
 
-void launch_wide_kernel(const WideArgs &a, int blocks, hipStream_t s) {
-    hipLaunchKernelGGL(wide_kernel, dim3(blocks), dim3(NT), 0, s, a);
+namespace {
+constexpr int kWideLogH[2] = {12, 14};
+constexpr int kWidePerCU[2] = {3, 1};
+#define RSAI_WIDE0 kWideLogH[0], 2048, 768, 128, kWidePerCU[0]
+#define RSAI_WIDE1 kWideLogH[1], 6144, 1536, 256, kWidePerCU[1]
+}  // namespace
+
+int wide_max_rows(int level) { return (1 << kWideLogH[level]) / 2; }
+int wide_rec_stride(int level) { return RHDR + 64 + wide_max_rows(level) + WIDE_RCAP + CMAX; }
+int wide_blocks_per_cu(int level) { return kWidePerCU[level]; }
+
+void launch_wide_kernel(int level, const WideArgs &a, int blocks, hipStream_t s) {
+    if (level == 0)
+        hipLaunchKernelGGL((wide_kernel<RSAI_WIDE0>), dim3(blocks), dim3(NT), 0, s, a);
+    else
+        hipLaunchKernelGGL((wide_kernel<RSAI_WIDE1>), dim3(blocks), dim3(NT), 0, s, a);
 }
 
 }  // namespace rsai
