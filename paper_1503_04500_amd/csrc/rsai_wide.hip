@@ -45,7 +45,7 @@ struct WLds {
     int hJ[HJ];             // J as a set
     double blk[BLK];
     double shv[SHV];
-    double s2[64], s2x[64]; // private rows of each column: sum of squares (all / without row k)
+    double s2[64];          // private rows of each column: sum of squares
     double mt[64], rd[64];  // solution by slot, diagonal of R
     int64_t cb[64];         // first entry of each column of J
     int clen[64];
@@ -82,6 +82,13 @@ __device__ __forceinline__ double wsum(double x) {
     return x;
 }
 
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 // (a desc, g asc) order of dominant-row candidates
 __device__ __forceinline__ bool better(double a, int g, double b, int h) { return a > b || (a == b && g < h); }
 
@@ -96,23 +103,20 @@ __device__ __forceinline__ int sfind(const int *srow, int nsh, int row) {
     }
     return -1;
 }
-constexpr int NCW = (64 + NW - 1) / NW;  // columns of J per wave
-
-// Visit every entry of the columns c0 + wid + NW*s (s < NCW, below c1) of J with the
-// lanes of one wave: the first 64 entries of all of the wave's columns are loaded
-// together, then the entries beyond 64 of long columns. f(s, c, row, val) is called
-// with s a compile-time constant after unrolling.
-template <bool VAL, class L, class F>
-__device__ __forceinline__ void wave_cols(const L &S, const MatDev &A, int c0, int c1, int wid, int lane, F &&f) {
-    constexpr int HB = NCW / 2;  // columns per batch of loads
-#pragma unroll
-    for (int h = 0; h < NCW; h += HB) {
-        if (c0 + wid + NW * h >= c1) break;
+// Visit every entry of the columns c0 + wid + NW*s (below c1) of J with the lanes of
+// one wave, one column after another: f(c, row, val) for each entry, then done(c).
+// The first 64 entries of the next HB columns are loaded together ahead of use; the
+// loop over columns stays rolled to keep the code small.
+template <bool VAL, class L, class F, class D>
+__device__ __forceinline__ void wave_cols(const L &S, const MatDev &A, int c0, int c1, int wid, int lane, F &&f,
+                                          D &&done) {
+    constexpr int HB = 8;
+    for (int cb0 = c0 + wid; cb0 < c1; cb0 += NW * HB) {
         int rr[HB];
         double vv[HB];
 #pragma unroll
         for (int s = 0; s < HB; ++s) {
-            const int c = c0 + wid + NW * (h + s);
+            const int c = cb0 + NW * s;
             rr[s] = -1;
             vv[s] = 0.0;
             if (c < c1 && lane < S.clen[c]) {
@@ -121,16 +125,24 @@ __device__ __forceinline__ void wave_cols(const L &S, const MatDev &A, int c0, i
                 if (VAL) vv[s] = A.val[e];
             }
         }
+#pragma unroll 1
+        for (int s = 0; s < HB; ++s) {
+            const int c = cb0 + NW * s;
+            if (c >= c1) break;
+            const int r0 = rr[0];
+            const double v0 = vv[0];
 #pragma unroll
-        for (int s = 0; s < HB; ++s)
-            if (rr[s] >= 0) f(h + s, c0 + wid + NW * (h + s), rr[s], vv[s]);
-    }
-#pragma unroll
-    for (int s = 0; s < NCW; ++s) {
-        const int c = c0 + wid + NW * s;
-        if (c < c1 && S.clen[c] > 64) {
-            const int64_t e0 = S.cb[c];
-            for (int t = 64 + lane; t < S.clen[c]; t += 64) f(s, c, A.rowidx[e0 + t], VAL ? A.val[e0 + t] : 0.0);
+            for (int t = 0; t < HB - 1; ++t) {
+                rr[t] = rr[t + 1];
+                vv[t] = vv[t + 1];
+            }
+            if (r0 >= 0) f(c, r0, v0);
+            const int len = S.clen[c];
+            if (len > 64) {
+                const int64_t e0 = S.cb[c];
+                for (int t = 64 + lane; t < len; t += 64) f(c, A.rowidx[e0 + t], VAL ? A.val[e0 + t] : 0.0);
+            }
+            done(c);
         }
     }
 }
@@ -187,10 +199,13 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
         __syncthreads();
         if (status == ST_OK) {
             // how many columns of J hold each row (every row of a column of J is in I)
-            wave_cols<false>(S, A, 0, q, wid, lane, [&](int, int, int row, double) {
-                const int sl = hfind<LOGH>(S.hk, row);
-                if (sl >= 0) hinc(S, sl); else lookup_fail = true;
-            });
+            wave_cols<false>(
+                S, A, 0, q, wid, lane,
+                [&](int, int row, double) {
+                    const int sl = hfind<LOGH>(S.hk, row);
+                    if (sl >= 0) hinc(S, sl); else lookup_fail = true;
+                },
+                [](int) {});
             for (int t = tid; t < nR0; t += NT) {
                 const int row = RR[t];
                 const int sl = hfind<LOGH>(S.hk, row);
@@ -285,11 +300,14 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
                 if (tid == 0) S.cnt = 0;
                 __syncthreads();
                 int added = 0;
-                wave_cols<false>(S, A, q, q + p, wid, lane, [&](int, int, int row, double) {
-                    int sl;
-                    if (hinsert<LOGH>(S.hk, row, sl)) ++added;
-                    if (sl >= 0) hinc(S, sl); else lookup_fail = true;
-                });
+                wave_cols<false>(
+                    S, A, q, q + p, wid, lane,
+                    [&](int, int row, double) {
+                        int sl;
+                        if (hinsert<LOGH>(S.hk, row, sl)) ++added;
+                        if (sl >= 0) hinc(S, sl); else lookup_fail = true;
+                    },
+                    [](int) {});
                 if (added) atomicAdd(&S.cnt, added);
                 __syncthreads();
                 m += S.cnt;
@@ -342,139 +360,184 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
                 __syncthreads();
                 // ---- gather: shared entries into the block, private rows into column sums
                 {
-                    double a2[NCW];
-#pragma unroll
-                    for (int t = 0; t < NCW; ++t) a2[t] = 0.0;
-                    wave_cols<true>(S, A, 0, q, wid, lane, [&](int sI, int c, int row, double v) {
-                        const int sl = hfind<LOGH>(S.hk, row);
-                        const unsigned cn = sl >= 0 ? (hget(S, sl) & 0x7Fu) : 0u;
-                        if (cn == 1u) {
-                            a2[sI] += v * v;
-                            if (row == k) { S.kcol = c; S.akv = v; }
-                        } else if (cn >= 2u) {
-                            const int si = sfind(S.srow, nsh, row);
-                            if (si >= 0) {
-                                S.blk[si * ld + c] = v;
-                                S.shv[si * q + c] = v;
+                    double a2 = 0.0;  // private rows of the current column: sum of squares
+                    wave_cols<true>(
+                        S, A, 0, q, wid, lane,
+                        [&](int c, int row, double v) {
+                            const int sl = hfind<LOGH>(S.hk, row);
+                            const unsigned cn = sl >= 0 ? (hget(S, sl) & 0x7Fu) : 0u;
+                            if (cn == 1u) {
+                                a2 += v * v;
+                                if (row == k) { S.kcol = c; S.akv = v; }
+                            } else if (cn >= 2u) {
+                                const int si = sfind(S.srow, nsh, row);
+                                if (si >= 0) {
+                                    S.blk[(q + si) * ld + c] = v;
+                                    S.shv[si * q + c] = v;
+                                } else {
+                                    lookup_fail = true;
+                                }
                             } else {
                                 lookup_fail = true;
                             }
-                        } else {
-                            lookup_fail = true;
-                        }
-                    });
-#pragma unroll
-                    for (int t = 0; t < NCW; ++t) {
-                        const int c = wid + NW * t;
-                        if (c < q) {
-                            const double x = wsum(a2[t]);
+                        },
+                        [&](int c) {
+                            const double x = wsum(a2);
                             if (lane == 0) S.s2[c] = x;
-                        }
-                    }
-                }
-                __syncthreads();
-                // the column holding row k as a private row: its private sum without row k
-                if (S.kcol >= 0 && wid == (S.kcol % NW)) {
-                    const int c = S.kcol;
-                    const int64_t e0 = S.cb[c];
-                    double x = 0.0;
-                    for (int t = lane; t < S.clen[c]; t += 64) {
-                        const int row = A.rowidx[e0 + t];
-                        const double v = A.val[e0 + t];
-                        const int sl = hfind<LOGH>(S.hk, row);
-                        if (row != k && sl >= 0 && (hget(S, sl) & 0x7Fu) == 1u) x += v * v;
-                    }
-                    x = wsum(x);
-                    if (lane == 0) S.s2x[c] = x;
+                            a2 = 0.0;
+                        });
                 }
                 __syncthreads();
                 // ---- the row of row k: shared (right-hand side 1), private (compressed), or
-                // outside the pattern (a constant 1 in ||r||^2)
+                // outside the pattern (a constant 1 in ||r||^2). Private in column j: the
+                // collapsed row carries beta = a_kj / s_j and ||r||^2 gains 1 - beta^2.
                 const int ksl = hfind<LOGH>(S.hk, k);
                 const int kcn = ksl >= 0 ? (int)(hget(S, ksl) & 0x7Fu) : -1;
-                double kconst = 0.0;
-                if (kcn <= 0) kconst = 1.0;
+                double kconst = (kcn <= 0) ? 1.0 : 0.0;
                 if (kcn == 1 && S.kcol >= 0) {
-                    const double s2k = S.s2[S.kcol];
-                    kconst = s2k > 0.0 ? S.s2x[S.kcol] / s2k : 1.0;
+                    const double sk = sqrt(S.s2[S.kcol]);
+                    const double bk = sk > 0.0 ? S.akv / sk : 0.0;
+                    kconst = fmax(0.0, 1.0 - bk * bk);
                 }
+                // rows 0..q-1: the collapsed private rows (diagonal), rows q..q+S-1: shared
                 if (tid < q) {
                     const double sj = sqrt(S.s2[tid]);
-                    S.blk[(nsh + tid) * ld + tid] = sj;
-                    if (kcn == 1 && S.kcol == tid && sj > 0.0) S.blk[(nsh + tid) * ld + q] = S.akv / sj;
+                    S.blk[tid * ld + tid] = sj;
+                    if (kcn == 1 && S.kcol == tid && sj > 0.0) S.blk[tid * ld + q] = S.akv / sj;
                 }
                 if (kcn >= 2 && tid == 0) {
                     const int si = sfind(S.srow, nsh, k);
-                    if (si >= 0) S.blk[si * ld + q] = 1.0;
+                    if (si >= 0) S.blk[(q + si) * ld + q] = 1.0;
                 }
                 __syncthreads();
                 // ---- Householder QR of the compressed block and Q^T e (wave 0: lane c
-                // holds column c, lane q the right-hand side), back substitution
+                // holds column c, lane q the right-hand side). Column j has nonzeros only
+                // in row j and the shared rows (the reflectors of earlier columns touch
+                // exactly those rows), so each reflector has 1 + S entries.
                 if (wid == 0) {
                     bool singular = false;
-                    for (int j = 0; j < q; ++j) {
-                        double s = 0.0;
-                        for (int i = j + lane; i < mp; i += 64) {
-                            const double x = S.blk[i * ld + j];
-                            s += x * x;
+                    constexpr int SU = 8;
+                    if (nsh <= SU) {
+                        // Few shared rows: lane c keeps the shared-row entries of column c in
+                        // registers; the reflector of step j is read from lane j. Row j of
+                        // column c > j is zero before step j, except the right-hand side of
+                        // the collapsed row of the column where k is private.
+                        double b[SU];
+#pragma unroll
+                        for (int t = 0; t < SU; ++t) b[t] = (lane <= q && t < nsh) ? S.blk[(q + t) * ld + lane] : 0.0;
+                        const double sjl = (lane < q) ? S.blk[lane * ld + lane] : 0.0;
+                        const int kc = (kcn == 1) ? S.kcol : -1;
+                        const double rk = (kc >= 0) ? S.blk[kc * ld + q] : 0.0;
+                        for (int j = 0; j < q; ++j) {
+                            double u[SU];
+#pragma unroll
+                            for (int t = 0; t < SU; ++t) u[t] = readlane_f64(b[t], j);
+                            const double x0 = readlane_f64(sjl, j);
+                            double s0 = x0 * x0, s1 = 0.0;
+#pragma unroll
+                            for (int t = 0; t < SU; t += 2) {
+                                s0 += u[t] * u[t];
+                                s1 += u[t + 1] * u[t + 1];
+                            }
+                            const double nx = sqrt(s0 + s1);
+                            const double alpha = (x0 >= 0.0) ? -nx : nx;
+                            const double be = (nx > 0.0) ? 1.0 / (nx * (nx + fabs(x0))) : 0.0;
+                            const double v0 = x0 - alpha;
+                            if (!(nx > 0.0)) singular = true;
+                            if (lane > j && lane <= q) {
+                                const double bj = (lane == q && j == kc) ? rk : 0.0;
+                                double w0 = v0 * bj, w1 = 0.0;
+#pragma unroll
+                                for (int t = 0; t < SU; t += 2) {
+                                    w0 += u[t] * b[t];
+                                    w1 += u[t + 1] * b[t + 1];
+                                }
+                                const double w = (w0 + w1) * be;
+                                S.blk[j * ld + lane] = bj - w * v0;
+#pragma unroll
+                                for (int t = 0; t < SU; ++t) b[t] -= w * u[t];
+                            }
+                            if (lane == 0) S.rd[j] = alpha;
                         }
-                        s = wsum(s);
+                        // the right-hand side left in the shared rows (lane q)
+                        double r2 = 0.0;
+#pragma unroll
+                        for (int t = 0; t < SU; ++t) r2 += b[t] * b[t];
+                        r2 = readlane_f64(r2, q);
+                        if (lane == 0) S.rn = sqrt(r2 + kconst);
+                    } else {
+                    for (int j = 0; j < q; ++j) {
+                        // the reflector's entries (row j and the first shared rows) and this
+                        // lane's column, loaded together
+                        double u[SU], b[SU];
+                        const bool act = lane > j && lane <= q;
                         const double x0 = S.blk[j * ld + j];
+                        const double bj = act ? S.blk[j * ld + lane] : 0.0;
+#pragma unroll
+                        for (int t = 0; t < SU; ++t) {
+                            u[t] = (t < nsh) ? S.blk[(q + t) * ld + j] : 0.0;
+                            b[t] = (act && t < nsh) ? S.blk[(q + t) * ld + lane] : 0.0;
+                        }
+                        double s0 = x0 * x0, s1 = 0.0;
+#pragma unroll
+                        for (int t = 0; t < SU; t += 2) {
+                            s0 += u[t] * u[t];
+                            s1 += u[t + 1] * u[t + 1];
+                        }
+                        double s = s0 + s1;
+                        if (nsh > SU) {
+                            double r = 0.0;
+                            for (int t = SU + lane; t < nsh; t += 64) {
+                                const double x = S.blk[(q + t) * ld + j];
+                                r += x * x;
+                            }
+                            s += wsum(r);
+                        }
                         const double nx = sqrt(s);
                         const double alpha = (x0 >= 0.0) ? -nx : nx;
                         const double be = (nx > 0.0) ? 1.0 / (nx * (nx + fabs(x0))) : 0.0;
+                        const double v0 = x0 - alpha;
                         if (!(nx > 0.0)) singular = true;
-                        wave_sync();
-                        if (lane == 0) {
-                            S.blk[j * ld + j] = x0 - alpha;
-                            S.rd[j] = alpha;
-                        }
-                        wave_sync();
-                        if (lane > j && lane <= q) {
-                            // four independent partial sums, loads grouped ahead of use
-                            double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
-                            int i = j;
-                            for (; i + 3 < mp; i += 4) {
-                                const double v0 = S.blk[i * ld + j], v1 = S.blk[(i + 1) * ld + j];
-                                const double v2 = S.blk[(i + 2) * ld + j], v3 = S.blk[(i + 3) * ld + j];
-                                const double b0 = S.blk[i * ld + lane], b1 = S.blk[(i + 1) * ld + lane];
-                                const double b2 = S.blk[(i + 2) * ld + lane], b3 = S.blk[(i + 3) * ld + lane];
-                                w0 += v0 * b0;
-                                w1 += v1 * b1;
-                                w2 += v2 * b2;
-                                w3 += v3 * b3;
+                        if (act) {
+                            double w0 = v0 * bj, w1 = 0.0;
+#pragma unroll
+                            for (int t = 0; t < SU; t += 2) {
+                                w0 += u[t] * b[t];
+                                w1 += u[t + 1] * b[t + 1];
                             }
-                            for (; i < mp; ++i) w0 += S.blk[i * ld + j] * S.blk[i * ld + lane];
-                            const double w = ((w0 + w1) + (w2 + w3)) * be;
-                            i = j;
-                            for (; i + 3 < mp; i += 4) {
-                                const double v0 = S.blk[i * ld + j], v1 = S.blk[(i + 1) * ld + j];
-                                const double v2 = S.blk[(i + 2) * ld + j], v3 = S.blk[(i + 3) * ld + j];
-                                const double b0 = S.blk[i * ld + lane], b1 = S.blk[(i + 1) * ld + lane];
-                                const double b2 = S.blk[(i + 2) * ld + lane], b3 = S.blk[(i + 3) * ld + lane];
-                                S.blk[i * ld + lane] = b0 - w * v0;
-                                S.blk[(i + 1) * ld + lane] = b1 - w * v1;
-                                S.blk[(i + 2) * ld + lane] = b2 - w * v2;
-                                S.blk[(i + 3) * ld + lane] = b3 - w * v3;
-                            }
-                            for (; i < mp; ++i) S.blk[i * ld + lane] -= w * S.blk[i * ld + j];
+                            for (int t = SU; t < nsh; ++t) w0 += S.blk[(q + t) * ld + j] * S.blk[(q + t) * ld + lane];
+                            const double w = (w0 + w1) * be;
+                            S.blk[j * ld + lane] = bj - w * v0;
+#pragma unroll
+                            for (int t = 0; t < SU; ++t)
+                                if (t < nsh) S.blk[(q + t) * ld + lane] = b[t] - w * u[t];
+                            for (int t = SU; t < nsh; ++t) S.blk[(q + t) * ld + lane] -= w * S.blk[(q + t) * ld + j];
                         }
+                        if (lane == 0) S.rd[j] = alpha;
                         wave_sync();
                     }
+                    // the right-hand side left in the shared rows
+                    double r2 = 0.0;
+                    for (int t = lane; t < nsh; t += 64) {
+                        const double x = S.blk[(q + t) * ld + q];
+                        r2 += x * x;
+                    }
+                    r2 = wsum(r2);
+                    if (lane == 0) S.rn = sqrt(r2 + kconst);
+                    }
+                    wave_sync();
                     if (!singular) {
+                        // back substitution: lane i holds (Q^T e)_i; m_j broadcast by readlane
                         double y = (lane < q) ? S.blk[lane * ld + q] : 0.0;
                         for (int j = q - 1; j >= 0; --j) {
-                            const double mj = __shfl(y, j) / S.rd[j];
+                            const long long yb = __double_as_longlong(y);
+                            const int lo = __builtin_amdgcn_readlane((int)(yb & 0xffffffffLL), j);
+                            const int hi = __builtin_amdgcn_readlane((int)(yb >> 32), j);
+                            const double yj = __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+                            const double mj = yj / S.rd[j];
                             if (lane == 0) S.mt[j] = mj;
                             if (lane < j) y -= S.blk[lane * ld + j] * mj;
                         }
-                        double s = 0.0;
-                        for (int i = q + lane; i < mp; i += 64) {
-                            const double x = S.blk[i * ld + q];
-                            s += x * x;
-                        }
-                        s = wsum(s);
-                        if (lane == 0) S.rn = sqrt(s + kconst);
                     } else if (lane == 0) {
                         S.flag = 1;
                     }
@@ -496,12 +559,15 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
                     }
                     if (nk < q) {
                         // rows of the dropped columns lose one holder
-                        wave_cols<false>(S, A, 0, q, wid, lane, [&](int, int c, int row, double) {
-                            const bool keep = (nk == 0) ? (c == bc) : (fabs(S.mt[c]) > th);
-                            if (keep) return;
-                            const int sl = hfind<LOGH>(S.hk, row);
-                            if (sl >= 0) hdec(S, sl); else lookup_fail = true;
-                        });
+                        wave_cols<false>(
+                            S, A, 0, q, wid, lane,
+                            [&](int c, int row, double) {
+                                const bool keep = (nk == 0) ? (c == bc) : (fabs(S.mt[c]) > th);
+                                if (keep) return;
+                                const int sl = hfind<LOGH>(S.hk, row);
+                                if (sl >= 0) hdec(S, sl); else lookup_fail = true;
+                            },
+                            [](int) {});
                         __syncthreads();
                         if (tid == 0) {
                             int w = 0;
@@ -576,14 +642,17 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
                 if (ri != 0.0 && sl >= 0 && !(hget(S, sl) & 0x80u)) offer(fabs(ri), row);
             }
             // private rows: one product each
-            wave_cols<true>(S, A, 0, q, wid, lane, [&](int, int c, int row, double v) {
-                const int sl = hfind<LOGH>(S.hk, row);
-                const unsigned hvv = sl >= 0 ? hget(S, sl) : 0u;
-                if ((hvv & 0x7Fu) == 1u && !(hvv & 0x80u)) {
-                    const double ri = __fma_rn(v, S.mt[c], 0.0) - ((row == k) ? 1.0 : 0.0);
-                    if (ri != 0.0) offer(fabs(ri), row);
-                }
-            });
+            wave_cols<true>(
+                S, A, 0, q, wid, lane,
+                [&](int c, int row, double v) {
+                    const int sl = hfind<LOGH>(S.hk, row);
+                    const unsigned hvv = sl >= 0 ? hget(S, sl) : 0u;
+                    if ((hvv & 0x7Fu) == 1u && !(hvv & 0x80u)) {
+                        const double ri = __fma_rn(v, S.mt[c], 0.0) - ((row == k) ? 1.0 : 0.0);
+                        if (ri != 0.0) offer(fabs(ri), row);
+                    }
+                },
+                [](int) {});
             // row k outside the columns of J: r(k) = -1
             if (tid == 0) {
                 const int ksl = hfind<LOGH>(S.hk, k);
