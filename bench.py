@@ -36,14 +36,17 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--grid", type=int, default=512)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the power-law (n = 10^6), 64-matrix batch and 3D fwd+bwd legs")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many batched builds (for rocprofv3), print nothing else")
     return ap.parse_args()
 
 
-def time_builds(rsai, A, sched, steps, warmup, torch):
+def time_builds(rsai, A, sched, steps, warmup, torch, prm=None):
+    prm = PARAMS if prm is None else prm
     for _ in range(warmup):
-        p = rsai.build(A, sched=sched, **PARAMS)
+        p = rsai.build(A, sched=sched, **prm)
         p.nnz()
         p.close()
     torch.cuda.synchronize()
@@ -52,7 +55,7 @@ def time_builds(rsai, A, sched, steps, warmup, torch):
     for _ in range(steps):
         if plan is not None:
             plan.close()
-        plan = rsai.build(A, sched=sched, **PARAMS)
+        plan = rsai.build(A, sched=sched, **prm)
         plan.nnz()
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
@@ -131,6 +134,55 @@ def main():
             fb.append(time.perf_counter() - t0)
     fwd_bwd_ms = float(np.median(fb)) * 1e3
 
+    # ---- further workloads (reported beside the value): power-law n = 10^6, the
+    # 64-matrix batch in one build, fwd+bwd on the 64^3 3D matrix
+    extra = None
+    if not args.no_extra:
+        extra = {}
+        P3 = dict(PARAMS, lmax=10)
+        H3 = gen.c3()
+        A3 = rsai.Matrix.from_host(H3, "cuda:0")
+        dt3 = time_builds(rsai, A3, "batched", 3, 1, torch, prm=P3)
+        extra["powerlaw_1e6"] = {"value": H3.n / dt3, "unit": "columns/s", "ms_per_step": dt3 * 1e3,
+                                 "workload": "power-law columns (min 2, mean 7, max 200), n=10^6, seed 0; "
+                                             "c=3 lmax=10 eps=0.4 tol=1e-3"}
+        del A3, H3
+        specs = gen.batch64_specs()
+        H5 = [gen.make(sp) for sp in specs]
+        A5 = [rsai.Matrix.from_host(h, "cuda:0") for h in H5]
+        n5 = sum(h.n for h in H5)
+        for _ in range(1):
+            p5 = rsai.build_batched(A5, **PARAMS)
+            p5.nnz()
+            p5.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            p5 = rsai.build_batched(A5, **PARAMS)
+            p5.nnz()
+            p5.close()
+        torch.cuda.synchronize()
+        dt5 = (time.perf_counter() - t0) / 3
+        extra["batch64"] = {"value": n5 / dt5, "unit": "columns/s", "ms_per_step": dt5 * 1e3,
+                            "workload": f"64 matrices in one build (2D/3D convection-diffusion, power-law; "
+                                        f"sum n = {n5})"}
+        del A5, H5
+        H4 = gen.c4()
+        A4 = rsai.Matrix.from_host(H4, "cuda:0")
+        b4 = torch.from_numpy(np.random.default_rng(0).standard_normal(H4.n)).to("cuda:0")
+        fb4 = []
+        for it in range(4):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            val = A4.val.clone().requires_grad_(True)
+            L = ag.rsai_loss(A4, val, b4, **PARAMS)
+            L.backward()
+            torch.cuda.synchronize()
+            if it > 0:
+                fb4.append(time.perf_counter() - t0)
+        extra["fwd_bwd_cd3d64_ms"] = float(np.median(fb4)) * 1e3
+        del A4, H4
+
     # ---- CPU oracle on the host cores (full matrix, repeated up to ~10 s)
     cpu = None
     if not args.no_cpu:
@@ -167,6 +219,7 @@ def main():
         "plain": plain,
         "speedup_vs_plain": (plain["ms_per_step"] / (dt_b * 1e3)) if plain else None,
         "fwd_bwd_ms": fwd_bwd_ms,
+        "extra": extra,
         "build_event_ms": float(np.median(build_ms)),
         "phase_ms": {k: float(v) for k, v in t.items()},
         "cpu_baseline": cpu,

@@ -1,0 +1,65 @@
+"""Several matrices in one build (rsai_build_batched): every matrix's result equals
+the oracle's, and equals the result of building that matrix alone."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1503_04500_amd import gen
+from tests.parity import compare, subset
+
+pytestmark = pytest.mark.gpu
+
+KW = dict(c=3, lmax=8, eps=0.4, tol=1e-3)
+
+
+def _run_batched(mats, **kw):
+    import paper_1503_04500_amd.rsai as rsai
+    dms = [rsai.Matrix.from_host(A, "cuda:0") for A in mats]
+    plan = rsai.build_batched(dms, **kw)
+    out = []
+    for i in range(len(mats)):
+        cp, ri, va = (t.cpu().numpy() for t in plan.export(i))
+        st = {k: v.cpu().numpy() for k, v in plan.stats(i).items()}
+        out.append(dict(colptr=cp, rowidx=ri, val=va, **st))
+    return out
+
+
+def _mix():
+    rng = np.random.default_rng(5)
+    d = np.where(rng.random((60, 60)) < 0.07, rng.standard_normal((60, 60)), 0.0)
+    np.fill_diagonal(d, 0.0)
+    np.fill_diagonal(d, 1.5 * (np.abs(d).sum(axis=0) + 0.5))
+    return [gen.c1(), gen.cd2d(23, seed=4), gen.cd3d(9, seed=2), gen.powerlaw(4000, seed=8),
+            gen.tridiag(7), gen.from_dense(d), gen.powerlaw(2500, seed=9, lmax=30)]
+
+
+def test_batched_mix_full_parity():
+    mats = _mix()
+    res = _run_batched(mats, **KW)
+    for i, (A, g) in enumerate(zip(mats, res)):
+        ref = oracle.rsai(A, drop=1, **KW)
+        compare(A, g, ref, label=f"batched[{i}]")
+
+
+def test_batched_equals_single_builds():
+    mats = _mix()
+    res = _run_batched(mats, **KW)
+    for i, A in enumerate(mats):
+        one = _run_batched([A], **KW)[0]
+        for key in ("colptr", "rowidx", "val", "loops", "nI", "nJ", "resnorm", "flops", "status"):
+            assert np.array_equal(res[i][key], one[key]), f"matrix {i}: {key}"
+
+
+def test_c5_sampled_columns():
+    """The 64-matrix batch (2D/3D convection-diffusion and power-law, n log-uniform in
+    [4096, 262144], sum about 4e6) in one build; 40 seeded columns of every matrix
+    recomputed by the oracle."""
+    specs = gen.batch64_specs()
+    mats = [gen.make(s) for s in specs]
+    assert 3.0e6 < sum(A.n for A in mats) < 5.5e6
+    res = _run_batched(mats, **KW)
+    rng = np.random.default_rng(3)
+    for i, (A, g) in enumerate(zip(mats, res)):
+        cols = np.sort(rng.choice(A.n, 40, replace=False))
+        ref = oracle.rsai(A, drop=1, cols=cols, **KW)
+        compare(A, subset(g, cols), ref, label=f"C5[{i}] {specs[i][0]}")
