@@ -117,6 +117,16 @@ rsai_status rsai_build(const rsai_csc *A, const rsai_params *p, void *stream, rs
 rsai_status rsai_build_batched(int32_t count, const rsai_csc *A, const rsai_params *p, void *stream,
                                rsai_plan **out);
 
+/* Run the build again on the plan's buffers: Algorithm 1 for every column of every
+   matrix, with the values the plan's matrices hold now (same pointers, same pattern;
+   e.g. the next step of a time-dependent problem). Stream-ordered on stream; results
+   of the previous build (M, statistics, cached nnz) are replaced. use_graph = 1 runs
+   the build's kernel sequence as a HIP graph, captured on first use (no host
+   synchronisation, no allocation; the CSC contract check of validate = 1 is not
+   repeated, validate = 2 stays on the device). Returns RSAI_E_HIP if capture or
+   launch fails. */
+rsai_status rsai_rebuild(rsai_plan *P, int32_t use_graph, void *stream);
+
 /* Number of matrices in a plan. */
 rsai_status rsai_plan_count(const rsai_plan *P, int32_t *count);
 

@@ -6,6 +6,7 @@
 #include <cstdlib>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -70,6 +71,9 @@ struct MatPlan {
     int32_t maxq = -1, maxm = -1;  // largest final |J_k| and |I_k| (first backward)
     // transpose of M (rows) for y = M x
     int64_t *rowptrT = nullptr;
+    int32_t *rowcntT = nullptr;  // 2n: row counts and fill positions
+    int64_t capT = 0;        // entries the transpose buffers hold
+    bool t_valid = false;    // transpose matches the current M
     int32_t *colidxT = nullptr;
     double *valT = nullptr;
 };
@@ -96,9 +100,16 @@ struct rsai_plan {
     bool recorded[8] = {};
     bool have_events = false;
     void record(int i, hipStream_t s) {
-        if (have_events && hipEventRecord(ev[i], s) == hipSuccess) recorded[i] = true;
+        if (have_events && !capturing && hipEventRecord(ev[i], s) == hipSuccess) recorded[i] = true;
     }
     int ntiers_used = 0;
+    // the build's kernel sequence (everything after allocation and table upload), kept
+    // for rsai_rebuild; first = the initial build (may check the CSC contract on the host)
+    std::function<rsai_status(hipStream_t, bool)> enqueue;
+    bool capturing = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
 
     template <class T>
     T *alloc(int64_t count, rsai_status &st) {
@@ -114,6 +125,12 @@ struct rsai_plan {
     void release() {
         if (stream) (void)hipStreamSynchronize(stream);
         else (void)hipDeviceSynchronize();
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        gexec = nullptr;
+        graph = nullptr;
+        cap_stream = nullptr;
         for (void *q : owned) dev_free(q, stream);
         owned.clear();
         if (have_events)
@@ -346,41 +363,12 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
     if (st != RSAI_OK) return bail(st);
     layout(L1);
 
-    // ---- preprocessing: CSC contract, row pattern, ||A||_1 (all on the stream)
-    {
-        int32_t *fp[6] = {P->err, (int32_t *)P->stats, P->rec_count, P->out.status, P->out.nJ, nullptr};
-        int64_t fc[6] = {4, 4 * (int64_t)count, nlaunch + 1, ncols, ncols, 0};
-        int32_t fv[6] = {0, 0, 0, ST_INTERNAL, 0, 0};  // every column's status must be written
-        launch_fill_many(fp, fc, fv, 5, s);
-    }
-    if (P->p.validate)
-        for (int i = 0; i < count; ++i) launch_validate(As[i].n, As[i].nnz, As[i].colptr, As[i].rowidx, P->err, s);
-    if (P->p.validate == 1) {
-        // synchronous check: RSAI_E_CSC is returned here; with validate = 2 the later
-        // kernels skip their work and the error is reported by rsai_plan_nnz
-        int32_t herr = 0;
-        if (hipMemcpyAsync(&herr, P->err, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess)
-            return bail(fail(RSAI_E_HIP, "validation readback failed"));
-        if (herr) return bail(fail(RSAI_E_CSC, "malformed CSC (flags %d: 1 colptr, 2 row indices, 4 empty column)", herr));
-    }
+    // ---- the matrix table (device pointers only: no kernel result is needed)
     P->hmats.resize(count);
     for (int i = 0; i < count; ++i) {
         MatPlan &M = P->mats[i];
-        const int64_t n = As[i].n, nnz = As[i].nnz;
-        {
-            int32_t *fp[6] = {M.rowcnt, fillpos[i], nullptr, nullptr, nullptr, nullptr};
-            int64_t fc[6] = {n, n, 0, 0, 0, 0};
-            int32_t fv[6] = {0, 0, 0, 0, 0, 0};
-            launch_fill_many(fp, fc, fv, 2, s);
-        }
-        launch_row_counts(nnz, As[i].rowidx, M.rowcnt, P->err, s);
-        launch_scan_i32(M.rowcnt, n, M.rowptr, P->scan_tmp, s);
-        launch_row_fill(n, As[i].colptr, As[i].rowidx, M.rowptr, fillpos[i], M.colidx, P->err, s);
-        if (P->p.drop == RSAI_DROP_ADAPTIVE)
-            launch_mat_stats(n, As[i].colptr, As[i].val, M.rowcnt, P->stats + 2 * i, P->err, s);
         MatDev &D = P->hmats[i];
-        D.n = n;
+        D.n = As[i].n;
         D.colptr = As[i].colptr;
         D.rowidx = As[i].rowidx;
         D.val = As[i].val;
@@ -393,134 +381,178 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
         hipMemcpyAsync(P->d_colbase, P->hcolbase.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice, s) !=
             hipSuccess)
         return bail(fail(RSAI_E_HIP, "matrix table upload failed"));
-    P->record(1, s);
 
-    TierArgs base{};
-    base.mats = P->d_mats;
-    base.nmat = count;
-    base.col_base = P->d_colbase;
-    base.P.c = P->p.c;
-    base.P.lmax = P->p.lmax;
-    base.P.drop = P->p.drop;
-    base.P.eps = P->p.eps;
-    base.P.tol = P->p.tol;
-    base.out = P->out;
-    base.qlen = ncols;
-    base.err = P->err;
-    base.sync_refill = sync_refill_default(P->p.refill);
-    const int cus = device_cus();
-    if (plain) {
-        // ---- plain schedule: one size class, one launch per loop of Algorithm 1;
-        // the state of every unfinished column goes through HBM between launches
-        const int t = kPlainTier;
-        const int gpw = 64 / kTiers[t].G;
-        for (int L = 0; L < nlaunch; ++L) {
-            TierArgs a = base;
-            a.arena_base = slot_base[t];
-            a.one_loop = 1;
-            a.sync_refill = 0;
-            if (L == 0) {
-                a.rec_in = nullptr;
-            } else {
-                a.rec_in = P->rec[(L - 1) % 2];
-                a.rec_in_stride = kTiers[t].REC;
-                a.rec_in_count = P->rec_count + (L - 1);
-                a.rec_in_cap = ncols;
-            }
-            a.nq = 1;
-            a.q_rec[0] = P->rec[L % 2];
-            a.q_stride[0] = kTiers[t].REC;
-            a.q_count[0] = P->rec_count + L;
-            a.q_cap[0] = ncols;
-            int64_t want = (L == 0) ? (ncols + gpw - 1) / gpw : (int64_t)cus * 8;
-            int waves = (int)std::max<int64_t>(8, std::min<int64_t>(want, (int64_t)cus * 16));
-            waves = (waves + 7) / 8 * 8;
-            launch_tier_kernel(t, a, waves, s);
+    // ---- the kernel sequence: CSC contract, row pattern, ||A||_1, the size classes,
+    // assembly of M (stream-ordered; kept for rsai_rebuild)
+    std::vector<rsai_csc> Av(As, As + count);
+    P->enqueue = [=](hipStream_t s, bool first) -> rsai_status {
+        const rsai_csc *As = Av.data();
+        // ---- preprocessing: CSC contract, row pattern, ||A||_1 (all on the stream)
+        {
+            int32_t *fp[6] = {P->err, (int32_t *)P->stats, P->rec_count, P->out.status, P->out.nJ, nullptr};
+            int64_t fc[6] = {4, 4 * (int64_t)count, nlaunch + 1, ncols, ncols, 0};
+            int32_t fv[6] = {0, 0, 0, ST_INTERNAL, 0, 0};  // every column's status must be written
+            launch_fill_many(fp, fc, fv, 5, s);
         }
-        P->record(2, s);
-    } else {
-        for (int t = t0; t <= tlast; ++t) {
-            TierArgs a = base;
-            a.arena_base = slot_base[t];
-            a.one_loop = 0;
-            if (t != t0) a.sync_refill = 0;
-            if (t == t0) {
-                a.rec_in = nullptr;
-            } else {
-                a.rec_in = P->rec[t - 1];
-                a.rec_in_stride = kTiers[t - 1].REC;
-                a.rec_in_count = P->rec_count + (t - t0 - 1);
-                a.rec_in_cap = ncols;
+        if (P->p.validate)
+            for (int i = 0; i < count; ++i) launch_validate(As[i].n, As[i].nnz, As[i].colptr, As[i].rowidx, P->err, s);
+        if (P->p.validate == 1 && first) {
+            // synchronous check: RSAI_E_CSC is returned here; with validate = 2 the later
+            // kernels skip their work and the error is reported by rsai_plan_nnz
+            int32_t herr = 0;
+            if (hipMemcpyAsync(&herr, P->err, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return fail(RSAI_E_HIP, "validation readback failed");
+            if (herr) return fail(RSAI_E_CSC, "malformed CSC (flags %d: 1 colptr, 2 row indices, 4 empty column)", herr);
+        }
+        for (int i = 0; i < count; ++i) {
+            MatPlan &M = P->mats[i];
+            const int64_t n = As[i].n, nnz = As[i].nnz;
+            {
+                int32_t *fp[6] = {M.rowcnt, fillpos[i], nullptr, nullptr, nullptr, nullptr};
+                int64_t fc[6] = {n, n, 0, 0, 0, 0};
+                int32_t fv[6] = {0, 0, 0, 0, 0, 0};
+                launch_fill_many(fp, fc, fv, 2, s);
             }
-            // queues of the later classes: queue i feeds class t + 1 + i (the register
-            // tiers, then the sparse-block class); records use the stride its reader expects
-            a.nq = 0;
-            const int nq_max = route_default() ? TierArgs::MAXQ : 1;
-            for (int c = t + 1; c <= tlast + (big ? 1 : 0) && a.nq < nq_max; ++c) {
-                const int i = a.nq++;
-                a.q_rec[i] = P->rec[c - 1];
-                a.q_stride[i] = kTiers[c - 1].REC;
-                a.q_count[i] = P->rec_count + (c - 1 - t0);
-                a.q_cap[i] = ncols;
-                a.q_mmax[i] = c <= tlast ? kTiers[c].MMAX : wide_max_rows(0);
-                a.q_qmax[i] = c <= tlast ? kTiers[c].QMAX : WIDE_QMAX;
-            }
+            launch_row_counts(nnz, As[i].rowidx, M.rowcnt, P->err, s);
+            launch_scan_i32(M.rowcnt, n, M.rowptr, P->scan_tmp, s);
+            launch_row_fill(n, As[i].colptr, As[i].rowidx, M.rowptr, fillpos[i], M.colidx, P->err, s);
+            if (P->p.drop == RSAI_DROP_ADAPTIVE)
+                launch_mat_stats(n, As[i].colptr, As[i].val, M.rowcnt, P->stats + 2 * i, P->err, s);
+        }
+        P->record(1, s);
+
+        TierArgs base{};
+        base.mats = P->d_mats;
+        base.nmat = count;
+        base.col_base = P->d_colbase;
+        base.P.c = P->p.c;
+        base.P.lmax = P->p.lmax;
+        base.P.drop = P->p.drop;
+        base.P.eps = P->p.eps;
+        base.P.tol = P->p.tol;
+        base.out = P->out;
+        base.qlen = ncols;
+        base.err = P->err;
+        base.sync_refill = sync_refill_default(P->p.refill);
+        const int cus = device_cus();
+        if (plain) {
+            // ---- plain schedule: one size class, one launch per loop of Algorithm 1;
+            // the state of every unfinished column goes through HBM between launches
+            const int t = kPlainTier;
             const int gpw = 64 / kTiers[t].G;
-            int64_t want = (t == t0) ? (ncols + gpw - 1) / gpw : (int64_t)cus * 2;
-            int waves = (int)std::max<int64_t>(8, std::min<int64_t>(want, (int64_t)cus * 16));
-            waves = (waves + 7) / 8 * 8;
-            launch_tier_kernel(t, a, waves, s);
-            if (t == t0) P->record(2, s);
-        }
-        if (big) {
-            // columns that outgrew the last register tier: one workgroup per column,
-            // first on the compressed block, then (rarely) on the dense block
-            for (int lv = 0; lv < WIDE_LEVELS; ++lv) {
-                WideArgs w{};
-                w.mats = P->d_mats;
-                w.P = base.P;
-                w.out = P->out;
-                w.arena_base = big_base;
-                w.rec_in = P->rec[tlast + lv];
-                w.rec_in_stride = lv == 0 ? kTiers[tlast].REC : wide_rec_stride(lv - 1);
-                w.rec_in_count = P->rec_count + (tlast - t0 + lv);
-                w.rec_in_cap = lv == 0 ? ncols : wide_rec_cap[lv - 1];
-                w.rec_out = P->rec[tlast + 1 + lv];
-                w.rec_out_stride = wide_rec_stride(lv);
-                w.rec_out_count = P->rec_count + (tlast - t0 + 1 + lv);
-                w.rec_out_cap = wide_rec_cap[lv];
-                w.err = P->err;
-                launch_wide_kernel(lv, w, device_cus() * wide_blocks_per_cu(lv), s);
+            for (int L = 0; L < nlaunch; ++L) {
+                TierArgs a = base;
+                a.arena_base = slot_base[t];
+                a.one_loop = 1;
+                a.sync_refill = 0;
+                if (L == 0) {
+                    a.rec_in = nullptr;
+                } else {
+                    a.rec_in = P->rec[(L - 1) % 2];
+                    a.rec_in_stride = kTiers[t].REC;
+                    a.rec_in_count = P->rec_count + (L - 1);
+                    a.rec_in_cap = ncols;
+                }
+                a.nq = 1;
+                a.q_rec[0] = P->rec[L % 2];
+                a.q_stride[0] = kTiers[t].REC;
+                a.q_count[0] = P->rec_count + L;
+                a.q_cap[0] = ncols;
+                int64_t want = (L == 0) ? (ncols + gpw - 1) / gpw : (int64_t)cus * 8;
+                int waves = (int)std::max<int64_t>(8, std::min<int64_t>(want, (int64_t)cus * 16));
+                waves = (waves + 7) / 8 * 8;
+                launch_tier_kernel(t, a, waves, s);
             }
-            BigArgs b{};
-            b.mats = P->d_mats;
-            b.P = base.P;
-            b.out = P->out;
-            b.arena_base = big_base;
-            b.rec_in = P->rec[tlast + WIDE_LEVELS];
-            b.rec_in_stride = wide_rec_stride(WIDE_LEVELS - 1);
-            b.rec_in_count = P->rec_count + (tlast - t0 + WIDE_LEVELS);
-            b.rec_in_cap = wide_rec_cap[WIDE_LEVELS - 1];
-            b.scratch = P->big_scratch;
-            b.scratch_stride = big_scratch_stride();
-            b.err = P->err;
-            launch_big_kernel(b, big_blocks, s);
+            P->record(2, s);
+        } else {
+            for (int t = t0; t <= tlast; ++t) {
+                TierArgs a = base;
+                a.arena_base = slot_base[t];
+                a.one_loop = 0;
+                if (t != t0) a.sync_refill = 0;
+                if (t == t0) {
+                    a.rec_in = nullptr;
+                } else {
+                    a.rec_in = P->rec[t - 1];
+                    a.rec_in_stride = kTiers[t - 1].REC;
+                    a.rec_in_count = P->rec_count + (t - t0 - 1);
+                    a.rec_in_cap = ncols;
+                }
+                // queues of the later classes: queue i feeds class t + 1 + i (the register
+                // tiers, then the sparse-block class); records use the stride its reader expects
+                a.nq = 0;
+                const int nq_max = route_default() ? TierArgs::MAXQ : 1;
+                for (int c = t + 1; c <= tlast + (big ? 1 : 0) && a.nq < nq_max; ++c) {
+                    const int i = a.nq++;
+                    a.q_rec[i] = P->rec[c - 1];
+                    a.q_stride[i] = kTiers[c - 1].REC;
+                    a.q_count[i] = P->rec_count + (c - 1 - t0);
+                    a.q_cap[i] = ncols;
+                    a.q_mmax[i] = c <= tlast ? kTiers[c].MMAX : wide_max_rows(0);
+                    a.q_qmax[i] = c <= tlast ? kTiers[c].QMAX : WIDE_QMAX;
+                }
+                const int gpw = 64 / kTiers[t].G;
+                int64_t want = (t == t0) ? (ncols + gpw - 1) / gpw : (int64_t)cus * 2;
+                int waves = (int)std::max<int64_t>(8, std::min<int64_t>(want, (int64_t)cus * 16));
+                waves = (waves + 7) / 8 * 8;
+                launch_tier_kernel(t, a, waves, s);
+                if (t == t0) P->record(2, s);
+            }
+            if (big) {
+                // columns that outgrew the last register tier: one workgroup per column,
+                // first on the compressed block, then (rarely) on the dense block
+                for (int lv = 0; lv < WIDE_LEVELS; ++lv) {
+                    WideArgs w{};
+                    w.mats = P->d_mats;
+                    w.P = base.P;
+                    w.out = P->out;
+                    w.arena_base = big_base;
+                    w.rec_in = P->rec[tlast + lv];
+                    w.rec_in_stride = lv == 0 ? kTiers[tlast].REC : wide_rec_stride(lv - 1);
+                    w.rec_in_count = P->rec_count + (tlast - t0 + lv);
+                    w.rec_in_cap = lv == 0 ? ncols : wide_rec_cap[lv - 1];
+                    w.rec_out = P->rec[tlast + 1 + lv];
+                    w.rec_out_stride = wide_rec_stride(lv);
+                    w.rec_out_count = P->rec_count + (tlast - t0 + 1 + lv);
+                    w.rec_out_cap = wide_rec_cap[lv];
+                    w.err = P->err;
+                    launch_wide_kernel(lv, w, device_cus() * wide_blocks_per_cu(lv), s);
+                }
+                BigArgs b{};
+                b.mats = P->d_mats;
+                b.P = base.P;
+                b.out = P->out;
+                b.arena_base = big_base;
+                b.rec_in = P->rec[tlast + WIDE_LEVELS];
+                b.rec_in_stride = wide_rec_stride(WIDE_LEVELS - 1);
+                b.rec_in_count = P->rec_count + (tlast - t0 + WIDE_LEVELS);
+                b.rec_in_cap = wide_rec_cap[WIDE_LEVELS - 1];
+                b.scratch = P->big_scratch;
+                b.scratch_stride = big_scratch_stride();
+                b.err = P->err;
+                launch_big_kernel(b, big_blocks, s);
+            }
         }
-    }
-    P->ntiers_used = tlast - t0 + 1 + (big ? 1 + WIDE_LEVELS : 0);
-    P->record(3, s);
+        P->ntiers_used = tlast - t0 + 1 + (big ? 1 + WIDE_LEVELS : 0);
+        P->record(3, s);
 
-    // ---- assembly of M per matrix: colptr = scan(nJ), then compaction
-    for (int i = 0; i < count; ++i) {
-        MatPlan &M = P->mats[i];
-        const int64_t n = As[i].n;
-        launch_scan_i32(P->out.nJ + M.col_base, n, M.colptrM, P->scan_tmp, s);
-        launch_assemble(n, (int)qlast, P->out.off + M.col_base, P->out.nJ + M.col_base, M.colptrM, P->out.arenaJ,
-                        P->out.arenaV, M.rowidxM, M.valM, s);
-    }
-    P->record(4, s);
-    hipError_t le = hipGetLastError();
-    if (le != hipSuccess) return bail(fail(RSAI_E_HIP, "launch failed: %s", hipGetErrorString(le)));
+        // ---- assembly of M per matrix: colptr = scan(nJ), then compaction
+        for (int i = 0; i < count; ++i) {
+            MatPlan &M = P->mats[i];
+            const int64_t n = As[i].n;
+            launch_scan_i32(P->out.nJ + M.col_base, n, M.colptrM, P->scan_tmp, s);
+            launch_assemble(n, (int)qlast, P->out.off + M.col_base, P->out.nJ + M.col_base, M.colptrM, P->out.arenaJ,
+                            P->out.arenaV, M.rowidxM, M.valM, s);
+        }
+        P->record(4, s);
+        hipError_t le = hipGetLastError();
+        if (le != hipSuccess) return fail(RSAI_E_HIP, "launch failed: %s", hipGetErrorString(le));
+        return RSAI_OK;
+
+    };
+    st = P->enqueue(s, true);
+    if (st != RSAI_OK) return bail(st);
     *out = P;
     return RSAI_OK;
 }
@@ -532,6 +564,57 @@ rsai_status rsai_build(const rsai_csc *A, const rsai_params *p, void *stream, rs
 rsai_status rsai_build_batched(int32_t count, const rsai_csc *A, const rsai_params *p, void *stream,
                                rsai_plan **out) {
     return build_impl(count, A, p, stream, out);
+}
+
+// later plan calls run on the plan's stream: order it after work queued on s
+static rsai_status order_after(rsai_plan *P, hipStream_t s) {
+    if (s == P->stream) return RSAI_OK;
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return fail(RSAI_E_HIP, "event creation failed");
+    const bool ok = hipEventRecord(e, s) == hipSuccess && hipStreamWaitEvent(P->stream, e, 0) == hipSuccess;
+    (void)hipEventDestroy(e);
+    return ok ? RSAI_OK : fail(RSAI_E_HIP, "stream ordering failed");
+}
+
+rsai_status rsai_rebuild(rsai_plan *P, int32_t use_graph, void *stream) {
+    if (!P || !P->enqueue) return fail(RSAI_E_ARG, "plan is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    (void)hipGetLastError();
+    // results of the previous build are out of date
+    for (MatPlan &M : P->mats) {
+        M.nnzM = -1;
+        M.maxq = M.maxm = -1;
+        M.t_valid = false;
+    }
+    for (bool &r : P->recorded) r = false;
+    if (!use_graph) {
+        const rsai_status st = P->enqueue(s, false);
+        return st != RSAI_OK ? st : order_after(P, s);
+    }
+    if (!P->gexec) {
+        // capture the sequence once on a private stream, then replay it on any stream
+        if (!P->cap_stream && hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking) != hipSuccess)
+            return fail(RSAI_E_HIP, "stream creation failed");
+        if (hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return fail(RSAI_E_HIP, "graph capture could not start");
+        P->capturing = true;
+        rsai_status st = P->enqueue(P->cap_stream, false);
+        P->capturing = false;
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(P->cap_stream, &g);
+        if (st != RSAI_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (ec != hipSuccess || !g) return fail(RSAI_E_HIP, "graph capture failed: %s", hipGetErrorString(ec));
+        P->graph = g;
+        if (hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0) != hipSuccess) {
+            P->gexec = nullptr;
+            return fail(RSAI_E_HIP, "graph instantiation failed");
+        }
+    }
+    if (hipGraphLaunch(P->gexec, s) != hipSuccess) return fail(RSAI_E_HIP, "graph launch failed");
+    return order_after(P, s);
 }
 
 rsai_status rsai_plan_count(const rsai_plan *P, int32_t *count) {
@@ -611,24 +694,27 @@ rsai_status rsai_apply(const rsai_plan *Pc, int32_t mat, const double *x, double
     MatPlan &M = P->mats[mat];
     const int64_t n = M.A.n;
     hipStream_t s = (hipStream_t)stream;
-    if (!M.rowptrT) {
-        // rows of M once: counts, scan, fill, sort each row by column
-        int32_t *cnt = P->alloc<int32_t>(n, st);
-        int32_t *fill = P->alloc<int32_t>(n, st);
-        int64_t *rp = P->alloc<int64_t>(n + 1, st);
-        int32_t *ci = P->alloc<int32_t>(nz, st);
-        double *vv = P->alloc<double>(nz, st);
-        if (st != RSAI_OK) return st;
-        launch_fill_i32(cnt, 0, n, P->stream);
-        launch_fill_i32(fill, 0, n, P->stream);
+    if (!M.t_valid) {
+        // rows of M once per build: counts, scan, fill, sort each row by column
+        if (!M.rowptrT || nz > M.capT) {
+            M.rowcntT = P->alloc<int32_t>(2 * n, st);
+            M.rowptrT = P->alloc<int64_t>(n + 1, st);
+            M.colidxT = P->alloc<int32_t>(nz, st);
+            M.valT = P->alloc<double>(nz, st);
+            if (st != RSAI_OK) {
+                M.rowptrT = nullptr;
+                return st;
+            }
+            M.capT = nz;
+        }
+        int32_t *cnt = M.rowcntT, *fill = M.rowcntT + n;
+        launch_fill_i32(cnt, 0, 2 * n, P->stream);
         launch_row_counts(nz, M.rowidxM, cnt, P->err, P->stream);
-        launch_scan_i32(cnt, n, rp, P->scan_tmp, P->stream);
-        launch_csc_transpose_fill(n, M.colptrM, M.rowidxM, M.valM, rp, fill, ci, vv, P->stream);
-        launch_sort_rows(n, rp, ci, vv, P->stream);
+        launch_scan_i32(cnt, n, M.rowptrT, P->scan_tmp, P->stream);
+        launch_csc_transpose_fill(n, M.colptrM, M.rowidxM, M.valM, M.rowptrT, fill, M.colidxT, M.valT, P->stream);
+        launch_sort_rows(n, M.rowptrT, M.colidxT, M.valT, P->stream);
         HIPCHK(hipStreamSynchronize(P->stream));
-        M.rowptrT = rp;
-        M.colidxT = ci;
-        M.valT = vv;
+        M.t_valid = true;
     }
     launch_csr_spmv(n, M.rowptrT, M.colidxT, M.valT, x, y, s);
     HIPCHK(hipGetLastError());

@@ -90,6 +90,7 @@ def load():
         "rsai_spmv_vjp": [P, P, P, P, P],
         "rsai_plan_timing": [P, P, I32],
         "rsai_tier_info": [I32, P, P, P],
+        "rsai_rebuild": [P, I32, P],
         "rsai_destroy": [P],
     }
     for name, args in sigs.items():
@@ -231,6 +232,11 @@ class Plan:
             ptr = dM_val.data_ptr()
         _check(load().rsai_backward(self._hv(), mat, ptr, float(w_frob), dA_val.data_ptr(), _stream()))
         return dA_val
+
+    def rebuild(self, graph=True, stream=None):
+        """Run the build again with the values the plan's matrices hold now
+        (rsai_rebuild; graph=True replays a captured HIP graph)."""
+        _check(load().rsai_rebuild(self._hv(), 1 if graph else 0, _stream(stream)))
 
     def timing(self):
         ms = (ctypes.c_double * 6)()
