@@ -83,11 +83,13 @@ typedef struct {
                          build with one host synchronisation (RSAI_E_CSC from rsai_build),
                          2 checked on the device without synchronising (the build's kernels
                          then do nothing and rsai_plan_nnz reports RSAI_E_CSC) */
-    int32_t tier0;    /* first size tier for the batched schedule: -1 = choose from the
-                         tuning table / defaults, else a tier index (rsai_tier_info) */
+    int32_t tier0;    /* first size tier for the batched schedule: -1 default (0), else a
+                         register tier index (rsai_tier_info) */
     int32_t timing;   /* 1: record per-kernel HIP event times (rsai_plan_timing) */
-    int32_t refill;   /* first tier: -1 default, 0 a finished column's lanes take the next
+    int32_t refill;   /* first tier: -1 default (1), 0 a finished column's lanes take the next
                          column at once, 1 the lanes of a wave take new columns together */
+    int32_t route;    /* spilled columns: -1 default (1), 0 to the next size class, 1 to the
+                         first class that holds their estimated |I_k|, |J_k| */
     int32_t keep_factors;        /* 1: keep R factors of the final solves for backward */
     int64_t factor_budget_bytes; /* keep factors only if they fit; else recompute */
 } rsai_params;
@@ -105,6 +107,19 @@ rsai_status rsai_params_default(rsai_params *p);
    Passing NULLs restores hipMalloc/hipFree. Process-wide; not thread-safe against
    concurrent builds. */
 rsai_status rsai_set_allocator(rsai_alloc_fn alloc, rsai_free_fn dealloc, void *ctx);
+
+/* Result of one autotuning candidate. */
+typedef struct {
+    int32_t tier0, refill, route, reserved;
+    double ms; /* median build time over the repetitions (HIP events) */
+} rsai_tune_choice;
+
+/* Time the batched build of A for every combination of tier0 (each register tier),
+   refill (0, 1) and route (0, 1), reps builds each (p gives the method parameters).
+   Writes up to cap results to out (host array), their number to *count and the index
+   of the fastest to *best. Synchronises the stream. */
+rsai_status rsai_autotune(const rsai_csc *A, const rsai_params *p, int32_t reps, void *stream,
+                          rsai_tune_choice *out, int32_t cap, int32_t *count, int32_t *best);
 
 /* Build M for one matrix. Queues all work on stream; with p->validate = 1 it first
    synchronises once to check the CSC contract (RSAI_E_CSC on violation); with

@@ -150,6 +150,7 @@ static rsai_status check_params(const rsai_params *p) {
     if (p->validate < 0 || p->validate > 2) return fail(RSAI_E_ARG, "validate must be 0, 1 or 2");
     if (p->tier0 < -1 || p->tier0 >= kNumTiers) return fail(RSAI_E_ARG, "tier0 out of range");
     if (p->refill < -1 || p->refill > 1) return fail(RSAI_E_ARG, "refill must be -1, 0 or 1");
+    if (p->route < -1 || p->route > 1) return fail(RSAI_E_ARG, "route must be -1, 0 or 1");
     return RSAI_OK;
 }
 
@@ -180,6 +181,7 @@ rsai_status rsai_params_default(rsai_params *p) {
     p->tier0 = -1;
     p->timing = 0;
     p->refill = -1;
+    p->route = -1;
     p->keep_factors = 0;
     p->factor_budget_bytes = 0;
     return RSAI_OK;
@@ -236,7 +238,8 @@ static int sync_refill_default(int requested) {
 
 // spill routing by size estimate (1, default) or always to the next class (0);
 // RSAI_ROUTE overrides
-static int route_default() {
+static int route_default(int requested) {
+    if (requested == 0 || requested == 1) return requested;
     const char *e = getenv("RSAI_ROUTE");
     if (e && (e[0] == '0' || e[0] == '1')) return e[0] - '0';
     return 1;
@@ -260,6 +263,7 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
     (void)hipGetLastError();  // clear an error left by an unrelated earlier call
     rsai_plan *P = new rsai_plan();
     P->p = *prm;
+
     P->stream = (hipStream_t)stream;
     hipStream_t s = P->stream;
     auto bail = [&](rsai_status code) {
@@ -482,7 +486,7 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
                 // queues of the later classes: queue i feeds class t + 1 + i (the register
                 // tiers, then the sparse-block class); records use the stride its reader expects
                 a.nq = 0;
-                const int nq_max = route_default() ? TierArgs::MAXQ : 1;
+                const int nq_max = route_default(P->p.route) ? TierArgs::MAXQ : 1;
                 for (int c = t + 1; c <= tlast + (big ? 1 : 0) && a.nq < nq_max; ++c) {
                     const int i = a.nq++;
                     a.q_rec[i] = P->rec[c - 1];
@@ -615,6 +619,51 @@ rsai_status rsai_rebuild(rsai_plan *P, int32_t use_graph, void *stream) {
     }
     if (hipGraphLaunch(P->gexec, s) != hipSuccess) return fail(RSAI_E_HIP, "graph launch failed");
     return order_after(P, s);
+}
+
+rsai_status rsai_autotune(const rsai_csc *A, const rsai_params *p, int32_t reps, void *stream,
+                          rsai_tune_choice *out, int32_t cap, int32_t *count, int32_t *best) {
+    if (!A || !p || !out || !count || !best || cap < 1 || reps < 1) return fail(RSAI_E_ARG, "NULL or bad argument");
+    rsai_status st = check_params(p);
+    if (st != RSAI_OK) return st;
+    int32_t nout = 0, ib = -1;
+    for (int t0 = 0; t0 < kNumTiers; ++t0)
+        for (int rf = 0; rf <= 1; ++rf)
+            for (int rt = 0; rt <= 1; ++rt) {
+                rsai_params q = *p;
+                q.sched = RSAI_SCHED_BATCHED;
+                q.tier0 = t0;
+                q.refill = rf;
+                q.route = rt;
+                q.timing = 1;
+                std::vector<double> ms;
+                for (int r = 0; r < reps + 1; ++r) {
+                    rsai_plan *P = nullptr;
+                    st = rsai_build(A, &q, stream, &P);
+                    if (st != RSAI_OK) return st;
+                    int64_t nz = 0;
+                    st = rsai_plan_nnz(P, 0, &nz);
+                    double tm[6] = {};
+                    if (st == RSAI_OK) st = rsai_plan_timing(P, tm, 6);
+                    rsai_destroy(P);
+                    if (st != RSAI_OK) return st;
+                    if (r > 0) ms.push_back(tm[4]);  // the first build warms the allocator
+                }
+                std::sort(ms.begin(), ms.end());
+                if (nout < cap) {
+                    rsai_tune_choice &c = out[nout];
+                    c.tier0 = t0;
+                    c.refill = rf;
+                    c.route = rt;
+                    c.reserved = 0;
+                    c.ms = ms[ms.size() / 2];
+                    if (ib < 0 || c.ms < out[ib].ms) ib = nout;
+                    ++nout;
+                }
+            }
+    *count = nout;
+    *best = ib;
+    return RSAI_OK;
 }
 
 rsai_status rsai_plan_count(const rsai_plan *P, int32_t *count) {

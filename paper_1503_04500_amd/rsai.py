@@ -32,7 +32,7 @@ class Params(ctypes.Structure):
     _fields_ = [("c", ctypes.c_int32), ("lmax", ctypes.c_int32), ("eps", ctypes.c_double),
                 ("drop", ctypes.c_int32), ("tol", ctypes.c_double), ("sched", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("tier0", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("refill", ctypes.c_int32),
+                ("refill", ctypes.c_int32), ("route", ctypes.c_int32),
                 ("keep_factors", ctypes.c_int32), ("factor_budget_bytes", ctypes.c_int64)]
 
 
@@ -91,6 +91,7 @@ def load():
         "rsai_plan_timing": [P, P, I32],
         "rsai_tier_info": [I32, P, P, P],
         "rsai_rebuild": [P, I32, P],
+        "rsai_autotune": [P, P, I32, P, P, I32, P, P],
         "rsai_destroy": [P],
     }
     for name, args in sigs.items():
@@ -141,12 +142,23 @@ class Matrix:
         self.val = _dev(val, torch.float64, "val")
         self.n = self.colptr.numel() - 1
         self.nnz = self.rowidx.numel()
+        self._max_col_len = None
 
     @classmethod
     def from_host(cls, A, device="cuda"):
-        return cls(torch.as_tensor(A.colptr, dtype=torch.int64).to(device),
-                   torch.as_tensor(A.rowidx, dtype=torch.int32).to(device),
-                   torch.as_tensor(A.val, dtype=torch.float64).to(device))
+        M = cls(torch.as_tensor(A.colptr, dtype=torch.int64).to(device),
+                torch.as_tensor(A.rowidx, dtype=torch.int32).to(device),
+                torch.as_tensor(A.val, dtype=torch.float64).to(device))
+        cp = A.colptr
+        M._max_col_len = int((cp[1:] - cp[:-1]).max()) if len(cp) > 1 else 0
+        return M
+
+    @property
+    def max_col_len(self):
+        """Longest column (computed once; one device synchronisation if not known)."""
+        if self._max_col_len is None:
+            self._max_col_len = int((self.colptr[1:] - self.colptr[:-1]).max().item())
+        return self._max_col_len
 
     def view(self, val=None):
         v = self.val if val is None else val
@@ -154,7 +166,7 @@ class Matrix:
 
 
 def params(c=3, lmax=10, eps=0.4, drop="fixed", tol=1e-3, sched="batched", validate=True, tier0=-1,
-           timing=False, refill=-1):
+           timing=False, refill=-1, route=-1):
     p = Params()
     _check(load().rsai_params_default(ctypes.byref(p)))
     p.c, p.lmax, p.eps, p.tol = int(c), int(lmax), float(eps), float(tol)
@@ -164,6 +176,7 @@ def params(c=3, lmax=10, eps=0.4, drop="fixed", tol=1e-3, sched="batched", valid
     p.tier0 = int(tier0)
     p.timing = 1 if timing else 0
     p.refill = int(refill)
+    p.route = int(route)
     return p
 
 
@@ -249,11 +262,29 @@ def build(A: Matrix, stream=None, **kw) -> Plan:
     return build_batched([A], stream=stream, **kw)
 
 
+def _tuned(mats, kw):
+    """Fill schedule choices left at their defaults from the tuning table."""
+    keys = ("tier0", "refill", "route")
+    if kw.get("sched", "batched") not in ("batched", 0) or all(kw.get(k, -1) != -1 for k in keys):
+        return kw
+    from . import tune
+    n = sum(m.n for m in mats)
+    ch = tune.choose(n, sum(m.nnz for m in mats) / max(n, 1), max(m.max_col_len for m in mats))
+    if not ch:
+        return kw
+    kw = dict(kw)
+    for k in keys:
+        if kw.get(k, -1) == -1:
+            kw[k] = ch[k]
+    return kw
+
+
 def build_batched(mats, stream=None, **kw) -> Plan:
-    """Build M for several matrices in one pass (rsai_build_batched)."""
+    """Build M for several matrices in one pass (rsai_build_batched). Schedule choices
+    left at -1 come from the tuning table (tune.choose) when it has a matching entry."""
     lib = load()
     _use_torch_allocator()
-    prm = params(**kw)
+    prm = params(**_tuned(mats, kw))
     views = (CSCView * len(mats))(*[m.view() for m in mats])
     h = ctypes.c_void_p()
     st = _stream(stream)

@@ -70,6 +70,12 @@ def test_argument_errors_without_gpu():
     assert lib.rsai_plan_nnz(None, 0, ctypes.byref(n)) == -1
     assert lib.rsai_destroy(None) == 0
     assert lib.rsai_set_allocator(ctypes.c_void_p(1), None, None) == -1
+    assert lib.rsai_rebuild(None, 1, None) == -1
+    cnt, best = ctypes.c_int32(), ctypes.c_int32()
+    assert lib.rsai_autotune(None, ctypes.byref(p), 1, None, None, 0, ctypes.byref(cnt), ctypes.byref(best)) == -1
+    bad = rsai.params()
+    bad.route = 3
+    assert lib.rsai_build(ctypes.byref(rsai.CSCView(4, 4, 8, 8, 8)), ctypes.byref(bad), None, ctypes.byref(out)) == -1
 
 
 def test_no_cpu_fallback():
