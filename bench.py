@@ -38,9 +38,32 @@ def parse():
     ap.add_argument("--grid", type=int, default=512)
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the power-law (n = 10^6), 64-matrix batch and 3D fwd+bwd legs")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 64 MiB device to device three times (calibrates the HBM byte counters)")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many batched builds (for rocprofv3), print nothing else")
     return ap.parse_args()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the tier-0 kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "tier_kernel_cd2d512_pmc.md")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and line.startswith("    ") and not line.strip().startswith("rocprofv3"):
+            k, v = line.strip().split(":", 1)
+            kv[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in ("rsai_tier.hip", "rsai_tier.h", "rsai_dev.h"):
+        with open(os.path.join(ROOT, "paper_1503_04500_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if kv.get("kernel_source_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in kv:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def time_builds(rsai, A, sched, steps, warmup, torch, prm=None):
@@ -71,6 +94,15 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
+
+    if args.copy_probe:
+        a = torch.ones(64 * 1024 * 1024 // 8, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": a.numel() * 8, "copies": 3}))
+        return
 
     import paper_1503_04500_amd.rsai as rsai
     from paper_1503_04500_amd import gen
@@ -213,7 +245,7 @@ def main():
                                "seed 0 (n=%d, nnz=%d); RSAI(tol) c=3 lmax=8 eps=0.4 tol=1e-3" % (n, nnz),
                    "n": n, "nnz": nnz, "nnzM": int(nnzM), "schedule": "batched"},
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tf / FP64_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved_tf / FP64_PEAK_TFLOPS, "traffic": measured_traffic(),
                      "kernel": "tier_kernel<8,3,12,4>", "kernel_ms": t0_ms, "alg_flops": flops,
                      "hbm_alg_bytes": bytes_alg, "hbm_achieved_GBs": hbm_gbs, "hbm_frac": hbm_gbs / HBM_PEAK_GBS},
         "plain": plain,
