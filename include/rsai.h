@@ -90,8 +90,10 @@ typedef struct {
                          column at once, 1 the lanes of a wave take new columns together */
     int32_t route;    /* spilled columns: -1 default (1), 0 to the next size class, 1 to the
                          first class that holds their estimated |I_k|, |J_k| */
-    int32_t keep_factors;        /* 1: keep R factors of the final solves for backward */
-    int64_t factor_budget_bytes; /* keep factors only if they fit; else recompute */
+    int32_t keep_factors;        /* 1: keep the R factor of every column's final solve for
+                                    rsai_backward (R^T R = A(I,J)^T A(I,J)) */
+    int64_t factor_budget_bytes; /* size of the factor store (0: 256 MB); columns that do not
+                                    fit are refactorised by rsai_backward */
 } rsai_params;
 
 typedef struct rsai_plan rsai_plan; /* opaque host handle */
@@ -167,9 +169,11 @@ rsai_status rsai_apply(const rsai_plan *P, int32_t mat, const double *x, double 
 /* Adjoint of the fixed-pattern LS map A -> M (pattern of M fixed, values from (2.3)):
    dA_val += d/dA [ <dM_val, M> + w_frob * sum_k ||A m_k - e_k||^2 ] restricted to
    the structural nonzeros of A. dM_val (nnzM entries, CSC order of rsai_export_M)
-   may be NULL. dA_val has nnz(A) entries and is accumulated into. Columns with
-   |J_k| > 32 or |I_k| > 64 are not supported: RSAI_E_CAP (checked before any
-   accumulation, one host synchronisation on the first call of a plan). */
+   may be NULL. dA_val has nnz(A) entries and is accumulated into. Columns whose R
+   factor the build kept (keep_factors) are solved on it; the others re-gather and
+   refactorise A(I_k, J_k). Columns with |J_k| > 32, or without a kept factor and
+   |I_k| > 64, are not supported: RSAI_E_CAP (checked before any accumulation, one
+   host synchronisation on the first call of a plan). */
 rsai_status rsai_backward(rsai_plan *P, int32_t mat, const double *dM_val, double w_frob, double *dA_val,
                           void *stream);
 

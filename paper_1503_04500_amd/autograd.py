@@ -4,7 +4,9 @@ RSAIFunction.apply(val, A, params) -> (valM, frob):
   valM = values of M = RSAI(tol)(A) (pattern fixed by the forward pass),
   frob = sum_k ||A m_k - e_k||^2.
 Its backward calls rsai_backward (the adjoint kernel): the pattern of M is held
-fixed, each m_k is the solution of (2.3) on its pattern.
+fixed, each m_k is the solution of (2.3) on its pattern. The forward build keeps the
+R factors of its final solves (keep_factors) so that the adjoint reuses them; the
+columns that do not fit the factor budget are refactorised.
 
 SpMV.apply(val, x, A) -> A x, differentiable in the values and in x.
 rsai_loss(A, val, b) = sum_k ||A m_k - e_k||^2 + ||A M b - b||^2.
@@ -41,7 +43,9 @@ class RSAIFunction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, val, A, params):
         Av = rsai.Matrix(A.colptr, A.rowidx, val.detach())
-        plan = rsai.build(Av, **params)
+        Av._max_col_len = A._max_col_len
+        # keep the R factors of the final solves for the adjoint unless told not to
+        plan = rsai.build(Av, **dict({"keep_factors": True}, **params))
         cp, ri, vm = plan.export()
         rn = plan.stats()["resnorm"]
         frob = torch.sum(rn * rn)

@@ -44,17 +44,17 @@ struct BLds {
 int backward_max_cols() { return BQMAX; }
 int backward_max_rows() { return BMMAX; }
 
-__global__ void k_max2(int64_t n, const int32_t *a, const int32_t *b, int32_t *out2) {
+__global__ void k_max2(int64_t n, const int32_t *a, const int32_t *b, const int64_t *mask, int32_t *out2) {
     int ma = 0, mb = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         ma = max(ma, a[i]);
-        mb = max(mb, b[i]);
+        if (!mask || mask[i] < 0) mb = max(mb, b[i]);
     }
     atomicMax(&out2[0], ma);
     atomicMax(&out2[1], mb);
 }
-void launch_max2(int64_t n, const int32_t *a, const int32_t *b, int32_t *out2, hipStream_t s) {
-    hipLaunchKernelGGL(k_max2, dim3(256), dim3(256), 0, s, n, a, b, out2);
+void launch_max2(int64_t n, const int32_t *a, const int32_t *b, const int64_t *mask, int32_t *out2, hipStream_t s) {
+    hipLaunchKernelGGL(k_max2, dim3(256), dim3(256), 0, s, n, a, b, mask, out2);
 }
 
 __global__ __launch_bounds__(64) void backward_kernel(BwdArgs a) {
@@ -78,9 +78,10 @@ __global__ __launch_bounds__(64) void backward_kernel(BwdArgs a) {
             mb = a.Mcolptr[k];
             q = (int)(a.Mcolptr[k + 1] - mb);
             if (q > QMAX || q < 1) {
-                if (q > QMAX && gl == 0) atomicOr(a.err, 8);
+                if (q > QMAX && gl == 0 && !(a.foff && a.foff[k] >= 0)) atomicOr(a.err, 8);
                 act = false;
             }
+            if (a.foff && a.foff[k] >= 0) act = false;  // kept factor: the factored kernel
         }
         bool any_g = false;
         if (act && a.gM)
@@ -326,6 +327,142 @@ __global__ __launch_bounds__(64) void backward_kernel(BwdArgs a) {
 
 void launch_backward(const BwdArgs &a, int waves, hipStream_t s) {
     hipLaunchKernelGGL(backward_kernel, dim3(waves), dim3(64), 0, s, a);
+}
+
+// ---------------------------------------------------------------- kept factors
+// The same adjoint for the columns whose R factor the build kept: z = R^{-1} R^{-T} g
+// by two triangular solves on the stored R (R^T R = A_k^T A_k for any QR of A_k,
+// compressed or not), then r = A_k m - e_k and A_k z row by row from the sparse
+// data: the columns of row i (row pattern of A) that belong to J_k, each value
+// a_ij found by binary search in column j (rows ascending). No dense block, no
+// row-set hash, so |I_k| is not limited here.
+namespace {
+constexpr int FG = 16, FGPW = 64 / FG, FQ = 32, FLOGHJ = 7, FHJ = 1 << FLOGHJ;
+struct FLds {
+    double z[FQ];       // z in ascending column order
+    double u[FQ];       // R^{-T} g, solve order
+    int js[FQ];         // J ascending (the order of M's column)
+    int rk[FQ];         // position in ascending order of the solve-order slot
+    int hJ[FHJ];        // column -> ascending position
+    int hv[FHJ];
+};
+__device__ __forceinline__ int fhfind(const FLds &S, int key) {
+    const int sl = hfind<FLOGHJ>(S.hJ, key);
+    return sl >= 0 ? S.hv[sl] : -1;
+}
+// value of A(i, j), or 0 if not stored (rows of a column ascending)
+__device__ __forceinline__ double aval(const MatDev &A, int j, int i) {
+    int64_t lo = A.colptr[j], hi = A.colptr[j + 1] - 1;
+    while (lo <= hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        const int v = A.rowidx[mid];
+        if (v == i) return A.val[mid];
+        if (v < i) lo = mid + 1; else hi = mid - 1;
+    }
+    return 0.0;
+}
+}  // namespace
+
+int backward_factored_max_cols() { return FQ; }
+
+__global__ __launch_bounds__(64) void backward_factored_kernel(BwdArgs a) {
+    constexpr int G = FG;
+    __shared__ FLds lds[FGPW];
+    const int gl = threadIdx.x % G;
+    const int grp = threadIdx.x / G;
+    FLds &S = lds[grp];
+    const MatDev A = a.mats[a.mat];
+    const int64_t n = a.n;
+    const int64_t gstride = (int64_t)gridDim.x * FGPW;
+    const int64_t iters = (n + gstride - 1) / gstride;
+    for (int64_t itk = 0; itk < iters; ++itk) {
+        const int64_t k = itk * gstride + (int64_t)blockIdx.x * FGPW + grp;
+        bool act = k < n;
+        int q = 0;
+        int64_t mb = 0, fo = -1;
+        if (act) {
+            fo = a.foff[k];
+            mb = a.Mcolptr[k];
+            q = (int)(a.Mcolptr[k + 1] - mb);
+            act = fo >= 0 && q >= 1 && q <= FQ;
+        }
+        bool any_g = false;
+        if (act && a.gM)
+            for (int c = 0; c < q; ++c) any_g |= (a.gM[mb + c] != 0.0);
+        if (act && !any_g && a.w_frob == 0.0) act = false;
+        const double *F = a.fac + (act ? fo : 0);
+        for (int t = gl; t < FHJ; t += G) S.hJ[t] = HEMPTY;
+        wave_sync();
+        if (act) {
+            for (int c = gl; c < q; c += G) {
+                S.js[c] = a.Mrowidx[mb + c];
+                int sl;
+                hinsert<FLOGHJ>(S.hJ, S.js[c], sl);
+                if (sl >= 0) S.hv[sl] = c;
+            }
+        }
+        wave_sync();
+        if (act)
+            for (int c = gl; c < q; c += G) S.rk[c] = fhfind(S, (int)F[c]);
+        wave_sync();
+        // u = R^{-T} g (forward substitution), g taken in solve order
+        for (int j = 0; j < FQ; ++j) {
+            if (!wave_any(act && j < q)) break;
+            double part = 0.0;
+            if (act && j < q)
+                for (int i = gl; i < j; i += G) part += F[fac_row(q, i) + (j - i)] * S.u[i];
+            part = gsum<G>(part);
+            if (act && j < q && gl == 0) {
+                const int rj = S.rk[j];
+                const double gj = (a.gM && rj >= 0) ? a.gM[mb + rj] : 0.0;
+                S.u[j] = (gj - part) / F[fac_row(q, j)];
+            }
+            wave_sync();
+        }
+        // z = R^{-1} u (back substitution), stored by ascending position
+        for (int j = FQ - 1; j >= 0; --j) {
+            if (!wave_any(act && j < q)) continue;
+            double part = 0.0;
+            if (act && j < q)
+                for (int c = j + 1 + gl; c < q; c += G) {
+                    const int rc = S.rk[c];
+                    part += F[fac_row(q, j) + (c - j)] * (rc >= 0 ? S.z[rc] : 0.0);
+                }
+            part = gsum<G>(part);
+            if (act && j < q && gl == 0) {
+                const int rj = S.rk[j];
+                if (rj >= 0) S.z[rj] = (S.u[j] - part) / F[fac_row(q, j)];
+            }
+            wave_sync();
+        }
+        // scatter onto the nonzeros of A(:, J_k); r_i and (A_k z)_i from row i's pattern
+        if (act) {
+            const double w2 = 2.0 * a.w_frob;
+            for (int c = 0; c < q; ++c) {
+                const int j = S.js[c];
+                const double zc = S.z[c], mc = a.Mval[mb + c];
+                for (int64_t e = A.colptr[j] + gl; e < A.colptr[j + 1]; e += G) {
+                    const int i = A.rowidx[e];
+                    double ri = (i == (int)k) ? -1.0 : 0.0, azi = 0.0;
+                    for (int64_t f = A.rowptr[i]; f < A.rowptr[i + 1]; ++f) {
+                        const int jj = A.colidx[f];
+                        const int t = fhfind(S, jj);
+                        if (t < 0) continue;
+                        const double aij = (jj == j) ? A.val[e] : aval(A, jj, i);
+                        ri += aij * a.Mval[mb + t];
+                        azi += aij * S.z[t];
+                    }
+                    const double gv = -(ri * zc + azi * mc) + w2 * ri * mc;
+                    atomicAdd(&a.dA[e], gv);
+                }
+            }
+        }
+        wave_sync();
+    }
+}
+
+void launch_backward_factored(const BwdArgs &a, int waves, hipStream_t s) {
+    hipLaunchKernelGGL(backward_factored_kernel, dim3(waves), dim3(64), 0, s, a);
 }
 
 }  // namespace rsai

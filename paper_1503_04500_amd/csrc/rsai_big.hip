@@ -549,6 +549,25 @@ __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
             args.out.resnorm[ucol] = rn;
             args.out.flops[ucol] = fl;
         }
+        if (args.out.fac != nullptr) {
+            // R of the final solve: strict upper part in the block, diagonal in rd
+            if (tid == 0) {
+                const long long fo = (qq > 0) ? fac_reserve(args.out, qq) : -1LL;
+                args.out.foff[ucol] = fo;
+                S.cnt = (int)(fo & 0xffffffffLL);
+                S.misc = (int)(fo >> 32);
+            }
+            __syncthreads();
+            const long long fo = ((long long)S.misc << 32) | (long long)(unsigned)S.cnt;
+            if (fo >= 0) {
+                double *F = args.out.fac + fo;
+                for (int c = tid; c < qq; c += NT) F[c] = (double)S.Jlist[c];
+                for (int t = tid; t < qq * qq; t += NT) {
+                    const int i = t / qq, c = t % qq;
+                    if (c >= i) F[fac_row(qq, i) + (c - i)] = (c == i) ? S.rd[i] : B[(int64_t)c * BMMAX_BIG + i];
+                }
+            }
+        }
         __syncthreads();
     }
 }

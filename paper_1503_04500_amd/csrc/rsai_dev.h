@@ -35,7 +35,23 @@ struct ColOut {              // per global column
     double *resnorm, *flops;
     int32_t *arenaJ;         // arena of J lists (global column ids, solve order)
     double *arenaV;          // arena of values
+    // R factors of the final solves, kept for the adjoint (fac == nullptr: not kept).
+    // Record of a column at foff[col] (-1: not stored): J in solve order (q values),
+    // then the upper triangle of R row by row (row i: R(i, i..q-1)).
+    double *fac;
+    unsigned long long *fac_cur;  // doubles handed out so far
+    int64_t fac_cap;
+    int64_t *foff;
 };
+
+// Reserve a factor record of q columns; -1 when the arena is full (the adjoint then
+// refactorises that column).
+__device__ __forceinline__ long long fac_reserve(const ColOut &o, int q) {
+    const unsigned long long need = (unsigned long long)(q + q * (q + 1) / 2);
+    const unsigned long long at = atomicAdd(o.fac_cur, need);
+    return (at + need <= (unsigned long long)o.fac_cap) ? (long long)at : -1LL;
+}
+__host__ __device__ inline int64_t fac_row(int q, int i) { return q + (int64_t)i * q - (int64_t)i * (i - 1) / 2; }
 
 // ----------------------------------------------------------------- DPP helpers
 // Data-parallel-primitive lane moves within a 16-lane row. Patterns used:

@@ -316,6 +316,13 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
     wide_rec_cap[0] = std::min<int64_t>(ncols, std::max<int64_t>(4096, ncols / 64));
     wide_rec_cap[1] = std::min<int64_t>(ncols, std::max<int64_t>(4096, ncols / 256));
 
+    // R factors kept for the adjoint: an arena of the requested size (default 256 MB);
+    // columns that do not fit are refactorised by the adjoint
+    const int64_t fac_cap = P->p.keep_factors
+                                ? std::max<int64_t>(1, (P->p.factor_budget_bytes > 0 ? P->p.factor_budget_bytes
+                                                                                     : (int64_t)256 << 20) / 8)
+                                : 0;
+
     // ---- every device buffer of the build, from one allocation
     std::vector<int32_t *> fillpos(count);
     auto layout = [&](Layout &L) {
@@ -346,6 +353,17 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
         P->out.flops = L.take<double>(ncols);
         P->out.arenaJ = L.take<int32_t>(acap);
         P->out.arenaV = L.take<double>(acap);
+        if (fac_cap > 0) {
+            P->out.fac = L.take<double>(fac_cap);
+            P->out.fac_cur = L.take<unsigned long long>(1);
+            P->out.foff = L.take<int64_t>(ncols);
+            P->out.fac_cap = fac_cap;
+        } else {
+            P->out.fac = nullptr;
+            P->out.fac_cur = nullptr;
+            P->out.foff = nullptr;
+            P->out.fac_cap = 0;
+        }
         P->rec_count = L.take<int32_t>(nlaunch + 1);
         for (int t = 0; t < 8; ++t) P->rec[t] = nullptr;
         if (plain) {
@@ -397,6 +415,13 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
             int64_t fc[6] = {4, 4 * (int64_t)count, nlaunch + 1, ncols, ncols, 0};
             int32_t fv[6] = {0, 0, 0, ST_INTERNAL, 0, 0};  // every column's status must be written
             launch_fill_many(fp, fc, fv, 5, s);
+        }
+        if (P->out.fac) {
+            // no factor record yet: foff = -1 (two int32 -1 words), cursor = 0
+            int32_t *fp[6] = {(int32_t *)P->out.foff, (int32_t *)P->out.fac_cur, nullptr, nullptr, nullptr, nullptr};
+            int64_t fc[6] = {2 * ncols, 2, 0, 0, 0, 0};
+            int32_t fv[6] = {-1, 0, 0, 0, 0, 0};
+            launch_fill_many(fp, fc, fv, 2, s);
         }
         if (P->p.validate)
             for (int i = 0; i < count; ++i) launch_validate(As[i].n, As[i].nnz, As[i].colptr, As[i].rowidx, P->err, s);
@@ -825,20 +850,23 @@ rsai_status rsai_backward(rsai_plan *P, int32_t mat, const double *dM_val, doubl
     if (!dA_val) return fail(RSAI_E_ARG, "dA_val is NULL");
     MatPlan &M = P->mats[mat];
     hipStream_t s = (hipStream_t)stream;
+    const int64_t *foff = P->out.foff ? P->out.foff + M.col_base : nullptr;
     if (M.maxq < 0) {
+        // largest |J_k|, and largest |I_k| among the columns without a kept factor
         int32_t *d2 = P->alloc<int32_t>(2, st);
         if (st != RSAI_OK) return st;
         int32_t h2[2] = {0, 0};
         launch_fill_i32(d2, 0, 2, P->stream);
-        launch_max2(M.A.n, P->out.nJ + M.col_base, P->out.nI + M.col_base, d2, P->stream);
+        launch_max2(M.A.n, P->out.nJ + M.col_base, P->out.nI + M.col_base, foff, d2, P->stream);
         HIPCHK(hipMemcpyAsync(h2, d2, sizeof(h2), hipMemcpyDeviceToHost, P->stream));
         HIPCHK(hipStreamSynchronize(P->stream));
         M.maxq = h2[0];
         M.maxm = h2[1];
     }
-    if (M.maxq > backward_max_cols() || M.maxm > backward_max_rows())
-        return fail(RSAI_E_CAP, "adjoint supports |J_k| <= %d and |I_k| <= %d; this M has %d and %d",
-                    backward_max_cols(), backward_max_rows(), M.maxq, M.maxm);
+    const int qlim = foff ? std::min(backward_max_cols(), backward_factored_max_cols()) : backward_max_cols();
+    if (M.maxq > qlim || M.maxm > backward_max_rows())
+        return fail(RSAI_E_CAP, "adjoint supports |J_k| <= %d and (without a kept factor) |I_k| <= %d; "
+                    "this M has %d and %d", qlim, backward_max_rows(), M.maxq, M.maxm);
     BwdArgs a{};
     a.mats = P->d_mats;
     a.mat = mat;
@@ -850,7 +878,10 @@ rsai_status rsai_backward(rsai_plan *P, int32_t mat, const double *dM_val, doubl
     a.w_frob = w_frob;
     a.dA = dA_val;
     a.err = P->err;
+    a.fac = P->out.fac;
+    a.foff = foff;
     P->record(5, s);
+    if (foff) launch_backward_factored(a, device_cus() * 8, s);
     launch_backward(a, device_cus() * 8, s);
     P->record(6, s);
     HIPCHK(hipGetLastError());

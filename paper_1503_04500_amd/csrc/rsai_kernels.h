@@ -115,10 +115,15 @@ struct BwdArgs {
     double w_frob;
     double *dA;
     int32_t *err;
+    const double *fac;      // kept R factors (nullable)
+    const int64_t *foff;    // per column of this matrix: record offset or -1 (nullable)
 };
 int backward_max_cols();
 int backward_max_rows();
-void launch_max2(int64_t n, const int32_t *a, const int32_t *b, int32_t *out2, hipStream_t s);
+int backward_factored_max_cols();
+// out2[0] = max a; out2[1] = max b over the entries with mask < 0 (all if mask is null)
+void launch_max2(int64_t n, const int32_t *a, const int32_t *b, const int64_t *mask, int32_t *out2, hipStream_t s);
 void launch_backward(const BwdArgs &a, int waves, hipStream_t s);
+void launch_backward_factored(const BwdArgs &a, int waves, hipStream_t s);
 
 }  // namespace rsai

@@ -859,6 +859,33 @@ __global__ __launch_bounds__(64, RSAI_TIER_WAVES_PER_SIMD) void tier_kernel(Tier
                 args.out.resnorm[ucol] = rn;
                 args.out.flops[ucol] = fl;
             }
+            // R of the final solve for the adjoint: row i of R is held by the owner lane
+            // of row i (diagonal in rd, the rest in the block)
+            if (args.out.fac != nullptr) {
+                long long fo = -1;
+                if (gl == 0) {
+                    fo = (qq > 0) ? fac_reserve(args.out, qq) : -1LL;
+                    args.out.foff[ucol] = fo;
+                }
+                const int flo = gbcast_i<G>((int)(fo & 0xffffffffLL), gl == 0);
+                const int fhi = gbcast_i<G>((int)(fo >> 32), gl == 0);
+                fo = ((long long)fhi << 32) | (long long)(unsigned)flo;
+                if (fo >= 0) {
+                    double *F = args.out.fac + fo;
+                    for (int c = gl; c < qq; c += G) F[c] = (double)S.Jlist[c];
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r) {
+                        const int i = r * G + gl;
+                        if (i < qq) {
+                            double *Fr = F + fac_row(qq, i);
+                            Fr[0] = rd[r];
+#pragma unroll
+                            for (int c = 0; c < QMAX; ++c)
+                                if (c > i && c < qq) Fr[c - i] = b[r][c];
+                        }
+                    }
+                }
+            }
             busy = false;
         }
         wave_sync();

@@ -771,6 +771,27 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
             args.out.resnorm[ucol] = rn;
             args.out.flops[ucol] = fl;
         }
+        if (args.out.fac != nullptr) {
+            // R of the final (compressed) solve: R^T R = A(I,J)^T A(I,J); rows 0..q-1 of
+            // the block hold its strict upper part, rd the diagonal
+            if (tid == 0) {
+                const long long fo = (qq > 0) ? fac_reserve(args.out, qq) : -1LL;
+                args.out.foff[ucol] = fo;
+                S.cnt = (int)(fo & 0xffffffffLL);
+                S.nsh = (int)(fo >> 32);
+            }
+            __syncthreads();
+            const long long fo = ((long long)S.nsh << 32) | (long long)(unsigned)S.cnt;
+            if (fo >= 0) {
+                double *F = args.out.fac + fo;
+                const int ld = qq + 1;
+                for (int c = tid; c < qq; c += NT) F[c] = (double)S.Jl[c];
+                for (int t = tid; t < qq * qq; t += NT) {
+                    const int i = t / qq, c = t % qq;
+                    if (c >= i) F[fac_row(qq, i) + (c - i)] = (c == i) ? S.rd[i] : S.blk[i * ld + c];
+                }
+            }
+        }
         __syncthreads();
     }
 }

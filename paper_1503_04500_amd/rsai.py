@@ -166,7 +166,7 @@ class Matrix:
 
 
 def params(c=3, lmax=10, eps=0.4, drop="fixed", tol=1e-3, sched="batched", validate=True, tier0=-1,
-           timing=False, refill=-1, route=-1):
+           timing=False, refill=-1, route=-1, keep_factors=False, factor_budget_bytes=0):
     p = Params()
     _check(load().rsai_params_default(ctypes.byref(p)))
     p.c, p.lmax, p.eps, p.tol = int(c), int(lmax), float(eps), float(tol)
@@ -177,6 +177,8 @@ def params(c=3, lmax=10, eps=0.4, drop="fixed", tol=1e-3, sched="batched", valid
     p.timing = 1 if timing else 0
     p.refill = int(refill)
     p.route = int(route)
+    p.keep_factors = 1 if keep_factors else 0
+    p.factor_budget_bytes = int(factor_budget_bytes)
     return p
 
 

@@ -25,12 +25,21 @@ def _oracle_grad(A, Mcp, Mri, b):
     return dA, gM
 
 
-@pytest.mark.parametrize("name", ["c1", "cd3d20"])
-def test_backward_kernel_vs_oracle(name):
+@pytest.mark.parametrize("name,keep", [("c1", False), ("cd3d20", False), ("c1", True), ("cd3d20", True),
+                                       ("cd3d20", "tiny"), ("cd3d12", True), ("powerlaw", True)])
+def test_backward_kernel_vs_oracle(name, keep):
+    """Refactorising adjoint, adjoint on the kept R factors, and a factor budget too
+    small for all columns (both kernels in one call); with kept factors the |I_k|
+    limit of the refactorising kernel does not apply (3D corner columns reach
+    |I| = 71, power-law columns |I| = 232)."""
     import torch
-    A = gen.c1() if name == "c1" else gen.cd3d(20, seed=1)
-    ref = oracle.rsai(A, **C1)
-    gpu = run_gpu(A, **C1)
+    A = {"c1": gen.c1, "cd3d20": lambda: gen.cd3d(20, seed=1), "cd3d12": lambda: gen.cd3d(12, seed=3),
+         "powerlaw": lambda: gen.powerlaw(3000, seed=11, lmax=20)}[name]()
+    kw = dict(C1, lmax=2) if name == "powerlaw" else C1
+    ref = oracle.rsai(A, **kw)
+    fk = {} if keep is False else (dict(keep_factors=True, factor_budget_bytes=8 * 20000) if keep == "tiny"
+                                   else dict(keep_factors=True))
+    gpu = run_gpu(A, **kw, **fk)
     b = np.random.default_rng(0).standard_normal(A.n)
     want, gM = _oracle_grad(A, ref["colptr"], ref["rowidx"], b)
     assert np.array_equal(gpu["rowidx"], ref["rowidx"])
@@ -49,7 +58,7 @@ def test_backward_reports_cap_for_oversize_columns():
     import torch
     import paper_1503_04500_amd.rsai as rsai
     A = gen.cd3d(12, seed=3)   # corner columns reach |J| = 26, |I| = 71
-    gpu = run_gpu(A, **C1)
+    gpu = run_gpu(A, keep_factors=False, **C1)
     dA = torch.zeros(A.nnz, dtype=torch.float64, device="cuda:0")
     with pytest.raises(rsai.RSAIError) as ei:
         gpu["plan"].backward(None, 1.0, dA)
