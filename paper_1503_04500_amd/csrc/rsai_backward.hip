@@ -45,13 +45,17 @@ int backward_max_cols() { return BQMAX; }
 int backward_max_rows() { return BMMAX; }
 
 __global__ void k_max2(int64_t n, const int32_t *a, const int32_t *b, const int64_t *mask, int32_t *out2) {
-    int ma = 0, mb = 0;
+    int ma = 0, mb = 0, nm = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         ma = max(ma, a[i]);
-        if (!mask || mask[i] < 0) mb = max(mb, b[i]);
+        if (!mask || mask[i] < 0) {
+            mb = max(mb, b[i]);
+            ++nm;
+        }
     }
     atomicMax(&out2[0], ma);
     atomicMax(&out2[1], mb);
+    atomicAdd(&out2[2], nm);
 }
 void launch_max2(int64_t n, const int32_t *a, const int32_t *b, const int64_t *mask, int32_t *out2, hipStream_t s) {
     hipLaunchKernelGGL(k_max2, dim3(256), dim3(256), 0, s, n, a, b, mask, out2);
@@ -338,13 +342,21 @@ void launch_backward(const BwdArgs &a, int waves, hipStream_t s) {
 // row-set hash, so |I_k| is not limited here.
 namespace {
 constexpr int FG = 16, FGPW = 64 / FG, FQ = 32, FLOGHJ = 7, FHJ = 1 << FLOGHJ;
+constexpr int FM = 128, FLOGHI = 8, FHI = 1 << FLOGHI;  // rows accumulated in LDS
 struct FLds {
     double z[FQ];       // z in ascending column order
     double u[FQ];       // R^{-T} g, solve order
+    double racc[FM];    // r_i and (A_k z)_i by local row (|I_k| <= FM)
+    double aacc[FM];
+    int64_t cb[FQ];     // first entry of each column of J
+    int pre[FQ + 1];    // prefix of the column lengths
     int js[FQ];         // J ascending (the order of M's column)
     int rk[FQ];         // position in ascending order of the solve-order slot
     int hJ[FHJ];        // column -> ascending position
     int hv[FHJ];
+    int hI[FHI];        // row -> local row
+    int hIv[FHI];
+    int cnt;
 };
 __device__ __forceinline__ int fhfind(const FLds &S, int key) {
     const int sl = hfind<FLOGHJ>(S.hJ, key);
@@ -435,8 +447,68 @@ __global__ __launch_bounds__(64) void backward_factored_kernel(BwdArgs a) {
             }
             wave_sync();
         }
-        // scatter onto the nonzeros of A(:, J_k); r_i and (A_k z)_i from row i's pattern
+        // entries of the columns of J, flattened: start and prefix of lengths
         if (act) {
+            for (int c = gl; c < q; c += G) {
+                const int j = S.js[c];
+                S.cb[c] = A.colptr[j];
+            }
+            if (gl == 0) {
+                int acc = 0;
+                for (int c = 0; c < q; ++c) {
+                    S.pre[c] = acc;
+                    acc += (int)(A.colptr[S.js[c] + 1] - A.colptr[S.js[c]]);
+                }
+                S.pre[q] = acc;
+                S.cnt = 0;
+            }
+        }
+        for (int t = gl; t < FHI; t += G) S.hI[t] = HEMPTY;
+        wave_sync();
+        const int tot = act ? S.pre[q] : 0;
+        // small I_k: r and A_k z accumulated once per row in LDS
+        bool small = act && tot <= FM;
+        if (wave_any(small)) {
+            for (int u = gl; u < tot && small; u += G) {
+                int c = 0;
+                while (c + 1 < q && S.pre[c + 1] <= u) ++c;
+                const int64_t e = S.cb[c] + (u - S.pre[c]);
+                int sl;
+                if (hinsert<FLOGHI>(S.hI, A.rowidx[e], sl)) {
+                    const int li = atomicAdd(&S.cnt, 1);
+                    S.hIv[sl] = li;
+                    S.racc[li] = 0.0;
+                    S.aacc[li] = 0.0;
+                }
+            }
+            wave_sync();
+            for (int u = gl; u < tot && small; u += G) {
+                int c = 0;
+                while (c + 1 < q && S.pre[c + 1] <= u) ++c;
+                const int64_t e = S.cb[c] + (u - S.pre[c]);
+                const int li = S.hIv[hfind<FLOGHI>(S.hI, A.rowidx[e])];
+                const double v = A.val[e];
+                atomicAdd(&S.racc[li], v * a.Mval[mb + c]);
+                atomicAdd(&S.aacc[li], v * S.z[c]);
+            }
+            wave_sync();
+            if (small) {
+                const double w2 = 2.0 * a.w_frob;
+                for (int u = gl; u < tot; u += G) {
+                    int c = 0;
+                    while (c + 1 < q && S.pre[c + 1] <= u) ++c;
+                    const int64_t e = S.cb[c] + (u - S.pre[c]);
+                    const int i = A.rowidx[e];
+                    const int li = S.hIv[hfind<FLOGHI>(S.hI, i)];
+                    const double ri = S.racc[li] - ((i == (int)k) ? 1.0 : 0.0), azi = S.aacc[li];
+                    const double zc = S.z[c], mc = a.Mval[mb + c];
+                    atomicAdd(&a.dA[e], -(ri * zc + azi * mc) + w2 * ri * mc);
+                }
+            }
+            wave_sync();
+        }
+        // larger I_k: r_i and (A_k z)_i from row i's pattern, per entry
+        if (act && !small) {
             const double w2 = 2.0 * a.w_frob;
             for (int c = 0; c < q; ++c) {
                 const int j = S.js[c];

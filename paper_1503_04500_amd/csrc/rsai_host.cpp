@@ -69,6 +69,7 @@ struct MatPlan {
     int64_t nnzM = -1;
     int64_t *summary = nullptr;  // device: nnz(M), error flags, failed-column counts
     int32_t maxq = -1, maxm = -1;  // largest final |J_k| and |I_k| (first backward)
+    int32_t nofac = -1;            // columns without a kept factor
     // transpose of M (rows) for y = M x
     int64_t *rowptrT = nullptr;
     int32_t *rowcntT = nullptr;  // 2n: row counts and fill positions
@@ -853,15 +854,16 @@ rsai_status rsai_backward(rsai_plan *P, int32_t mat, const double *dM_val, doubl
     const int64_t *foff = P->out.foff ? P->out.foff + M.col_base : nullptr;
     if (M.maxq < 0) {
         // largest |J_k|, and largest |I_k| among the columns without a kept factor
-        int32_t *d2 = P->alloc<int32_t>(2, st);
+        int32_t *d2 = P->alloc<int32_t>(3, st);
         if (st != RSAI_OK) return st;
-        int32_t h2[2] = {0, 0};
-        launch_fill_i32(d2, 0, 2, P->stream);
+        int32_t h2[3] = {0, 0, 0};
+        launch_fill_i32(d2, 0, 3, P->stream);
         launch_max2(M.A.n, P->out.nJ + M.col_base, P->out.nI + M.col_base, foff, d2, P->stream);
         HIPCHK(hipMemcpyAsync(h2, d2, sizeof(h2), hipMemcpyDeviceToHost, P->stream));
         HIPCHK(hipStreamSynchronize(P->stream));
         M.maxq = h2[0];
         M.maxm = h2[1];
+        M.nofac = h2[2];
     }
     const int qlim = foff ? std::min(backward_max_cols(), backward_factored_max_cols()) : backward_max_cols();
     if (M.maxq > qlim || M.maxm > backward_max_rows())
@@ -882,7 +884,7 @@ rsai_status rsai_backward(rsai_plan *P, int32_t mat, const double *dM_val, doubl
     a.foff = foff;
     P->record(5, s);
     if (foff) launch_backward_factored(a, device_cus() * 8, s);
-    launch_backward(a, device_cus() * 8, s);
+    if (!foff || M.nofac > 0) launch_backward(a, device_cus() * 8, s);
     P->record(6, s);
     HIPCHK(hipGetLastError());
     return RSAI_OK;
