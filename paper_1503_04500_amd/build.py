@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librsai.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["rsai_tier.hip", "rsai_wide.hip", "rsai_big.hip", "rsai_prep.hip", "rsai_backward.hip", "rsai_host.cpp"]
+SOURCES = ["rsai_tier.hip", "rsai_tier2.hip", "rsai_wide.hip", "rsai_big.hip", "rsai_prep.hip", "rsai_backward.hip", "rsai_host.cpp"]
 ARCH = os.environ.get("RSAI_ARCH", "gfx950")
 
 
@@ -32,6 +32,11 @@ def flags() -> list[str]:
             "-Wno-unused-command-line-argument", "-I", os.path.join(HERE, "..", "include")]
 
 
+# per-source flags: the tier kernel's QR loops must unroll completely (constant register
+# indices), which exceeds the default threshold for the larger tiers
+SOURCE_FLAGS = {"rsai_tier.hip": ["-mllvm", "-pragma-unroll-threshold=262144"]}
+
+
 def build(verbose: bool = False, extra: list[str] | None = None, out: str | None = None) -> str:
     """Compile all sources and link ``librsai.so`` (or ``out``). Returns the library path."""
     bdir = BUILD_DIR if out is None else BUILD_DIR + "_" + os.path.basename(out).replace(".so", "")
@@ -41,7 +46,7 @@ def build(verbose: bool = False, extra: list[str] | None = None, out: str | None
 
     def compile_one(src):
         obj = os.path.join(bdir, src + ".o")
-        cmd = [hipcc] + flags() + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc] + flags() + SOURCE_FLAGS.get(src, []) + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -28,9 +28,10 @@ namespace rsai {
 // [11] kept columns of the flop model of that solve.
 constexpr int RHDR = 12;
 
-template <int G_, int RPL_, int QMAX_, int STAGE_, int HSF_ = 2>
+template <int G_, int RPL_, int QMAX_, int STAGE_, int HSF_ = 2, int WPS_ = 2>
 struct TierCfg {
     static constexpr int G = G_, RPL = RPL_, QMAX = QMAX_, STAGE = STAGE_;
+    static constexpr int WPS = WPS_;  // waves per SIMD the register budget is cut for
     static constexpr int MMAX = G * RPL;
     static constexpr int GPW = 64 / G;
     static constexpr int LOGHSI = ilog2ceil(HSF_ * MMAX);  // row hash: HSF x MMAX slots
@@ -42,6 +43,9 @@ struct TierCfg {
     static constexpr int RJN = HSJ - QMAX - 1;  // (J)
     static constexpr int PREF = (QMAX > CMAX ? QMAX : CMAX) + 1;
     static constexpr int REC = RHDR + QMAX + MMAX + (MMAX + 1) + CMAX;  // spill record ints
+    // small tiers keep a row of every column in registers for the residual of step 4
+    // (all loads in flight together); larger tiers would spill those registers
+    static constexpr bool FASTSEL = QMAX <= 12;
     static_assert(RPL <= 32 && QMAX <= 32, "bit masks");
     static_assert(RIN >= 1 && RJN >= 1, "hash sizes");
     static_assert(QMAX <= MMAX, "row j of the block must exist for every column j");
@@ -93,6 +97,7 @@ struct GLds {
     int hJ[C::HSJ];
     int Rh[CMAX];             // pending dominant rows
     int cnt;
+    int fo_lo, fo_hi;         // factor record of a finished column (kept R)
     int pad;
     unsigned char hIv[C::HSI];  // local row of each key in hI
 
@@ -109,5 +114,23 @@ struct GLds {
     static_assert(C::MMAX * 8 + C::QMAX * 4 <= C::STAGE * C::MMAX * 8, "scratch fits the tile");
     static_assert(C::MMAX < 256, "local rows fit a byte");
 };
+
+
+// ----------------------------------------------------------------- tiers
+// t0: up to 24 x 12 blocks (2D 5-point stencils), 8 columns per wave
+// t1: up to 64 x 24 blocks (3D 7-point stencils), 4 columns per wave; one wave per
+//     SIMD so that the fully unrolled QR keeps its 96 block entries per lane in
+//     registers
+// t2: up to 128 x 32 blocks, 4 columns per wave
+#ifndef RSAI_T0_STAGE
+#define RSAI_T0_STAGE 4
+#endif
+#ifndef RSAI_T0_HSF
+#define RSAI_T0_HSF 2
+#endif
+using Tier0 = TierCfg<8, 3, 12, RSAI_T0_STAGE, RSAI_T0_HSF>;
+using Tier1 = TierCfg<16, 4, 24, 4, 2, 1>;
+using Tier2 = TierCfg<16, 8, 32, 4, 2, 2>;
+void launch_tier2(const TierArgs &a, int waves, hipStream_t s);
 
 }  // namespace rsai
