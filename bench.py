@@ -145,6 +145,22 @@ def main():
     bytes_alg = (nnz * (8 + 4) + (n + 1) * 8) + (nnz * 4 + (n + 1) * 8) + nnzM * (4 + 8) + n * (8 + 4 * 4 + 8 * 3)
     hbm_gbs = bytes_alg / (t0_ms * 1e-3) / 1e9
 
+    # ---- the same build replayed as a captured HIP graph on the plan's buffers
+    # (rsai_rebuild: no allocation, no host-side setup)
+    gp = rsai.build(A, sched="batched", **PARAMS)
+    gp.nnz()
+    for _ in range(args.warmup + 1):
+        gp.rebuild(graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        gp.rebuild(graph=True)
+    torch.cuda.synchronize()
+    dt_g = (time.perf_counter() - t0) / args.steps
+    graph = {"value": H.n / dt_g, "ms_per_step": dt_g * 1e3, "unit": "columns/s",
+             "nnzM_equal": gp.nnz() == nnzM}
+    gp.close()
+
     # ---- plain schedule
     plain = None
     if not args.no_plain:
@@ -250,6 +266,7 @@ def main():
                      "hbm_alg_bytes": bytes_alg, "hbm_achieved_GBs": hbm_gbs, "hbm_frac": hbm_gbs / HBM_PEAK_GBS},
         "plain": plain,
         "speedup_vs_plain": (plain["ms_per_step"] / (dt_b * 1e3)) if plain else None,
+        "graph_rebuild": graph,
         "fwd_bwd_ms": fwd_bwd_ms,
         "extra": extra,
         "build_event_ms": float(np.median(build_ms)),
