@@ -314,8 +314,9 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
     // records out of each sparse-block instance: few columns need the next class;
     // more than this many end with RSAI_E_CAP
     int64_t wide_rec_cap[WIDE_LEVELS];
-    wide_rec_cap[0] = std::min<int64_t>(ncols, std::max<int64_t>(4096, ncols / 64));
-    wide_rec_cap[1] = std::min<int64_t>(ncols, std::max<int64_t>(4096, ncols / 256));
+    wide_rec_cap[0] = std::min<int64_t>(ncols, std::max<int64_t>(4096, ncols / 4));
+    wide_rec_cap[1] = std::min<int64_t>(ncols, std::max<int64_t>(4096, ncols / 64));
+    wide_rec_cap[2] = std::min<int64_t>(ncols, std::max<int64_t>(4096, ncols / 256));
 
     // R factors kept for the adjoint: an arena of the requested size (default 256 MB);
     // columns that do not fit are refactorised by the adjoint
@@ -510,16 +511,17 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
                     a.rec_in_cap = ncols;
                 }
                 // queues of the later classes: queue i feeds class t + 1 + i (the register
-                // tiers, then the sparse-block class); records use the stride its reader expects
+                // tiers, then the first two sparse-block levels); records use the stride
+                // their reader expects
                 a.nq = 0;
                 const int nq_max = route_default(P->p.route) ? TierArgs::MAXQ : 1;
-                for (int c = t + 1; c <= tlast + (big ? 1 : 0) && a.nq < nq_max; ++c) {
+                for (int c = t + 1; c <= tlast + (big ? 2 : 0) && a.nq < nq_max; ++c) {
                     const int i = a.nq++;
                     a.q_rec[i] = P->rec[c - 1];
-                    a.q_stride[i] = kTiers[c - 1].REC;
+                    a.q_stride[i] = c <= tlast + 1 ? kTiers[c - 1].REC : wide_rec_stride(0);
                     a.q_count[i] = P->rec_count + (c - 1 - t0);
-                    a.q_cap[i] = ncols;
-                    a.q_mmax[i] = c <= tlast ? kTiers[c].MMAX : wide_max_rows(0);
+                    a.q_cap[i] = c <= tlast + 1 ? ncols : wide_rec_cap[0];
+                    a.q_mmax[i] = c <= tlast ? kTiers[c].MMAX : wide_max_rows(c - tlast - 1);
                     a.q_qmax[i] = c <= tlast ? kTiers[c].QMAX : WIDE_QMAX;
                 }
                 const int gpw = 64 / kTiers[t].G;

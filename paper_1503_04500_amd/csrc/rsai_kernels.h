@@ -19,7 +19,7 @@ void launch_tier_kernel(int tier, const TierArgs &a, int waves, hipStream_t s);
 
 // ---- sparse-block size class (rsai_wide.hip): one workgroup per column, LS solved
 // on the compressed block (shared rows + one row per column)
-constexpr int WIDE_LEVELS = 2;   // instances: |I| <= 2048, |I| <= 8192
+constexpr int WIDE_LEVELS = 3;   // instances: |I| <= 1024, 2048, 8192
 constexpr int WIDE_QMAX = 63;    // columns of J
 constexpr int WIDE_RCAP = 8 * 64 + 1;  // dominant rows in a record: c * lmax + 1
 struct WideArgs {

@@ -32,8 +32,8 @@ constexpr int QM = WIDE_QMAX;
 constexpr int LOGHJ = 8;                // column hash: 256 slots
 constexpr int HJ = 1 << LOGHJ;
 
-// Two instances: rows of I up to 2048 (4096-slot row hash, three workgroups per CU)
-// and up to 8192 (16384 slots, one workgroup per CU, larger compressed blocks).
+// Three instances: rows of I up to 1024 (2048-slot row hash, four workgroups per CU),
+// up to 2048 (three per CU) and up to 8192 (one per CU, larger compressed blocks).
 //   BLK  doubles of the compressed block, (S + q) x (q + 1), row-major
 //   SHV  doubles of the shared rows' values, S x q
 //   SMAX shared rows
@@ -797,10 +797,11 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
 }
 
 namespace {
-constexpr int kWideLogH[2] = {12, 14};
-constexpr int kWidePerCU[2] = {3, 1};
+constexpr int kWideLogH[WIDE_LEVELS] = {11, 12, 14};
+constexpr int kWidePerCU[WIDE_LEVELS] = {4, 3, 1};
 #define RSAI_WIDE0 kWideLogH[0], 2048, 768, 128, kWidePerCU[0]
-#define RSAI_WIDE1 kWideLogH[1], 6144, 1536, 256, kWidePerCU[1]
+#define RSAI_WIDE1 kWideLogH[1], 2048, 768, 128, kWidePerCU[1]
+#define RSAI_WIDE2 kWideLogH[2], 6144, 1536, 256, kWidePerCU[2]
 }  // namespace
 
 int wide_max_rows(int level) { return (1 << kWideLogH[level]) / 2; }
@@ -810,8 +811,10 @@ int wide_blocks_per_cu(int level) { return kWidePerCU[level]; }
 void launch_wide_kernel(int level, const WideArgs &a, int blocks, hipStream_t s) {
     if (level == 0)
         hipLaunchKernelGGL((wide_kernel<RSAI_WIDE0>), dim3(blocks), dim3(NT), 0, s, a);
-    else
+    else if (level == 1)
         hipLaunchKernelGGL((wide_kernel<RSAI_WIDE1>), dim3(blocks), dim3(NT), 0, s, a);
+    else
+        hipLaunchKernelGGL((wide_kernel<RSAI_WIDE2>), dim3(blocks), dim3(NT), 0, s, a);
 }
 
 }  // namespace rsai
