@@ -270,10 +270,14 @@ def _tuned(mats, kw):
     if kw.get("sched", "batched") not in ("batched", 0) or all(kw.get(k, -1) != -1 for k in keys):
         return kw
     from . import tune
-    n = sum(m.n for m in mats)
-    ch = tune.choose(n, sum(m.nnz for m in mats) / max(n, 1), max(m.max_col_len for m in mats))
-    if not ch:
+    # one choice per matrix; a batch starts in the smallest tier any of its matrices
+    # wants (a column that outgrows it moves on; one that starts too large is slow)
+    chs = [c for c in (tune.choose(m.n, m.nnz / max(m.n, 1), m.max_col_len) for m in mats) if c]
+    if not chs:
         return kw
+    big = max(range(len(mats)), key=lambda i: mats[i].n)
+    ch = {"tier0": min(c["tier0"] for c in chs), "refill": chs[min(big, len(chs) - 1)]["refill"],
+          "route": max(c["route"] for c in chs)}
     kw = dict(kw)
     for k in keys:
         if kw.get(k, -1) == -1:
