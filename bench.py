@@ -58,7 +58,7 @@ def measured_traffic():
             k, v = line.strip().split(":", 1)
             kv[k.strip()] = v.strip()
     h = hashlib.sha256()
-    for f in ("rsai_tier.hip", "rsai_tier.h", "rsai_dev.h"):
+    for f in ("rsai_tier.hip", "rsai_tier_kernel.h", "rsai_tier.h", "rsai_dev.h"):
         with open(os.path.join(ROOT, "paper_1503_04500_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     if kv.get("kernel_source_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in kv:

@@ -37,3 +37,23 @@ def test_params_route_field():
     p = rsai.params(route=0, refill=1, tier0=2)
     assert (p.route, p.refill, p.tier0) == (0, 1, 2)
     assert rsai.params().route == -1
+
+
+def test_bench_traffic_requires_matching_kernel_sources(tmp_path, monkeypatch):
+    """bench.py reports the counter-derived HBM traffic only while the tier kernel's
+    sources hash to the value recorded beside the counters."""
+    import shutil
+    import bench
+    root = tmp_path
+    (root / "profiles").mkdir()
+    (root / "paper_1503_04500_amd" / "csrc").mkdir(parents=True)
+    src = os.path.join(bench.ROOT, "paper_1503_04500_amd", "csrc")
+    for f in ("rsai_tier.hip", "rsai_tier_kernel.h", "rsai_tier.h", "rsai_dev.h"):
+        shutil.copy(os.path.join(src, f), root / "paper_1503_04500_amd" / "csrc" / f)
+    shutil.copy(os.path.join(bench.ROOT, "profiles", "tier_kernel_cd2d512_pmc.md"), root / "profiles")
+    monkeypatch.setattr(bench, "ROOT", str(root))
+    got = bench.measured_traffic()
+    assert got is not None and got > 0
+    with open(root / "paper_1503_04500_amd" / "csrc" / "rsai_tier.hip", "a") as f:
+        f.write("\n// changed\n")
+    assert bench.measured_traffic() is None
