@@ -211,7 +211,28 @@ def main():
             p5.close()
         torch.cuda.synchronize()
         dt5 = (time.perf_counter() - t0) / 3
+        # the same 64 matrices built one after another, and the batched build replayed
+        # as a captured graph
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for a5 in A5:
+            p1 = rsai.build(a5, **PARAMS)
+            p1.nnz()
+            p1.close()
+        torch.cuda.synchronize()
+        dt5s = time.perf_counter() - t0
+        p5 = rsai.build_batched(A5, **PARAMS)
+        p5.nnz()
+        p5.rebuild(graph=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            p5.rebuild(graph=True)
+        torch.cuda.synchronize()
+        dt5g = (time.perf_counter() - t0) / 3
+        p5.close()
         extra["batch64"] = {"value": n5 / dt5, "unit": "columns/s", "ms_per_step": dt5 * 1e3,
+                            "sequential_ms": dt5s * 1e3, "graph_replay_ms": dt5g * 1e3,
                             "workload": f"64 matrices in one build (2D/3D convection-diffusion, power-law; "
                                         f"sum n = {n5})"}
         del A5, H5
@@ -243,6 +264,11 @@ def main():
             reps += 1
         cpu = {"value": reps * n / tot, "unit": "columns/s", "cores": int(thr), "kind": "oracle",
                "sample": f"the full {args.grid}x{args.grid} matrix ({n} columns) built {reps} times"}
+        # one host thread, on a seeded sample of 32768 columns
+        cols = np.sort(np.random.default_rng(0).choice(n, 32768, replace=False))
+        R1 = oracle.rsai(H, c=3, lmax=8, eps=0.4, drop=oracle.DROP_FIXED, tol=1e-3, threads=1, cols=cols)
+        cpu["one_core"] = {"value": cols.size / R1["seconds"], "unit": "columns/s", "cores": 1,
+                           "sample": "32768 seeded columns of the same matrix"}
 
     out = {
         "metric": METRIC,

@@ -29,6 +29,9 @@ constexpr int BH = 1 << BLOGH;
 constexpr int BLOGHJ = 8;                  // column hash: 256 slots
 constexpr int BHJ = 1 << BLOGHJ;
 constexpr int SORTN = 8192;                // bitonic buffer for new rows
+constexpr int NB = 16;                     // panel width of the blocked QR
+constexpr int NCTMAX = (BQMAX_BIG + 1 - NB + 15) / 16;  // column tiles after a panel (+ Q^T e)
+constexpr int REDN = NW * (NCTMAX + 1) * 256;            // doubles of per-wave MFMA partials
 
 struct BigLds {
     int hI[BH];
@@ -40,6 +43,8 @@ struct BigLds {
     double rd[BQMAX_BIG];
     double bt[BQMAX_BIG];
     double red[NW * 8];
+    double Tm[16 * 16];            // T of the compact WY form of a panel
+    double Wp[16 * NCTMAX * 16];   // T^T V^T C of a panel
     int ired[NW * 2];
     double dred[NW];
     int Rh[CMAX];
@@ -100,6 +105,123 @@ __device__ __forceinline__ void bargmax(double &a, int &g, BigLds &S) {
     __syncthreads();
 }
 
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+
+// V(r, i) of the current panel: reflector i (column p0 + i) below its diagonal,
+// its head on the diagonal, zero above and outside the panel or the block
+__device__ __forceinline__ double vget(const double *B, int m, int p0, int pw, int r, int i) {
+    if (i >= pw || r >= m || r < p0 + i) return 0.0;
+    return B[(int64_t)(p0 + i) * BMMAX_BIG + r];
+}
+// column c of the trailing part: a column of the block, or Q^T e for c == qn
+__device__ __forceinline__ double *colp(double *B, double *y, int qn, int c) {
+    return (c < qn) ? B + (int64_t)c * BMMAX_BIG : y;
+}
+
+// Apply Q_p^T = I - V T^T V^T of the panel (columns p0 .. p0+pw-1, pw <= 16) to the
+// ntr columns c_lo .. c_lo+ntr-1 (the last one is Q^T e). W = V^T C and the Gram
+// matrix V^T V are FP64 MFMA reductions over the rows, split across the waves;
+// C -= V (T^T W) is an MFMA per 16x16 tile of C.
+// MFMA 16x16x4 f64 operands (lane l): A(l % 16, l / 16), B(l / 16, l % 16); result
+// element t of lane l is D(l / 16 + 4 t, l % 16).
+__device__ void panel_update(double *B, double *y, int m, int qn, int p0, int pw, int c_lo, int ntr,
+                             BigLds &S, double *red) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int nct = (ntr + 15) / 16;  // column tiles of the trailing part (<= 5)
+    // red: [NW][NCTMAX + 1][64][4] partials in the workgroup's slab
+    // ---- G = V^T V (tile 0) and W = V^T C (tiles 1..nct), K = rows p0..m-1
+    mfma_d4 acc[NCTMAX + 1];
+#pragma unroll
+    for (int t = 0; t <= NCTMAX; ++t) acc[t] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+    for (int r0 = p0 + 4 * w; r0 < m; r0 += 4 * NW) {
+        const int r = r0 + lk;
+        const double a = vget(B, m, p0, pw, r, li);
+        acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, a, acc[0], 0, 0, 0);
+#pragma unroll
+        for (int t = 0; t < NCTMAX; ++t) {
+            if (t < nct) {
+                const int c = c_lo + 16 * t + li;
+                const double bv = (c < c_lo + ntr && r < m) ? colp(B, y, qn, c)[r] : 0.0;
+                acc[t + 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[t + 1], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t <= NCTMAX; ++t)
+        if (t <= nct)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) red[((w * (NCTMAX + 1) + t) * 64 + lane) * 4 + e] = acc[t][e];
+    __syncthreads();
+    // sum over the waves into wave 0's slots; element (row, col) of tile t sits in
+    // lane col + 16 * (row % 4), entry row / 4
+    for (int x = tid; x < (nct + 1) * 256; x += NT) {
+        double v = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) v += red[(ww * (NCTMAX + 1)) * 256 + x];
+        red[x] = v;
+    }
+    __syncthreads();
+    auto tile = [&](int t, int row, int col) -> double {
+        return red[(t * 64 + col + 16 * (row & 3)) * 4 + (row >> 2)];
+    };
+    // ---- T (upper triangular): T(j,j) = beta_j, T(0:j, j) = -beta_j T(0:j,0:j) G(0:j, j)
+    double *T = S.Tm;  // [16][16], row-major
+    if (tid < 64) {
+        for (int j = 0; j < pw; ++j) {
+            double v = 0.0;
+            if (lane < j) {
+                for (int t = lane; t < j; ++t) v += T[lane * 16 + t] * tile(0, t, j);
+                v *= -S.bt[p0 + j];
+            }
+            if (lane < j) T[lane * 16 + j] = v;
+            if (lane == j) T[j * 16 + j] = S.bt[p0 + j];
+            if (lane > j && lane < 16) T[lane * 16 + j] = 0.0;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+    }
+    __syncthreads();
+    // ---- W' = T^T W (16 x ntr), stored as Wp[i][c]
+    double *Wp = S.Wp;  // [16][NCTMAX * 16]
+    for (int x = tid; x < 16 * nct * 16; x += NT) {
+        const int i = x / (nct * 16), c = x % (nct * 16);
+        double v = 0.0;
+        if (i < pw)
+            for (int t = 0; t <= i; ++t) v += T[t * 16 + i] * tile(1 + c / 16, t, c % 16);
+        Wp[i * (NCTMAX * 16) + c] = v;
+    }
+    __syncthreads();
+    // ---- C -= V W': 16-row tiles of rows p0..m-1 times the column tiles
+    const int nrt = (m - p0 + 15) / 16;
+    for (int x = w; x < nrt * nct; x += NW) {
+        const int rt = x / nct, ct = x % nct;
+        const int r0 = p0 + 16 * rt;
+        const int c = c_lo + 16 * ct + li;
+        const bool cok = c < c_lo + ntr;
+        double *cp = cok ? colp(B, y, qn, c) : nullptr;
+        mfma_d4 d;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r = r0 + lk + 4 * e;
+            d[e] = (cok && r < m) ? cp[r] : 0.0;
+        }
+#pragma unroll
+        for (int k0 = 0; k0 < 16; k0 += 4) {
+            const double a = -vget(B, m, p0, pw, r0 + li, k0 + lk);
+            const double bv = Wp[(k0 + lk) * (NCTMAX * 16) + 16 * ct + li];
+            d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, d, 0, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r = r0 + lk + 4 * e;
+            if (cok && r < m) cp[r] = d[e];
+        }
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
     __shared__ BigLds S;
     const int tid = threadIdx.x;
@@ -111,6 +233,7 @@ __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
     double *racc = y + BMMAX_BIG;                                          // residual
     int *Il = reinterpret_cast<int *>(racc + BMMAX_BIG);                   // rows of I
     unsigned char *rfl = reinterpret_cast<unsigned char *>(Il + BMMAX_BIG);  // row in R
+    double *gred = racc + BMMAX_BIG + (BMMAX_BIG * 5 + 7) / 8 + 8;           // panel partials
 
     for (int64_t pos = blockIdx.x; pos < Q; pos += gridDim.x) {
         const int32_t *rec = args.rec_in + pos * (int64_t)args.rec_in_stride;
@@ -336,70 +459,77 @@ __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
                 }
                 __syncthreads();
                 bool singular = false;
-                for (int j = 0; j < qn; ++j) {
-                    double *bj = B + (int64_t)j * BMMAX_BIG;
-                    double s2 = 0.0;
-                    for (int i = j + tid; i < m; i += NT) s2 += bj[i] * bj[i];
-                    s2 = bsum(s2, S);
-                    const double x0 = bj[j];
-                    const double nx = sqrt(s2);
-                    const double alpha = (x0 >= 0.0) ? -nx : nx;
-                    const double vj = x0 - alpha;
-                    const double be = (nx > 0.0) ? 1.0 / (nx * (nx + fabs(x0))) : 0.0;
-                    if (!(nx > 0.0)) singular = true;
-                    __syncthreads();
-                    if (tid == 0) {
-                        bj[j] = vj;
-                        S.rd[j] = alpha;
-                        S.bt[j] = be;
-                    }
-                    __syncthreads();
-                    // trailing columns and Q^T e, eight at a time
-                    for (int c0 = j + 1; c0 <= qn; c0 += 8) {
-                        double part[8];
+                // Blocked Householder QR: panels of NB columns are factored column by
+                // column; the rest of the block (and Q^T e) is updated once per panel
+                // with the compact WY form Q_p = I - V T V^T (FP64 MFMA 16x16x4).
+                for (int p0 = 0; p0 < qn; p0 += NB) {
+                    const int pw = min(NB, qn - p0);
+                    for (int j = p0; j < p0 + pw; ++j) {
+                        double *bj = B + (int64_t)j * BMMAX_BIG;
+                        double s2 = 0.0;
+                        for (int i = j + tid; i < m; i += NT) s2 += bj[i] * bj[i];
+                        s2 = bsum(s2, S);
+                        const double x0 = bj[j];
+                        const double nx = sqrt(s2);
+                        const double alpha = (x0 >= 0.0) ? -nx : nx;
+                        const double vj = x0 - alpha;
+                        const double be = (nx > 0.0) ? 1.0 / (nx * (nx + fabs(x0))) : 0.0;
+                        if (!(nx > 0.0)) singular = true;
+                        __syncthreads();
+                        if (tid == 0) {
+                            bj[j] = vj;
+                            S.rd[j] = alpha;
+                            S.bt[j] = be;
+                        }
+                        __syncthreads();
+                        // the remaining columns of the panel, eight at a time
+                        for (int c0 = j + 1; c0 < p0 + pw; c0 += 8) {
+                            double part[8];
 #pragma unroll
-                        for (int u = 0; u < 8; ++u) part[u] = 0.0;
-                        for (int i = j + tid; i < m; i += NT) {
-                            const double vi = bj[i];
+                            for (int u = 0; u < 8; ++u) part[u] = 0.0;
+                            for (int i = j + tid; i < m; i += NT) {
+                                const double vi = bj[i];
+#pragma unroll
+                                for (int u = 0; u < 8; ++u) {
+                                    const int c = c0 + u;
+                                    if (c < p0 + pw) part[u] += vi * B[(int64_t)c * BMMAX_BIG + i];
+                                }
+                            }
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) part[u] = gsum<16>(part[u]);
+                            const int lane = tid & 63, w = tid >> 6;
 #pragma unroll
                             for (int u = 0; u < 8; ++u) {
-                                const int c = c0 + u;
-                                if (c < qn) part[u] += vi * B[(int64_t)c * BMMAX_BIG + i];
-                                else if (c == qn) part[u] += vi * y[i];
+                                part[u] += __shfl_xor(part[u], 16);
+                                part[u] += __shfl_xor(part[u], 32);
                             }
-                        }
+                            if (lane == 0)
 #pragma unroll
-                        for (int u = 0; u < 8; ++u) part[u] = gsum<16>(part[u]);
-                        const int lane = tid & 63, w = tid >> 6;
-#pragma unroll
-                        for (int u = 0; u < 8; ++u) {
-                            part[u] += __shfl_xor(part[u], 16);
-                            part[u] += __shfl_xor(part[u], 32);
-                        }
-                        if (lane == 0)
-#pragma unroll
-                            for (int u = 0; u < 8; ++u) S.red[w * 8 + u] = part[u];
-                        __syncthreads();
-                        double wv[8];
-#pragma unroll
-                        for (int u = 0; u < 8; ++u) {
-                            double t = 0.0;
-#pragma unroll
-                            for (int ww = 0; ww < NW; ++ww) t += S.red[ww * 8 + u];
-                            wv[u] = t * be;
-                        }
-                        __syncthreads();
-                        for (int i = j + tid; i < m; i += NT) {
-                            const double vi = bj[i];
+                                for (int u = 0; u < 8; ++u) S.red[w * 8 + u] = part[u];
+                            __syncthreads();
+                            double wv[8];
 #pragma unroll
                             for (int u = 0; u < 8; ++u) {
-                                const int c = c0 + u;
-                                if (c < qn) B[(int64_t)c * BMMAX_BIG + i] -= wv[u] * vi;
-                                else if (c == qn) y[i] -= wv[u] * vi;
+                                double t = 0.0;
+#pragma unroll
+                                for (int ww = 0; ww < NW; ++ww) t += S.red[ww * 8 + u];
+                                wv[u] = t * be;
                             }
+                            __syncthreads();
+                            for (int i = j + tid; i < m; i += NT) {
+                                const double vi = bj[i];
+#pragma unroll
+                                for (int u = 0; u < 8; ++u) {
+                                    const int c = c0 + u;
+                                    if (c < p0 + pw) B[(int64_t)c * BMMAX_BIG + i] -= wv[u] * vi;
+                                }
+                            }
+                            __syncthreads();
                         }
-                        __syncthreads();
                     }
+                    // columns after the panel plus the right-hand side (column qn)
+                    const int c_lo = p0 + pw, ntr = qn + 1 - c_lo;
+                    if (ntr > 0) panel_update(B, y, m, qn, p0, pw, c_lo, ntr, S, gred);
                 }
                 if (singular) { status = ST_SINGULAR; break; }
                 // back substitution by wave 0: lane c holds m_c
@@ -574,7 +704,7 @@ __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
 
 int64_t big_scratch_stride() {
     // doubles per workgroup: block, Q^T e, residual, then rows (int) and flags (byte)
-    return (int64_t)BQMAX_BIG * BMMAX_BIG + 2 * (int64_t)BMMAX_BIG + (BMMAX_BIG * 5 + 7) / 8 + 8;
+    return (int64_t)BQMAX_BIG * BMMAX_BIG + 2 * (int64_t)BMMAX_BIG + (BMMAX_BIG * 5 + 7) / 8 + 8 + REDN;
 }
 
 void launch_big_kernel(const BigArgs &a, int blocks, hipStream_t s) {
