@@ -42,6 +42,8 @@ def parse():
                     help="only copy 64 MiB device to device three times (calibrates the HBM byte counters)")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many batched builds (for rocprofv3), print nothing else")
+    ap.add_argument("--profile-workload", choices=("cd2d", "batch64"), default="cd2d",
+                    help="workload of --profile-steps: the cd2d matrix or the 64-matrix batch")
     return ap.parse_args()
 
 
@@ -106,6 +108,16 @@ def main():
 
     import paper_1503_04500_amd.rsai as rsai
     from paper_1503_04500_amd import gen
+
+    if args.profile_steps and args.profile_workload == "batch64":
+        A5 = [rsai.Matrix.from_host(gen.make(sp), "cuda:0") for sp in gen.batch64_specs()]
+        for _ in range(args.profile_steps):
+            p = rsai.build_batched(A5, **PARAMS)
+            p.nnz()
+            p.close()
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_steps": args.profile_steps, "workload": "batch64"}))
+        return
 
     H = gen.cd2d(args.grid, seed=0)
     A = rsai.Matrix.from_host(H, "cuda:0")
