@@ -199,6 +199,23 @@ def main():
     extra = None
     if not args.no_extra:
         extra = {}
+        # right-preconditioned BiCGStab on the device with this M (x0 = 0, b = A*1,
+        # stop at ||b - A x|| / ||b|| < 1e-8), and without a preconditioner
+        pb = rsai.build(A, sched="batched", **PARAMS)
+        pb.nnz()
+        bvec = rsai.spmv(A, torch.ones(n, dtype=torch.float64, device="cuda:0"))
+        sol = {}
+        for key, pre in (("rsai", True), ("none", False)):
+            pb.bicgstab(bvec, precond=pre)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                _, its, rel = pb.bicgstab(bvec, precond=pre)
+            dts = (time.perf_counter() - t0) / 3
+            sol[key] = {"iterations": its, "relres": rel, "ms": dts * 1e3,
+                        "us_per_iteration": dts * 1e6 / max(its, 1)}
+        pb.close()
+        extra["bicgstab_cd2d512"] = sol
         P3 = dict(PARAMS, lmax=10)
         H3 = gen.c3()
         A3 = rsai.Matrix.from_host(H3, "cuda:0")

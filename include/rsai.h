@@ -177,6 +177,26 @@ rsai_status rsai_apply(const rsai_plan *P, int32_t mat, const double *x, double 
 rsai_status rsai_backward(rsai_plan *P, int32_t mat, const double *dM_val, double w_frob, double *dA_val,
                           void *stream);
 
+/* Solve A x = b by BiCGStab, right-preconditioned with M of matrix mat (use_M = 1;
+   use_M = 0 runs it unpreconditioned), as in the experiments of Section 5: the
+   iteration runs on A M y = b with x = M y carried directly, x0 = 0, shadow residual
+   b, and it stops as soon as the true relative residual ||b - A x||_2 / ||b||_2 falls
+   below tol, tested after the half step and after the full step of each iteration
+   (the right-preconditioned form of (1.2)).
+   b (input) and x (output) are device arrays of n doubles, distinct; A is the matrix
+   the plan was built from (its values as they are now). The scalars of the recurrence
+   stay on the device; the host reads them once per chunk of 16 iterations, and with
+   use_graph = 1 the chunk is captured once as a HIP graph and replayed. Work buffers
+   (9 n doubles plus a row-sorted copy of A) come from the allocator and are released
+   before return. Host-synchronising.
+   On return *iters is the iteration in which the test passed (0 if b = 0 or
+   tol > 1), -1 on a breakdown (rho, r^.v or t.t exactly zero, or omega = 0), or
+   maxit + 1 if it did not converge; *relres is the last tested relative residual.
+   Errors: RSAI_E_ARG (NULL pointer, tol < 0, maxit < 0), the errors of
+   rsai_plan_nnz when use_M = 1, RSAI_E_NOMEM, RSAI_E_HIP. */
+rsai_status rsai_bicgstab(rsai_plan *P, int32_t mat, const double *b, double *x, double tol, int32_t maxit,
+                          int32_t use_M, int32_t use_graph, int32_t *iters, double *relres, void *stream);
+
 /* y = A x (transpose = 0) or y = A^T x (transpose = 1) for a CSC matrix. */
 rsai_status rsai_spmv(const rsai_csc *A, const double *x, double *y, int32_t transpose, void *stream);
 

@@ -762,15 +762,13 @@ rsai_status rsai_export_stats(const rsai_plan *P, int32_t mat, int32_t *loops, d
     return RSAI_OK;
 }
 
-rsai_status rsai_apply(const rsai_plan *Pc, int32_t mat, const double *x, double *y, void *stream) {
+// rows of M (row-sorted CSR), built once per build; needs a finished build
+static rsai_status rows_of_M(rsai_plan *P, int32_t mat) {
     int64_t nz = 0;
-    rsai_status st = rsai_plan_nnz(Pc, mat, &nz);
+    rsai_status st = rsai_plan_nnz(P, mat, &nz);
     if (st != RSAI_OK) return st;
-    if (!x || !y) return fail(RSAI_E_ARG, "NULL vector");
-    rsai_plan *P = const_cast<rsai_plan *>(Pc);
     MatPlan &M = P->mats[mat];
     const int64_t n = M.A.n;
-    hipStream_t s = (hipStream_t)stream;
     if (!M.t_valid) {
         // rows of M once per build: counts, scan, fill, sort each row by column
         if (!M.rowptrT || nz > M.capT) {
@@ -793,9 +791,34 @@ rsai_status rsai_apply(const rsai_plan *Pc, int32_t mat, const double *x, double
         HIPCHK(hipStreamSynchronize(P->stream));
         M.t_valid = true;
     }
+    return RSAI_OK;
+}
+
+rsai_status rsai_apply(const rsai_plan *Pc, int32_t mat, const double *x, double *y, void *stream) {
+    rsai_plan *P = const_cast<rsai_plan *>(Pc);
+    rsai_status st = rows_of_M(P, mat);
+    if (st != RSAI_OK) return st;
+    if (!x || !y) return fail(RSAI_E_ARG, "NULL vector");
+    MatPlan &M = P->mats[mat];
+    const int64_t n = M.A.n;
+    hipStream_t s = (hipStream_t)stream;
     launch_csr_spmv(n, M.rowptrT, M.colidxT, M.valT, x, y, s);
     HIPCHK(hipGetLastError());
     return RSAI_OK;
+}
+
+// rows of a CSC matrix with values, each row sorted by column so that row sums have a
+// fixed order. Work buffers: cnt, fill (n each), stmp (scan_tmp_elems(n + 1)), zerr (4).
+static void enqueue_rows(const rsai_csc *A, int64_t *rp, int32_t *ci, double *vv, int32_t *cnt, int32_t *fill,
+                         int64_t *stmp, int32_t *zerr, hipStream_t s) {
+    const int64_t n = A->n, nnz = A->nnz;
+    launch_fill_i32(zerr, 0, 4, s);
+    launch_fill_i32(cnt, 0, n, s);
+    launch_fill_i32(fill, 0, n, s);
+    launch_row_counts(nnz, A->rowidx, cnt, zerr, s);
+    launch_scan_i32(cnt, n, rp, stmp, s);
+    launch_csc_transpose_fill(n, A->colptr, A->rowidx, A->val, rp, fill, ci, vv, s);
+    launch_sort_rows(n, rp, ci, vv, s);
 }
 
 rsai_status rsai_spmv(const rsai_csc *A, const double *x, double *y, int32_t transpose, void *stream) {
@@ -824,13 +847,7 @@ rsai_status rsai_spmv(const rsai_csc *A, const double *x, double *y, int32_t tra
     int64_t *stmp = (int64_t *)al(8 * scan_tmp_elems(n + 1));
     int32_t *zerr = (int32_t *)al(16);
     if (st == RSAI_OK) {
-        launch_fill_i32(zerr, 0, 4, s);
-        launch_fill_i32(cnt, 0, n, s);
-        launch_fill_i32(fill, 0, n, s);
-        launch_row_counts(nnz, A->rowidx, cnt, zerr, s);
-        launch_scan_i32(cnt, n, rp, stmp, s);
-        launch_csc_transpose_fill(n, A->colptr, A->rowidx, A->val, rp, fill, ci, vv, s);
-        launch_sort_rows(n, rp, ci, vv, s);
+        enqueue_rows(A, rp, ci, vv, cnt, fill, stmp, zerr, s);
         launch_csr_spmv(n, rp, ci, vv, x, y, s);
         if (hipStreamSynchronize(s) != hipSuccess) st = fail(RSAI_E_HIP, "spmv failed");
     }
@@ -843,6 +860,158 @@ rsai_status rsai_spmv_vjp(const rsai_csc *A, const double *dy, const double *x, 
     launch_spmv_vjp(A->n, A->colptr, A->rowidx, dy, x, dval, (hipStream_t)stream);
     HIPCHK(hipGetLastError());
     return RSAI_OK;
+}
+
+// SELL-64 copy of a row-sorted CSR matrix (one host synchronisation for its size)
+static rsai_status to_sell(int64_t n, const int64_t *rp, const int32_t *ci, const double *va, int64_t *stmp,
+                           const std::function<void *(size_t)> &al, const int64_t *&sp, const int32_t *&sw,
+                           const int32_t *&sci, const double *&sva, hipStream_t s) {
+    const int64_t nsl = sell_slices(n);
+    int32_t *cnt = (int32_t *)al(4 * (size_t)nsl);
+    int32_t *w = (int32_t *)al(4 * (size_t)nsl);
+    int64_t *p = (int64_t *)al(8 * (size_t)(nsl + 1));
+    if (!cnt || !w || !p) return RSAI_E_NOMEM;
+    launch_sell_widths(n, rp, cnt, w, s);
+    launch_scan_i32(cnt, nsl, p, stmp, s);
+    int64_t total = 0;
+    HIPCHK(hipMemcpyAsync(&total, p + nsl, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int32_t *c2 = (int32_t *)al(4 * (size_t)total);
+    double *v2 = (double *)al(8 * (size_t)total);
+    if (!c2 || !v2) return RSAI_E_NOMEM;
+    launch_sell_fill(n, rp, ci, va, p, w, c2, v2, s);
+    sp = p;
+    sw = w;
+    sci = c2;
+    sva = v2;
+    return RSAI_OK;
+}
+
+rsai_status rsai_bicgstab(rsai_plan *P, int32_t mat, const double *b, double *x, double tol, int32_t maxit,
+                          int32_t use_M, int32_t use_graph, int32_t *iters, double *relres, void *stream) {
+    rsai_status st = check_mat(P, mat);
+    if (st != RSAI_OK) return st;
+    if (!b || !x || !iters || !relres) return fail(RSAI_E_ARG, "NULL argument");
+    if (!(tol >= 0.0) || maxit < 0) return fail(RSAI_E_ARG, "tol must be >= 0 and maxit >= 0");
+    if (use_M) {
+        st = rows_of_M(P, mat);
+        if (st != RSAI_OK) return st;
+    }
+    MatPlan &M = P->mats[mat];
+    const rsai_csc &A = M.A;
+    const int64_t n = A.n, nnz = A.nnz;
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<void *> tmp;
+    std::function<void *(size_t)> al = [&](size_t bytes) -> void * {
+        void *q = dev_alloc(std::max<size_t>(bytes, 8), s);
+        if (!q) st = fail(RSAI_E_NOMEM, "allocation failed");
+        tmp.push_back(q);
+        return q;
+    };
+    auto cleanup = [&](rsai_status r) {
+        (void)hipStreamSynchronize(s);
+        for (void *q : tmp) dev_free(q, s);
+        return r;
+    };
+    BicgSeq seq;
+    BicgArgs &a = seq.a;
+    a.n = n;
+    {
+        // rows of A (sorted), then both matrices in SELL-64
+        int64_t *arp = (int64_t *)al(8 * (n + 1));
+        int32_t *aci = (int32_t *)al(4 * nnz);
+        double *ava = (double *)al(8 * nnz);
+        int32_t *cnt = (int32_t *)al(4 * n), *fill = (int32_t *)al(4 * n), *zerr = (int32_t *)al(16);
+        int64_t *stmp = (int64_t *)al(8 * scan_tmp_elems(n + 1));
+        if (st != RSAI_OK) return cleanup(st);
+        enqueue_rows(&A, arp, aci, ava, cnt, fill, stmp, zerr, s);
+        rsai_status r2 = to_sell(n, arp, aci, ava, stmp, al, a.asp, a.aw, a.aci, a.ava, s);
+        if (r2 == RSAI_OK && use_M)
+            r2 = to_sell(n, M.rowptrT, M.colidxT, M.valT, stmp, al, a.msp, a.mw, a.mci, a.mva, s);
+        if (st != RSAI_OK || r2 != RSAI_OK) return cleanup(st != RSAI_OK ? st : r2);
+    }
+    double *vec = (double *)al(8 * 9 * (size_t)n);
+    a.part = (double *)al(8 * 4 * (size_t)BICG_MAXGRID);
+    a.st = (BicgState *)al(2 * sizeof(BicgState));
+    if (st != RSAI_OK) return cleanup(st);
+    a.b = b;
+    a.x = x;
+    double *vp = vec;
+    a.r = vp; vp += n;
+    a.rh = vp; vp += n;
+    a.p = vp; vp += n;
+    a.v = vp; vp += n;
+    a.s = vp; vp += n;
+    a.t = vp; vp += n;
+    a.ph = vp; vp += n;
+    a.sh = vp; vp += n;
+    a.xh = vp;
+    if (!use_M) {
+        a.ph = a.p;
+        a.sh = a.s;
+    }
+    seq.grid = bicg_grid(n);
+    seq.precond = use_M != 0;
+    BicgState h[2] = {};
+    h[0].tol = h[1].tol = tol;
+    h[0].maxit = h[1].maxit = maxit;
+    if (hipMemcpyAsync(a.st, h, sizeof(h), hipMemcpyHostToDevice, s) != hipSuccess)
+        return cleanup(fail(RSAI_E_HIP, "state upload failed"));
+    seq.init(s);
+    // iterations are enqueued in chunks, each ending with a settle; the host reads the
+    // state once per chunk
+    constexpr int CHUNK = 16;
+    hipGraphExec_t gx = nullptr;
+    hipStream_t cs = nullptr;
+    if (use_graph) {
+        hipGraph_t g = nullptr;
+        bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess &&
+                  hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            seq.iterations(CHUNK, cs);
+            seq.settle(cs);
+            ok = hipStreamEndCapture(cs, &g) == hipSuccess && g;
+        }
+        if (ok) ok = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0) == hipSuccess;
+        if (g) (void)hipGraphDestroy(g);
+        if (!ok) {
+            if (cs) (void)hipStreamDestroy(cs);
+            return cleanup(fail(RSAI_E_HIP, "graph capture of the iteration failed"));
+        }
+    }
+    int done_iters = 0;
+    int chunk = use_graph ? CHUNK : 4;
+    hipError_t he = hipSuccess;
+    bool stuck = false;
+    BicgState hs{};
+    for (;;) {
+        he = hipMemcpyAsync(&hs, a.st, sizeof(hs), hipMemcpyDeviceToHost, s);
+        if (he == hipSuccess) he = hipStreamSynchronize(s);
+        if (he != hipSuccess || hs.done) break;
+        if (use_graph) {
+            he = hipGraphLaunch(gx, s);
+        } else {
+            seq.iterations(chunk, s);
+            seq.settle(s);
+            he = hipGetLastError();
+        }
+        if (he != hipSuccess) break;
+        done_iters += chunk;
+        if (!use_graph) chunk = std::min(chunk * 2, CHUNK);
+        if (done_iters > maxit + 2 * CHUNK) {  // every iteration advances or ends the solve
+            stuck = true;
+            break;
+        }
+    }
+    if (gx) (void)hipGraphExecDestroy(gx);
+    if (cs) (void)hipStreamDestroy(cs);
+    if (stuck) return cleanup(fail(RSAI_E_STATE, "BiCGStab state did not advance"));
+    if (he != hipSuccess) return cleanup(fail(RSAI_E_HIP, "BiCGStab iteration failed: %s", hipGetErrorString(he)));
+    if (hs.half && hipMemcpyAsync(x, a.xh, 8 * n, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return cleanup(fail(RSAI_E_HIP, "copy of the half-step solution failed"));
+    *iters = hs.ret;
+    *relres = hs.rel;
+    return cleanup(RSAI_OK);
 }
 
 rsai_status rsai_backward(rsai_plan *P, int32_t mat, const double *dM_val, double w_frob, double *dA_val,

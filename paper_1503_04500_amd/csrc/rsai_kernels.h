@@ -95,6 +95,56 @@ void launch_csc_transpose_fill(int64_t n, const int64_t *colptr, const int32_t *
                                const int64_t *rowptr, int32_t *fillpos, int32_t *colidxT, double *valT,
                                hipStream_t s);
 void launch_sort_rows(int64_t n, const int64_t *rowptr, int32_t *colidx, double *val, hipStream_t s);
+// ---- right-preconditioned BiCGStab (rsai_krylov.hip)
+struct BicgState {
+    double rho, rho1, rho1n, alpha, omega, rel, nb, tol;
+    int32_t done;   // 0 running, 1 converged, 2 breakdown, 3 iteration limit
+    int32_t ret;    // iterations (0: b itself passed), -1 breakdown, maxit + 1
+    int32_t it;     // current iteration, from 1
+    int32_t half;   // converged after a half step: the solution is xh
+    int32_t maxit, pad;
+};
+constexpr int BICG_MAXGRID = 1024;  // workgroups of a vector kernel (partial sums per value)
+struct BicgArgs {
+    int64_t n;
+    // A and M in SELL-64: per slice of 64 rows its first entry and width; entry k of
+    // row i at sp[i / 64] + k * 64 + i % 64 (column, value), zero-valued padding
+    const int64_t *asp;
+    const int32_t *aw, *aci;
+    const double *ava;
+    const int64_t *msp;
+    const int32_t *mw, *mci;
+    const double *mva;
+    const double *b;
+    double *x, *r, *rh, *p, *v, *s, *t, *ph, *sh, *xh;  // ph == p, sh == s without M
+    double *part;        // 2 buffers of 2 * BICG_MAXGRID partial sums
+    BicgState *st;       // 2 copies of the state
+};
+struct BicgStep {
+    int stage;             // partial sums to fold in first (0: none)
+    int np;                // partial sums per value (the producer's grid)
+    const double *pin;     // partial sums to fold in
+    double *pout;          // partial sums this kernel writes
+    const BicgState *sin;  // state to read
+    BicgState *sout;       // state to write (workgroup 0)
+};
+// host-side launch sequence: which state copy and partial-sum buffer each kernel uses
+struct BicgSeq {
+    BicgArgs a{};
+    int grid = 1;
+    bool precond = true;
+    int sp = 0, pb = 0, pending = 0;
+    void step(int stage, bool produces, BicgStep &q);
+    void init(hipStream_t s);                    // x0 = 0 and the initial test; state in copy 0
+    void iterations(int count, hipStream_t s);   // count iterations (no-ops once ended)
+    void settle(hipStream_t s);                  // fold pending sums; both copies equal
+};
+int bicg_grid(int64_t n);
+int64_t sell_slices(int64_t n);
+void launch_sell_widths(int64_t n, const int64_t *rp, int32_t *cnt, int32_t *sw, hipStream_t s);
+void launch_sell_fill(int64_t n, const int64_t *rp, const int32_t *ci, const double *va, const int64_t *sp,
+                      const int32_t *sw, int32_t *sci, double *sva, hipStream_t s);
+
 void launch_csr_spmv(int64_t n, const int64_t *rowptr, const int32_t *colidx, const double *val, const double *x,
                      double *y, hipStream_t s);
 void launch_csc_spmv_t(int64_t n, const int64_t *colptr, const int32_t *rowidx, const double *val,

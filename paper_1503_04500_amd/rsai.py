@@ -86,6 +86,7 @@ def load():
         "rsai_export_stats": [P, I32, P, P, P, P, P, P, P],
         "rsai_apply": [P, I32, P, P, P],
         "rsai_backward": [P, I32, P, D, P, P],
+        "rsai_bicgstab": [P, I32, P, P, D, I32, I32, I32, P, P, P],
         "rsai_spmv": [P, P, P, I32, P],
         "rsai_spmv_vjp": [P, P, P, P, P],
         "rsai_plan_timing": [P, P, I32],
@@ -237,6 +238,19 @@ class Plan:
         y = torch.empty_like(x)
         _check(load().rsai_apply(self._hv(), mat, x.data_ptr(), y.data_ptr(), _stream()))
         return y
+
+    def bicgstab(self, b, tol=1e-8, maxit=1000, precond=True, graph=True, mat=0):
+        """Solve A x = b by BiCGStab right-preconditioned with M (rsai_bicgstab).
+        Returns (x, iterations, relative residual); iterations is -1 on a breakdown
+        and maxit + 1 without convergence."""
+        b = _dev(b, torch.float64, "b")
+        x = torch.empty_like(b)
+        it = ctypes.c_int32(0)
+        rel = ctypes.c_double(0.0)
+        _check(load().rsai_bicgstab(self._hv(), mat, b.data_ptr(), x.data_ptr(), float(tol), int(maxit),
+                                    1 if precond else 0, 1 if graph else 0, ctypes.byref(it),
+                                    ctypes.byref(rel), _stream()))
+        return x, it.value, rel.value
 
     def backward(self, dM_val, w_frob, dA_val, mat=0):
         """dA_val += adjoint(dM_val) + w_frob * d(sum_k ||A m_k - e_k||^2)/dA (in place)."""
