@@ -930,7 +930,7 @@ rsai_status rsai_bicgstab(rsai_plan *P, int32_t mat, const double *b, double *x,
             r2 = to_sell(n, M.rowptrT, M.colidxT, M.valT, stmp, al, a.msp, a.mw, a.mci, a.mva, s);
         if (st != RSAI_OK || r2 != RSAI_OK) return cleanup(st != RSAI_OK ? st : r2);
     }
-    double *vec = (double *)al(8 * 9 * (size_t)n);
+    double *vec = (double *)al(8 * 12 * (size_t)n);
     a.part = (double *)al(8 * 4 * (size_t)BICG_MAXGRID);
     a.st = (BicgState *)al(2 * sizeof(BicgState));
     if (st != RSAI_OK) return cleanup(st);
@@ -940,16 +940,15 @@ rsai_status rsai_bicgstab(rsai_plan *P, int32_t mat, const double *b, double *x,
     a.r = vp; vp += n;
     a.rh = vp; vp += n;
     a.p = vp; vp += n;
+    a.w = vp; vp += n;
     a.v = vp; vp += n;
     a.s = vp; vp += n;
     a.t = vp; vp += n;
     a.ph = vp; vp += n;
     a.sh = vp; vp += n;
+    a.res = vp; vp += n;
+    a.mr = vp; vp += n;
     a.xh = vp;
-    if (!use_M) {
-        a.ph = a.p;
-        a.sh = a.s;
-    }
     seq.grid = bicg_grid(n);
     seq.precond = use_M != 0;
     BicgState h[2] = {};

@@ -116,7 +116,7 @@ struct BicgArgs {
     const int32_t *mw, *mci;
     const double *mva;
     const double *b;
-    double *x, *r, *rh, *p, *v, *s, *t, *ph, *sh, *xh;  // ph == p, sh == s without M
+    double *x, *r, *rh, *p, *w, *v, *s, *t, *ph, *sh, *xh, *res, *mr;  // without M: ph = p, sh = s
     double *part;        // 2 buffers of 2 * BICG_MAXGRID partial sums
     BicgState *st;       // 2 copies of the state
 };

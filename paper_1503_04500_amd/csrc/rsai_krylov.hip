@@ -20,15 +20,24 @@
 //    partials in index order (the same order everywhere, so all workgroups agree to
 //    the bit) before applying the scalar step. The kernel boundary orders the two.
 //
-// Kernels of one iteration (| the partial sums a kernel produces, [] the step it
+//  * Products are split by linearity so that no kernel gathers more than two vectors
+//    and no kernel exists for an elementwise update alone: with w = p - omega v kept
+//    from the previous iteration, M p = M r + beta M w; M s = M r - alpha M v; and the
+//    half-step residual b - A (x + alpha ph) = (b - A x) - alpha v. Every residual is
+//    still formed from fresh products of the current vectors (b - A x by an SpMV of
+//    x in each iteration, v = A ph), not carried by a recurrence.
+//
+// Kernels of one iteration k (| the partial sums a kernel produces, [] the step it
 // applies first from the previous kernel's partials):
-//   pre   [end tests of the last iteration]  ph = M p
-//   av    v = A ph | r^.v
-//   half  [alpha] s = r - alpha v, xh = x + alpha ph, sh = M s | ||b - A xh||^2
+//   pre   [r^.r of iteration k-1: beta] p = r + beta w, ph = M r + beta M w (M r
+//         kept), res = b - A x | ||res||^2
+//   av    [full-step test of x_k (for k = 1 the initial test), end tests] v = A ph
+//         | r^.v
+//   half  [alpha] s = r - alpha v, xh = x + alpha ph, sh = M r - alpha M v
+//         | ||res - alpha v||^2
 //   at    [half-step test] t = A sh | t.t, t.s
-//   upd   [omega] x += alpha ph + omega sh, r = s - omega t | r^.r
-//   full  [beta] p = r + beta (p - omega v) | ||b - A x||^2
-// Without M the first kernel is av (ph = p, sh = s), which then applies the tests.
+//   uf    [omega] x = xh + omega sh, r = s - omega t, w = p - omega v | r^.r
+// Without M, ph = p and sh = s. In the first iteration beta = 0 and w = 0, so p = r.
 #include <algorithm>
 
 #include "rsai_kernels.h"
@@ -39,9 +48,10 @@ namespace {
 constexpr int KT = 256;  // threads per workgroup; rows per thread-pass = KT
 constexpr int SL = 64;   // rows per SELL slice (one wavefront)
 
-enum Stage { BS_NONE = 0, BS_INIT, BS_AV, BS_HALF, BS_AT, BS_UPD, BS_FULL };
+enum Stage { BS_NONE = 0, BS_INIT, BS_RES, BS_AV, BS_HALF, BS_AT, BS_UF };
 
-// The scalar step of a stage, from the totals of its partial sums.
+// The scalar step of a stage, from the totals of its partial sums. S.it is the
+// iteration that runs next (pre .. uf).
 __device__ void apply_stage(BicgState &S, int stage, const double *tot) {
     switch (stage) {
     case BS_INIT: {
@@ -49,7 +59,7 @@ __device__ void apply_stage(BicgState &S, int stage, const double *tot) {
         S.nb = (nb == 0.0) ? 1.0 : nb;
         S.rel = nb / S.nb;
         S.rho = S.alpha = S.omega = 1.0;
-        S.rho1 = tot[0];
+        S.rho1 = S.rho1n = tot[0];
         S.it = 1;
         S.half = 0;
         if (S.rel < S.tol) { S.done = 1; S.ret = 0; }
@@ -58,6 +68,23 @@ __device__ void apply_stage(BicgState &S, int stage, const double *tot) {
         else S.done = 0;
         break;
     }
+    case BS_UF:  // r^.r after the full step of iteration it; iteration it + 1 is next
+        S.rho1n = tot[0];
+        S.it += 1;
+        break;
+    case BS_RES:  // ||b - A x|| for the x of the last full step (the initial x when it == 1)
+        S.rel = sqrt(tot[0]) / S.nb;
+        if (S.rel < S.tol) { S.done = 1; S.ret = S.it - 1; }
+        else if (S.it > 1) {
+            if (S.omega == 0.0) { S.done = 2; S.ret = -1; }
+            else {
+                S.rho = S.rho1;
+                S.rho1 = S.rho1n;
+                if (S.it > S.maxit) { S.done = 3; S.ret = S.maxit + 1; }
+                else if (S.rho1 == 0.0) { S.done = 2; S.ret = -1; }
+            }
+        }
+        break;
     case BS_AV:
         if (tot[0] == 0.0) { S.done = 2; S.ret = -1; }
         else S.alpha = S.rho1 / tot[0];
@@ -70,21 +97,6 @@ __device__ void apply_stage(BicgState &S, int stage, const double *tot) {
         if (tot[0] == 0.0) { S.done = 2; S.ret = -1; }
         else S.omega = tot[1] / tot[0];
         break;
-    case BS_UPD:
-        S.rho1n = tot[0];
-        break;
-    case BS_FULL:
-        S.rel = sqrt(tot[0]) / S.nb;
-        if (S.rel < S.tol) { S.done = 1; S.ret = S.it; }
-        else if (S.omega == 0.0) { S.done = 2; S.ret = -1; }
-        else {
-            S.rho = S.rho1;
-            S.rho1 = S.rho1n;
-            S.it += 1;
-            if (S.it > S.maxit) { S.done = 3; S.ret = S.maxit + 1; }
-            else if (S.rho1 == 0.0) { S.done = 2; S.ret = -1; }
-        }
-        break;
     default:
         break;
     }
@@ -94,7 +106,7 @@ __device__ __forceinline__ int stage_values(int stage) { return stage == BS_AT ?
 
 // Read the state, fold in the pending partial sums, pass the state on (workgroup 0).
 // Every thread of every workgroup ends with the same S. Returns false when the solve
-// has ended and the kernel has nothing to do.
+// has ended.
 __device__ bool take_state(const BicgStep &q, BicgState &S) {
     __shared__ double red[2][KT / 64];
     S = *q.sin;
@@ -140,7 +152,7 @@ __device__ void write_partials(double (&x)[NV], double *pout) {
         }
 }
 
-// row i of a SELL-64 matrix times x (entries in column order, padding adds 0 * x[i])
+// row i of a SELL-64 matrix times x (entries in column order; padding adds 0 * x[i])
 __device__ __forceinline__ double sell_row(const int64_t *sp, const int32_t *sw, const int32_t *ci,
                                            const double *va, const double *x, int64_t i) {
     const int64_t sl = i / SL;
@@ -152,10 +164,28 @@ __device__ __forceinline__ double sell_row(const int64_t *sp, const int32_t *sw,
     return q;
 }
 
+// row i of a SELL-64 matrix times two vectors (one pass over the row)
+__device__ __forceinline__ void sell_row2(const int64_t *sp, const int32_t *sw, const int32_t *ci, const double *va,
+                                          const double *x, const double *y, int64_t i, double &qx, double &qy) {
+    const int64_t sl = i / SL;
+    const int64_t e0 = sp[sl] + (i % SL);
+    const int w = sw[sl];
+    qx = 0.0;
+    qy = 0.0;
+#pragma unroll 4
+    for (int k = 0; k < w; ++k) {
+        const int64_t e = e0 + (int64_t)k * SL;
+        const int j = ci[e];
+        const double m = va[e];
+        qx += m * x[j];
+        qy += m * y[j];
+    }
+}
+
 #define ROWS(i, n) for (int64_t i = blockIdx.x * (int64_t)KT + threadIdx.x; i < (n); i += (int64_t)gridDim.x * KT)
 }  // namespace
 
-// x = 0, r = r^ = p = b, v = 0 | ||b||^2
+// x = 0, r = r^ = p = b, w = v = 0 | ||b||^2
 __global__ __launch_bounds__(KT) void kb_init(BicgArgs a, BicgStep q) {
     double acc[1] = {0.0};
     ROWS(i, a.n) {
@@ -164,6 +194,7 @@ __global__ __launch_bounds__(KT) void kb_init(BicgArgs a, BicgStep q) {
         a.r[i] = bi;
         a.rh[i] = bi;
         a.p[i] = bi;
+        a.w[i] = 0.0;
         a.v[i] = 0.0;
         acc[0] += bi * bi;
     }
@@ -177,71 +208,71 @@ __global__ __launch_bounds__(KT) void kb_settle(BicgArgs a, BicgStep q, BicgStat
     if (threadIdx.x == 0) *other = S;
 }
 
-// ph = M p
+// [beta] p = r + beta w, ph = M r + beta M w (M r kept), res = b - A x | ||res||^2
+template <bool PRE>
 __global__ __launch_bounds__(KT) void kb_pre(BicgArgs a, BicgStep q) {
     BicgState S;
     if (!take_state(q, S)) return;
-    ROWS(i, a.n) a.ph[i] = sell_row(a.msp, a.mw, a.mci, a.mva, a.p, i);
+    const double beta = (S.it == 1) ? 0.0 : (S.rho1n / S.rho1) * (S.alpha / S.omega);
+    double acc[1] = {0.0};
+    ROWS(i, a.n) {
+        a.p[i] = a.r[i] + beta * a.w[i];
+        if (PRE) {
+            double mr, mw;
+            sell_row2(a.msp, a.mw, a.mci, a.mva, a.r, a.w, i, mr, mw);
+            a.mr[i] = mr;
+            a.ph[i] = mr + beta * mw;
+        }
+        const double d = a.b[i] - sell_row(a.asp, a.aw, a.aci, a.ava, a.x, i);
+        a.res[i] = d;
+        acc[0] += d * d;
+    }
+    write_partials<1>(acc, q.pout);
 }
 
-// v = A ph | r^.v
+// [full-step test] v = A ph | r^.v
+template <bool PRE>
 __global__ __launch_bounds__(KT) void kb_av(BicgArgs a, BicgStep q) {
     BicgState S;
     if (!take_state(q, S)) return;
+    const double *ph = PRE ? a.ph : a.p;
     double acc[1] = {0.0};
     ROWS(i, a.n) {
-        const double vi = sell_row(a.asp, a.aw, a.aci, a.ava, a.ph, i);
+        const double vi = sell_row(a.asp, a.aw, a.aci, a.ava, ph, i);
         a.v[i] = vi;
         acc[0] += a.rh[i] * vi;
     }
     write_partials<1>(acc, q.pout);
 }
 
-// [alpha] s = r - alpha v, xh = x + alpha ph, sh = M s (s formed on the fly)
-// | ||b - A xh||^2 (xh formed on the fly)
+// [alpha] s = r - alpha v, xh = x + alpha ph, sh = M r - alpha M v | ||res - alpha v||^2
 template <bool PRE>
 __global__ __launch_bounds__(KT) void kb_half(BicgArgs a, BicgStep q) {
     BicgState S;
     if (!take_state(q, S)) return;
     const double al = S.alpha;
+    const double *ph = PRE ? a.ph : a.p;
     double acc[1] = {0.0};
     ROWS(i, a.n) {
-        a.s[i] = a.r[i] - al * a.v[i];
-        a.xh[i] = a.x[i] + al * a.ph[i];
-        if (PRE) {
-            const int64_t sl = i / SL, e0 = a.msp[sl] + (i % SL);
-            const int w = a.mw[sl];
-            double u = 0.0;
-#pragma unroll 4
-            for (int k = 0; k < w; ++k) {
-                const int64_t e = e0 + (int64_t)k * SL;
-                const int j = a.mci[e];
-                u += a.mva[e] * (a.r[j] - al * a.v[j]);
-            }
-            a.sh[i] = u;
-        }
-        const int64_t sl = i / SL, e0 = a.asp[sl] + (i % SL);
-        const int w = a.aw[sl];
-        double z = 0.0;
-#pragma unroll 4
-        for (int k = 0; k < w; ++k) {
-            const int64_t e = e0 + (int64_t)k * SL;
-            const int j = a.aci[e];
-            z += a.ava[e] * (a.x[j] + al * a.ph[j]);
-        }
-        const double d = a.b[i] - z;
+        const double vi = a.v[i];
+        a.s[i] = a.r[i] - al * vi;
+        a.xh[i] = a.x[i] + al * ph[i];
+        if (PRE) a.sh[i] = a.mr[i] - al * sell_row(a.msp, a.mw, a.mci, a.mva, a.v, i);
+        const double d = a.res[i] - al * vi;
         acc[0] += d * d;
     }
     write_partials<1>(acc, q.pout);
 }
 
 // [half-step test] t = A sh | t.t, t.s
+template <bool PRE>
 __global__ __launch_bounds__(KT) void kb_at(BicgArgs a, BicgStep q) {
     BicgState S;
     if (!take_state(q, S)) return;
+    const double *sh = PRE ? a.sh : a.s;
     double acc[2] = {0.0, 0.0};
     ROWS(i, a.n) {
-        const double ti = sell_row(a.asp, a.aw, a.aci, a.ava, a.sh, i);
+        const double ti = sell_row(a.asp, a.aw, a.aci, a.ava, sh, i);
         a.t[i] = ti;
         acc[0] += ti * ti;
         acc[1] += ti * a.s[i];
@@ -249,31 +280,20 @@ __global__ __launch_bounds__(KT) void kb_at(BicgArgs a, BicgStep q) {
     write_partials<2>(acc, q.pout);
 }
 
-// [omega] x += alpha ph + omega sh, r = s - omega t | r^.r
-__global__ __launch_bounds__(KT) void kb_upd(BicgArgs a, BicgStep q) {
+// [omega] x = xh + omega sh, r = s - omega t, w = p - omega v | r^.r
+template <bool PRE>
+__global__ __launch_bounds__(KT) void kb_uf(BicgArgs a, BicgStep q) {
     BicgState S;
     if (!take_state(q, S)) return;
-    const double al = S.alpha, om = S.omega;
+    const double om = S.omega;
+    const double *sh = PRE ? a.sh : a.s;
     double acc[1] = {0.0};
     ROWS(i, a.n) {
-        a.x[i] = a.x[i] + al * a.ph[i] + om * a.sh[i];
+        a.x[i] = a.xh[i] + om * sh[i];
         const double ri = a.s[i] - om * a.t[i];
         a.r[i] = ri;
+        a.w[i] = a.p[i] - om * a.v[i];
         acc[0] += a.rh[i] * ri;
-    }
-    write_partials<1>(acc, q.pout);
-}
-
-// [beta] p = r + beta (p - omega v) | ||b - A x||^2
-__global__ __launch_bounds__(KT) void kb_full(BicgArgs a, BicgStep q) {
-    BicgState S;
-    if (!take_state(q, S)) return;
-    const double beta = (S.rho1n / S.rho1) * (S.alpha / S.omega), om = S.omega;
-    double acc[1] = {0.0};
-    ROWS(i, a.n) {
-        const double d = a.b[i] - sell_row(a.asp, a.aw, a.aci, a.ava, a.x, i);
-        acc[0] += d * d;
-        a.p[i] = a.r[i] + beta * (a.p[i] - om * a.v[i]);
     }
     write_partials<1>(acc, q.pout);
 }
@@ -361,27 +381,28 @@ void BicgSeq::settle(hipStream_t s) {
     pending = BS_NONE;
 }
 
+namespace {
+template <bool PRE>
+void one_iteration(BicgSeq &z, hipStream_t s) {
+    BicgStep q{};
+    z.step(z.pending, true, q);
+    hipLaunchKernelGGL(kb_pre<PRE>, dim3(z.grid), dim3(KT), 0, s, z.a, q);
+    z.step(BS_RES, true, q);
+    hipLaunchKernelGGL(kb_av<PRE>, dim3(z.grid), dim3(KT), 0, s, z.a, q);
+    z.step(BS_AV, true, q);
+    hipLaunchKernelGGL(kb_half<PRE>, dim3(z.grid), dim3(KT), 0, s, z.a, q);
+    z.step(BS_HALF, true, q);
+    hipLaunchKernelGGL(kb_at<PRE>, dim3(z.grid), dim3(KT), 0, s, z.a, q);
+    z.step(BS_AT, true, q);
+    hipLaunchKernelGGL(kb_uf<PRE>, dim3(z.grid), dim3(KT), 0, s, z.a, q);
+    z.pending = BS_UF;
+}
+}  // namespace
+
 void BicgSeq::iterations(int count, hipStream_t s) {
     for (int it = 0; it < count; ++it) {
-        BicgStep q{};
-        if (precond) {
-            step(pending, false, q);
-            hipLaunchKernelGGL(kb_pre, dim3(grid), dim3(KT), 0, s, a, q);
-            step(BS_NONE, true, q);
-        } else {
-            step(pending, true, q);
-        }
-        hipLaunchKernelGGL(kb_av, dim3(grid), dim3(KT), 0, s, a, q);
-        step(BS_AV, true, q);
-        if (precond) hipLaunchKernelGGL(kb_half<true>, dim3(grid), dim3(KT), 0, s, a, q);
-        else hipLaunchKernelGGL(kb_half<false>, dim3(grid), dim3(KT), 0, s, a, q);
-        step(BS_HALF, true, q);
-        hipLaunchKernelGGL(kb_at, dim3(grid), dim3(KT), 0, s, a, q);
-        step(BS_AT, true, q);
-        hipLaunchKernelGGL(kb_upd, dim3(grid), dim3(KT), 0, s, a, q);
-        step(BS_UPD, true, q);
-        hipLaunchKernelGGL(kb_full, dim3(grid), dim3(KT), 0, s, a, q);
-        pending = BS_FULL;
+        if (precond) one_iteration<true>(*this, s);
+        else one_iteration<false>(*this, s);
     }
 }
 
