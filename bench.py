@@ -42,8 +42,9 @@ def parse():
                     help="only copy 64 MiB device to device three times (calibrates the HBM byte counters)")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many batched builds (for rocprofv3), print nothing else")
-    ap.add_argument("--profile-workload", choices=("cd2d", "batch64"), default="cd2d",
-                    help="workload of --profile-steps: the cd2d matrix or the 64-matrix batch")
+    ap.add_argument("--profile-workload", choices=("cd2d", "batch64", "bicgstab"), default="cd2d",
+                    help="workload of --profile-steps: builds of the cd2d matrix or of the 64-matrix "
+                         "batch, or BiCGStab solves (100 iterations) with M of the cd2d matrix")
     return ap.parse_args()
 
 
@@ -122,6 +123,17 @@ def main():
     H = gen.cd2d(args.grid, seed=0)
     A = rsai.Matrix.from_host(H, "cuda:0")
     torch.cuda.synchronize()
+
+    if args.profile_steps and args.profile_workload == "bicgstab":
+        pb = rsai.build(A, sched="batched", **PARAMS)
+        pb.nnz()
+        bvec = rsai.spmv(A, torch.ones(H.n, dtype=torch.float64, device="cuda:0"))
+        for _ in range(args.profile_steps):
+            _, its, _ = pb.bicgstab(bvec, maxit=100)
+        torch.cuda.synchronize()
+        pb.close()
+        print(json.dumps({"profile_steps": args.profile_steps, "workload": "bicgstab", "iterations": its}))
+        return
 
     if args.profile_steps:
         for _ in range(args.profile_steps):
@@ -216,6 +228,37 @@ def main():
                         "us_per_iteration": dts * 1e6 / max(its, 1)}
         pb.close()
         extra["bicgstab_cd2d512"] = sol
+        # the stopping criterion, the number of dominant indices and the dropping mode
+        # varied on the same matrix: density of M, columns left above eps, build time,
+        # device BiCGStab iterations and time
+        sweep = []
+        for eps, c, drop in ((0.5, 3, "fixed"), (0.4, 3, "fixed"), (0.3, 3, "fixed"), (0.2, 3, "fixed"),
+                             (0.4, 1, "fixed"), (0.4, 5, "fixed"), (0.4, 3, "adaptive"), (0.4, 3, "none")):
+            prm = dict(PARAMS, eps=eps, c=c, drop=drop)
+            dt = time_builds(rsai, A, "batched", 3, 1, torch, prm=prm)
+            ps = rsai.build(A, sched="batched", **prm)
+            nzm = ps.nnz()
+            rn = ps.stats()["resnorm"]
+            t0 = time.perf_counter()
+            _, its, rel = ps.bicgstab(bvec)
+            dts = time.perf_counter() - t0
+            sweep.append({"eps": eps, "c": c, "drop": drop, "build_ms": dt * 1e3, "spar": nzm / nnz,
+                          "n_c": int((rn > eps).sum().item()), "bicgstab_iterations": its,
+                          "bicgstab_ms": dts * 1e3})
+            ps.close()
+        extra["sweep_cd2d512"] = sweep
+        # relatively dense rows (Section 4): 512x512 grid plus 1024 rows of 32 entries
+        Hd = gen.dense_rows(512, 1024, 32)
+        Ad = rsai.Matrix.from_host(Hd, "cuda:0")
+        dtd = time_builds(rsai, Ad, "batched", 5, 1, torch)
+        pdn = rsai.build(Ad, sched="batched", timing=True, **PARAMS)
+        pdn.nnz()
+        extra["dense_rows_512"] = {"value": Hd.n / dtd, "unit": "columns/s", "ms_per_step": dtd * 1e3,
+                                   "phase_ms": pdn.timing(),
+                                   "workload": "cd2d 512x512 seed 0 plus 1024 rows of 32 entries U(-1,1), "
+                                               "seed 7919; RSAI(tol) c=3 lmax=8 eps=0.4 tol=1e-3"}
+        pdn.close()
+        del Ad, Hd
         P3 = dict(PARAMS, lmax=10)
         H3 = gen.c3()
         A3 = rsai.Matrix.from_host(H3, "cuda:0")

@@ -68,7 +68,7 @@ typedef enum {
 typedef enum {
     RSAI_SCHED_BATCHED = 0, /* size-bucketed persistent kernels, whole loop fused; columns
                                that outgrow the register tiers finish in a large class (one
-                               256-thread workgroup per column, |I_k| <= 8192, |J_k| <= 64) */
+                               256-thread workgroup per column, |I_k| <= 8192, |J_k| <= 128) */
     RSAI_SCHED_PLAIN = 1    /* one wave per column, one launch per loop, state in HBM */
 } rsai_sched;
 

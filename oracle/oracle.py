@@ -50,6 +50,8 @@ def _load():
     lib.oracle_threads.argtypes = [_P]
     lib.oracle_export.restype = None
     lib.oracle_export.argtypes = [_P] * 16
+    lib.oracle_export_peaks.restype = None
+    lib.oracle_export_peaks.argtypes = [_P] * 3
     lib.oracle_free.restype = None
     lib.oracle_free.argtypes = [_P]
     lib.oracle_fixed_pattern.restype = _I64
@@ -79,8 +81,9 @@ def rsai(A, c: int = 3, lmax: int = 8, eps: float = 0.4, drop: int = DROP_FIXED,
     per-column statistics: loops, resnorm (||A m_k - e_k||), nI, nJ, status,
     sel_margin / drop_margin (smallest decision gaps), flops (the oracle's own
     from-scratch count), mflops (the QR-update work model), nsolve (loop solves),
-    ndrop (re-solves after a drop), and optionally hist (residual norm after each
-    loop solve).
+    ndrop (re-solves after a drop), nImax / nJmax (the largest |I_k|, |J_k| of any
+    solve, i.e. before a drop shrinks J_k), and optionally hist (residual norm after
+    each loop solve).
     """
     if not (1 <= c <= 64):
         raise ValueError("c must be in 1..64")
@@ -106,6 +109,9 @@ def rsai(A, c: int = 3, lmax: int = 8, eps: float = 0.4, drop: int = DROP_FIXED,
                                                       "nJ", "status", "sel_margin", "drop_margin", "flops",
                                                       "nsolve")], _ptr(hh), _ptr(out["ndrop"]),
                            _ptr(out["mflops"]))
+        out["nImax"] = np.zeros(ncols, np.int32)
+        out["nJmax"] = np.zeros(ncols, np.int32)
+        lib.oracle_export_peaks(h, _ptr(out["nImax"]), _ptr(out["nJmax"]))
         if hist:
             out["hist"] = hh.reshape(ncols, 2 * (lmax + 1))
         out["seconds"] = lib.oracle_seconds(h)

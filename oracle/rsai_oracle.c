@@ -298,6 +298,7 @@ static int drop_step(const omat *A, int32_t k, const oparams *p, work *w, double
 
 typedef struct {
     int32_t loops, nI, nJ, status, nsolve, ndrop;
+    int32_t nImax, nJmax; /* largest |I|, |J| of any solve of the column (before dropping) */
     double resnorm, sel_margin, drop_margin, flops, mflops;
 } colstat;
 
@@ -318,6 +319,7 @@ static void rsai_column(const omat *A, int32_t k, const oparams *p, work *w, col
     w->I.n = 0;
     for (int64_t e = A->colptr[k]; e < A->colptr[k + 1]; ++e) iv_push(&w->I, A->rowidx[e]);
     int l = 0;
+    int32_t nImax = w->I.n, nJmax = w->J.n;
     status = ls_solve(A, k, w, &rn, &flops);
     mflops += model_solve_flops(w->I.n, 0, 1);
     if (status == OR_OK) status = drop_step(A, k, p, w, &rn, &flops, &drop_margin, &ndrop, &mflops);
@@ -399,6 +401,8 @@ static void rsai_column(const omat *A, int32_t k, const oparams *p, work *w, col
             set_union_into(&w->I, &w->Ihat, &scratch);
             free(scratch.a);
         }
+        if (w->I.n > nImax) nImax = w->I.n;
+        if (w->J.n > nJmax) nJmax = w->J.n;
         /* step 7: new LS solution and residual on the augmented pattern */
         status = ls_solve(A, k, w, &rn, &flops);
         mflops += model_solve_flops(w->I.n, qprev, w->J.n);
@@ -417,6 +421,8 @@ static void rsai_column(const omat *A, int32_t k, const oparams *p, work *w, col
     st->nsolve = nsolve;
     st->ndrop = ndrop;
     st->mflops = mflops;
+    st->nImax = nImax;
+    st->nJmax = nJmax;
 }
 
 /* ---------------- result handle ---------------- */
@@ -541,6 +547,15 @@ void oracle_export(void *h, int64_t *colptr, int32_t *rowidx, double *val, int32
         if (mflops) mflops[t] = R->st[t].mflops;
     }
     if (hist && R->hist) memcpy(hist, R->hist, sizeof(double) * (size_t)R->ncols * (size_t)R->hist_len);
+}
+
+/* Largest |I_k| and |J_k| over the solves of each column (either may be NULL). */
+void oracle_export_peaks(void *h, int32_t *nImax, int32_t *nJmax) {
+    oresult *R = (oresult *)h;
+    for (int64_t t = 0; t < R->ncols; ++t) {
+        if (nImax) nImax[t] = R->st[t].nImax;
+        if (nJmax) nJmax[t] = R->st[t].nJmax;
+    }
 }
 
 void oracle_free(void *h) {

@@ -109,13 +109,13 @@ typedef double mfma_d4 __attribute__((ext_vector_type(4)));
 
 // V(r, i) of the current panel: reflector i (column p0 + i) below its diagonal,
 // its head on the diagonal, zero above and outside the panel or the block
-__device__ __forceinline__ double vget(const double *B, int m, int p0, int pw, int r, int i) {
+__device__ __forceinline__ double vget(const double *B, int64_t ld, int m, int p0, int pw, int r, int i) {
     if (i >= pw || r >= m || r < p0 + i) return 0.0;
-    return B[(int64_t)(p0 + i) * BMMAX_BIG + r];
+    return B[(int64_t)(p0 + i) * ld + r];
 }
 // column c of the trailing part: a column of the block, or Q^T e for c == qn
-__device__ __forceinline__ double *colp(double *B, double *y, int qn, int c) {
-    return (c < qn) ? B + (int64_t)c * BMMAX_BIG : y;
+__device__ __forceinline__ double *colp(double *B, int64_t ld, double *y, int qn, int c) {
+    return (c < qn) ? B + (int64_t)c * ld : y;
 }
 
 // Apply Q_p^T = I - V T^T V^T of the panel (columns p0 .. p0+pw-1, pw <= 16) to the
@@ -124,7 +124,7 @@ __device__ __forceinline__ double *colp(double *B, double *y, int qn, int c) {
 // C -= V (T^T W) is an MFMA per 16x16 tile of C.
 // MFMA 16x16x4 f64 operands (lane l): A(l % 16, l / 16), B(l / 16, l % 16); result
 // element t of lane l is D(l / 16 + 4 t, l % 16).
-__device__ void panel_update(double *B, double *y, int m, int qn, int p0, int pw, int c_lo, int ntr,
+__device__ void panel_update(double *B, int64_t ld, double *y, int m, int qn, int p0, int pw, int c_lo, int ntr,
                              BigLds &S, double *red) {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
@@ -136,13 +136,13 @@ __device__ void panel_update(double *B, double *y, int m, int qn, int p0, int pw
     for (int t = 0; t <= NCTMAX; ++t) acc[t] = mfma_d4{0.0, 0.0, 0.0, 0.0};
     for (int r0 = p0 + 4 * w; r0 < m; r0 += 4 * NW) {
         const int r = r0 + lk;
-        const double a = vget(B, m, p0, pw, r, li);
+        const double a = vget(B, ld, m, p0, pw, r, li);
         acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, a, acc[0], 0, 0, 0);
 #pragma unroll
         for (int t = 0; t < NCTMAX; ++t) {
             if (t < nct) {
                 const int c = c_lo + 16 * t + li;
-                const double bv = (c < c_lo + ntr && r < m) ? colp(B, y, qn, c)[r] : 0.0;
+                const double bv = (c < c_lo + ntr && r < m) ? colp(B, ld, y, qn, c)[r] : 0.0;
                 acc[t + 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[t + 1], 0, 0, 0);
             }
         }
@@ -200,7 +200,7 @@ __device__ void panel_update(double *B, double *y, int m, int qn, int p0, int pw
         const int r0 = p0 + 16 * rt;
         const int c = c_lo + 16 * ct + li;
         const bool cok = c < c_lo + ntr;
-        double *cp = cok ? colp(B, y, qn, c) : nullptr;
+        double *cp = cok ? colp(B, ld, y, qn, c) : nullptr;
         mfma_d4 d;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -209,7 +209,7 @@ __device__ void panel_update(double *B, double *y, int m, int qn, int p0, int pw
         }
 #pragma unroll
         for (int k0 = 0; k0 < 16; k0 += 4) {
-            const double a = -vget(B, m, p0, pw, r0 + li, k0 + lk);
+            const double a = -vget(B, ld, m, p0, pw, r0 + li, k0 + lk);
             const double bv = Wp[(k0 + lk) * (NCTMAX * 16) + 16 * ct + li];
             d = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, d, 0, 0, 0);
         }
@@ -229,11 +229,12 @@ __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
     const BuildParams P = args.P;
     const int64_t Q = min((int64_t)(*args.rec_in_count), args.rec_in_cap);
     double *B = args.scratch + (int64_t)blockIdx.x * args.scratch_stride;  // [BQMAX][BMMAX]
-    double *y = B + (int64_t)BQMAX_BIG * BMMAX_BIG;                         // Q^T e
-    double *racc = y + BMMAX_BIG;                                          // residual
-    int *Il = reinterpret_cast<int *>(racc + BMMAX_BIG);                   // rows of I
-    unsigned char *rfl = reinterpret_cast<unsigned char *>(Il + BMMAX_BIG);  // row in R
-    double *gred = racc + BMMAX_BIG + (BMMAX_BIG * 5 + 7) / 8 + 8;           // panel partials
+    const int64_t ld = args.ld;                                            // rows per block column
+    double *y = B + (int64_t)BQMAX_BIG * ld;                               // Q^T e
+    double *racc = y + ld;                                                 // residual
+    int *Il = reinterpret_cast<int *>(racc + ld);                          // rows of I
+    unsigned char *rfl = reinterpret_cast<unsigned char *>(Il + ld);       // row in R
+    double *gred = racc + ld + (ld * 5 + 7) / 8 + 8;                       // panel partials
 
     for (int64_t pos = blockIdx.x; pos < Q; pos += gridDim.x) {
         const int32_t *rec = args.rec_in + pos * (int64_t)args.rec_in_stride;
@@ -254,7 +255,7 @@ __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
         for (int t = tid; t < BH; t += NT) S.hI[t] = HEMPTY;
         for (int t = tid; t < BHJ; t += NT) S.hJ[t] = HEMPTY;
         __syncthreads();
-        if (q > BQMAX_BIG || m > BMMAX_BIG) status = ST_CAP;
+        if (q > BQMAX_BIG || m > ld) status = ST_CAP;
         int np2 = 1;
         while (np2 < m) np2 <<= 1;
         if (status == ST_OK) {
@@ -386,7 +387,7 @@ __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
                         int sl;
                         if (hinsert<BLOGH>(S.hI, row, sl)) {
                             const int ps = atomicAdd(&S.cnt, 1);
-                            if (m + ps < BMMAX_BIG && ps < SORTN) S.skey[ps] = row; else ovf = true;
+                            if (m + ps < ld && ps < SORTN) S.skey[ps] = row; else ovf = true;
                         } else if (sl < 0) {
                             ovf = true;  // table full
                         }
@@ -447,14 +448,14 @@ __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
                 const int qn = q;
                 // gather: zero the block, scatter the columns' entries, Q^T e = e_k
                 for (int c = 0; c < qn; ++c)
-                    for (int i = tid; i < m; i += NT) B[(int64_t)c * BMMAX_BIG + i] = 0.0;
+                    for (int i = tid; i < m; i += NT) B[(int64_t)c * ld + i] = 0.0;
                 for (int i = tid; i < m; i += NT) y[i] = (i == kidx) ? 1.0 : 0.0;
                 __syncthreads();
                 for (int c = 0; c < qn; ++c) {
                     const int j = S.Jlist[c];
                     for (int64_t e = A.colptr[j] + tid; e < A.colptr[j + 1]; e += NT) {
                         const int sl = hfind<BLOGH>(S.hI, A.rowidx[e]);
-                        if (sl >= 0) B[(int64_t)c * BMMAX_BIG + S.hIv[sl]] = A.val[e];
+                        if (sl >= 0) B[(int64_t)c * ld + S.hIv[sl]] = A.val[e];
                     }
                 }
                 __syncthreads();
@@ -465,7 +466,7 @@ __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
                 for (int p0 = 0; p0 < qn; p0 += NB) {
                     const int pw = min(NB, qn - p0);
                     for (int j = p0; j < p0 + pw; ++j) {
-                        double *bj = B + (int64_t)j * BMMAX_BIG;
+                        double *bj = B + (int64_t)j * ld;
                         double s2 = 0.0;
                         for (int i = j + tid; i < m; i += NT) s2 += bj[i] * bj[i];
                         s2 = bsum(s2, S);
@@ -492,7 +493,7 @@ __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
 #pragma unroll
                                 for (int u = 0; u < 8; ++u) {
                                     const int c = c0 + u;
-                                    if (c < p0 + pw) part[u] += vi * B[(int64_t)c * BMMAX_BIG + i];
+                                    if (c < p0 + pw) part[u] += vi * B[(int64_t)c * ld + i];
                                 }
                             }
 #pragma unroll
@@ -521,7 +522,7 @@ __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
 #pragma unroll
                                 for (int u = 0; u < 8; ++u) {
                                     const int c = c0 + u;
-                                    if (c < p0 + pw) B[(int64_t)c * BMMAX_BIG + i] -= wv[u] * vi;
+                                    if (c < p0 + pw) B[(int64_t)c * ld + i] -= wv[u] * vi;
                                 }
                             }
                             __syncthreads();
@@ -529,7 +530,7 @@ __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
                     }
                     // columns after the panel plus the right-hand side (column qn)
                     const int c_lo = p0 + pw, ntr = qn + 1 - c_lo;
-                    if (ntr > 0) panel_update(B, y, m, qn, p0, pw, c_lo, ntr, S, gred);
+                    if (ntr > 0) panel_update(B, ld, y, m, qn, p0, pw, c_lo, ntr, S, gred);
                 }
                 if (singular) { status = ST_SINGULAR; break; }
                 // back substitution by wave 0: lane c holds m_c
@@ -538,7 +539,7 @@ __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
                     for (int j = qn - 1; j >= 0; --j) {
                         double part = 0.0;
                         for (int c = j + 1 + tid; c < qn; c += 64)
-                            part += B[(int64_t)c * BMMAX_BIG + j] * S.mt[c];
+                            part += B[(int64_t)c * ld + j] * S.mt[c];
                         part = gsum<16>(part);
                         part += __shfl_xor(part, 16);
                         part += __shfl_xor(part, 32);
@@ -662,7 +663,7 @@ __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
 
         // ================= output (rows of m_k ascending)
         const int qq = (status == ST_OK) ? q : 0;
-        const int64_t slot = args.arena_base + (int64_t)ucol * BQMAX_BIG;
+        const int64_t slot = args.arena_base + pos * BQMAX_BIG;  // one slot per record
         for (int c = tid; c < qq; c += NT) {
             const int jc = S.Jlist[c];
             int rank = 0;
@@ -694,7 +695,7 @@ __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
                 for (int c = tid; c < qq; c += NT) F[c] = (double)S.Jlist[c];
                 for (int t = tid; t < qq * qq; t += NT) {
                     const int i = t / qq, c = t % qq;
-                    if (c >= i) F[fac_row(qq, i) + (c - i)] = (c == i) ? S.rd[i] : B[(int64_t)c * BMMAX_BIG + i];
+                    if (c >= i) F[fac_row(qq, i) + (c - i)] = (c == i) ? S.rd[i] : B[(int64_t)c * ld + i];
                 }
             }
         }
@@ -702,9 +703,9 @@ __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
     }
 }
 
-int64_t big_scratch_stride() {
+int64_t big_scratch_stride(int64_t ld) {
     // doubles per workgroup: block, Q^T e, residual, then rows (int) and flags (byte)
-    return (int64_t)BQMAX_BIG * BMMAX_BIG + 2 * (int64_t)BMMAX_BIG + (BMMAX_BIG * 5 + 7) / 8 + 8 + REDN;
+    return (int64_t)BQMAX_BIG * ld + 2 * ld + (ld * 5 + 7) / 8 + 8 + REDN;
 }
 
 void launch_big_kernel(const BigArgs &a, int blocks, hipStream_t s) {

@@ -302,21 +302,28 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
         slot_base[t] = acap;
         acap += ncols * (int64_t)kTiers[t].QMAX;
     }
-    // the batched schedule ends with two workgroup-per-column classes: the sparse-block
-    // class, then the dense large class; they share one arena slot of 64 per column
-    const bool big = !plain;
-    int64_t big_base = acap;
-    if (big) acap += ncols * (int64_t)BQMAX_BIG;
-    P->arena_cap = acap;
-    const int nlaunch = plain ? P->p.lmax + 1 : (tlast - t0 + 1 + (big ? 1 + WIDE_LEVELS : 0));
-    const int64_t qlast = big ? std::max<int64_t>(kTiers[tlast].QMAX, BQMAX_BIG) : kTiers[tlast].QMAX;
-    const int big_blocks = device_cus();
     // records out of each sparse-block instance: few columns need the next class;
     // more than this many end with RSAI_E_CAP
     int64_t wide_rec_cap[WIDE_LEVELS];
     wide_rec_cap[0] = std::min<int64_t>(ncols, std::max<int64_t>(4096, ncols / 4));
     wide_rec_cap[1] = std::min<int64_t>(ncols, std::max<int64_t>(4096, ncols / 64));
     wide_rec_cap[2] = std::min<int64_t>(ncols, std::max<int64_t>(4096, ncols / 256));
+    // the batched schedule ends with two workgroup-per-column classes: the sparse-block
+    // class (an arena slot of 64 per column) and the dense large class, whose columns
+    // (at most its record capacity) get a slot of BQMAX_BIG per record
+    const bool big = !plain;
+    const int64_t big_cap = big ? wide_rec_cap[WIDE_LEVELS - 1] : 0;
+    const int64_t wide_base = acap;
+    if (big) acap += ncols * (int64_t)(WIDE_QMAX + 1);
+    const int64_t big_base = acap;
+    if (big) acap += big_cap * (int64_t)BQMAX_BIG;
+    P->arena_cap = acap;
+    const int nlaunch = plain ? P->p.lmax + 1 : (tlast - t0 + 1 + (big ? 1 + WIDE_LEVELS : 0));
+    const int64_t qlast = big ? std::max<int64_t>(kTiers[tlast].QMAX, BQMAX_BIG) : kTiers[tlast].QMAX;
+    const int64_t qmid = big ? std::max<int64_t>(kTiers[tlast].QMAX, WIDE_QMAX + 1) : qlast;
+    const int big_blocks = device_cus();
+    // slab rows of the dense class: no LS block has more rows than the matrix
+    const int64_t big_ld = std::min<int64_t>(BMMAX_BIG, (maxn + 63) / 64 * 64);
 
     // R factors kept for the adjoint: an arena of the requested size (default 256 MB);
     // columns that do not fit are refactorised by the adjoint
@@ -340,7 +347,9 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
             M.colidx = L.take<int32_t>(nnz);
             M.rowcnt = L.take<int32_t>(n);
             fillpos[i] = L.take<int32_t>(n);
-            M.capM = n * qlast;
+            // entries of M: at most qmid per column, and up to qlast for the columns the
+            // dense class finishes (no more than its record capacity)
+            M.capM = n * qmid + std::min<int64_t>(n, big_cap) * (qlast - qmid);
             M.summary = L.take<int64_t>(8);
             M.colptrM = L.take<int64_t>(n + 1);
             M.rowidxM = L.take<int32_t>(M.capM);
@@ -378,7 +387,7 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
                 for (int w = 0; w < WIDE_LEVELS; ++w)
                     P->rec[tlast + 1 + w] = L.take<int32_t>(wide_rec_cap[w] * (int64_t)wide_rec_stride(w));
         }
-        P->big_scratch = big ? L.take<double>((int64_t)big_blocks * big_scratch_stride()) : nullptr;
+        P->big_scratch = big ? L.take<double>((int64_t)big_blocks * big_scratch_stride(big_ld)) : nullptr;
     };
     Layout L0;
     layout(L0);
@@ -539,7 +548,7 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
                     w.mats = P->d_mats;
                     w.P = base.P;
                     w.out = P->out;
-                    w.arena_base = big_base;
+                    w.arena_base = wide_base;
                     w.rec_in = P->rec[tlast + lv];
                     w.rec_in_stride = lv == 0 ? kTiers[tlast].REC : wide_rec_stride(lv - 1);
                     w.rec_in_count = P->rec_count + (tlast - t0 + lv);
@@ -561,7 +570,8 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
                 b.rec_in_count = P->rec_count + (tlast - t0 + WIDE_LEVELS);
                 b.rec_in_cap = wide_rec_cap[WIDE_LEVELS - 1];
                 b.scratch = P->big_scratch;
-                b.scratch_stride = big_scratch_stride();
+                b.scratch_stride = big_scratch_stride(big_ld);
+                b.ld = big_ld;
                 b.err = P->err;
                 launch_big_kernel(b, big_blocks, s);
             }

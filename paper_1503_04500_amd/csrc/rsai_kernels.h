@@ -44,23 +44,25 @@ void launch_wide_kernel(int level, const WideArgs &a, int blocks, hipStream_t s)
 
 // ---- large size class (rsai_big.hip): one workgroup per column
 constexpr int BMMAX_BIG = 8192;  // rows of the LS block
-constexpr int BQMAX_BIG = 64;    // columns of the LS block
+constexpr int BQMAX_BIG = 128;   // columns of the LS block
 struct BigArgs {
     const MatDev *mats;
     BuildParams P;
     ColOut out;
-    int64_t arena_base;
+    int64_t arena_base;       // slot of the record at queue position pos: arena_base + pos * BQMAX_BIG
     const int32_t *rec_in;
     int rec_in_stride;
     const int32_t *rec_in_count;
     int64_t rec_in_cap;
     double *scratch;          // per-workgroup slabs
     int64_t scratch_stride;   // doubles per slab
+    int64_t ld;               // rows per block column in the slab: min(BMMAX_BIG, largest n)
     int32_t *err;
 };
 int big_max_rows();
 int big_max_cols();
-int64_t big_scratch_stride();
+// doubles of one workgroup's slab for blocks of ld rows (ld <= BMMAX_BIG)
+int64_t big_scratch_stride(int64_t ld);
 void launch_big_kernel(const BigArgs &a, int blocks, hipStream_t s);
 
 // ---- preprocessing (rsai_prep.hip)

@@ -192,6 +192,35 @@ def powerlaw(n: int, seed: int = 0, lmin: int = 2, lmax: int = 200,
     return from_coo(n, allr, allc, allv, f"powerlaw_{n}")
 
 
+def dense_rows(N: int, nrows: int, rowlen: int, scale: float = 1.0, seed: int = 0) -> CSC:
+    """2D convection-diffusion matrix (cd2d(N, seed)) with nrows relatively dense rows.
+
+    Each chosen row (distinct, uniform) gets rowlen - 1 extra off-diagonal entries in
+    distinct uniform columns not already in the row, values scale * U(-1, 1). Such
+    rows pull their whole pattern into J_k when they are selected as dominant, which
+    is the regime where the LS problems grow large (Section 4).
+    """
+    base = cd2d(N, seed=seed)
+    n = base.n
+    rng = np.random.default_rng(seed + 7919)
+    rows = [base.rowidx.astype(np.int64)]
+    cols = [base.col_of_entry().astype(np.int64)]
+    vals = [base.val]
+    have = set(zip(rows[0].tolist(), cols[0].tolist()))
+    for i in rng.choice(n, size=nrows, replace=False):
+        picked = []
+        while len(picked) < rowlen - 1:
+            j = int(rng.integers(0, n))
+            if j != i and (int(i), j) not in have:
+                have.add((int(i), j))
+                picked.append(j)
+        rows.append(np.full(len(picked), i, np.int64))
+        cols.append(np.asarray(picked, np.int64))
+        vals.append(scale * rng.uniform(-1.0, 1.0, len(picked)))
+    return from_coo(n, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals),
+                    f"dense_rows_{N}_{nrows}_{rowlen}")
+
+
 def tridiag(n: int, lower: float = -1.0, diag: float = 2.0, upper: float = -1.0) -> CSC:
     d = np.diag(np.full(n, diag)) + np.diag(np.full(n - 1, lower), -1) + np.diag(np.full(n - 1, upper), 1)
     return from_dense(d, f"tridiag_{n}")

@@ -168,6 +168,9 @@ def test_cap_error_beyond_large_class():
     assert ei.value.code == -6
     st = plan.stats()["status"].cpu().numpy()
     assert set(np.unique(st).tolist()) <= {0, 6}
+    # exactly the columns whose J_k passes the dense class's 128 columns at some solve
+    ref = _ref(A, c=3, lmax=2, eps=0.4, drop=1, tol=1e-3)
+    assert np.array_equal(st == 6, ref["nJmax"] > 128)
     assert (st == 6).sum() > 200
 
 

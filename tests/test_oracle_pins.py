@@ -269,3 +269,24 @@ def test_bicgstab_c1_preconditioned_fewer_iterations():
     it1, rel, x = oracle.bicgstab(A, b, (R["colptr"], R["rowidx"], R["val"]))
     assert rel < 1e-8 and it1 < it0
     assert np.allclose(x, 1.0, atol=1e-5)
+
+
+def test_peak_sizes_bound_final_sizes():
+    """nJmax / nImax are the largest |J_k|, |I_k| of any solve: they equal the final
+    sizes when nothing is dropped (J and I only grow, Algorithm 1), bound them
+    otherwise, and on an arrow matrix (row 0 full) reach all n columns."""
+    A = gen.cd2d(20, seed=4)
+    r0 = oracle.rsai(A, c=3, lmax=6, eps=0.3, drop=oracle.DROP_NONE, tol=1e-3)
+    assert np.array_equal(r0["nJmax"], r0["nJ"]) and np.array_equal(r0["nImax"], r0["nI"])
+    r1 = oracle.rsai(A, c=3, lmax=6, eps=0.3, drop=oracle.DROP_FIXED, tol=0.05)
+    assert np.all(r1["nJmax"] >= r1["nJ"]) and np.all(r1["nImax"] >= r1["nI"])
+    assert np.any(r1["nJmax"] > r1["nJ"])
+    n = 40
+    rows, cols, vals = [], [], []
+    for k in range(n):
+        rows.append(k); cols.append(k); vals.append(4.0 if k else 2.0 * n)
+        if k:
+            rows += [0, k]; cols += [k, 0]; vals += [3.0, 1.0]
+    Aa = gen.from_coo(n, np.array(rows), np.array(cols), np.array(vals))
+    ra = oracle.rsai(Aa, c=3, lmax=2, eps=0.4, drop=oracle.DROP_FIXED, tol=1e-3)
+    assert ra["nJmax"][1:].min() == n
