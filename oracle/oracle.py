@@ -60,6 +60,8 @@ def _load():
     lib.oracle_backward.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _D, _P]
     lib.oracle_bicgstab.restype = _I32
     lib.oracle_bicgstab.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _D, _I32, _P, _P]
+    lib.oracle_bicgstab_left.restype = _I32
+    lib.oracle_bicgstab_left.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _D, _I32, _P, _P]
     _lib = lib
     return lib
 
@@ -154,11 +156,13 @@ def backward(A, Mcolptr, Mrowidx, Mval, gM=None, w_frob: float = 0.0):
     return dA
 
 
-def bicgstab(A, b, M=None, tol: float = 1e-8, maxit: int = 1000):
-    """Right-preconditioned BiCGStab on A M y = b. Returns (iterations, relres, x).
+def bicgstab(A, b, M=None, tol: float = 1e-8, maxit: int = 1000, left: bool = False):
+    """BiCGStab preconditioned with M: on A M y = b (right, x = M y) or, with
+    left=True, on M A x = M b. Returns (iterations, relres, x); the test is the true
+    relative residual ||b - A x|| / ||b|| < tol after each half and full step.
 
     iterations = maxit + 1 means no convergence; -1 means breakdown.
-    ``M`` is None or a (colptr, rowidx, val) tuple.
+    ``M`` is None or a (colptr, rowidx, val) tuple (required for left=True).
     """
     lib = _load()
     cp, ri, va = _csc(A.colptr, A.rowidx, A.val)
@@ -169,6 +173,9 @@ def bicgstab(A, b, M=None, tol: float = 1e-8, maxit: int = 1000):
         mcp = mri = mv = None
     else:
         mcp, mri, mv = _csc(*M)
-    it = lib.oracle_bicgstab(int(A.n), _ptr(cp), _ptr(ri), _ptr(va), _ptr(mcp), _ptr(mri), _ptr(mv), _ptr(bb),
-                             float(tol), int(maxit), _ptr(x), ctypes.byref(rel))
+    if left and M is None:
+        raise ValueError("left preconditioning needs M")
+    fn = lib.oracle_bicgstab_left if left else lib.oracle_bicgstab
+    it = fn(int(A.n), _ptr(cp), _ptr(ri), _ptr(va), _ptr(mcp), _ptr(mri), _ptr(mv), _ptr(bb),
+            float(tol), int(maxit), _ptr(x), ctypes.byref(rel))
     return int(it), float(rel.value), x

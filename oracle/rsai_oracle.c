@@ -818,3 +818,76 @@ done:
     free(r); free(rh); free(p); free(v); free(s); free(t); free(ph); free(sh); free(tmp);
     return ret;
 }
+
+/*
+ * Left-preconditioned BiCGStab: the textbook iteration on M A x = M b (the left form
+ * of (1.2)), x0 = 0, shadow residual r^ = r0 = M b. The stopping test is the one of
+ * Section 5 on the true residual, ||b - A x|| / ||b|| < tol, after the half step
+ * (x + alpha p) and after the full step. Return values as oracle_bicgstab.
+ */
+int32_t oracle_bicgstab_left(int64_t n, const int64_t *colptr, const int32_t *rowidx, const double *val,
+                             const int64_t *Mcolptr, const int32_t *Mrowidx, const double *Mval,
+                             const double *b, double tol, int32_t maxit, double *x, double *relres) {
+    size_t sz = sizeof(double) * (size_t)(n > 0 ? n : 1);
+    double *r = malloc(sz), *rh = malloc(sz), *p = malloc(sz), *v = malloc(sz), *s = malloc(sz),
+           *t = malloc(sz), *tmp = malloc(sz), *ax = malloc(sz);
+    csc_matvec(n, Mcolptr, Mrowidx, Mval, b, r);
+    for (int64_t i = 0; i < n; ++i) { x[i] = 0.0; rh[i] = r[i]; p[i] = 0.0; v[i] = 0.0; }
+    double nb = sqrt(dot(n, b, b));
+    double rel = (nb == 0.0) ? 0.0 : 1.0;
+    if (nb == 0.0) nb = 1.0;
+    double rho = 1.0, alpha = 1.0, omega = 1.0;
+    int32_t it = 0, ret = -1;
+    if (rel < tol) { ret = 0; goto done; }
+    for (it = 1; it <= maxit; ++it) {
+        double rho1 = dot(n, rh, r);
+        if (rho1 == 0.0) { ret = -1; goto done; }
+        if (it == 1) {
+            for (int64_t i = 0; i < n; ++i) p[i] = r[i];
+        } else {
+            double beta = (rho1 / rho) * (alpha / omega);
+            for (int64_t i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+        }
+        csc_matvec(n, colptr, rowidx, val, p, tmp);            /* A p */
+        csc_matvec(n, Mcolptr, Mrowidx, Mval, tmp, v);         /* v = M A p */
+        double rv = dot(n, rh, v);
+        if (rv == 0.0) { ret = -1; goto done; }
+        alpha = rho1 / rv;
+        for (int64_t i = 0; i < n; ++i) s[i] = r[i] - alpha * v[i];
+        for (int64_t i = 0; i < n; ++i) tmp[i] = x[i] + alpha * p[i];
+        csc_matvec(n, colptr, rowidx, val, tmp, ax);
+        {
+            double nr = 0.0;
+            for (int64_t i = 0; i < n; ++i) nr += (b[i] - ax[i]) * (b[i] - ax[i]);
+            rel = sqrt(nr) / nb;
+        }
+        if (rel < tol) {
+            for (int64_t i = 0; i < n; ++i) x[i] = tmp[i];
+            ret = it;
+            goto done;
+        }
+        csc_matvec(n, colptr, rowidx, val, s, tmp);            /* A s */
+        csc_matvec(n, Mcolptr, Mrowidx, Mval, tmp, t);         /* t = M A s */
+        double tt = dot(n, t, t);
+        if (tt == 0.0) { ret = -1; goto done; }
+        omega = dot(n, t, s) / tt;
+        for (int64_t i = 0; i < n; ++i) {
+            x[i] = x[i] + alpha * p[i] + omega * s[i];
+            r[i] = s[i] - omega * t[i];
+        }
+        csc_matvec(n, colptr, rowidx, val, x, ax);
+        {
+            double nr = 0.0;
+            for (int64_t i = 0; i < n; ++i) nr += (b[i] - ax[i]) * (b[i] - ax[i]);
+            rel = sqrt(nr) / nb;
+        }
+        if (rel < tol) { ret = it; goto done; }
+        if (omega == 0.0) { ret = -1; goto done; }
+        rho = rho1;
+    }
+    ret = maxit + 1;
+done:
+    *relres = rel;
+    free(r); free(rh); free(p); free(v); free(s); free(t); free(tmp); free(ax);
+    return ret;
+}

@@ -147,6 +147,31 @@ def test_c3_sampled_columns():
     print("C3 sample", s, "max |I|", int(ref["nI"].max()))
 
 
+def test_zero_diagonals_parity():
+    """Rows of a 24x24 grid matrix permuted at random: 567 of 576 diagonal entries are
+    zero, so k is not in I_k at the start and r(k) = -1 enters the selection."""
+    A = gen.cd2d(24, seed=2)
+    perm = np.random.default_rng(5).permutation(A.n)
+    inv = np.empty(A.n, np.int64)
+    inv[perm] = np.arange(A.n)
+    B = gen.from_coo(A.n, inv[A.rowidx], A.col_of_entry(), A.val)
+    assert (B.to_dense().diagonal() == 0).sum() > 500
+    ref = _ref(B)
+    gpu = run_gpu(B, **C1)
+    compare(B, gpu, ref, label="zero-diagonals")
+
+
+def test_permutation_matrix_gives_its_transpose():
+    n = 500
+    pi = np.random.default_rng(2).permutation(n)
+    P = gen.from_coo(n, pi, np.arange(n), np.ones(n))
+    gpu = run_gpu(P, c=3, lmax=4, eps=0.1, drop="fixed", tol=1e-3)
+    M = gen.CSC(n, gpu["colptr"], gpu["rowidx"], gpu["val"]).to_dense()
+    fixed = pi == np.arange(n)
+    assert np.array_equal(M, P.to_dense().T)
+    assert np.all(gpu["loops"][~fixed] == 1) and np.all(gpu["resnorm"] == 0.0)
+
+
 def _arrow(n, a0=3.0, d=4.0):
     """Row 0 and column 0 full, diagonal d: every column's residual picks row 0,
     whose pattern brings all n columns into J-hat."""

@@ -290,3 +290,70 @@ def test_peak_sizes_bound_final_sizes():
     Aa = gen.from_coo(n, np.array(rows), np.array(cols), np.array(vals))
     ra = oracle.rsai(Aa, c=3, lmax=2, eps=0.4, drop=oracle.DROP_FIXED, tol=1e-3)
     assert ra["nJmax"][1:].min() == n
+
+
+def test_permutation_matrix_gives_its_transpose():
+    """A permutation matrix with no fixed point: loop 0 finds m = 0 (column k of A is
+    orthogonal to e_k) and r = -e_k, so k is the dominant index (r(k) = -1 with k not
+    in I, Algorithm 1 step 4); row k brings column pi^-1(k) into J and the LS is then
+    solved exactly. After the drop of the zero coefficient, M = P^T in one loop."""
+    n = 50
+    pi = np.random.default_rng(2).permutation(n)
+    assert not np.any(pi == np.arange(n))
+    P = gen.from_coo(n, pi, np.arange(n), np.ones(n))
+    R = oracle.rsai(P, c=3, lmax=4, eps=0.1, drop=oracle.DROP_FIXED, tol=1e-3)
+    M = gen.CSC(n, R["colptr"], R["rowidx"], R["val"]).to_dense()
+    assert np.array_equal(M, P.to_dense().T)
+    assert np.all(R["loops"] == 1) and np.all(R["resnorm"] == 0.0)
+
+
+def test_left_bicgstab_exact_preconditioner_one_half_step():
+    """M A = I: the first half step of the left form solves the system."""
+    d = np.array([2.0, 3.0, -1.5, 4.0, 0.5])
+    A = gen.diagonal(d)
+    b = np.array([1.0, -2.0, 0.25, 3.0, 1.5])
+    Minv = (np.arange(6, dtype=np.int64), np.arange(5, dtype=np.int32), 1.0 / d)
+    it, rel, x = oracle.bicgstab(A, b, Minv, left=True)
+    assert it == 1 and rel < 1e-15
+    assert np.allclose(x, b / d, rtol=1e-15, atol=0)
+
+
+def test_left_bicgstab_identity_equals_unpreconditioned():
+    """With M = I both forms are the plain iteration: the same iterates to the bit."""
+    A = gen.cd2d(12, seed=6)
+    b = np.random.default_rng(3).standard_normal(A.n)
+    I = (np.arange(A.n + 1, dtype=np.int64), np.arange(A.n, dtype=np.int32), np.ones(A.n))
+    r0 = oracle.bicgstab(A, b, None)
+    r1 = oracle.bicgstab(A, b, I, left=True)
+    assert r0[0] == r1[0] and r0[1] == r1[1] and np.array_equal(r0[2], r1[2])
+
+
+def test_left_bicgstab_matches_dense_textbook_iterate():
+    """Three iterations of the left form against BiCGStab written out on dense
+    matrices (B = M A, c = M b); the iterates agree to rounding."""
+    A = gen.cd2d(6, seed=8)
+    n = A.n
+    Ad = A.to_dense()
+    R = oracle.rsai(gen.from_dense(Ad.T.copy()), c=2, lmax=3, eps=0.3, tol=1e-3)
+    Md = gen.CSC(n, R["colptr"], R["rowidx"], R["val"]).to_dense().T  # rows from RSAI on A^T
+    Mcsc = gen.from_dense(Md)
+    b = np.random.default_rng(9).standard_normal(n)
+    it, rel, x = oracle.bicgstab(A, b, (Mcsc.colptr, Mcsc.rowidx, Mcsc.val), maxit=3, left=True)
+    B, c = Md @ Ad, Md @ b
+    xr, r = np.zeros(n), c.copy()
+    rh, p, v = r.copy(), np.zeros(n), np.zeros(n)
+    rho = al = om = 1.0
+    for k in range(1, 4):
+        rho1 = rh @ r
+        p = r.copy() if k == 1 else r + (rho1 / rho) * (al / om) * (p - om * v)
+        v = B @ p
+        al = rho1 / (rh @ v)
+        s = r - al * v
+        t = B @ s
+        om = (t @ s) / (t @ t)
+        xr = xr + al * p + om * s
+        r = s - om * t
+        rho = rho1
+    assert it == 4
+    assert np.allclose(x, xr, rtol=1e-12, atol=1e-14)
+    assert abs(rel - np.linalg.norm(b - Ad @ xr) / np.linalg.norm(b)) < 1e-12
