@@ -197,6 +197,24 @@ rsai_status rsai_backward(rsai_plan *P, int32_t mat, const double *dM_val, doubl
 rsai_status rsai_bicgstab(rsai_plan *P, int32_t mat, const double *b, double *x, double tol, int32_t maxit,
                           int32_t use_M, int32_t use_graph, int32_t *iters, double *relres, void *stream);
 
+/* The left form of (1.2): solve M A x = M b by BiCGStab, where the left
+   preconditioner is M = N^T for N the RSAI(tol) factor of A^T (columns of N
+   minimise ||A^T n_k - e_k||, so the rows of M minimise ||e_k^T - m_k^T A||).
+   PT is a plan built on A^T (see rsai_transpose) and A the matrix itself (device
+   CSC, same n and nnz). x0 = 0, shadow residual M b, and the stopping test of
+   Section 5 on the true residual ||b - A x|| / ||b|| < tol after each half and full
+   step. Arguments, results, buffers and errors otherwise as rsai_bicgstab; also
+   RSAI_E_ARG if A does not match the plan's matrix in n and nnz. */
+rsai_status rsai_bicgstab_left(const rsai_csc *A, rsai_plan *PT, int32_t mat, const double *b, double *x,
+                               double tol, int32_t maxit, int32_t use_graph, int32_t *iters, double *relres,
+                               void *stream);
+
+/* A^T of a CSC matrix, as CSC (rows ascending in each column), into caller device
+   buffers colptrT[n+1], rowidxT[nnz], valT[nnz]. Deterministic. Work buffers come
+   from the allocator. Host-synchronising. Errors: RSAI_E_ARG (NULL pointer,
+   n < 1 or nnz < n), RSAI_E_NOMEM, RSAI_E_HIP. */
+rsai_status rsai_transpose(const rsai_csc *A, int64_t *colptrT, int32_t *rowidxT, double *valT, void *stream);
+
 /* y = A x (transpose = 0) or y = A^T x (transpose = 1) for a CSC matrix. */
 rsai_status rsai_spmv(const rsai_csc *A, const double *x, double *y, int32_t transpose, void *stream);
 

@@ -897,20 +897,13 @@ static rsai_status to_sell(int64_t n, const int64_t *rp, const int32_t *ci, cons
     return RSAI_OK;
 }
 
-rsai_status rsai_bicgstab(rsai_plan *P, int32_t mat, const double *b, double *x, double tol, int32_t maxit,
-                          int32_t use_M, int32_t use_graph, int32_t *iters, double *relres, void *stream) {
-    rsai_status st = check_mat(P, mat);
-    if (st != RSAI_OK) return st;
-    if (!b || !x || !iters || !relres) return fail(RSAI_E_ARG, "NULL argument");
-    if (!(tol >= 0.0) || maxit < 0) return fail(RSAI_E_ARG, "tol must be >= 0 and maxit >= 0");
-    if (use_M) {
-        st = rows_of_M(P, mat);
-        if (st != RSAI_OK) return st;
-    }
-    MatPlan &M = P->mats[mat];
-    const rsai_csc &A = M.A;
+// BiCGStab on A with the preconditioner given by its rows (mode 1 right, 2 left;
+// mrp == nullptr and mode 0 without one)
+static rsai_status bicg_solve(const rsai_csc &A, int mode, const int64_t *mrp, const int32_t *mci,
+                              const double *mva, const double *b, double *x, double tol, int32_t maxit,
+                              int32_t use_graph, int32_t *iters, double *relres, hipStream_t s) {
+    rsai_status st = RSAI_OK;
     const int64_t n = A.n, nnz = A.nnz;
-    hipStream_t s = (hipStream_t)stream;
     std::vector<void *> tmp;
     std::function<void *(size_t)> al = [&](size_t bytes) -> void * {
         void *q = dev_alloc(std::max<size_t>(bytes, 8), s);
@@ -936,8 +929,7 @@ rsai_status rsai_bicgstab(rsai_plan *P, int32_t mat, const double *b, double *x,
         if (st != RSAI_OK) return cleanup(st);
         enqueue_rows(&A, arp, aci, ava, cnt, fill, stmp, zerr, s);
         rsai_status r2 = to_sell(n, arp, aci, ava, stmp, al, a.asp, a.aw, a.aci, a.ava, s);
-        if (r2 == RSAI_OK && use_M)
-            r2 = to_sell(n, M.rowptrT, M.colidxT, M.valT, stmp, al, a.msp, a.mw, a.mci, a.mva, s);
+        if (r2 == RSAI_OK && mode != 0) r2 = to_sell(n, mrp, mci, mva, stmp, al, a.msp, a.mw, a.mci, a.mva, s);
         if (st != RSAI_OK || r2 != RSAI_OK) return cleanup(st != RSAI_OK ? st : r2);
     }
     double *vec = (double *)al(8 * 12 * (size_t)n);
@@ -954,13 +946,13 @@ rsai_status rsai_bicgstab(rsai_plan *P, int32_t mat, const double *b, double *x,
     a.v = vp; vp += n;
     a.s = vp; vp += n;
     a.t = vp; vp += n;
-    a.ph = vp; vp += n;
-    a.sh = vp; vp += n;
+    a.fp = vp; vp += n;
+    a.fs = vp; vp += n;
     a.res = vp; vp += n;
-    a.mr = vp; vp += n;
+    a.fr = vp; vp += n;
     a.xh = vp;
     seq.grid = bicg_grid(n);
-    seq.precond = use_M != 0;
+    seq.mode = mode;
     BicgState h[2] = {};
     h[0].tol = h[1].tol = tol;
     h[0].maxit = h[1].maxit = maxit;
@@ -1021,6 +1013,68 @@ rsai_status rsai_bicgstab(rsai_plan *P, int32_t mat, const double *b, double *x,
     *iters = hs.ret;
     *relres = hs.rel;
     return cleanup(RSAI_OK);
+}
+
+rsai_status rsai_bicgstab(rsai_plan *P, int32_t mat, const double *b, double *x, double tol, int32_t maxit,
+                          int32_t use_M, int32_t use_graph, int32_t *iters, double *relres, void *stream) {
+    rsai_status st = check_mat(P, mat);
+    if (st != RSAI_OK) return st;
+    if (!b || !x || !iters || !relres) return fail(RSAI_E_ARG, "NULL argument");
+    if (!(tol >= 0.0) || maxit < 0) return fail(RSAI_E_ARG, "tol must be >= 0 and maxit >= 0");
+    MatPlan &M = P->mats[mat];
+    if (use_M) {
+        st = rows_of_M(P, mat);
+        if (st != RSAI_OK) return st;
+        return bicg_solve(M.A, 1, M.rowptrT, M.colidxT, M.valT, b, x, tol, maxit, use_graph, iters, relres,
+                          (hipStream_t)stream);
+    }
+    return bicg_solve(M.A, 0, nullptr, nullptr, nullptr, b, x, tol, maxit, use_graph, iters, relres,
+                      (hipStream_t)stream);
+}
+
+rsai_status rsai_bicgstab_left(const rsai_csc *A, rsai_plan *PT, int32_t mat, const double *b, double *x, double tol,
+                               int32_t maxit, int32_t use_graph, int32_t *iters, double *relres, void *stream) {
+    rsai_status st = check_mat(PT, mat);
+    if (st != RSAI_OK) return st;
+    if (!A || !A->colptr || !A->rowidx || !A->val || !b || !x || !iters || !relres)
+        return fail(RSAI_E_ARG, "NULL argument");
+    if (!(tol >= 0.0) || maxit < 0) return fail(RSAI_E_ARG, "tol must be >= 0 and maxit >= 0");
+    MatPlan &M = PT->mats[mat];
+    if (A->n != M.A.n || A->nnz != M.A.nnz)
+        return fail(RSAI_E_ARG, "A does not match the transposed matrix of the plan (n %lld vs %lld, nnz %lld vs %lld)",
+                    (long long)A->n, (long long)M.A.n, (long long)A->nnz, (long long)M.A.nnz);
+    int64_t nz = 0;
+    st = rsai_plan_nnz(PT, mat, &nz);
+    if (st != RSAI_OK) return st;
+    // rows of the left preconditioner M^T are the columns of the plan's M (CSC, rows
+    // ascending within each column)
+    return bicg_solve(*A, 2, M.colptrM, M.rowidxM, M.valM, b, x, tol, maxit, use_graph, iters, relres,
+                      (hipStream_t)stream);
+}
+
+rsai_status rsai_transpose(const rsai_csc *A, int64_t *colptrT, int32_t *rowidxT, double *valT, void *stream) {
+    if (!A || !A->colptr || !A->rowidx || !A->val || !colptrT || !rowidxT || !valT)
+        return fail(RSAI_E_ARG, "NULL argument");
+    if (A->n < 1 || A->nnz < A->n) return fail(RSAI_E_ARG, "bad sizes");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = A->n;
+    rsai_status st = RSAI_OK;
+    std::vector<void *> tmp;
+    auto al = [&](size_t bytes) -> void * {
+        void *q = dev_alloc(std::max<size_t>(bytes, 8), s);
+        if (!q) st = fail(RSAI_E_NOMEM, "allocation failed");
+        tmp.push_back(q);
+        return q;
+    };
+    int32_t *cnt = (int32_t *)al(4 * n), *fill = (int32_t *)al(4 * n), *zerr = (int32_t *)al(16);
+    int64_t *stmp = (int64_t *)al(8 * scan_tmp_elems(n + 1));
+    if (st == RSAI_OK) {
+        // the rows of A, sorted by column, are the columns of A^T sorted by row
+        enqueue_rows(A, colptrT, rowidxT, valT, cnt, fill, stmp, zerr, s);
+        if (hipStreamSynchronize(s) != hipSuccess) st = fail(RSAI_E_HIP, "transpose failed");
+    }
+    for (void *q : tmp) dev_free(q, s);
+    return st;
 }
 
 rsai_status rsai_backward(rsai_plan *P, int32_t mat, const double *dM_val, double w_frob, double *dA_val,

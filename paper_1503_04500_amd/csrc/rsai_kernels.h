@@ -118,7 +118,9 @@ struct BicgArgs {
     const int32_t *mw, *mci;
     const double *mva;
     const double *b;
-    double *x, *r, *rh, *p, *w, *v, *s, *t, *ph, *sh, *xh, *res, *mr;  // without M: ph = p, sh = s
+    // iterate and recurrence vectors; fr, fp, fs = F r, F p, F s for the operator F
+    // applied first (right: M, left: A), unused without a preconditioner
+    double *x, *r, *rh, *p, *w, *v, *s, *t, *xh, *res, *fr, *fp, *fs;
     double *part;        // 2 buffers of 2 * BICG_MAXGRID partial sums
     BicgState *st;       // 2 copies of the state
 };
@@ -134,7 +136,7 @@ struct BicgStep {
 struct BicgSeq {
     BicgArgs a{};
     int grid = 1;
-    bool precond = true;
+    int mode = 1;  // 0 no preconditioner, 1 right (A M y = b), 2 left (M A x = M b)
     int sp = 0, pb = 0, pending = 0;
     void step(int stage, bool produces, BicgStep &q);
     void init(hipStream_t s);                    // x0 = 0 and the initial test; state in copy 0

@@ -1,9 +1,11 @@
-// Right-preconditioned BiCGStab on the device: the solve step of the paper's
-// experiments (Section 5) with the RSAI(tol) factor M as right preconditioner.
+// Preconditioned BiCGStab on the device: the solve step of the paper's experiments
+// (Section 5) with the RSAI(tol) factor M, in the right form A M y = b, x = M y, or
+// the left form M A x = M b of (1.2) (M then comes from RSAI on A^T, transposed).
 //
-// A M y = b is iterated with x = M y carried directly; the stopping test is the true
-// relative residual ||b - A x|| / ||b|| < tol, evaluated after the half step and after
-// the full step of every iteration, x0 = 0 and shadow residual r^ = b.
+// x0 = 0; shadow residual r^ = r0 (b, or M b in the left form). The stopping test is
+// the true relative residual ||b - A x|| / ||b|| < tol, evaluated after the half step
+// and after the full step of every iteration (x = M y is carried directly in the
+// right form).
 //
 // Device design:
 //  * A and M are held in SELL-64 form (slices of 64 rows, one wavefront; a slice is
@@ -19,25 +21,28 @@
 //    one partial sum per workgroup, and every workgroup of the next kernel adds all
 //    partials in index order (the same order everywhere, so all workgroups agree to
 //    the bit) before applying the scalar step. The kernel boundary orders the two.
-//
-//  * Products are split by linearity so that no kernel gathers more than two vectors
-//    and no kernel exists for an elementwise update alone: with w = p - omega v kept
-//    from the previous iteration, M p = M r + beta M w; M s = M r - alpha M v; and the
-//    half-step residual b - A (x + alpha ph) = (b - A x) - alpha v. Every residual is
-//    still formed from fresh products of the current vectors (b - A x by an SpMV of
-//    x in each iteration, v = A ph), not carried by a recurrence.
+//  * Products are split by linearity so that no kernel gathers more than needed and
+//    no kernel exists for an elementwise update alone. With F the operator applied
+//    first to a direction and G the second (right: F = M, G = A; left: F = A,
+//    G = M), and w = p - omega v kept from the previous iteration:
+//    F p = F r + beta F w; F s = F r - alpha F v; and the half-step residual
+//    b - A (x + alpha d) = (b - A x) - alpha A d with A d = v (right, d = M p) or
+//    A d = F p (left, d = p). Every residual is still formed from fresh products of
+//    the current vectors (b - A x by an SpMV of x in each iteration), not carried by
+//    a recurrence.
 //
 // Kernels of one iteration k (| the partial sums a kernel produces, [] the step it
 // applies first from the previous kernel's partials):
-//   pre   [r^.r of iteration k-1: beta] p = r + beta w, ph = M r + beta M w (M r
+//   pre   [r^.r of iteration k-1: beta] p = r + beta w, fp = F r + beta F w (F r
 //         kept), res = b - A x | ||res||^2
-//   av    [full-step test of x_k (for k = 1 the initial test), end tests] v = A ph
+//   av    [full-step test of x_k (for k = 1 the initial test), end tests] v = G fp
 //         | r^.v
-//   half  [alpha] s = r - alpha v, xh = x + alpha ph, sh = M r - alpha M v
-//         | ||res - alpha v||^2
-//   at    [half-step test] t = A sh | t.t, t.s
-//   uf    [omega] x = xh + omega sh, r = s - omega t, w = p - omega v | r^.r
-// Without M, ph = p and sh = s. In the first iteration beta = 0 and w = 0, so p = r.
+//   half  [alpha] s = r - alpha v, xh = x + alpha d, fs = F r - alpha F v
+//         | ||res - alpha A d||^2
+//   at    [half-step test] t = G fs | t.t, t.s
+//   uf    [omega] x = xh + omega (M s right, s otherwise), r = s - omega t,
+//         w = p - omega v | r^.r
+// Without M, F = I and G = A. In the first iteration beta = 0 and w = 0, so p = r.
 #include <algorithm>
 
 #include "rsai_kernels.h"
@@ -54,12 +59,12 @@ enum Stage { BS_NONE = 0, BS_INIT, BS_RES, BS_AV, BS_HALF, BS_AT, BS_UF };
 // iteration that runs next (pre .. uf).
 __device__ void apply_stage(BicgState &S, int stage, const double *tot) {
     switch (stage) {
-    case BS_INIT: {
+    case BS_INIT: {  // ||b||^2, r^.r of the initial residual
         const double nb = sqrt(tot[0]);
         S.nb = (nb == 0.0) ? 1.0 : nb;
         S.rel = nb / S.nb;
         S.rho = S.alpha = S.omega = 1.0;
-        S.rho1 = S.rho1n = tot[0];
+        S.rho1 = S.rho1n = tot[1];
         S.it = 1;
         S.half = 0;
         if (S.rel < S.tol) { S.done = 1; S.ret = 0; }
@@ -102,7 +107,7 @@ __device__ void apply_stage(BicgState &S, int stage, const double *tot) {
     }
 }
 
-__device__ __forceinline__ int stage_values(int stage) { return stage == BS_AT ? 2 : 1; }
+__device__ __forceinline__ int stage_values(int stage) { return (stage == BS_AT || stage == BS_INIT) ? 2 : 1; }
 
 // Read the state, fold in the pending partial sums, pass the state on (workgroup 0).
 // Every thread of every workgroup ends with the same S. Returns false when the solve
@@ -185,20 +190,29 @@ __device__ __forceinline__ void sell_row2(const int64_t *sp, const int32_t *sw, 
 #define ROWS(i, n) for (int64_t i = blockIdx.x * (int64_t)KT + threadIdx.x; i < (n); i += (int64_t)gridDim.x * KT)
 }  // namespace
 
-// x = 0, r = r^ = p = b, w = v = 0 | ||b||^2
+// Modes: 0 no preconditioner, 1 right (A M y = b, x = M y), 2 left (M A x = M b).
+// F is the operator applied first to a direction and G the second: right F = M,
+// G = A; left F = A, G = M; none F = I, G = A. fr = F r, fp = F p, fs = F s.
+#define SELL_A a.asp, a.aw, a.aci, a.ava
+#define SELL_M a.msp, a.mw, a.mci, a.mva
+
+// x = 0, r = r^ = p = b (left: M b), w = v = 0 | ||b||^2, r^.r
+template <int MODE>
 __global__ __launch_bounds__(KT) void kb_init(BicgArgs a, BicgStep q) {
-    double acc[1] = {0.0};
+    double acc[2] = {0.0, 0.0};
     ROWS(i, a.n) {
         const double bi = a.b[i];
+        const double ri = (MODE == 2) ? sell_row(SELL_M, a.b, i) : bi;
         a.x[i] = 0.0;
-        a.r[i] = bi;
-        a.rh[i] = bi;
-        a.p[i] = bi;
+        a.r[i] = ri;
+        a.rh[i] = ri;
+        a.p[i] = ri;
         a.w[i] = 0.0;
         a.v[i] = 0.0;
         acc[0] += bi * bi;
+        acc[1] += ri * ri;
     }
-    write_partials<1>(acc, q.pout);
+    write_partials<2>(acc, q.pout);
 }
 
 // one workgroup: fold in pending partial sums and write the state to both copies
@@ -208,8 +222,8 @@ __global__ __launch_bounds__(KT) void kb_settle(BicgArgs a, BicgStep q, BicgStat
     if (threadIdx.x == 0) *other = S;
 }
 
-// [beta] p = r + beta w, ph = M r + beta M w (M r kept), res = b - A x | ||res||^2
-template <bool PRE>
+// [beta] p = r + beta w, fp = F r + beta F w (F r kept), res = b - A x | ||res||^2
+template <int MODE>
 __global__ __launch_bounds__(KT) void kb_pre(BicgArgs a, BicgStep q) {
     BicgState S;
     if (!take_state(q, S)) return;
@@ -217,62 +231,87 @@ __global__ __launch_bounds__(KT) void kb_pre(BicgArgs a, BicgStep q) {
     double acc[1] = {0.0};
     ROWS(i, a.n) {
         a.p[i] = a.r[i] + beta * a.w[i];
-        if (PRE) {
-            double mr, mw;
-            sell_row2(a.msp, a.mw, a.mci, a.mva, a.r, a.w, i, mr, mw);
-            a.mr[i] = mr;
-            a.ph[i] = mr + beta * mw;
+        double ax;
+        if (MODE == 2) {
+            // one pass over the rows of A for A r, A w and A x
+            const int64_t sl = i / SL, e0 = a.asp[sl] + (i % SL);
+            const int wd = a.aw[sl];
+            double qr = 0.0, qw = 0.0, qx = 0.0;
+#pragma unroll 4
+            for (int k = 0; k < wd; ++k) {
+                const int64_t e = e0 + (int64_t)k * SL;
+                const int j = a.aci[e];
+                const double m = a.ava[e];
+                qr += m * a.r[j];
+                qw += m * a.w[j];
+                qx += m * a.x[j];
+            }
+            a.fr[i] = qr;
+            a.fp[i] = qr + beta * qw;
+            ax = qx;
+        } else {
+            if (MODE == 1) {
+                double mr, mw;
+                sell_row2(SELL_M, a.r, a.w, i, mr, mw);
+                a.fr[i] = mr;
+                a.fp[i] = mr + beta * mw;
+            }
+            ax = sell_row(SELL_A, a.x, i);
         }
-        const double d = a.b[i] - sell_row(a.asp, a.aw, a.aci, a.ava, a.x, i);
+        const double d = a.b[i] - ax;
         a.res[i] = d;
         acc[0] += d * d;
     }
     write_partials<1>(acc, q.pout);
 }
 
-// [full-step test] v = A ph | r^.v
-template <bool PRE>
+// [full-step test] v = G fp | r^.v
+template <int MODE>
 __global__ __launch_bounds__(KT) void kb_av(BicgArgs a, BicgStep q) {
     BicgState S;
     if (!take_state(q, S)) return;
-    const double *ph = PRE ? a.ph : a.p;
+    const double *fp = (MODE == 0) ? a.p : a.fp;
     double acc[1] = {0.0};
     ROWS(i, a.n) {
-        const double vi = sell_row(a.asp, a.aw, a.aci, a.ava, ph, i);
+        const double vi = (MODE == 2) ? sell_row(SELL_M, fp, i) : sell_row(SELL_A, fp, i);
         a.v[i] = vi;
         acc[0] += a.rh[i] * vi;
     }
     write_partials<1>(acc, q.pout);
 }
 
-// [alpha] s = r - alpha v, xh = x + alpha ph, sh = M r - alpha M v | ||res - alpha v||^2
-template <bool PRE>
+// [alpha] s = r - alpha v, xh = x + alpha (M p or p), fs = F r - alpha F v
+// | ||b - A xh||^2 = ||res - alpha A (M p or p)||^2 (A M p = v right, A p = v none,
+// A p = fp left)
+template <int MODE>
 __global__ __launch_bounds__(KT) void kb_half(BicgArgs a, BicgStep q) {
     BicgState S;
     if (!take_state(q, S)) return;
     const double al = S.alpha;
-    const double *ph = PRE ? a.ph : a.p;
+    const double *step = (MODE == 1) ? a.fp : a.p;
+    const double *astep = (MODE == 2) ? a.fp : a.v;
     double acc[1] = {0.0};
     ROWS(i, a.n) {
         const double vi = a.v[i];
         a.s[i] = a.r[i] - al * vi;
-        a.xh[i] = a.x[i] + al * ph[i];
-        if (PRE) a.sh[i] = a.mr[i] - al * sell_row(a.msp, a.mw, a.mci, a.mva, a.v, i);
-        const double d = a.res[i] - al * vi;
+        a.xh[i] = a.x[i] + al * step[i];
+        if (MODE == 1) a.fs[i] = a.fr[i] - al * sell_row(SELL_M, a.v, i);
+        if (MODE == 2) a.fs[i] = a.fr[i] - al * sell_row(SELL_A, a.v, i);
+        const double d = a.res[i] - al * astep[i];
         acc[0] += d * d;
     }
     write_partials<1>(acc, q.pout);
 }
 
-// [half-step test] t = A sh | t.t, t.s
-template <bool PRE>
+// [half-step test] t = G fs | t.t, t.s
+template <int MODE>
 __global__ __launch_bounds__(KT) void kb_at(BicgArgs a, BicgStep q) {
     BicgState S;
     if (!take_state(q, S)) return;
-    const double *sh = PRE ? a.sh : a.s;
+    const double *fs = (MODE == 0) ? a.s : a.fs;
     double acc[2] = {0.0, 0.0};
     ROWS(i, a.n) {
-        const double ti = sell_row(a.asp, a.aw, a.aci, a.ava, sh, i);
+        const double ti = (MODE == 2) ? sell_row(SELL_M, fs, i) : sell_row(SELL_A, fs, i);
         a.t[i] = ti;
         acc[0] += ti * ti;
         acc[1] += ti * a.s[i];
@@ -280,16 +319,16 @@ __global__ __launch_bounds__(KT) void kb_at(BicgArgs a, BicgStep q) {
     write_partials<2>(acc, q.pout);
 }
 
-// [omega] x = xh + omega sh, r = s - omega t, w = p - omega v | r^.r
-template <bool PRE>
+// [omega] x = xh + omega (M s or s), r = s - omega t, w = p - omega v | r^.r
+template <int MODE>
 __global__ __launch_bounds__(KT) void kb_uf(BicgArgs a, BicgStep q) {
     BicgState S;
     if (!take_state(q, S)) return;
     const double om = S.omega;
-    const double *sh = PRE ? a.sh : a.s;
+    const double *sstep = (MODE == 1) ? a.fs : a.s;
     double acc[1] = {0.0};
     ROWS(i, a.n) {
-        a.x[i] = a.xh[i] + om * sh[i];
+        a.x[i] = a.xh[i] + om * sstep[i];
         const double ri = a.s[i] - om * a.t[i];
         a.r[i] = ri;
         a.w[i] = a.p[i] - om * a.v[i];
@@ -364,11 +403,36 @@ void BicgSeq::step(int stage, bool produces, BicgStep &q) {
     if (produces) pb ^= 1;
 }
 
+namespace {
+template <int MODE>
+void launch_init(BicgSeq &z, const BicgStep &q, hipStream_t s) {
+    hipLaunchKernelGGL(kb_init<MODE>, dim3(z.grid), dim3(KT), 0, s, z.a, q);
+}
+
+template <int MODE>
+void one_iteration(BicgSeq &z, hipStream_t s) {
+    BicgStep q{};
+    z.step(z.pending, true, q);
+    hipLaunchKernelGGL(kb_pre<MODE>, dim3(z.grid), dim3(KT), 0, s, z.a, q);
+    z.step(BS_RES, true, q);
+    hipLaunchKernelGGL(kb_av<MODE>, dim3(z.grid), dim3(KT), 0, s, z.a, q);
+    z.step(BS_AV, true, q);
+    hipLaunchKernelGGL(kb_half<MODE>, dim3(z.grid), dim3(KT), 0, s, z.a, q);
+    z.step(BS_HALF, true, q);
+    hipLaunchKernelGGL(kb_at<MODE>, dim3(z.grid), dim3(KT), 0, s, z.a, q);
+    z.step(BS_AT, true, q);
+    hipLaunchKernelGGL(kb_uf<MODE>, dim3(z.grid), dim3(KT), 0, s, z.a, q);
+    z.pending = BS_UF;
+}
+}  // namespace
+
 void BicgSeq::init(hipStream_t s) {
     BicgStep q{};
     step(BS_NONE, true, q);
     sp = 0;  // kb_init touches no state
-    hipLaunchKernelGGL(kb_init, dim3(grid), dim3(KT), 0, s, a, q);
+    if (mode == 1) launch_init<1>(*this, q, s);
+    else if (mode == 2) launch_init<2>(*this, q, s);
+    else launch_init<0>(*this, q, s);
     pending = BS_INIT;
     settle(s);
 }
@@ -381,28 +445,11 @@ void BicgSeq::settle(hipStream_t s) {
     pending = BS_NONE;
 }
 
-namespace {
-template <bool PRE>
-void one_iteration(BicgSeq &z, hipStream_t s) {
-    BicgStep q{};
-    z.step(z.pending, true, q);
-    hipLaunchKernelGGL(kb_pre<PRE>, dim3(z.grid), dim3(KT), 0, s, z.a, q);
-    z.step(BS_RES, true, q);
-    hipLaunchKernelGGL(kb_av<PRE>, dim3(z.grid), dim3(KT), 0, s, z.a, q);
-    z.step(BS_AV, true, q);
-    hipLaunchKernelGGL(kb_half<PRE>, dim3(z.grid), dim3(KT), 0, s, z.a, q);
-    z.step(BS_HALF, true, q);
-    hipLaunchKernelGGL(kb_at<PRE>, dim3(z.grid), dim3(KT), 0, s, z.a, q);
-    z.step(BS_AT, true, q);
-    hipLaunchKernelGGL(kb_uf<PRE>, dim3(z.grid), dim3(KT), 0, s, z.a, q);
-    z.pending = BS_UF;
-}
-}  // namespace
-
 void BicgSeq::iterations(int count, hipStream_t s) {
     for (int it = 0; it < count; ++it) {
-        if (precond) one_iteration<true>(*this, s);
-        else one_iteration<false>(*this, s);
+        if (mode == 1) one_iteration<1>(*this, s);
+        else if (mode == 2) one_iteration<2>(*this, s);
+        else one_iteration<0>(*this, s);
     }
 }
 

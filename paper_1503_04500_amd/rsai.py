@@ -87,6 +87,8 @@ def load():
         "rsai_apply": [P, I32, P, P, P],
         "rsai_backward": [P, I32, P, D, P, P],
         "rsai_bicgstab": [P, I32, P, P, D, I32, I32, I32, P, P, P],
+        "rsai_bicgstab_left": [P, P, I32, P, P, D, I32, I32, P, P, P],
+        "rsai_transpose": [P, P, P, P, P],
         "rsai_spmv": [P, P, P, I32, P],
         "rsai_spmv_vjp": [P, P, P, P, P],
         "rsai_plan_timing": [P, P, I32],
@@ -164,6 +166,15 @@ class Matrix:
     def view(self, val=None):
         v = self.val if val is None else val
         return CSCView(self.n, self.nnz, self.colptr.data_ptr(), self.rowidx.data_ptr(), v.data_ptr())
+
+    def transpose(self):
+        """A^T on the same device (rsai_transpose)."""
+        cp = torch.empty(self.n + 1, dtype=torch.int64, device=self.colptr.device)
+        ri = torch.empty(self.nnz, dtype=torch.int32, device=self.colptr.device)
+        va = torch.empty(self.nnz, dtype=torch.float64, device=self.colptr.device)
+        v = self.view()
+        _check(load().rsai_transpose(ctypes.byref(v), cp.data_ptr(), ri.data_ptr(), va.data_ptr(), _stream()))
+        return Matrix(cp, ri, va)
 
 
 def params(c=3, lmax=10, eps=0.4, drop="fixed", tol=1e-3, sched="batched", validate=True, tier0=-1,
@@ -310,6 +321,20 @@ def build_batched(mats, stream=None, **kw) -> Plan:
     st = _stream(stream)
     _check(lib.rsai_build_batched(len(mats), views, ctypes.byref(prm), st, ctypes.byref(h)))
     return Plan(h, list(mats), prm, st)
+
+
+def bicgstab_left(A: Matrix, plan_t: "Plan", b, tol=1e-8, maxit=1000, graph=True, mat=0):
+    """Solve M A x = b's left-preconditioned form M A x = M b by BiCGStab, with M the
+    transpose of the RSAI factor of A^T (plan_t built on A.transpose()); the test is
+    ||b - A x|| / ||b|| < tol (rsai_bicgstab_left). Returns (x, iterations, relres)."""
+    b = _dev(b, torch.float64, "b")
+    x = torch.empty_like(b)
+    it = ctypes.c_int32(0)
+    rel = ctypes.c_double(0.0)
+    v = A.view()
+    _check(load().rsai_bicgstab_left(ctypes.byref(v), plan_t._hv(), mat, b.data_ptr(), x.data_ptr(), float(tol),
+                                     int(maxit), 1 if graph else 0, ctypes.byref(it), ctypes.byref(rel), _stream()))
+    return x, it.value, rel.value
 
 
 def spmv(A: Matrix, x, transpose=False, val=None):

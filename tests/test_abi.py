@@ -73,6 +73,9 @@ def test_argument_errors_without_gpu():
     assert lib.rsai_rebuild(None, 1, None) == -1
     it, rel = ctypes.c_int32(), ctypes.c_double()
     assert lib.rsai_bicgstab(None, 0, None, None, 1e-8, 10, 1, 1, ctypes.byref(it), ctypes.byref(rel), None) == -1
+    assert lib.rsai_bicgstab_left(None, None, 0, None, None, 1e-8, 10, 1, ctypes.byref(it), ctypes.byref(rel),
+                                  None) == -1
+    assert lib.rsai_transpose(None, None, None, None, None) == -1
     cnt, best = ctypes.c_int32(), ctypes.c_int32()
     assert lib.rsai_autotune(None, ctypes.byref(p), 1, None, None, 0, ctypes.byref(cnt), ctypes.byref(best)) == -1
     bad = rsai.params()

@@ -123,3 +123,96 @@ def test_bad_arguments():
         gpu["plan"].bicgstab(b, tol=-1.0)
     with pytest.raises(rsai.RSAIError):
         gpu["plan"].bicgstab(b, maxit=-1)
+
+
+# ---------------------------------------------------------------- left form
+
+def _host_transpose(A):
+    return gen.from_coo(A.n, A.col_of_entry(), A.rowidx, A.val)
+
+
+def _left_setup(A, **kw):
+    """Plan of RSAI on A^T (built from the device transpose) and the left
+    preconditioner M = N^T as host CSC."""
+    import paper_1503_04500_amd.rsai as rsai
+    dA = rsai.Matrix.from_host(A, "cuda:0")
+    dAt = dA.transpose()
+    plan = rsai.build(dAt, **kw)
+    cp, ri, va = (t.cpu().numpy() for t in plan.export())
+    ML = _host_transpose(gen.CSC(A.n, cp, ri, va))
+    return dA, dAt, plan, ML, (cp, ri, va)
+
+
+def test_transpose_is_exact():
+    import paper_1503_04500_amd.rsai as rsai
+    for A in (gen.c1(), gen.powerlaw(5000, seed=3), gen.dense_rows(40, 8, 30)):
+        T = rsai.Matrix.from_host(A, "cuda:0").transpose()
+        H = _host_transpose(A)
+        assert np.array_equal(T.colptr.cpu().numpy(), H.colptr)
+        assert np.array_equal(T.rowidx.cpu().numpy(), H.rowidx)
+        assert np.array_equal(T.val.cpu().numpy(), H.val)
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_left_c1_matches_oracle(graph):
+    """RSAI on A^T (parity with the oracle on A^T), then the left form against the
+    oracle's left BiCGStab with the same M: equal counts, x to rounding."""
+    import paper_1503_04500_amd.rsai as rsai
+    from tests.parity import compare
+    A = gen.c1()
+    dA, dAt, plan, ML, Ncsc = _left_setup(A, **C1)
+    At = _host_transpose(A)
+    ref = oracle.rsai(At, c=3, lmax=8, eps=0.4, drop=oracle.DROP_FIXED, tol=1e-3)
+    gpu = dict(colptr=Ncsc[0], rowidx=Ncsc[1], val=Ncsc[2],
+               **{k: v.cpu().numpy() for k, v in plan.stats().items()})
+    compare(At, gpu, ref, label="C1^T")
+    b = A.matvec(np.ones(A.n))
+    it_o, rel_o, x_o = oracle.bicgstab(A, b, (ML.colptr, ML.rowidx, ML.val), left=True)
+    import torch
+    x, it, rel = rsai.bicgstab_left(dA, plan, torch.from_numpy(b).cuda(), graph=graph)
+    x = x.cpu().numpy()
+    assert it == it_o and 0 < it < 1000
+    assert _true_rel(A, x, b) < 1e-8
+    assert abs(rel - rel_o) <= 1e-3 * rel_o
+    assert np.max(np.abs(x - x_o)) <= 1e-10 * np.max(np.abs(x_o))
+
+
+def test_left_exact_preconditioner_half_step():
+    import torch
+    import paper_1503_04500_amd.rsai as rsai
+    d = np.random.default_rng(13).uniform(1.0, 4.0, 400)
+    A = gen.diagonal(d)
+    dA, dAt, plan, ML, _ = _left_setup(A, **C1)
+    b = np.random.default_rng(14).standard_normal(A.n)
+    x, it, rel = rsai.bicgstab_left(dA, plan, torch.from_numpy(b).cuda())
+    assert it == 1 and np.allclose(x.cpu().numpy(), b / d, rtol=1e-14, atol=0)
+
+
+def test_left_cd2d_256_converges_like_oracle():
+    """Left form on a 256x256 random-convection grid: the solve passes the test
+    (recomputed on the host) and its count is within the rounding chaos of the
+    oracle's on the same M; repeated solves give the same bits."""
+    import torch
+    import paper_1503_04500_amd.rsai as rsai
+    A = gen.cd2d(256, seed=1)
+    dA, dAt, plan, ML, _ = _left_setup(A, **C1)
+    b = A.matvec(np.ones(A.n))
+    bt = torch.from_numpy(b).cuda()
+    x, it, rel = rsai.bicgstab_left(dA, plan, bt)
+    x2, it2, rel2 = rsai.bicgstab_left(dA, plan, bt, graph=False)
+    assert it2 == it and torch.equal(x, x2)
+    x = x.cpu().numpy()
+    assert 0 < it <= 1000 and rel < 1e-8 and _true_rel(A, x, b) < 1e-8 * (1 + 1e-6)
+    it_o, _, _ = oracle.bicgstab(A, b, (ML.colptr, ML.rowidx, ML.val), left=True)
+    assert 0 < it_o <= 1000
+    assert abs(it - it_o) <= max(3, it_o // 5), (it, it_o)
+
+
+def test_left_rejects_mismatched_matrix():
+    import torch
+    import paper_1503_04500_amd.rsai as rsai
+    A = gen.c1()
+    dA, dAt, plan, ML, _ = _left_setup(A, **C1)
+    other = rsai.Matrix.from_host(gen.cd2d(20, seed=1), "cuda:0")
+    with pytest.raises(rsai.RSAIError):
+        rsai.bicgstab_left(other, plan, torch.ones(other.n, dtype=torch.float64, device="cuda:0"))
