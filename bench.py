@@ -227,6 +227,21 @@ def main():
             sol[key] = {"iterations": its, "relres": rel, "ms": dts * 1e3,
                         "us_per_iteration": dts * 1e6 / max(its, 1)}
         pb.close()
+        # the left form: RSAI on A^T (its build timed too), M A x = M b
+        At = A.transpose()
+        dtt = time_builds(rsai, At, "batched", 3, 1, torch)
+        pt = rsai.build(At, sched="batched", **PARAMS)
+        pt.nnz()
+        rsai.bicgstab_left(A, pt, bvec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            _, its, rel = rsai.bicgstab_left(A, pt, bvec)
+        dts = (time.perf_counter() - t0) / 3
+        sol["rsai_left"] = {"iterations": its, "relres": rel, "ms": dts * 1e3,
+                            "us_per_iteration": dts * 1e6 / max(its, 1), "build_on_At_ms": dtt * 1e3}
+        pt.close()
+        del At
         extra["bicgstab_cd2d512"] = sol
         # the stopping criterion, the number of dominant indices and the dropping mode
         # varied on the same matrix: density of M, columns left above eps, build time,
@@ -307,6 +322,22 @@ def main():
                             "sequential_ms": dt5s * 1e3, "graph_replay_ms": dt5g * 1e3,
                             "workload": f"64 matrices in one build (2D/3D convection-diffusion, power-law; "
                                         f"sum n = {n5})"}
+        # fwd + bwd of the summed loss over the 64 matrices (one batched build keeping
+        # every R factor, one adjoint per matrix)
+        b5 = [torch.from_numpy(np.random.default_rng(2000 + i).standard_normal(h.n)).to("cuda:0")
+              for i, h in enumerate(H5)]
+        fb5 = []
+        for it in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            v5 = [a5.val.clone().requires_grad_(True) for a5 in A5]
+            L5 = ag.rsai_loss_batched(A5, v5, b5, factor_budget_bytes=8 << 30, **PARAMS)
+            L5.backward()
+            torch.cuda.synchronize()
+            if it > 0:
+                fb5.append(time.perf_counter() - t0)
+            del v5, L5
+        extra["batch64"]["fwd_bwd_ms"] = float(np.median(fb5)) * 1e3
         del A5, H5
         H4 = gen.c4()
         A4 = rsai.Matrix.from_host(H4, "cuda:0")

@@ -44,21 +44,29 @@ struct BLds {
 int backward_max_cols() { return BQMAX; }
 int backward_max_rows() { return BMMAX; }
 
-__global__ void k_max2(int64_t n, const int32_t *a, const int32_t *b, const int64_t *mask, int32_t *out2) {
-    int ma = 0, mb = 0, nm = 0;
+// out5: largest |J_k|; over the columns without a kept factor (mask[k] < 0, or all
+// columns without a mask) the largest |I_k|, their count and their largest |J_k|;
+// the number of columns with a factor and |J_k| > 32
+__global__ void k_max2(int64_t n, const int32_t *a, const int32_t *b, const int64_t *mask, int32_t *out5) {
+    int ma = 0, mb = 0, nm = 0, mq = 0, nl = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         ma = max(ma, a[i]);
         if (!mask || mask[i] < 0) {
             mb = max(mb, b[i]);
+            mq = max(mq, a[i]);
             ++nm;
+        } else if (a[i] > 32) {
+            ++nl;
         }
     }
-    atomicMax(&out2[0], ma);
-    atomicMax(&out2[1], mb);
-    atomicAdd(&out2[2], nm);
+    atomicMax(&out5[0], ma);
+    atomicMax(&out5[1], mb);
+    atomicAdd(&out5[2], nm);
+    atomicMax(&out5[3], mq);
+    atomicAdd(&out5[4], nl);
 }
-void launch_max2(int64_t n, const int32_t *a, const int32_t *b, const int64_t *mask, int32_t *out2, hipStream_t s) {
-    hipLaunchKernelGGL(k_max2, dim3(256), dim3(256), 0, s, n, a, b, mask, out2);
+void launch_max2(int64_t n, const int32_t *a, const int32_t *b, const int64_t *mask, int32_t *out5, hipStream_t s) {
+    hipLaunchKernelGGL(k_max2, dim3(256), dim3(256), 0, s, n, a, b, mask, out5);
 }
 
 __global__ __launch_bounds__(64) void backward_kernel(BwdArgs a) {
@@ -341,9 +349,24 @@ void launch_backward(const BwdArgs &a, int waves, hipStream_t s) {
 // a_ij found by binary search in column j (rows ascending). No dense block, no
 // row-set hash, so |I_k| is not limited here.
 namespace {
-constexpr int FG = 16, FGPW = 64 / FG, FQ = 32, FLOGHJ = 7, FHJ = 1 << FLOGHJ;
+// sum over a group of G lanes (G up to 64), every lane of the group gets it
+template <int G>
+__device__ __forceinline__ double group_sum(double x) {
+    if constexpr (G <= 16) {
+        return gsum<G>(x);
+    } else {
+        x = gsum<16>(x);
+        x += __shfl_xor(x, 16);
+        if constexpr (G == 64) x += __shfl_xor(x, 32);
+        return x;
+    }
+}
 constexpr int FM = 128, FLOGHI = 8, FHI = 1 << FLOGHI;  // rows accumulated in LDS
+// instances: 16 lanes per column for |J_k| <= 32, a wavefront per column for
+// 32 < |J_k| <= 128 (the columns of the dense class)
+template <int FQ, int FLOGHJ>
 struct FLds {
+    static constexpr int FHJ = 1 << FLOGHJ;
     double z[FQ];       // z in ascending column order
     double u[FQ];       // R^{-T} g, solve order
     double racc[FM];    // r_i and (A_k z)_i by local row (|I_k| <= FM)
@@ -358,8 +381,10 @@ struct FLds {
     int hIv[FHI];
     int cnt;
 };
-__device__ __forceinline__ int fhfind(const FLds &S, int key) {
-    const int sl = hfind<FLOGHJ>(S.hJ, key);
+template <class L>
+__device__ __forceinline__ int fhfind(const L &S, int key) {
+    constexpr int LOG = ilog2ceil(L::FHJ);
+    const int sl = hfind<LOG>(S.hJ, key);
     return sl >= 0 ? S.hv[sl] : -1;
 }
 // value of A(i, j), or 0 if not stored (rows of a column ascending)
@@ -375,14 +400,15 @@ __device__ __forceinline__ double aval(const MatDev &A, int j, int i) {
 }
 }  // namespace
 
-int backward_factored_max_cols() { return FQ; }
+int backward_factored_max_cols() { return 128; }
 
+template <int FG, int FQ, int FLOGHJ, int QLO>
 __global__ __launch_bounds__(64) void backward_factored_kernel(BwdArgs a) {
-    constexpr int G = FG;
-    __shared__ FLds lds[FGPW];
+    constexpr int G = FG, FGPW = 64 / FG, FHJ = 1 << FLOGHJ;
+    __shared__ FLds<FQ, FLOGHJ> lds[FGPW];
     const int gl = threadIdx.x % G;
     const int grp = threadIdx.x / G;
-    FLds &S = lds[grp];
+    FLds<FQ, FLOGHJ> &S = lds[grp];
     const MatDev A = a.mats[a.mat];
     const int64_t n = a.n;
     const int64_t gstride = (int64_t)gridDim.x * FGPW;
@@ -396,7 +422,7 @@ __global__ __launch_bounds__(64) void backward_factored_kernel(BwdArgs a) {
             fo = a.foff[k];
             mb = a.Mcolptr[k];
             q = (int)(a.Mcolptr[k + 1] - mb);
-            act = fo >= 0 && q >= 1 && q <= FQ;
+            act = fo >= 0 && q >= QLO && q <= FQ;
         }
         bool any_g = false;
         if (act && a.gM)
@@ -423,7 +449,7 @@ __global__ __launch_bounds__(64) void backward_factored_kernel(BwdArgs a) {
             double part = 0.0;
             if (act && j < q)
                 for (int i = gl; i < j; i += G) part += F[fac_row(q, i) + (j - i)] * S.u[i];
-            part = gsum<G>(part);
+            part = group_sum<G>(part);
             if (act && j < q && gl == 0) {
                 const int rj = S.rk[j];
                 const double gj = (a.gM && rj >= 0) ? a.gM[mb + rj] : 0.0;
@@ -440,7 +466,7 @@ __global__ __launch_bounds__(64) void backward_factored_kernel(BwdArgs a) {
                     const int rc = S.rk[c];
                     part += F[fac_row(q, j) + (c - j)] * (rc >= 0 ? S.z[rc] : 0.0);
                 }
-            part = gsum<G>(part);
+            part = group_sum<G>(part);
             if (act && j < q && gl == 0) {
                 const int rj = S.rk[j];
                 if (rj >= 0) S.z[rj] = (S.u[j] - part) / F[fac_row(q, j)];
@@ -533,8 +559,10 @@ __global__ __launch_bounds__(64) void backward_factored_kernel(BwdArgs a) {
     }
 }
 
-void launch_backward_factored(const BwdArgs &a, int waves, hipStream_t s) {
-    hipLaunchKernelGGL(backward_factored_kernel, dim3(waves), dim3(64), 0, s, a);
+void launch_backward_factored(const BwdArgs &a, int waves, int waves_large, hipStream_t s) {
+    hipLaunchKernelGGL((backward_factored_kernel<16, 32, 7, 1>), dim3(waves), dim3(64), 0, s, a);
+    if (waves_large > 0)
+        hipLaunchKernelGGL((backward_factored_kernel<64, 128, 8, 33>), dim3(waves_large), dim3(64), 0, s, a);
 }
 
 }  // namespace rsai

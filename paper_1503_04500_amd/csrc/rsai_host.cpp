@@ -70,6 +70,8 @@ struct MatPlan {
     int64_t *summary = nullptr;  // device: nnz(M), error flags, failed-column counts
     int32_t maxq = -1, maxm = -1;  // largest final |J_k| and |I_k| (first backward)
     int32_t nofac = -1;            // columns without a kept factor
+    int32_t maxq_nofac = -1;       // their largest |J_k|
+    int32_t nlarge = -1;           // columns with a kept factor and |J_k| > 32
     // transpose of M (rows) for y = M x
     int64_t *rowptrT = nullptr;
     int32_t *rowcntT = nullptr;  // 2n: row counts and fill positions
@@ -625,7 +627,7 @@ rsai_status rsai_rebuild(rsai_plan *P, int32_t use_graph, void *stream) {
     // results of the previous build are out of date
     for (MatPlan &M : P->mats) {
         M.nnzM = -1;
-        M.maxq = M.maxm = -1;
+        M.maxq = M.maxm = M.maxq_nofac = M.nlarge = -1;
         M.t_valid = false;
     }
     for (bool &r : P->recorded) r = false;
@@ -1087,22 +1089,28 @@ rsai_status rsai_backward(rsai_plan *P, int32_t mat, const double *dM_val, doubl
     hipStream_t s = (hipStream_t)stream;
     const int64_t *foff = P->out.foff ? P->out.foff + M.col_base : nullptr;
     if (M.maxq < 0) {
-        // largest |J_k|, and largest |I_k| among the columns without a kept factor
-        int32_t *d2 = P->alloc<int32_t>(3, st);
+        // largest |J_k|; for the columns without a kept factor their largest |I_k|,
+        // count and largest |J_k|; columns with a factor and |J_k| > 32
+        int32_t *d2 = P->alloc<int32_t>(5, st);
         if (st != RSAI_OK) return st;
-        int32_t h2[3] = {0, 0, 0};
-        launch_fill_i32(d2, 0, 3, P->stream);
+        int32_t h2[5] = {0, 0, 0, 0, 0};
+        launch_fill_i32(d2, 0, 5, P->stream);
         launch_max2(M.A.n, P->out.nJ + M.col_base, P->out.nI + M.col_base, foff, d2, P->stream);
         HIPCHK(hipMemcpyAsync(h2, d2, sizeof(h2), hipMemcpyDeviceToHost, P->stream));
         HIPCHK(hipStreamSynchronize(P->stream));
         M.maxq = h2[0];
         M.maxm = h2[1];
         M.nofac = h2[2];
+        M.maxq_nofac = h2[3];
+        M.nlarge = h2[4];
     }
-    const int qlim = foff ? std::min(backward_max_cols(), backward_factored_max_cols()) : backward_max_cols();
-    if (M.maxq > qlim || M.maxm > backward_max_rows())
-        return fail(RSAI_E_CAP, "adjoint supports |J_k| <= %d and (without a kept factor) |I_k| <= %d; "
-                    "this M has %d and %d", qlim, backward_max_rows(), M.maxq, M.maxm);
+    // columns on a kept factor: |J_k| <= 128; refactorised columns: |J_k| <= 32, |I_k| <= 64
+    if (foff && M.maxq > backward_factored_max_cols())
+        return fail(RSAI_E_CAP, "adjoint supports |J_k| <= %d; this M has %d", backward_factored_max_cols(), M.maxq);
+    if (M.nofac > 0 && (M.maxq_nofac > backward_max_cols() || M.maxm > backward_max_rows()))
+        return fail(RSAI_E_CAP, "adjoint without a kept factor supports |J_k| <= %d and |I_k| <= %d; "
+                    "%d such columns reach %d and %d (keep_factors lifts this)", backward_max_cols(),
+                    backward_max_rows(), M.nofac, M.maxq_nofac, M.maxm);
     BwdArgs a{};
     a.mats = P->d_mats;
     a.mat = mat;
@@ -1117,7 +1125,7 @@ rsai_status rsai_backward(rsai_plan *P, int32_t mat, const double *dM_val, doubl
     a.fac = P->out.fac;
     a.foff = foff;
     P->record(5, s);
-    if (foff) launch_backward_factored(a, device_cus() * 8, s);
+    if (foff) launch_backward_factored(a, device_cus() * 8, M.nlarge > 0 ? device_cus() * 4 : 0, s);
     if (!foff || M.nofac > 0) launch_backward(a, device_cus() * 8, s);
     P->record(6, s);
     HIPCHK(hipGetLastError());

@@ -26,7 +26,8 @@ def _oracle_grad(A, Mcp, Mri, b):
 
 
 @pytest.mark.parametrize("name,keep", [("c1", False), ("cd3d20", False), ("c1", True), ("cd3d20", True),
-                                       ("cd3d20", "tiny"), ("cd3d12", True), ("powerlaw", True)])
+                                       ("cd3d20", "tiny"), ("cd3d12", True), ("powerlaw", True),
+                                       ("denserows", True), ("cd3d12eps", True)])
 def test_backward_kernel_vs_oracle(name, keep):
     """Refactorising adjoint, adjoint on the kept R factors, and a factor budget too
     small for all columns (both kernels in one call); with kept factors the |I_k|
@@ -34,8 +35,9 @@ def test_backward_kernel_vs_oracle(name, keep):
     |I| = 71, power-law columns |I| = 232)."""
     import torch
     A = {"c1": gen.c1, "cd3d20": lambda: gen.cd3d(20, seed=1), "cd3d12": lambda: gen.cd3d(12, seed=3),
-         "powerlaw": lambda: gen.powerlaw(3000, seed=11, lmax=20)}[name]()
-    kw = dict(C1, lmax=2) if name == "powerlaw" else C1
+         "powerlaw": lambda: gen.powerlaw(3000, seed=11, lmax=20), "denserows": lambda: gen.dense_rows(64, 16, 48),
+         "cd3d12eps": lambda: gen.cd3d(12, seed=3)}[name]()
+    kw = {"powerlaw": dict(C1, lmax=2), "cd3d12eps": dict(C1, lmax=5, eps=0.1)}.get(name, C1)
     ref = oracle.rsai(A, **kw)
     fk = {} if keep is False else (dict(keep_factors=True, factor_budget_bytes=8 * 20000) if keep == "tiny"
                                    else dict(keep_factors=True))
@@ -52,6 +54,22 @@ def test_backward_kernel_vs_oracle(name, keep):
     # a different order and a normal-equation solve in the oracle)
     err = np.abs(got - only).max() / np.abs(only).max()
     assert err <= 1e-10, err
+
+
+def test_backward_large_columns_need_kept_factors():
+    """Columns with |J_k| > 32 (a dense-row matrix) are differentiated on their kept R
+    factors (a wavefront per column); without kept factors the refactorising adjoint
+    reports RSAI_E_CAP before accumulating anything."""
+    import torch
+    import paper_1503_04500_amd.rsai as rsai
+    A = gen.dense_rows(64, 16, 48)
+    gpu = run_gpu(A, **C1)
+    assert (np.diff(gpu["colptr"]) > 32).sum() > 10
+    dA = torch.zeros(A.nnz, dtype=torch.float64, device="cuda:0")
+    g = torch.ones(int(gpu["colptr"][-1]), dtype=torch.float64, device="cuda:0")
+    with pytest.raises(rsai.RSAIError) as ei:
+        gpu["plan"].backward(g, 1.0, dA)
+    assert ei.value.code == -6 and not dA.any()
 
 
 def test_backward_reports_cap_for_oversize_columns():
@@ -163,3 +181,28 @@ def test_bicgstab_iterations_within_rounding_ensemble():
     lo, hi = min(its), max(its)
     slack = max(5, (hi - lo) // 2)
     assert lo - slack <= it_g <= hi + slack, (it_g, its)
+
+
+def test_batched_loss_gradient_equals_single_builds():
+    """One batched build of several matrices (2D, 3D, power-law with |J_k| > 32 on
+    kept factors) differentiated at once: the loss and every matrix's gradient equal
+    those of the single-matrix builds (same kernels; the adjoint order of the FP64
+    atomics may differ, hence the rounding tolerance)."""
+    import torch
+    import paper_1503_04500_amd.rsai as rsai
+    from paper_1503_04500_amd import autograd as ag
+    Hs = [gen.cd2d(30, seed=1), gen.cd3d(9, seed=2), gen.dense_rows(32, 8, 40), gen.powerlaw(2000, seed=4, lmax=30)]
+    mats = [rsai.Matrix.from_host(h, "cuda:0") for h in Hs]
+    bs = [torch.from_numpy(np.random.default_rng(20 + i).standard_normal(h.n)).cuda() for i, h in enumerate(Hs)]
+    vals = [m.val.clone().requires_grad_(True) for m in mats]
+    L = ag.rsai_loss_batched(mats, vals, bs, **C1)
+    L.backward()
+    tot = 0.0
+    for m, v, b in zip(mats, vals, bs):
+        v1 = m.val.clone().requires_grad_(True)
+        Li = ag.rsai_loss(m, v1, b, **C1)
+        Li.backward()
+        tot += Li.item()
+        err = (v.grad - v1.grad).abs().max().item() / v1.grad.abs().max().item()
+        assert err <= 1e-11, err
+    assert abs(L.item() - tot) <= 1e-12 * abs(tot)
