@@ -301,11 +301,14 @@ def main():
         # the same 64 matrices built one after another, and the batched build replayed
         # as a captured graph
         torch.cuda.synchronize()
+        per5 = []
         t0 = time.perf_counter()
         for a5 in A5:
+            t1 = time.perf_counter()
             p1 = rsai.build(a5, **PARAMS)
             p1.nnz()
             p1.close()
+            per5.append((time.perf_counter() - t1) * 1e3)
         torch.cuda.synchronize()
         dt5s = time.perf_counter() - t0
         p5 = rsai.build_batched(A5, **PARAMS)
@@ -320,6 +323,7 @@ def main():
         p5.close()
         extra["batch64"] = {"value": n5 / dt5, "unit": "columns/s", "ms_per_step": dt5 * 1e3,
                             "sequential_ms": dt5s * 1e3, "graph_replay_ms": dt5g * 1e3,
+                            "sequential_per_matrix_ms": [round(v, 3) for v in per5],
                             "workload": f"64 matrices in one build (2D/3D convection-diffusion, power-law; "
                                         f"sum n = {n5})"}
         # fwd + bwd of the summed loss over the 64 matrices (one batched build keeping
@@ -401,6 +405,10 @@ def main():
         "build_event_ms": float(np.median(build_ms)),
         "phase_ms": {k: float(v) for k, v in t.items()},
         "cpu_baseline": cpu,
+        # the paper's own construction timings, context only: n / ptime of its Tables 2
+        # and 5 (collection matrices, n = 541 .. 21200), one core of the machine it names
+        "paper_context": {"columns_per_s_range": [202, 14286], "kind": "n / ptime, Tables 2 and 5",
+                          "hardware": "Intel Core 2 Quad E8400 3.0 GHz, 2 GB, Fortran 90, sequential"},
     }
     print(json.dumps(out))
 
