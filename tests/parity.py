@@ -43,9 +43,25 @@ def subset(gpu, cols):
     return out
 
 
-def compare(A, gpu, ref, check_flops=True, label=""):
+def _drop_cols(d, cols):
+    """d restricted to all columns but ``cols`` (CSC arrays and per-column stats)."""
+    cp = d["colptr"]
+    n = len(cp) - 1
+    keep = np.setdiff1d(np.arange(n), cols)
+    return subset(d, keep) if "sel_margin" not in d else dict(
+        subset(d, keep), sel_margin=d["sel_margin"][keep], drop_margin=d["drop_margin"][keep],
+        mflops=d["mflops"][keep], **({"cols": d["cols"][keep]} if "cols" in d else {}))
+
+
+def compare(A, gpu, ref, check_flops=True, label="", margin_tol=None):
     """Assert the parity bar; return a summary dict. ``A`` is only used for its
-    column count unless ``ref`` covers a subset of the columns (``ref['cols']``)."""
+    column count unless ``ref`` covers a subset of the columns (``ref['cols']``).
+
+    With margin_tol, a column whose pattern differs is accepted when the oracle took
+    one of its decisions (dominant-row cut or drop) at a margin below margin_tol: a
+    rounding-level tie, where either outcome is a result of the method. Such columns
+    are left out of the remaining checks, counted in the summary, and limited to 5%
+    of the columns."""
     n = len(ref["colptr"]) - 1
     report = []
     gcp, rcp = gpu["colptr"], ref["colptr"]
@@ -55,6 +71,11 @@ def compare(A, gpu, ref, check_flops=True, label=""):
         rs, re = rcp[k], rcp[k + 1]
         if ge - gs != re - rs or not np.array_equal(gpu["rowidx"][gs:ge], ref["rowidx"][rs:re]):
             bad_cols.append(k)
+    tied = []
+    if margin_tol is not None and bad_cols:
+        tied = [k for k in bad_cols if min(ref["sel_margin"][k], ref["drop_margin"][k]) < margin_tol]
+        assert len(tied) <= max(1, n // 20), f"{label}: {len(tied)} of {n} columns decided at rounding-level margins"
+        bad_cols = [k for k in bad_cols if k not in set(tied)]
     for k in bad_cols[:10]:
         report.append(f"col {k}: gpu J={gpu['rowidx'][gcp[k]:gcp[k+1]].tolist()} "
                       f"oracle J={ref['rowidx'][rcp[k]:rcp[k+1]].tolist()} "
@@ -62,6 +83,10 @@ def compare(A, gpu, ref, check_flops=True, label=""):
                       f"|r| gap at the cut={ref['sel_margin'][k]:.3e} "
                       f"drop gap={ref['drop_margin'][k]:.3e}")
     assert not bad_cols, f"{label}: {len(bad_cols)} pattern divergences\n" + "\n".join(report)
+    if tied:
+        s = compare(A, _drop_cols(gpu, tied), _drop_cols(ref, tied), check_flops=check_flops, label=label)
+        s["tied_columns"] = len(tied)
+        return s
     assert np.array_equal(gcp, rcp)
     # values, per column relative inf-norm
     diff = np.abs(gpu["val"] - ref["val"])
