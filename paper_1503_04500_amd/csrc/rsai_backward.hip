@@ -367,19 +367,29 @@ constexpr int FM = 128, FLOGHI = 8, FHI = 1 << FLOGHI;  // rows accumulated in L
 template <int FQ, int FLOGHJ>
 struct FLds {
     static constexpr int FHJ = 1 << FLOGHJ;
+    // the column's factor record (J in solve order, then R row by row) is staged here
+    // for the two triangular solves when |J_k| <= RQ, so that their q dependent steps
+    // read LDS instead of waiting on global memory; larger records are read in place
+    static constexpr int RQ = FQ <= 32 ? 24 : 0;
+    static constexpr int RSZ = RQ > 0 ? RQ + RQ * (RQ + 1) / 2 : 1;
     double z[FQ];       // z in ascending column order
     double u[FQ];       // R^{-T} g, solve order
-    double racc[FM];    // r_i and (A_k z)_i by local row (|I_k| <= FM)
-    double aacc[FM];
     int64_t cb[FQ];     // first entry of each column of J
     int pre[FQ + 1];    // prefix of the column lengths
     int js[FQ];         // J ascending (the order of M's column)
     int rk[FQ];         // position in ascending order of the solve-order slot
     int hJ[FHJ];        // column -> ascending position
     int hv[FHJ];
-    int hI[FHI];        // row -> local row
-    int hIv[FHI];
     int cnt;
+    union {
+        double R[RSZ];  // during the solves
+        struct {        // after them
+            double racc[FM];  // r_i and (A_k z)_i by local row (|I_k| <= FM)
+            double aacc[FM];
+            int hI[FHI];      // row -> local row
+            unsigned char hIv[FHI];
+        } acc;
+    } w;
 };
 template <class L>
 __device__ __forceinline__ int fhfind(const L &S, int key) {
@@ -440,20 +450,28 @@ __global__ __launch_bounds__(64) void backward_factored_kernel(BwdArgs a) {
             }
         }
         wave_sync();
+        using LT = FLds<FQ, FLOGHJ>;
+        const bool staged = act && q <= LT::RQ;
+        if constexpr (LT::RQ > 0) {
+            if (staged)
+                for (int t = gl; t < q + q * (q + 1) / 2; t += G) S.w.R[t] = F[t];
+            wave_sync();
+        }
+        const double *Fr = staged ? S.w.R : F;
         if (act)
-            for (int c = gl; c < q; c += G) S.rk[c] = fhfind(S, (int)F[c]);
+            for (int c = gl; c < q; c += G) S.rk[c] = fhfind(S, (int)Fr[c]);
         wave_sync();
         // u = R^{-T} g (forward substitution), g taken in solve order
         for (int j = 0; j < FQ; ++j) {
             if (!wave_any(act && j < q)) break;
             double part = 0.0;
             if (act && j < q)
-                for (int i = gl; i < j; i += G) part += F[fac_row(q, i) + (j - i)] * S.u[i];
+                for (int i = gl; i < j; i += G) part += Fr[fac_row(q, i) + (j - i)] * S.u[i];
             part = group_sum<G>(part);
             if (act && j < q && gl == 0) {
                 const int rj = S.rk[j];
                 const double gj = (a.gM && rj >= 0) ? a.gM[mb + rj] : 0.0;
-                S.u[j] = (gj - part) / F[fac_row(q, j)];
+                S.u[j] = (gj - part) / Fr[fac_row(q, j)];
             }
             wave_sync();
         }
@@ -464,71 +482,101 @@ __global__ __launch_bounds__(64) void backward_factored_kernel(BwdArgs a) {
             if (act && j < q)
                 for (int c = j + 1 + gl; c < q; c += G) {
                     const int rc = S.rk[c];
-                    part += F[fac_row(q, j) + (c - j)] * (rc >= 0 ? S.z[rc] : 0.0);
+                    part += Fr[fac_row(q, j) + (c - j)] * (rc >= 0 ? S.z[rc] : 0.0);
                 }
             part = group_sum<G>(part);
             if (act && j < q && gl == 0) {
                 const int rj = S.rk[j];
-                if (rj >= 0) S.z[rj] = (S.u[j] - part) / F[fac_row(q, j)];
+                if (rj >= 0) S.z[rj] = (S.u[j] - part) / Fr[fac_row(q, j)];
             }
             wave_sync();
         }
         // entries of the columns of J, flattened: start and prefix of lengths
+        // the columns of J: first entries and lengths (a lane per column), then the
+        // prefix of the lengths
         if (act) {
             for (int c = gl; c < q; c += G) {
                 const int j = S.js[c];
-                S.cb[c] = A.colptr[j];
-            }
-            if (gl == 0) {
-                int acc = 0;
-                for (int c = 0; c < q; ++c) {
-                    S.pre[c] = acc;
-                    acc += (int)(A.colptr[S.js[c] + 1] - A.colptr[S.js[c]]);
-                }
-                S.pre[q] = acc;
-                S.cnt = 0;
+                const int64_t b0 = A.colptr[j];
+                S.cb[c] = b0;
+                S.pre[c + 1] = (int)(A.colptr[j + 1] - b0);
             }
         }
-        for (int t = gl; t < FHI; t += G) S.hI[t] = HEMPTY;
+        for (int t = gl; t < FHI; t += G) S.w.acc.hI[t] = HEMPTY;
+        wave_sync();
+        if (act && gl == 0) {
+            S.pre[0] = 0;
+            for (int c = 0; c < q; ++c) S.pre[c + 1] += S.pre[c];
+            S.cnt = 0;
+        }
         wave_sync();
         const int tot = act ? S.pre[q] : 0;
         // small I_k: r and A_k z accumulated once per row in LDS
         bool small = act && tot <= FM;
         if (wave_any(small)) {
-            for (int u = gl; u < tot && small; u += G) {
-                int c = 0;
-                while (c + 1 < q && S.pre[c + 1] <= u) ++c;
-                const int64_t e = S.cb[c] + (u - S.pre[c]);
-                int sl;
-                if (hinsert<FLOGHI>(S.hI, A.rowidx[e], sl)) {
-                    const int li = atomicAdd(&S.cnt, 1);
-                    S.hIv[sl] = li;
-                    S.racc[li] = 0.0;
-                    S.aacc[li] = 0.0;
+            // entries u = gl + t G of the flattened columns, loaded once (all loads in
+            // flight together) and used by the three passes
+            constexpr int EPL = FM / G;
+            int erow[EPL], ecol[EPL], eli[EPL];
+            int64_t eidx[EPL];
+            double ev[EPL], em[EPL];
+#pragma unroll
+            for (int t = 0; t < EPL; ++t) {
+                const int u = gl + t * G;
+                erow[t] = -1;
+                ecol[t] = 0;
+                eli[t] = 0;
+                eidx[t] = 0;
+                ev[t] = 0.0;
+                em[t] = 0.0;
+                if (small && u < tot) {
+                    int lo = 0, hi = q - 1;  // the column holding entry u
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (S.pre[mid] <= u) lo = mid; else hi = mid - 1;
+                    }
+                    const int64_t e = S.cb[lo] + (u - S.pre[lo]);
+                    ecol[t] = lo;
+                    eidx[t] = e;
+                    erow[t] = A.rowidx[e];
+                    ev[t] = A.val[e];
+                    em[t] = a.Mval[mb + lo];
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < EPL; ++t) {
+                if (erow[t] >= 0) {
+                    int sl;
+                    if (hinsert<FLOGHI>(S.w.acc.hI, erow[t], sl)) {
+                        const int li = atomicAdd(&S.cnt, 1);
+                        S.w.acc.hIv[sl] = li;
+                        S.w.acc.racc[li] = 0.0;
+                        S.w.acc.aacc[li] = 0.0;
+                    }
                 }
             }
             wave_sync();
-            for (int u = gl; u < tot && small; u += G) {
-                int c = 0;
-                while (c + 1 < q && S.pre[c + 1] <= u) ++c;
-                const int64_t e = S.cb[c] + (u - S.pre[c]);
-                const int li = S.hIv[hfind<FLOGHI>(S.hI, A.rowidx[e])];
-                const double v = A.val[e];
-                atomicAdd(&S.racc[li], v * a.Mval[mb + c]);
-                atomicAdd(&S.aacc[li], v * S.z[c]);
+#pragma unroll
+            for (int t = 0; t < EPL; ++t) {
+                if (erow[t] >= 0) {
+                    const int li = S.w.acc.hIv[hfind<FLOGHI>(S.w.acc.hI, erow[t])];
+                    eli[t] = li;
+                    atomicAdd(&S.w.acc.racc[li], ev[t] * em[t]);
+                    atomicAdd(&S.w.acc.aacc[li], ev[t] * S.z[ecol[t]]);
+                }
             }
             wave_sync();
             if (small) {
                 const double w2 = 2.0 * a.w_frob;
-                for (int u = gl; u < tot; u += G) {
-                    int c = 0;
-                    while (c + 1 < q && S.pre[c + 1] <= u) ++c;
-                    const int64_t e = S.cb[c] + (u - S.pre[c]);
-                    const int i = A.rowidx[e];
-                    const int li = S.hIv[hfind<FLOGHI>(S.hI, i)];
-                    const double ri = S.racc[li] - ((i == (int)k) ? 1.0 : 0.0), azi = S.aacc[li];
-                    const double zc = S.z[c], mc = a.Mval[mb + c];
-                    atomicAdd(&a.dA[e], -(ri * zc + azi * mc) + w2 * ri * mc);
+#pragma unroll
+                for (int t = 0; t < EPL; ++t) {
+                    if (erow[t] >= 0) {
+                        const int li = eli[t];
+                        const double ri = S.w.acc.racc[li] - ((erow[t] == (int)k) ? 1.0 : 0.0);
+                        const double azi = S.w.acc.aacc[li];
+                        const double zc = S.z[ecol[t]], mc = em[t];
+                        atomicAdd(&a.dA[eidx[t]], -(ri * zc + azi * mc) + w2 * ri * mc);
+                    }
                 }
             }
             wave_sync();
@@ -560,7 +608,7 @@ __global__ __launch_bounds__(64) void backward_factored_kernel(BwdArgs a) {
 }
 
 void launch_backward_factored(const BwdArgs &a, int waves, int waves_large, hipStream_t s) {
-    hipLaunchKernelGGL((backward_factored_kernel<16, 32, 7, 1>), dim3(waves), dim3(64), 0, s, a);
+    hipLaunchKernelGGL((backward_factored_kernel<16, 32, 6, 1>), dim3(waves), dim3(64), 0, s, a);
     if (waves_large > 0)
         hipLaunchKernelGGL((backward_factored_kernel<64, 128, 8, 33>), dim3(waves_large), dim3(64), 0, s, a);
 }
