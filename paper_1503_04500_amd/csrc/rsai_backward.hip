@@ -46,24 +46,48 @@ int backward_max_rows() { return BMMAX; }
 
 // out5: largest |J_k|; over the columns without a kept factor (mask[k] < 0, or all
 // columns without a mask) the largest |I_k|, their count and their largest |J_k|;
-// the number of columns with a factor and |J_k| > 32
-__global__ void k_max2(int64_t n, const int32_t *a, const int32_t *b, const int64_t *mask, int32_t *out5) {
-    int ma = 0, mb = 0, nm = 0, mq = 0, nl = 0;
+// the number of columns with a factor and |J_k| > 32. Reduced per workgroup first,
+// then one atomic per workgroup and value.
+__global__ __launch_bounds__(256) void k_max2(int64_t n, const int32_t *a, const int32_t *b, const int64_t *mask,
+                                              int32_t *out5) {
+    __shared__ int red[5][4];
+    int v[5] = {0, 0, 0, 0, 0};  // max a, max b, count, max a (no factor), count large
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        ma = max(ma, a[i]);
+        v[0] = max(v[0], a[i]);
         if (!mask || mask[i] < 0) {
-            mb = max(mb, b[i]);
-            mq = max(mq, a[i]);
-            ++nm;
+            v[1] = max(v[1], b[i]);
+            v[3] = max(v[3], a[i]);
+            ++v[2];
         } else if (a[i] > 32) {
-            ++nl;
+            ++v[4];
         }
     }
-    atomicMax(&out5[0], ma);
-    atomicMax(&out5[1], mb);
-    atomicAdd(&out5[2], nm);
-    atomicMax(&out5[3], mq);
-    atomicAdd(&out5[4], nl);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        v[0] = max(v[0], __shfl_xor(v[0], off));
+        v[1] = max(v[1], __shfl_xor(v[1], off));
+        v[2] += __shfl_xor(v[2], off);
+        v[3] = max(v[3], __shfl_xor(v[3], off));
+        v[4] += __shfl_xor(v[4], off);
+    }
+    if (lane == 0)
+        for (int t = 0; t < 5; ++t) red[t][w] = v[t];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < 4; ++q) {
+            v[0] = max(v[0], red[0][q]);
+            v[1] = max(v[1], red[1][q]);
+            v[2] += red[2][q];
+            v[3] = max(v[3], red[3][q]);
+            v[4] += red[4][q];
+        }
+        atomicMax(&out5[0], v[0]);
+        atomicMax(&out5[1], v[1]);
+        atomicAdd(&out5[2], v[2]);
+        atomicMax(&out5[3], v[3]);
+        atomicAdd(&out5[4], v[4]);
+    }
 }
 void launch_max2(int64_t n, const int32_t *a, const int32_t *b, const int64_t *mask, int32_t *out5, hipStream_t s) {
     hipLaunchKernelGGL(k_max2, dim3(256), dim3(256), 0, s, n, a, b, mask, out5);

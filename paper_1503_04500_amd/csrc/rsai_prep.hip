@@ -4,6 +4,8 @@
 // per entry, coalesced over the CSC arrays.
 #include <algorithm>
 
+#include <climits>
+
 #include "rsai_kernels.h"
 
 namespace rsai {
@@ -291,10 +293,34 @@ void launch_csc_transpose_fill(int64_t n, const int64_t *colptr, const int32_t *
                        fillpos, colidxT, valT);
 }
 
-// sort each row's (col, value) pairs by column so that row sums have a fixed order
+// sort each row's (col, value) pairs by column so that row sums have a fixed order.
+// Rows of up to 32 entries are sorted in registers (each entry's place is the number
+// of smaller column indices in the row, which are distinct), longer ones in place.
 __global__ void k_sort_rows(int64_t n, const int64_t *rowptr, int32_t *colidx, double *val) {
+    constexpr int RS = 32;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t s = rowptr[i], e = rowptr[i + 1];
+        const int len = (int)(e - s);
+        if (len <= RS) {
+            int key[RS];
+            double v[RS];
+#pragma unroll
+            for (int t = 0; t < RS; ++t) {
+                key[t] = (t < len) ? colidx[s + t] : INT_MAX;
+                v[t] = (t < len && val) ? val[s + t] : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < RS; ++t) {
+                if (t < len) {
+                    int rank = 0;
+#pragma unroll
+                    for (int u = 0; u < RS; ++u) rank += (key[u] < key[t]) ? 1 : 0;
+                    colidx[s + rank] = key[t];
+                    if (val) val[s + rank] = v[t];
+                }
+            }
+            continue;
+        }
         for (int64_t a = s + 1; a < e; ++a) {
             int key = colidx[a];
             double v = val ? val[a] : 0.0;
