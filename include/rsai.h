@@ -107,7 +107,10 @@ rsai_status rsai_params_default(rsai_params *p);
 
 /* Route every device allocation of the library through (alloc, dealloc, ctx).
    Passing NULLs restores hipMalloc/hipFree. Process-wide; not thread-safe against
-   concurrent builds. */
+   concurrent builds. Frees are stream-ordered: dealloc(p, stream, ctx) may be called
+   while work queued on that stream still uses p, so the allocator must not hand p to
+   other work before that work completes (as PyTorch's caching allocator and
+   hipFreeAsync guarantee for work on the same stream). */
 rsai_status rsai_set_allocator(rsai_alloc_fn alloc, rsai_free_fn dealloc, void *ctx);
 
 /* Result of one autotuning candidate. */
@@ -215,7 +218,9 @@ rsai_status rsai_bicgstab_left(const rsai_csc *A, rsai_plan *PT, int32_t mat, co
    n < 1 or nnz < n), RSAI_E_NOMEM, RSAI_E_HIP. */
 rsai_status rsai_transpose(const rsai_csc *A, int64_t *colptrT, int32_t *rowidxT, double *valT, void *stream);
 
-/* y = A x (transpose = 0) or y = A^T x (transpose = 1) for a CSC matrix. */
+/* y = A x (transpose = 0) or y = A^T x (transpose = 1) for a CSC matrix; x, y device
+   arrays of n doubles. Stream-ordered, no host synchronisation. A x sums each row in
+   ascending column order (the rows are formed in allocator work buffers per call). */
 rsai_status rsai_spmv(const rsai_csc *A, const double *x, double *y, int32_t transpose, void *stream);
 
 /* Gradient of y = A x with respect to the values of A: dval[e] += dy[i] * x[j] for

@@ -861,8 +861,9 @@ rsai_status rsai_spmv(const rsai_csc *A, const double *x, double *y, int32_t tra
     if (st == RSAI_OK) {
         enqueue_rows(A, rp, ci, vv, cnt, fill, stmp, zerr, s);
         launch_csr_spmv(n, rp, ci, vv, x, y, s);
-        if (hipStreamSynchronize(s) != hipSuccess) st = fail(RSAI_E_HIP, "spmv failed");
+        if (hipGetLastError() != hipSuccess) st = fail(RSAI_E_HIP, "spmv launch failed");
     }
+    // stream-ordered release: the work queued on s above still uses these blocks
     for (void *p : tmp) dev_free(p, s);
     return st;
 }
