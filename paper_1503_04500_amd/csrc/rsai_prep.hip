@@ -127,11 +127,18 @@ void launch_row_counts(int64_t nnz, const int32_t *rowidx, int32_t *cnt, const i
 __global__ void k_row_fill(int64_t n, const int64_t *colptr, const int32_t *rowidx, const int64_t *rowptr,
                            int32_t *fillpos, int32_t *colidx, const int32_t *err) {
     if (*err) return;
+    constexpr int U = 8;  // entries of a column whose position atomics are in flight together
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-        for (int64_t e = colptr[j]; e < colptr[j + 1]; ++e) {
-            const int r = rowidx[e];
-            const int p = atomicAdd(&fillpos[r], 1);
-            colidx[rowptr[r] + p] = (int32_t)j;
+        const int64_t b = colptr[j], e = colptr[j + 1];
+        for (int64_t base = b; base < e; base += U) {
+            int r[U], p[U];
+#pragma unroll
+            for (int t = 0; t < U; ++t) r[t] = (base + t < e) ? rowidx[base + t] : -1;
+#pragma unroll
+            for (int t = 0; t < U; ++t) p[t] = (r[t] >= 0) ? atomicAdd(&fillpos[r[t]], 1) : 0;
+#pragma unroll
+            for (int t = 0; t < U; ++t)
+                if (r[t] >= 0) colidx[rowptr[r[t]] + p[t]] = (int32_t)j;
         }
     }
 }
@@ -277,12 +284,31 @@ void launch_assemble(int64_t n, int qcap, const int64_t *off, const int32_t *nJ,
 
 __global__ void k_csc_transpose_fill(int64_t n, const int64_t *colptr, const int32_t *rowidx, const double *val,
                                      const int64_t *rowptr, int32_t *fillpos, int32_t *colidxT, double *valT) {
+    constexpr int U = 8;  // entries of a column whose position atomics are in flight together
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-        for (int64_t e = colptr[j]; e < colptr[j + 1]; ++e) {
-            const int r = rowidx[e];
-            const int p = atomicAdd(&fillpos[r], 1);
-            colidxT[rowptr[r] + p] = (int32_t)j;
-            valT[rowptr[r] + p] = val[e];
+        const int64_t b = colptr[j], e = colptr[j + 1];
+        for (int64_t base = b; base < e; base += U) {
+            int r[U], p[U];
+            double v[U];
+#pragma unroll
+            for (int t = 0; t < U; ++t) {
+                r[t] = -1;
+                v[t] = 0.0;
+                if (base + t < e) {
+                    r[t] = rowidx[base + t];
+                    v[t] = val[base + t];
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < U; ++t) p[t] = (r[t] >= 0) ? atomicAdd(&fillpos[r[t]], 1) : 0;
+#pragma unroll
+            for (int t = 0; t < U; ++t) {
+                if (r[t] >= 0) {
+                    const int64_t d = rowptr[r[t]] + p[t];
+                    colidxT[d] = (int32_t)j;
+                    valT[d] = v[t];
+                }
+            }
         }
     }
 }
