@@ -42,9 +42,10 @@ def parse():
                     help="only copy 64 MiB device to device three times (calibrates the HBM byte counters)")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many batched builds (for rocprofv3), print nothing else")
-    ap.add_argument("--profile-workload", choices=("cd2d", "batch64", "bicgstab"), default="cd2d",
+    ap.add_argument("--profile-workload", choices=("cd2d", "batch64", "bicgstab", "fwdbwd"), default="cd2d",
                     help="workload of --profile-steps: builds of the cd2d matrix or of the 64-matrix "
-                         "batch, or BiCGStab solves (100 iterations) with M of the cd2d matrix")
+                         "batch, BiCGStab solves (100 iterations) with M of the cd2d matrix, or "
+                         "fwd + bwd steps of the loss on the cd2d matrix")
     return ap.parse_args()
 
 
@@ -133,6 +134,16 @@ def main():
         torch.cuda.synchronize()
         pb.close()
         print(json.dumps({"profile_steps": args.profile_steps, "workload": "bicgstab", "iterations": its}))
+        return
+
+    if args.profile_steps and args.profile_workload == "fwdbwd":
+        from paper_1503_04500_amd import autograd as ag
+        bv = torch.from_numpy(np.random.default_rng(0).standard_normal(H.n)).to("cuda:0")
+        for _ in range(args.profile_steps):
+            val = A.val.clone().requires_grad_(True)
+            ag.rsai_loss(A, val, bv, **PARAMS).backward()
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_steps": args.profile_steps, "workload": "fwdbwd"}))
         return
 
     if args.profile_steps:
