@@ -368,10 +368,16 @@ void launch_backward(const BwdArgs &a, int waves, hipStream_t s) {
 // ---------------------------------------------------------------- kept factors
 // The same adjoint for the columns whose R factor the build kept: z = R^{-1} R^{-T} g
 // by two triangular solves on the stored R (R^T R = A_k^T A_k for any QR of A_k,
-// compressed or not), then r = A_k m - e_k and A_k z row by row from the sparse
-// data: the columns of row i (row pattern of A) that belong to J_k, each value
-// a_ij found by binary search in column j (rows ascending). No dense block, no
-// row-set hash, so |I_k| is not limited here.
+// compressed or not), then r = A_k m - e_k and A_k z. For small column sets the
+// entries of the columns of J sit in registers and r, A_k z are accumulated per row
+// in LDS; otherwise row by row from the sparse data: the columns of row i (row
+// pattern of A) that belong to J_k, each value a_ij found by binary search in
+// column j (rows ascending). No dense block, so |I_k| is not limited here.
+//
+// The kernel is bound by the latency of each column's dependent steps, so its
+// throughput is the number of columns resident per CU: the LDS record of a column
+// is split by phase (the solves, then the accumulation) and the two halves share
+// storage.
 namespace {
 // sum over a group of G lanes (G up to 64), every lane of the group gets it
 template <int G>
@@ -385,41 +391,55 @@ __device__ __forceinline__ double group_sum(double x) {
         return x;
     }
 }
-constexpr int FM = 128, FLOGHI = 8, FHI = 1 << FLOGHI;  // rows accumulated in LDS
-// instances: 16 lanes per column for |J_k| <= 32, a wavefront per column for
-// 32 < |J_k| <= 128 (the columns of the dense class)
-template <int FQ, int FLOGHJ>
+// inclusive prefix sum over a group of G lanes (lane gl of the group)
+template <int G>
+__device__ __forceinline__ int group_scan(int x, int gl) {
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+        const int y = __shfl_up(x, d, G);
+        if (gl >= d) x += y;
+    }
+    return x;
+}
+// entries of the columns of J held in registers (small path), distinct rows
+// accumulated in LDS and the row hash
+constexpr int FM = 128, FR = 64, FLOGHI = 7, FHI = 1 << FLOGHI;
+template <int FQ>
 struct FLds {
-    static constexpr int FHJ = 1 << FLOGHJ;
-    // the column's factor record (J in solve order, then R row by row) is staged here
-    // for the two triangular solves when |J_k| <= RQ, so that their q dependent steps
-    // read LDS instead of waiting on global memory; larger records are read in place
+    // R is staged here for the two triangular solves when |J_k| <= RQ, so that their
+    // q dependent steps read LDS instead of waiting on global memory; larger
+    // records are read in place
     static constexpr int RQ = FQ <= 32 ? 24 : 0;
-    static constexpr int RSZ = RQ > 0 ? RQ + RQ * (RQ + 1) / 2 : 1;
-    double z[FQ];       // z in ascending column order
-    double u[FQ];       // R^{-T} g, solve order
-    int64_t cb[FQ];     // first entry of each column of J
-    int pre[FQ + 1];    // prefix of the column lengths
-    int js[FQ];         // J ascending (the order of M's column)
-    int rk[FQ];         // position in ascending order of the solve-order slot
-    int hJ[FHJ];        // column -> ascending position
-    int hv[FHJ];
+    static constexpr int RSZ = RQ > 0 ? RQ * (RQ + 1) / 2 : 1;
+    double z[FQ];  // g (ascending order) until the back substitution writes z over it
+    int js[FQ];    // J ascending (the order of M's column)
     int cnt;
     union {
-        double R[RSZ];  // during the solves
-        struct {        // after them
-            double racc[FM];  // r_i and (A_k z)_i by local row (|I_k| <= FM)
-            double aacc[FM];
-            int hI[FHI];      // row -> local row
+        struct {             // the triangular solves
+            double R[RSZ];   // R row by row
+            double u[FQ];    // g in solve order, then R^{-T} g
+            int rk[FQ];      // ascending position of each solve-order column
+        } sv;
+        struct {             // r and A_k z
+            int64_t cb[FQ];  // first entry of each column of J
+            int pre[FQ + 1]; // prefix of the column lengths
+            double racc[FR]; // r_i and (A_k z)_i by local row
+            double aacc[FR];
+            int hI[FHI];     // row -> local row
             unsigned char hIv[FHI];
         } acc;
     } w;
 };
-template <class L>
-__device__ __forceinline__ int fhfind(const L &S, int key) {
-    constexpr int LOG = ilog2ceil(L::FHJ);
-    const int sl = hfind<LOG>(S.hJ, key);
-    return sl >= 0 ? S.hv[sl] : -1;
+// position of column key in the ascending J (q entries), or -1
+__device__ __forceinline__ int jpos(const int *js, int q, int key) {
+    int lo = 0, hi = q - 1;
+    while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int v = js[mid];
+        if (v == key) return mid;
+        if (v < key) lo = mid + 1; else hi = mid - 1;
+    }
+    return -1;
 }
 // value of A(i, j), or 0 if not stored (rows of a column ascending)
 __device__ __forceinline__ double aval(const MatDev &A, int j, int i) {
@@ -432,71 +452,99 @@ __device__ __forceinline__ double aval(const MatDev &A, int j, int i) {
     }
     return 0.0;
 }
+// offset of row i of R (upper triangle stored row by row, q columns)
+__device__ __forceinline__ int rrow(int q, int i) { return i * q - i * (i - 1) / 2; }
 }  // namespace
 
 int backward_factored_max_cols() { return 128; }
 
-template <int FG, int FQ, int FLOGHJ, int QLO>
+template <int FG, int FQ, int QLO>
 __global__ __launch_bounds__(64) void backward_factored_kernel(BwdArgs a) {
-    constexpr int G = FG, FGPW = 64 / FG, FHJ = 1 << FLOGHJ;
-    __shared__ FLds<FQ, FLOGHJ> lds[FGPW];
+    constexpr int G = FG, FGPW = 64 / FG, CPL = FQ / G;
+    using LT = FLds<FQ>;
+    static_assert(FQ % G == 0 && FM % G == 0, "columns and entries split evenly over the lanes");
+    __shared__ LT lds[FGPW];
     const int gl = threadIdx.x % G;
     const int grp = threadIdx.x / G;
-    FLds<FQ, FLOGHJ> &S = lds[grp];
+    LT &S = lds[grp];
     const MatDev A = a.mats[a.mat];
     const int64_t n = a.n;
     const int64_t gstride = (int64_t)gridDim.x * FGPW;
     const int64_t iters = (n + gstride - 1) / gstride;
-    for (int64_t itk = 0; itk < iters; ++itk) {
-        const int64_t k = itk * gstride + (int64_t)blockIdx.x * FGPW + grp;
-        bool act = k < n;
-        int q = 0;
-        int64_t mb = 0, fo = -1;
-        if (act) {
-            fo = a.foff[k];
-            mb = a.Mcolptr[k];
-            q = (int)(a.Mcolptr[k + 1] - mb);
-            act = fo >= 0 && q >= QLO && q <= FQ;
+    uint64_t gmask = ~0ull;
+    if constexpr (G < 64) gmask = (1ull << G) - 1;
+    // the header of the group's first column; each iteration loads the next one's
+    int64_t k = (int64_t)blockIdx.x * FGPW + grp;
+    int64_t nfo = -1, nmb = 0, nme = 0;
+    if (k < n) {
+        nfo = a.foff[k];
+        nmb = a.Mcolptr[k];
+        nme = a.Mcolptr[k + 1];
+    }
+    for (int64_t itk = 0; itk < iters; ++itk, k += gstride) {
+        const int64_t fo = nfo, mb = nmb;
+        const int q = (int)(nme - nmb);
+        bool act = k < n && fo >= 0 && q >= QLO && q <= FQ;
+        {
+            const int64_t kn = k + gstride;
+            nfo = -1;
+            nmb = nme = 0;
+            if (kn < n) {
+                nfo = a.foff[kn];
+                nmb = a.Mcolptr[kn];
+                nme = a.Mcolptr[kn + 1];
+            }
         }
-        bool any_g = false;
-        if (act && a.gM)
-            for (int c = 0; c < q; ++c) any_g |= (a.gM[mb + c] != 0.0);
-        if (act && !any_g && a.w_frob == 0.0) act = false;
         const double *F = a.fac + (act ? fo : 0);
-        for (int t = gl; t < FHJ; t += G) S.hJ[t] = HEMPTY;
+        const bool staged = act && q <= LT::RQ;
+        // the pattern, the record's solve order, the incoming gradient and the column
+        // extents of J, loaded by the group's lanes together; R staged in LDS
+        int fj[CPL], clen[CPL];
+        int64_t cbr[CPL];
+        bool nzg = false;
+#pragma unroll
+        for (int t = 0; t < CPL; ++t) {
+            const int c = gl + t * G;
+            fj[t] = -1;
+            clen[t] = 0;
+            cbr[t] = 0;
+            if (act && c < q) {
+                const int j = a.Mrowidx[mb + c];
+                S.js[c] = j;
+                fj[t] = (int)F[c];
+                const double gc = a.gM ? a.gM[mb + c] : 0.0;
+                S.z[c] = gc;
+                nzg |= gc != 0.0;
+                cbr[t] = A.colptr[j];
+                clen[t] = (int)(A.colptr[j + 1] - cbr[t]);
+            }
+        }
+        if (staged)
+            for (int t = gl; t < q * (q + 1) / 2; t += G) S.w.sv.R[t] = F[q + t];
+        if (act && !(((__ballot(nzg) >> (grp * G)) & gmask) != 0) && a.w_frob == 0.0) act = false;
         wave_sync();
+        const double *Fr = staged ? S.w.sv.R : F + q;
+        // solve-order column -> ascending position; g in solve order
         if (act) {
-            for (int c = gl; c < q; c += G) {
-                S.js[c] = a.Mrowidx[mb + c];
-                int sl;
-                hinsert<FLOGHJ>(S.hJ, S.js[c], sl);
-                if (sl >= 0) S.hv[sl] = c;
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) {
+                const int c = gl + t * G;
+                if (c < q) {
+                    const int p = jpos(S.js, q, fj[t]);
+                    S.w.sv.rk[c] = p;
+                    S.w.sv.u[c] = p >= 0 ? S.z[p] : 0.0;
+                }
             }
         }
         wave_sync();
-        using LT = FLds<FQ, FLOGHJ>;
-        const bool staged = act && q <= LT::RQ;
-        if constexpr (LT::RQ > 0) {
-            if (staged)
-                for (int t = gl; t < q + q * (q + 1) / 2; t += G) S.w.R[t] = F[t];
-            wave_sync();
-        }
-        const double *Fr = staged ? S.w.R : F;
-        if (act)
-            for (int c = gl; c < q; c += G) S.rk[c] = fhfind(S, (int)Fr[c]);
-        wave_sync();
-        // u = R^{-T} g (forward substitution), g taken in solve order
+        // u = R^{-T} g (forward substitution)
         for (int j = 0; j < FQ; ++j) {
             if (!wave_any(act && j < q)) break;
             double part = 0.0;
             if (act && j < q)
-                for (int i = gl; i < j; i += G) part += Fr[fac_row(q, i) + (j - i)] * S.u[i];
+                for (int i = gl; i < j; i += G) part += Fr[rrow(q, i) + (j - i)] * S.w.sv.u[i];
             part = group_sum<G>(part);
-            if (act && j < q && gl == 0) {
-                const int rj = S.rk[j];
-                const double gj = (a.gM && rj >= 0) ? a.gM[mb + rj] : 0.0;
-                S.u[j] = (gj - part) / Fr[fac_row(q, j)];
-            }
+            if (act && j < q && gl == 0) S.w.sv.u[j] = (S.w.sv.u[j] - part) / Fr[rrow(q, j)];
             wave_sync();
         }
         // z = R^{-1} u (back substitution), stored by ascending position
@@ -505,36 +553,37 @@ __global__ __launch_bounds__(64) void backward_factored_kernel(BwdArgs a) {
             double part = 0.0;
             if (act && j < q)
                 for (int c = j + 1 + gl; c < q; c += G) {
-                    const int rc = S.rk[c];
-                    part += Fr[fac_row(q, j) + (c - j)] * (rc >= 0 ? S.z[rc] : 0.0);
+                    const int rc = S.w.sv.rk[c];
+                    part += Fr[rrow(q, j) + (c - j)] * (rc >= 0 ? S.z[rc] : 0.0);
                 }
             part = group_sum<G>(part);
             if (act && j < q && gl == 0) {
-                const int rj = S.rk[j];
-                if (rj >= 0) S.z[rj] = (S.u[j] - part) / Fr[fac_row(q, j)];
+                const int rj = S.w.sv.rk[j];
+                if (rj >= 0) S.z[rj] = (S.w.sv.u[j] - part) / Fr[rrow(q, j)];
             }
             wave_sync();
         }
-        // entries of the columns of J, flattened: start and prefix of lengths
-        // the columns of J: first entries and lengths (a lane per column), then the
-        // prefix of the lengths
-        if (act) {
-            for (int c = gl; c < q; c += G) {
-                const int j = S.js[c];
-                const int64_t b0 = A.colptr[j];
-                S.cb[c] = b0;
-                S.pre[c + 1] = (int)(A.colptr[j + 1] - b0);
+        // the columns of J: first entries and the prefix of their lengths
+        {
+            int base = 0;
+#pragma unroll
+            for (int t = 0; t < CPL; ++t) {
+                const int c = gl + t * G;
+                const int inc = group_scan<G>(clen[t], gl);
+                if (act && c < q) {
+                    S.w.acc.cb[c] = cbr[t];
+                    S.w.acc.pre[c + 1] = base + inc;
+                }
+                base += __shfl(inc, G - 1, G);
             }
         }
         for (int t = gl; t < FHI; t += G) S.w.acc.hI[t] = HEMPTY;
-        wave_sync();
-        if (act && gl == 0) {
-            S.pre[0] = 0;
-            for (int c = 0; c < q; ++c) S.pre[c + 1] += S.pre[c];
+        if (gl == 0) {
+            S.w.acc.pre[0] = 0;
             S.cnt = 0;
         }
         wave_sync();
-        const int tot = act ? S.pre[q] : 0;
+        const int tot = act ? S.w.acc.pre[q] : 0;
         // small I_k: r and A_k z accumulated once per row in LDS
         bool small = act && tot <= FM;
         if (wave_any(small)) {
@@ -557,9 +606,9 @@ __global__ __launch_bounds__(64) void backward_factored_kernel(BwdArgs a) {
                     int lo = 0, hi = q - 1;  // the column holding entry u
                     while (lo < hi) {
                         const int mid = (lo + hi + 1) >> 1;
-                        if (S.pre[mid] <= u) lo = mid; else hi = mid - 1;
+                        if (S.w.acc.pre[mid] <= u) lo = mid; else hi = mid - 1;
                     }
-                    const int64_t e = S.cb[lo] + (u - S.pre[lo]);
+                    const int64_t e = S.w.acc.cb[lo] + (u - S.w.acc.pre[lo]);
                     ecol[t] = lo;
                     eidx[t] = e;
                     erow[t] = A.rowidx[e];
@@ -567,26 +616,34 @@ __global__ __launch_bounds__(64) void backward_factored_kernel(BwdArgs a) {
                     em[t] = a.Mval[mb + lo];
                 }
             }
+            // the distinct rows; more than FR of them send the column to the row path
 #pragma unroll
             for (int t = 0; t < EPL; ++t) {
                 if (erow[t] >= 0) {
                     int sl;
                     if (hinsert<FLOGHI>(S.w.acc.hI, erow[t], sl)) {
                         const int li = atomicAdd(&S.cnt, 1);
-                        S.w.acc.hIv[sl] = li;
-                        S.w.acc.racc[li] = 0.0;
-                        S.w.acc.aacc[li] = 0.0;
+                        S.w.acc.hIv[sl] = (unsigned char)li;
+                        if (li < FR) {
+                            S.w.acc.racc[li] = 0.0;
+                            S.w.acc.aacc[li] = 0.0;
+                        }
+                    } else if (sl < 0) {
+                        atomicMax(&S.cnt, FR + 1);
                     }
                 }
             }
             wave_sync();
+            small = small && S.cnt <= FR;
+            if (small) {
 #pragma unroll
-            for (int t = 0; t < EPL; ++t) {
-                if (erow[t] >= 0) {
-                    const int li = S.w.acc.hIv[hfind<FLOGHI>(S.w.acc.hI, erow[t])];
-                    eli[t] = li;
-                    atomicAdd(&S.w.acc.racc[li], ev[t] * em[t]);
-                    atomicAdd(&S.w.acc.aacc[li], ev[t] * S.z[ecol[t]]);
+                for (int t = 0; t < EPL; ++t) {
+                    if (erow[t] >= 0) {
+                        const int li = S.w.acc.hIv[hfind<FLOGHI>(S.w.acc.hI, erow[t])];
+                        eli[t] = li;
+                        atomicAdd(&S.w.acc.racc[li], ev[t] * em[t]);
+                        atomicAdd(&S.w.acc.aacc[li], ev[t] * S.z[ecol[t]]);
+                    }
                 }
             }
             wave_sync();
@@ -616,7 +673,7 @@ __global__ __launch_bounds__(64) void backward_factored_kernel(BwdArgs a) {
                     double ri = (i == (int)k) ? -1.0 : 0.0, azi = 0.0;
                     for (int64_t f = A.rowptr[i]; f < A.rowptr[i + 1]; ++f) {
                         const int jj = A.colidx[f];
-                        const int t = fhfind(S, jj);
+                        const int t = jpos(S.js, q, jj);
                         if (t < 0) continue;
                         const double aij = (jj == j) ? A.val[e] : aval(A, jj, i);
                         ri += aij * a.Mval[mb + t];
@@ -631,10 +688,20 @@ __global__ __launch_bounds__(64) void backward_factored_kernel(BwdArgs a) {
     }
 }
 
-void launch_backward_factored(const BwdArgs &a, int waves, int waves_large, hipStream_t s) {
-    hipLaunchKernelGGL((backward_factored_kernel<16, 32, 6, 1>), dim3(waves), dim3(64), 0, s, a);
-    if (waves_large > 0)
-        hipLaunchKernelGGL((backward_factored_kernel<64, 128, 8, 33>), dim3(waves_large), dim3(64), 0, s, a);
+// resident workgroups per CU of each instance (the grids are persistent: a wave
+// beyond what fits would start only after a resident one finishes)
+static int factored_resident(const void *fn) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 64, 0) != hipSuccess || nb < 1) nb = 1;
+    return nb;
+}
+
+void launch_backward_factored(const BwdArgs &a, int cus, bool large, hipStream_t s) {
+    static const int r_small = factored_resident(reinterpret_cast<const void *>(&backward_factored_kernel<16, 32, 1>));
+    static const int r_large = factored_resident(reinterpret_cast<const void *>(&backward_factored_kernel<64, 128, 33>));
+    hipLaunchKernelGGL((backward_factored_kernel<16, 32, 1>), dim3(cus * r_small), dim3(64), 0, s, a);
+    if (large)
+        hipLaunchKernelGGL((backward_factored_kernel<64, 128, 33>), dim3(cus * r_large), dim3(64), 0, s, a);
 }
 
 }  // namespace rsai

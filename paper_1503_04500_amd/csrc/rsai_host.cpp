@@ -1126,7 +1126,7 @@ rsai_status rsai_backward(rsai_plan *P, int32_t mat, const double *dM_val, doubl
     a.fac = P->out.fac;
     a.foff = foff;
     P->record(5, s);
-    if (foff) launch_backward_factored(a, device_cus() * 8, M.nlarge > 0 ? device_cus() * 4 : 0, s);
+    if (foff) launch_backward_factored(a, device_cus(), M.nlarge > 0, s);
     if (!foff || M.nofac > 0) launch_backward(a, device_cus() * 8, s);
     P->record(6, s);
     HIPCHK(hipGetLastError());

@@ -179,8 +179,8 @@ int backward_factored_max_cols();
 // out2[2] = number of those entries
 void launch_max2(int64_t n, const int32_t *a, const int32_t *b, const int64_t *mask, int32_t *out5, hipStream_t s);
 void launch_backward(const BwdArgs &a, int waves, hipStream_t s);
-// 16 lanes per column for |J_k| <= 32; with waves_large > 0 also a wavefront per
-// column for 32 < |J_k| <= 128
-void launch_backward_factored(const BwdArgs &a, int waves, int waves_large, hipStream_t s);
+// 16 lanes per column for |J_k| <= 32; with large also a wavefront per column for
+// 32 < |J_k| <= 128. Persistent grids of as many workgroups as fit on cus CUs.
+void launch_backward_factored(const BwdArgs &a, int cus, bool large, hipStream_t s);
 
 }  // namespace rsai
