@@ -409,7 +409,7 @@ struct FLds {
     // R is staged here for the two triangular solves when |J_k| <= RQ, so that their
     // q dependent steps read LDS instead of waiting on global memory; larger
     // records are read in place
-    static constexpr int RQ = FQ <= 32 ? 24 : 0;
+    static constexpr int RQ = FQ <= 32 ? 20 : 0;
     static constexpr int RSZ = RQ > 0 ? RQ * (RQ + 1) / 2 : 1;
     double z[FQ];  // g (ascending order) until the back substitution writes z over it
     int js[FQ];    // J ascending (the order of M's column)
