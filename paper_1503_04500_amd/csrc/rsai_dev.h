@@ -42,6 +42,7 @@ struct ColOut {              // per global column
     unsigned long long *fac_cur;  // doubles handed out so far
     int64_t fac_cap;
     int64_t *foff;
+    int32_t fac_chunk;            // doubles a wave takes from the store at a time
 };
 
 // Reserve a factor record of q columns; -1 when the arena is full (the adjoint then
@@ -50,6 +51,18 @@ __device__ __forceinline__ long long fac_reserve(const ColOut &o, int q) {
     const unsigned long long need = (unsigned long long)(q + q * (q + 1) / 2);
     const unsigned long long at = atomicAdd(o.fac_cur, need);
     return (at + need <= (unsigned long long)o.fac_cap) ? (long long)at : -1LL;
+}
+// A wave's current chunk of the factor store (LDS).
+struct FacChunk {
+    long long base;  // store offset of the chunk, -1: none
+    int used, len;   // doubles handed out from it, its length
+};
+__device__ __forceinline__ void fac_chunk_init(FacChunk &W) {
+    if (threadIdx.x == 0) {
+        W.base = -1;
+        W.used = 0;
+        W.len = 0;
+    }
 }
 __host__ __device__ inline int64_t fac_row(int q, int i) { return q + (int64_t)i * q - (int64_t)i * (i - 1) / 2; }
 
@@ -155,6 +168,55 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 __device__ __forceinline__ bool wave_all(bool p) { return __ballot(!p) == 0; }
+
+// Factor records for the active lanes of a wave: every lane with need > 0 gets need
+// consecutive doubles of the wave's chunk (lanes in ascending order). A chunk that
+// cannot hold them all is replaced by a fresh one, taken from the store with a single
+// atomic (the rest of the old one stays unused), so the finishing columns of a wave
+// do not each wait on a contended device-wide atomic. -1 when the store is full.
+__device__ __forceinline__ long long fac_take(const ColOut &o, FacChunk &W, int need) {
+    const int lane = (int)__lane_id();
+    const unsigned long long lm = __ballot(need > 0);
+    if (lm == 0ull) return -1LL;
+    int pre = 0, total = 0;
+    for (unsigned long long mm = lm; mm != 0ull; mm &= mm - 1ull) {
+        const int src = __builtin_ctzll(mm);
+        const int nl = __shfl(need, src);
+        if (src < lane) pre += nl;
+        total += nl;
+    }
+    const int first = __builtin_ctzll(__ballot(1));
+    wave_sync();
+    long long base = W.base;
+    int used = W.used, len = W.len;
+    if (used + total > len) {
+        int blo = -1, bhi = -1, nl = 0;
+        if (lane == first) {
+            const int want = o.fac_chunk > total ? o.fac_chunk : total;
+            const unsigned long long at = atomicAdd(o.fac_cur, (unsigned long long)want);
+            const unsigned long long cap = (unsigned long long)o.fac_cap;
+            if (at < cap) {
+                blo = (int)(at & 0xffffffffull);
+                bhi = (int)(at >> 32);
+                nl = (int)((cap - at) < (unsigned long long)want ? (cap - at) : (unsigned long long)want);
+            }
+        }
+        blo = __shfl(blo, first);
+        bhi = __shfl(bhi, first);
+        len = __shfl(nl, first);
+        base = (bhi < 0) ? -1LL : (((long long)bhi << 32) | (long long)(unsigned)blo);
+        used = 0;
+    }
+    const long long fo = (need > 0 && base >= 0 && used + pre + need <= len) ? base + used + pre : -1LL;
+    wave_sync();
+    if (lane == first) {
+        W.base = base;
+        W.used = (used + total < len) ? used + total : len;
+        W.len = len;
+    }
+    wave_sync();
+    return fo;
+}
 
 // ----------------------------------------------------------------- LDS hash sets
 // Open addressing with linear probing, keys are global indices (>= 0), EMPTY = -1.

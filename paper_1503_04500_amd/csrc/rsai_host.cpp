@@ -371,11 +371,16 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
             P->out.fac_cur = L.take<unsigned long long>(1);
             P->out.foff = L.take<int64_t>(ncols);
             P->out.fac_cap = fac_cap;
+            // a wave's chunk: large enough that few finishing columns wait on the
+            // store's atomic, small enough that the chunks left partly unused at the
+            // end of a launch (at most one per wave) stay a small share of the store
+            P->out.fac_chunk = (int32_t)std::min<int64_t>(2048, std::max<int64_t>(128, fac_cap / (64 * (int64_t)device_cus())));
         } else {
             P->out.fac = nullptr;
             P->out.fac_cur = nullptr;
             P->out.foff = nullptr;
             P->out.fac_cap = 0;
+            P->out.fac_chunk = 0;
         }
         P->rec_count = L.take<int32_t>(nlaunch + 1);
         for (int t = 0; t < 8; ++t) P->rec[t] = nullptr;

@@ -21,12 +21,14 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
     constexpr int NNEW = (C::NEWC + G - 1) / G;
 
     __shared__ GLds<C> lds[GPW];
+    __shared__ FacChunk fch;
     const int lane = threadIdx.x;
     const int gl = lane % G;
     const int grp = lane / G;
     GLds<C> &S = lds[grp];
     const BuildParams P = args.P;
     if (*args.err & 7) return;  // the CSC contract failed: process nothing
+    fac_chunk_init(fch);
 
     // ---- static, XCD-aware schedule: each of the 8 XCDs takes a contiguous range
     const bool first_tier = (args.rec_in == nullptr);
@@ -866,8 +868,8 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
             // of row i (diagonal in rd, the rest in the block). Small tiers pack it in the
             // staging tile first, so the global stores need no per-entry addressing.
             if (args.out.fac != nullptr) {
+                const long long fo = fac_take(args.out, fch, (gl == 0 && qq > 0) ? qq + qq * (qq + 1) / 2 : 0);
                 if (gl == 0) {
-                    const long long fo = (qq > 0) ? fac_reserve(args.out, qq) : -1LL;
                     args.out.foff[ucol] = fo;
                     S.fo_lo = (int)(fo & 0xffffffffLL);
                     S.fo_hi = (int)(fo >> 32);
