@@ -237,6 +237,15 @@ rsai_status rsai_plan_timing(const rsai_plan *P, double *ms, int32_t n);
    batched schedule. Returns RSAI_E_ARG past that. */
 rsai_status rsai_tier_info(int32_t t, int32_t *lanes, int32_t *max_rows, int32_t *max_cols);
 
+/* Measurement support, not part of the method: the FP64 vector FMA rate of the current
+   device, for pricing the build's arithmetic against a measured peak beside the
+   published one. Runs a kernel of 16 waves per CU in which every lane performs
+   8 independent chains of iters fused multiply-adds (2 flops each), times it with HIP
+   events on stream and writes TFLOP/s to *tflops (host). Synchronises the stream;
+   one small work buffer from the allocator. Errors: RSAI_E_ARG (tflops NULL or
+   iters < 16), RSAI_E_NOMEM, RSAI_E_HIP. */
+rsai_status rsai_peak_fp64(int64_t iters, double *tflops, void *stream);
+
 /* Destroy a plan (NULL is allowed). Synchronises the build stream. */
 rsai_status rsai_destroy(rsai_plan *P);
 

@@ -1153,6 +1153,38 @@ rsai_status rsai_plan_timing(const rsai_plan *P, double *ms, int32_t n) {
     return RSAI_OK;
 }
 
+rsai_status rsai_peak_fp64(int64_t iters, double *tflops, void *stream) {
+    if (!tflops || iters < 16) return fail(RSAI_E_ARG, "tflops must be non-NULL and iters >= 16");
+    *tflops = 0.0;
+    hipStream_t s = (hipStream_t)stream;
+    const int blocks = device_cus() * 16;  // 16 waves per CU
+    double *out = (double *)dev_alloc(sizeof(double) * (size_t)blocks, s);
+    if (!out) return fail(RSAI_E_NOMEM, "probe output (%d doubles)", blocks);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    rsai_status st = RSAI_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        st = fail(RSAI_E_HIP, "hipEventCreate failed");
+    } else {
+        launch_fma_probe(blocks, iters / 16, out, s);  // warm-up
+        float ms = 0.f;
+        if (hipEventRecord(e0, s) != hipSuccess) st = fail(RSAI_E_HIP, "hipEventRecord failed");
+        if (st == RSAI_OK) {
+            launch_fma_probe(blocks, iters, out, s);
+            if (hipGetLastError() != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
+                hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess || ms <= 0.f)
+                st = fail(RSAI_E_HIP, "FMA probe launch or timing failed");
+        }
+        if (st == RSAI_OK) {
+            const double flops = 2.0 * fma_probe_chains() * (double)iters * (double)blocks * 256.0;
+            *tflops = flops / ((double)ms * 1e-3) / 1e12;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    dev_free(out, s);
+    return st;
+}
+
 rsai_status rsai_destroy(rsai_plan *P) {
     if (!P) return RSAI_OK;
     P->release();

@@ -178,6 +178,9 @@ int backward_factored_max_cols();
 // out2[0] = max a; out2[1] = max b over the entries with mask < 0 (all if mask is null);
 // out2[2] = number of those entries
 void launch_max2(int64_t n, const int32_t *a, const int32_t *b, const int64_t *mask, int32_t *out5, hipStream_t s);
+// FP64 FMA throughput probe (256-thread blocks, fma_probe_chains() chains per lane)
+int fma_probe_chains();
+void launch_fma_probe(int blocks, int64_t iters, double *out, hipStream_t s);
 void launch_backward(const BwdArgs &a, int waves, hipStream_t s);
 // 16 lanes per column for |J_k| <= 32; with large also a wavefront per column for
 // 32 < |J_k| <= 128. Persistent grids of as many workgroups as fit on cus CUs.

@@ -405,4 +405,28 @@ void launch_spmv_vjp(int64_t n, const int64_t *colptr, const int32_t *rowidx, co
     hipLaunchKernelGGL(k_spmv_vjp, dim3(nblocks(n, 256)), dim3(256), 0, s, n, colptr, rowidx, dy, x, dval);
 }
 
+// FP64 FMA throughput probe: every lane runs FMA_CHAINS independent dependency chains
+// of iters fused multiply-adds (enough in flight to cover the FMA latency at four
+// waves per SIMD). The result is stored only if it takes a value it cannot reach, so
+// the arithmetic stays while the stores do not.
+constexpr int FMA_CHAINS = 8;
+__global__ __launch_bounds__(256) void k_fma_probe(int64_t iters, double *out) {
+    double a[FMA_CHAINS];
+#pragma unroll
+    for (int u = 0; u < FMA_CHAINS; ++u) a[u] = 1.0 + 1e-9 * (double)(threadIdx.x + u);
+    const double mul = 0.9999999, add = 1e-7;
+    for (int64_t i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int u = 0; u < FMA_CHAINS; ++u) a[u] = __builtin_fma(a[u], mul, add);
+    }
+    double t = 0.0;
+#pragma unroll
+    for (int u = 0; u < FMA_CHAINS; ++u) t += a[u];
+    if (t == -1.0) out[blockIdx.x] = t;
+}
+int fma_probe_chains() { return FMA_CHAINS; }
+void launch_fma_probe(int blocks, int64_t iters, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_fma_probe, dim3(blocks), dim3(256), 0, s, iters, out);
+}
+
 }  // namespace rsai

@@ -92,6 +92,7 @@ def load():
         "rsai_spmv": [P, P, P, I32, P],
         "rsai_spmv_vjp": [P, P, P, P, P],
         "rsai_plan_timing": [P, P, I32],
+        "rsai_peak_fp64": [I64, P, P],
         "rsai_tier_info": [I32, P, P, P],
         "rsai_rebuild": [P, I32, P],
         "rsai_autotune": [P, P, I32, P, P, I32, P, P],
@@ -354,6 +355,14 @@ def spmv_vjp(A: Matrix, dy, x, dval, val=None):
     v = A.view(val)
     _check(load().rsai_spmv_vjp(ctypes.byref(v), dy.data_ptr(), x.data_ptr(), dval.data_ptr(), _stream()))
     return dval
+
+
+def peak_fp64(iters=1 << 16) -> float:
+    """Measured FP64 vector FMA rate of the current device in TFLOP/s (rsai_peak_fp64)."""
+    _use_torch_allocator()
+    out = ctypes.c_double()
+    _check(load().rsai_peak_fp64(int(iters), ctypes.byref(out), _stream()))
+    return out.value
 
 
 def tier_info(t):

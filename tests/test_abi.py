@@ -76,6 +76,9 @@ def test_argument_errors_without_gpu():
     assert lib.rsai_bicgstab_left(None, None, 0, None, None, 1e-8, 10, 1, ctypes.byref(it), ctypes.byref(rel),
                                   None) == -1
     assert lib.rsai_transpose(None, None, None, None, None) == -1
+    tf = ctypes.c_double()
+    assert lib.rsai_peak_fp64(1 << 16, None, None) == -1
+    assert lib.rsai_peak_fp64(15, ctypes.byref(tf), None) == -1
     cnt, best = ctypes.c_int32(), ctypes.c_int32()
     assert lib.rsai_autotune(None, ctypes.byref(p), 1, None, None, 0, ctypes.byref(cnt), ctypes.byref(best)) == -1
     bad = rsai.params()
