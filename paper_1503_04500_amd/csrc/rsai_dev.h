@@ -74,9 +74,12 @@ __host__ __device__ inline int64_t fac_row(int q, int i) { return q + (int64_t)i
 // so applying them in order all-reduces over aligned groups of G <= 16 lanes, and
 // every lane of a group ends with the bitwise-identical result (a+b == b+a).
 
+// Every lane reads a lane of its own row under these patterns and all rows and banks
+// are enabled, so no lane keeps its old value: the move needs no initialised
+// destination (one instruction per 32-bit word instead of two).
 template <int CTRL>
 __device__ __forceinline__ int dpp_i32(int x) {
-    return __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false);
+    return __builtin_amdgcn_mov_dpp(x, CTRL, 0xF, 0xF, true);
 }
 
 template <int CTRL>

@@ -91,6 +91,8 @@ template <class C>
 struct GLds {
     double stage[C::STAGE * C::MMAX];
     double mt[C::QMAX];       // solution of the last LS solve, by column slot
+    int64_t cb[C::QMAX];      // first entry of the column in each slot of J (CSC of A)
+    int cl[C::QMAX];          // its length
     int Ilist[C::MMAX];
     int Jlist[C::QMAX];
     int hI[C::HSI];

@@ -153,6 +153,9 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
                 for (int t = gl; t < rq; t += G) {
                     int col = RJ[t];
                     S.Jlist[t] = col;
+                    const int64_t b0 = A.colptr[col];
+                    S.cb[t] = b0;
+                    S.cl[t] = (int)(A.colptr[col + 1] - b0);
                     int sl;
                     hinsert<C::LOGHSJ>(S.hJ, col, sl);
                 }
@@ -301,8 +304,11 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
                 for (int t = gl; t < p; t += G) {
                     const int j = S.Jlist[q + t];
                     const int64_t b0 = A.colptr[j];
+                    const int len = (int)(A.colptr[j + 1] - b0);
                     S.segb()[t] = b0;
-                    S.pref()[t] = (int)(A.colptr[j + 1] - b0);
+                    S.pref()[t] = len;
+                    S.cb[q + t] = b0;  // kept by slot for the gathers and the residual
+                    S.cl[q + t] = len;
                 }
                 if (gl == 0) S.cnt = 0;
             }
@@ -484,9 +490,8 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
                     ce0[s] = 0;
                     ce1[s] = 0;
                     if (ract && c < qn) {
-                        const int j = S.Jlist[c];
-                        ce0[s] = A.colptr[j];
-                        ce1[s] = A.colptr[j + 1];
+                        ce0[s] = S.cb[c];
+                        ce1[s] = ce0[s] + S.cl[c];
                     }
                 }
 #pragma unroll
@@ -541,12 +546,17 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
                 const bool ja = act && j < qn;
                 const bool newr = j >= qlo;
                 double bj;
+                // the reflector's vector: column j from its head row down, exact zeros
+                // above it (the entries of R there), so that the products with the
+                // other columns need no per-row predicate
+                double vr[RPL];
                 {
                     double s2 = 0.0, x0p = 0.0;
 #pragma unroll
                     for (int r = 0; r < RPL; ++r) {
                         const int i = r * G + gl;
-                        if (i >= j) s2 += b[r][j] * b[r][j];
+                        vr[r] = (i >= j) ? b[r][j] : 0.0;
+                        s2 += vr[r] * vr[r];
                         if (i == j) x0p = b[r][j];
                     }
                     s2 = gsum<G>(s2);
@@ -559,7 +569,10 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
                         if (!(nx > 0.0)) singular = true;
 #pragma unroll
                         for (int r = 0; r < RPL; ++r)
-                            if (r * G + gl == j) b[r][j] = vj;
+                            if (r * G + gl == j) {
+                                b[r][j] = vj;
+                                vr[r] = vj;
+                            }
 #pragma unroll
                         for (int r = 0; r < RPL; ++r)
                             if (r * G + gl == j) {
@@ -578,27 +591,23 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
                     const bool ca = ja && c < qn && (newr || c >= qlo);
                     double w = 0.0;
 #pragma unroll
-                    for (int r = 0; r < RPL; ++r)
-                        if (r * G + gl >= j) w += b[r][j] * b[r][c];
+                    for (int r = 0; r < RPL; ++r) w += vr[r] * b[r][c];
                     w = gsum<G>(w);
                     if (ca) {
                         const double f = bj * w;
 #pragma unroll
-                        for (int r = 0; r < RPL; ++r)
-                            if (r * G + gl >= j) b[r][c] -= f * b[r][j];
+                        for (int r = 0; r < RPL; ++r) b[r][c] -= f * vr[r];
                     }
                 }
                 if (wave_any(ja && newr)) {
                     double w = 0.0;
 #pragma unroll
-                    for (int r = 0; r < RPL; ++r)
-                        if (r * G + gl >= j) w += b[r][j] * y[r];
+                    for (int r = 0; r < RPL; ++r) w += vr[r] * y[r];
                     w = gsum<G>(w);
                     if (ja && newr) {
                         const double f = bj * w;
 #pragma unroll
-                        for (int r = 0; r < RPL; ++r)
-                            if (r * G + gl >= j) y[r] -= f * b[r][j];
+                        for (int r = 0; r < RPL; ++r) y[r] -= f * vr[r];
                     }
                 }
             }
@@ -656,7 +665,8 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
                     if (__popc(keep) == q) dact = false;
                 }
                 if (wave_any(dact)) {
-                    int jv[(QMAX + G - 1) / G];
+                    int jv[(QMAX + G - 1) / G], lv[(QMAX + G - 1) / G];
+                    int64_t bv0[(QMAX + G - 1) / G];
                     if (dact) {
                         if (keep == 0u) {
                             // keep the largest |m_j| (smaller column index on ties)
@@ -676,6 +686,8 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
                         for (int s = 0; s < (QMAX + G - 1) / G; ++s) {
                             const int c = s * G + gl;
                             jv[s] = (c < q) ? S.Jlist[c] : 0;
+                            bv0[s] = (c < q) ? S.cb[c] : 0;
+                            lv[s] = (c < q) ? S.cl[c] : 0;
                         }
                     }
                     wave_sync();
@@ -683,7 +695,12 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
 #pragma unroll
                         for (int s = 0; s < (QMAX + G - 1) / G; ++s) {
                             const int c = s * G + gl;
-                            if (c < q && (keep & (1u << c))) S.Jlist[__popc(keep & ((1u << c) - 1u))] = jv[s];
+                            if (c < q && (keep & (1u << c))) {
+                                const int d = __popc(keep & ((1u << c) - 1u));
+                                S.Jlist[d] = jv[s];
+                                S.cb[d] = bv0[s];
+                                S.cl[d] = lv[s];
+                            }
                         }
                         for (int t = gl; t < C::HSJ; t += G) S.hJ[t] = HEMPTY;
                     }
@@ -747,8 +764,7 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
                     rw2[t] = -1;
                     vv2[t] = 0.0;
                     if (sel && t < q) {
-                        const int j = S.Jlist[ord[t]];
-                        const int64_t e0 = A.colptr[j], e1 = A.colptr[j + 1];
+                        const int64_t e0 = S.cb[ord[t]], e1 = e0 + S.cl[ord[t]];
                         if (e1 - e0 > G) shortcols = false;
                         const int64_t e = e0 + gl;
                         if (e < e1) {
@@ -774,10 +790,9 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
             for (int t = 0; t < qmaxw; ++t) {
                 if (sel && !shortcols && t < q) {
                     const int c = ord[t];
-                    const int j = S.Jlist[c];
                     const double mc = mts[c];
-                    const int64_t e1 = A.colptr[j + 1];
-                    for (int64_t e = A.colptr[j] + gl; e < e1; e += G) {
+                    const int64_t e1 = S.cb[c] + S.cl[c];
+                    for (int64_t e = S.cb[c] + gl; e < e1; e += G) {
                         const int sl = hfind<C::LOGHSI>(S.hI, A.rowidx[e]);
                         const int li = sl >= 0 ? S.hIv[sl] : -1;
                         if (li >= 0 && li < MMAX) racc[li] = __fma_rn(A.val[e], mc, racc[li]);
