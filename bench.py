@@ -220,6 +220,7 @@ def main():
     # ---- further workloads (reported beside the value): power-law n = 10^6, the
     # 64-matrix batch in one build, fwd+bwd on the 64^3 3D matrix
     extra = None
+    host_mats = {}  # host copies of the other workloads, for the CPU oracle's legs
     if not args.no_extra:
         extra = {}
         # right-preconditioned BiCGStab on the device with this M (x0 = 0, b = A*1,
@@ -292,6 +293,7 @@ def main():
         extra["powerlaw_1e6"] = {"value": H3.n / dt3, "unit": "columns/s", "ms_per_step": dt3 * 1e3,
                                  "workload": "power-law columns (min 2, mean 7, max 200), n=10^6, seed 0; "
                                              "c=3 lmax=10 eps=0.4 tol=1e-3"}
+        host_mats["c3"] = H3
         del A3, H3
         specs = gen.batch64_specs()
         H5 = [gen.make(sp) for sp in specs]
@@ -353,6 +355,7 @@ def main():
                 fb5.append(time.perf_counter() - t0)
             del v5, L5
         extra["batch64"]["fwd_bwd_ms"] = float(np.median(fb5)) * 1e3
+        host_mats["c5"] = H5
         del A5, H5
         H4 = gen.c4()
         A4 = rsai.Matrix.from_host(H4, "cuda:0")
@@ -368,6 +371,7 @@ def main():
             if it > 0:
                 fb4.append(time.perf_counter() - t0)
         extra["fwd_bwd_cd3d64_ms"] = float(np.median(fb4)) * 1e3
+        host_mats["c4"] = H4
         del A4, H4
 
     # ---- CPU oracle on the host cores (full matrix, repeated up to ~10 s)
@@ -387,6 +391,34 @@ def main():
         R1 = oracle.rsai(H, c=3, lmax=8, eps=0.4, drop=oracle.DROP_FIXED, tol=1e-3, threads=1, cols=cols)
         cpu["one_core"] = {"value": cols.size / R1["seconds"], "unit": "columns/s", "cores": 1,
                            "sample": "32768 seeded columns of the same matrix"}
+        # the other workloads: the 32x32 and 64^3 matrices in full, the power-law
+        # matrix and the 64-matrix batch on seeded column samples (seconds each)
+        # (the thread count is passed explicitly: the one-thread run above leaves it at 1)
+        P_o = dict(c=3, lmax=8, eps=0.4, drop=oracle.DROP_FIXED, tol=1e-3, threads=int(thr))
+
+        def oracle_leg(mats, kw, per):
+            secs, k, thr = 0.0, 0, 0
+            for i, Hx in enumerate(mats):
+                cs = None
+                if per is not None and per < Hx.n:
+                    cs = np.sort(np.random.default_rng(i).choice(Hx.n, per, replace=False))
+                Rx = oracle.rsai(Hx, cols=cs, **kw)
+                secs += Rx["seconds"]
+                k += Hx.n if cs is None else cs.size
+                thr = Rx["threads"]
+            return {"value": k / secs, "unit": "columns/s", "cores": int(thr), "columns": int(k),
+                    "of": int(sum(Hx.n for Hx in mats))}
+
+        by = {"cd2d_32x32": oracle_leg([gen.c1()], P_o, None)}
+        if "c4" in host_mats:
+            by["cd3d_64"] = oracle_leg([host_mats["c4"]], P_o, None)
+        if "c3" in host_mats:
+            by["powerlaw_1e6"] = dict(oracle_leg([host_mats["c3"]], dict(P_o, lmax=10), 20000),
+                                      sample="20000 seeded columns")
+        if "c5" in host_mats:
+            by["batch64"] = dict(oracle_leg(host_mats["c5"], P_o, 1000),
+                                 sample="1000 seeded columns of each of the 64 matrices")
+        cpu["by_workload"] = by
 
     # peaks measured on this device, beside the published ones: the FP64 FMA loop of
     # the library and a device-to-device copy of 1 GiB (read + write counted)
