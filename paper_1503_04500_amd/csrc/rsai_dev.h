@@ -237,11 +237,18 @@ template <int LOGHS>
 __device__ __forceinline__ bool hinsert(int *hk, int key, int &slot) {
     constexpr unsigned MASK = (1u << LOGHS) - 1u;
     unsigned h = hslot<LOGHS>(key);
-    for (int probe = 0; probe < (1 << LOGHS); ++probe) {
-        int old = atomicCAS(&hk[h], HEMPTY, key);
+    // first probe straight-line (the usual case at the load factors used here), the
+    // probing loop only after a collision
+    int old = atomicCAS(&hk[h], HEMPTY, key);
+    if (old == HEMPTY || old == key) {
+        slot = (int)h;
+        return old == HEMPTY;
+    }
+    for (int probe = 1; probe < (1 << LOGHS); ++probe) {
+        h = (h + 1u) & MASK;
+        old = atomicCAS(&hk[h], HEMPTY, key);
         if (old == HEMPTY) { slot = (int)h; return true; }
         if (old == key) { slot = (int)h; return false; }
-        h = (h + 1u) & MASK;
     }
     slot = -1;  // table full: callers size tables so this cannot happen
     return false;
@@ -252,11 +259,14 @@ template <int LOGHS>
 __device__ __forceinline__ int hfind(const int *hk, int key) {
     constexpr unsigned MASK = (1u << LOGHS) - 1u;
     unsigned h = hslot<LOGHS>(key);
-    for (int probe = 0; probe < (1 << LOGHS); ++probe) {
-        int v = hk[h];
+    int v = hk[h];  // first probe straight-line, as in hinsert
+    if (v == key) return (int)h;
+    if (v == HEMPTY) return -1;
+    for (int probe = 1; probe < (1 << LOGHS); ++probe) {
+        h = (h + 1u) & MASK;
+        v = hk[h];
         if (v == key) return (int)h;
         if (v == HEMPTY) return -1;
-        h = (h + 1u) & MASK;
     }
     return -1;
 }
