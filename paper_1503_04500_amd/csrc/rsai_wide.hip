@@ -551,36 +551,55 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
                     const double th = (P.drop == DROP_FIXED)
                                           ? P.tol
                                           : P.eps / ((double)q * __longlong_as_double((long long)*A.norm1_bits));
-                    int nk = 0, bc = 0;
-                    for (int c = 0; c < q; ++c) {
-                        nk += (fabs(S.mt[c]) > th) ? 1 : 0;
-                        const double a = fabs(S.mt[c]), b = fabs(S.mt[bc]);
-                        if (a > b || (a == b && S.Jl[c] < S.Jl[bc])) bc = c;
+                    // kept columns as a lane mask (q <= 63: one lane per column, each wave
+                    // forms the same mask); with none above the threshold, the largest |m_j|
+                    // stays (the smaller column index on ties)
+                    const bool inq = lane < q;
+                    const double am = inq ? fabs(S.mt[lane]) : -1.0;
+                    const int jg = inq ? S.Jl[lane] : INT_MAX;
+                    unsigned long long keepm = __ballot(inq && am > th);
+                    const int nk = __popcll(keepm);
+                    if (nk == 0) {
+                        double ba = am;
+                        int bg = jg;
+#pragma unroll
+                        for (int off = 32; off >= 1; off >>= 1) {
+                            const double a2 = __shfl_xor(ba, off);
+                            const int g2 = __shfl_xor(bg, off);
+                            if (a2 > ba || (a2 == ba && g2 < bg)) { ba = a2; bg = g2; }
+                        }
+                        keepm = __ballot(inq && jg == bg);
                     }
                     if (nk < q) {
                         // rows of the dropped columns lose one holder
                         wave_cols<false>(
                             S, A, 0, q, wid, lane,
                             [&](int c, int row, double) {
-                                const bool keep = (nk == 0) ? (c == bc) : (fabs(S.mt[c]) > th);
-                                if (keep) return;
+                                if ((keepm >> c) & 1ull) return;
                                 const int sl = hfind<LOGH>(S.hk, row);
                                 if (sl >= 0) hdec(S, sl); else lookup_fail = true;
                             },
                             [](int) {});
                         __syncthreads();
-                        if (tid == 0) {
-                            int w = 0;
-                            for (int c = 0; c < q; ++c) {
-                                const bool keep = (nk == 0) ? (c == bc) : (fabs(S.mt[c]) > th);
-                                if (keep) {
-                                    S.Jl[w] = S.Jl[c];
-                                    S.cb[w] = S.cb[c];
-                                    S.clen[w] = S.clen[c];
-                                    ++w;
-                                }
+                        if (wid == 0) {
+                            // compaction of the slots in order: lane c moves to the number of
+                            // kept slots below it
+                            const bool kc = inq && ((keepm >> lane) & 1ull);
+                            int jl = 0, cl = 0;
+                            int64_t cbv = 0;
+                            if (kc) {
+                                jl = S.Jl[lane];
+                                cbv = S.cb[lane];
+                                cl = S.clen[lane];
                             }
-                            S.cnt = w;
+                            const int d = __popcll(keepm & ((1ull << lane) - 1ull));
+                            wave_sync();
+                            if (kc) {
+                                S.Jl[d] = jl;
+                                S.cb[d] = cbv;
+                                S.clen[d] = cl;
+                            }
+                            if (lane == 0) S.cnt = __popcll(keepm);
                         }
                         for (int t = tid; t < HJ; t += NT) S.hJ[t] = HEMPTY;
                         __syncthreads();
