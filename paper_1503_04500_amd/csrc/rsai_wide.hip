@@ -360,32 +360,63 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
                 __syncthreads();
                 // ---- gather: shared entries into the block, private rows into column sums
                 {
-                    double a2 = 0.0;  // private rows of the current column: sum of squares
-                    wave_cols<true>(
-                        S, A, 0, q, wid, lane,
-                        [&](int c, int row, double v) {
-                            const int sl = hfind<LOGH>(S.hk, row);
-                            const unsigned cn = sl >= 0 ? (hget(S, sl) & 0x7Fu) : 0u;
-                            if (cn == 1u) {
-                                a2 += v * v;
-                                if (row == k) { S.kcol = c; S.akv = v; }
-                            } else if (cn >= 2u) {
-                                const int si = sfind(S.srow, nsh, row);
-                                if (si >= 0) {
-                                    S.blk[(q + si) * ld + c] = v;
-                                    S.shv[si * q + c] = v;
-                                } else {
-                                    lookup_fail = true;
-                                }
+                    auto visit = [&](int c, int row, double v, double &a2) {
+                        const int sl = hfind<LOGH>(S.hk, row);
+                        const unsigned cn = sl >= 0 ? (hget(S, sl) & 0x7Fu) : 0u;
+                        if (cn == 1u) {
+                            a2 += v * v;
+                            if (row == k) { S.kcol = c; S.akv = v; }
+                        } else if (cn >= 2u) {
+                            const int si = sfind(S.srow, nsh, row);
+                            if (si >= 0) {
+                                S.blk[(q + si) * ld + c] = v;
+                                S.shv[si * q + c] = v;
                             } else {
                                 lookup_fail = true;
                             }
-                        },
-                        [&](int c) {
-                            const double x = wsum(a2);
-                            if (lane == 0) S.s2[c] = x;
-                            a2 = 0.0;
-                        });
+                        } else {
+                            lookup_fail = true;
+                        }
+                    };
+                    // HB columns per wave at a time: entries loaded together, then the
+                    // private rows' sums of squares of the HB columns reduced together
+                    constexpr int HB = 8;
+                    for (int cb0 = wid; cb0 < q; cb0 += NW * HB) {
+                        int rr[HB];
+                        double vv[HB], a2[HB];
+#pragma unroll
+                        for (int t = 0; t < HB; ++t) {
+                            const int c = cb0 + NW * t;
+                            rr[t] = -1;
+                            vv[t] = 0.0;
+                            if (c < q && lane < S.clen[c]) {
+                                const int64_t e = S.cb[c] + lane;
+                                rr[t] = A.rowidx[e];
+                                vv[t] = A.val[e];
+                            }
+                        }
+#pragma unroll
+                        for (int t = 0; t < HB; ++t) {
+                            const int c = cb0 + NW * t;
+                            a2[t] = 0.0;
+                            if (c < q) {
+                                if (rr[t] >= 0) visit(c, rr[t], vv[t], a2[t]);
+                                const int len = S.clen[c];
+                                if (len > 64) {
+                                    const int64_t e0 = S.cb[c];
+                                    for (int u = 64 + lane; u < len; u += 64) visit(c, A.rowidx[e0 + u], A.val[e0 + u], a2[t]);
+                                }
+                            }
+                        }
+#pragma unroll
+                        for (int t = 0; t < HB; ++t) {
+                            const int c = cb0 + NW * t;
+                            if (c < q) {
+                                const double x = wsum(a2[t]);
+                                if (lane == 0) S.s2[c] = x;
+                            }
+                        }
+                    }
                 }
                 __syncthreads();
                 // ---- the row of row k: shared (right-hand side 1), private (compressed), or
