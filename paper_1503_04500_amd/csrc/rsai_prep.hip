@@ -10,6 +10,24 @@
 
 namespace rsai {
 
+// Grid-stride range of this thread with each XCD's workgroups on a contiguous eighth
+// of the work: the hardware deals workgroups to the eight XCDs round robin (block b
+// on XCD b % 8), so a plain grid stride spreads neighbouring items, and the rows they
+// touch, over all eight L2s. Grids of fewer than eight blocks keep the plain stride.
+struct XcdSpan {
+    int64_t i, end, step;
+};
+__device__ __forceinline__ XcdSpan xcd_span(int64_t work) {
+    const int nb = gridDim.x, bs = blockDim.x;
+    if (nb < 8) return {blockIdx.x * (int64_t)bs + threadIdx.x, work, (int64_t)nb * bs};
+    const int x = blockIdx.x % 8, w = blockIdx.x / 8;
+    const int nw = (nb - x + 7) / 8;  // blocks on XCD x
+    const int64_t chunk = (work + 7) / 8;
+    const int64_t lo = (int64_t)x * chunk;
+    const int64_t hi = lo + chunk < work ? lo + chunk : work;
+    return {lo + (int64_t)w * bs + threadIdx.x, hi, (int64_t)nw * bs};
+}
+
 static inline int nblocks(int64_t work, int per_block) {
     int64_t b = (work + per_block - 1) / per_block;
     if (b < 1) b = 1;
@@ -128,7 +146,8 @@ __global__ void k_row_fill(int64_t n, const int64_t *colptr, const int32_t *rowi
                            int32_t *fillpos, int32_t *colidx, const int32_t *err) {
     if (*err) return;
     constexpr int U = 8;  // entries of a column whose position atomics are in flight together
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    for (XcdSpan cs = xcd_span(n); cs.i < cs.end; cs.i += cs.step) {
+        const int64_t j = cs.i;
         const int64_t b = colptr[j], e = colptr[j + 1];
         for (int64_t base = b; base < e; base += U) {
             int r[U], p[U];
@@ -285,7 +304,8 @@ void launch_assemble(int64_t n, int qcap, const int64_t *off, const int32_t *nJ,
 __global__ void k_csc_transpose_fill(int64_t n, const int64_t *colptr, const int32_t *rowidx, const double *val,
                                      const int64_t *rowptr, int32_t *fillpos, int32_t *colidxT, double *valT) {
     constexpr int U = 8;  // entries of a column whose position atomics are in flight together
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    for (XcdSpan cs = xcd_span(n); cs.i < cs.end; cs.i += cs.step) {
+        const int64_t j = cs.i;
         const int64_t b = colptr[j], e = colptr[j + 1];
         for (int64_t base = b; base < e; base += U) {
             int r[U], p[U];
