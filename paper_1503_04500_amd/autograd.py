@@ -51,7 +51,7 @@ class RSAIFunction(torch.autograd.Function):
         # keep the R factors of the final solves for the adjoint unless told not to
         plan = rsai.build(Av, **dict({"keep_factors": True}, **params))
         cp, ri, vm = plan.export()
-        rn = plan.stats()["resnorm"]
+        rn = plan.stats(fields=("resnorm",))["resnorm"]
         frob = torch.sum(rn * rn)
         ctx.plan = plan
         ctx.Av = Av
@@ -79,7 +79,7 @@ class RSAIBatchFunction(torch.autograd.Function):
         outs, pattern = [], []
         for i in range(len(Avs)):
             cp, ri, vm = plan.export(i)
-            rn = plan.stats(i)["resnorm"]
+            rn = plan.stats(i, fields=("resnorm",))["resnorm"]
             pattern += [cp, ri]
             outs += [vm, torch.sum(rn * rn), cp, ri]
         ctx.mark_non_differentiable(*pattern)

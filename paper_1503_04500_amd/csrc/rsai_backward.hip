@@ -14,6 +14,8 @@
 // A_k z = Q [R z; 0] = Q [u; 0] with R^T u = g, and r = -Q [0; (Q^T e)(q:m)].
 #include <climits>
 
+#include <algorithm>
+
 #include "rsai_kernels.h"
 
 namespace rsai {
@@ -90,7 +92,9 @@ __global__ __launch_bounds__(256) void k_max2(int64_t n, const int32_t *a, const
     }
 }
 void launch_max2(int64_t n, const int32_t *a, const int32_t *b, const int64_t *mask, int32_t *out5, hipStream_t s) {
-    hipLaunchKernelGGL(k_max2, dim3(256), dim3(256), 0, s, n, a, b, mask, out5);
+    // one column per thread (the loads of a thread are then independent of each other)
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_max2, dim3((unsigned)blocks), dim3(256), 0, s, n, a, b, mask, out5);
 }
 
 __global__ __launch_bounds__(64) void backward_kernel(BwdArgs a) {

@@ -67,7 +67,8 @@ struct MatPlan {
     double *valM = nullptr;
     int64_t capM = 0;
     int64_t nnzM = -1;
-    int64_t *summary = nullptr;  // device: nnz(M), error flags, failed-column counts
+    int64_t *summary = nullptr;  // device: nnz(M), error flags, failed-column counts; [8..10] the
+                                 // adjoint's size maxima (five int32) when the factors are kept
     int32_t maxq = -1, maxm = -1;  // largest final |J_k| and |I_k| (first backward)
     int32_t nofac = -1;            // columns without a kept factor
     int32_t maxq_nofac = -1;       // their largest |J_k|
@@ -352,7 +353,7 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
             // entries of M: at most qmid per column, and up to qlast for the columns the
             // dense class finishes (no more than its record capacity)
             M.capM = n * qmid + std::min<int64_t>(n, big_cap) * (qlast - qmid);
-            M.summary = L.take<int64_t>(8);
+            M.summary = L.take<int64_t>(12);
             M.colptrM = L.take<int64_t>(n + 1);
             M.rowidxM = L.take<int32_t>(M.capM);
             M.valM = L.take<double>(M.capM);
@@ -731,11 +732,25 @@ rsai_status rsai_plan_nnz(const rsai_plan *Pc, int32_t mat, int64_t *nnzM) {
     MatPlan &M = P->mats[mat];
     if (M.nnzM < 0) {
         const int64_t n = M.A.n;
-        int64_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        launch_fill_i64(M.summary, 0, 8, P->stream);
+        int64_t h[12] = {};
+        launch_fill_i64(M.summary, 0, 12, P->stream);
         launch_summary(n, M.colptrM, P->out.status + M.col_base, P->err, M.summary, P->stream);
+        // with kept factors the adjoint's size maxima come back in the same copy
+        const bool sizes = P->out.foff != nullptr && M.maxq < 0;
+        if (sizes)
+            launch_max2(n, P->out.nJ + M.col_base, P->out.nI + M.col_base, P->out.foff + M.col_base,
+                        (int32_t *)(M.summary + 8), P->stream);
         HIPCHK(hipMemcpyAsync(h, M.summary, sizeof(h), hipMemcpyDeviceToHost, P->stream));
         HIPCHK(hipStreamSynchronize(P->stream));
+        if (sizes) {
+            int32_t h2[5];
+            std::memcpy(h2, h + 8, sizeof(h2));
+            M.maxq = h2[0];
+            M.maxm = h2[1];
+            M.nofac = h2[2];
+            M.maxq_nofac = h2[3];
+            M.nlarge = h2[4];
+        }
         const int64_t herr = h[1];
         if (herr & 7) return fail(RSAI_E_CSC, "malformed CSC (flags %lld: 1 colptr, 2 row indices, 4 empty column)",
                                   (long long)herr);

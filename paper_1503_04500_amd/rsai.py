@@ -234,15 +234,22 @@ class Plan:
         _check(load().rsai_export_M(self._hv(), mat, cp.data_ptr(), ri.data_ptr(), va.data_ptr(), _stream()))
         return cp, ri[:nz], va[:nz]
 
-    def stats(self, mat=0):
+    _STATS = {"loops": torch.int32, "resnorm": torch.float64, "nI": torch.int32, "nJ": torch.int32,
+              "flops": torch.float64, "status": torch.int32}
+
+    def stats(self, mat=0, fields=None):
+        """Per-column statistics of matrix mat (rsai_export_stats); fields names the ones
+        to export (default all of loops, resnorm, nI, nJ, flops, status)."""
         n = self.mats[mat].n
         dev = self.mats[mat].colptr.device
-        t = {k: torch.empty(n, dtype=torch.int32, device=dev) for k in ("loops", "nI", "nJ", "status")}
-        t["resnorm"] = torch.empty(n, dtype=torch.float64, device=dev)
-        t["flops"] = torch.empty(n, dtype=torch.float64, device=dev)
-        _check(load().rsai_export_stats(self._hv(), mat, t["loops"].data_ptr(), t["resnorm"].data_ptr(),
-                                        t["nI"].data_ptr(), t["nJ"].data_ptr(), t["flops"].data_ptr(),
-                                        t["status"].data_ptr(), _stream()))
+        names = tuple(self._STATS) if fields is None else tuple(fields)
+        unknown = [f for f in names if f not in self._STATS]
+        if unknown:
+            raise ValueError(f"unknown statistics {unknown}")
+        t = {k: torch.empty(n, dtype=self._STATS[k], device=dev) for k in names}
+        ptr = {k: (t[k].data_ptr() if k in t else None) for k in self._STATS}
+        _check(load().rsai_export_stats(self._hv(), mat, ptr["loops"], ptr["resnorm"], ptr["nI"], ptr["nJ"],
+                                        ptr["flops"], ptr["status"], _stream()))
         return t
 
     def apply(self, x, mat=0):

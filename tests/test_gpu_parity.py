@@ -284,3 +284,19 @@ def test_async_validation_matches_sync_on_valid_input():
     a = run_gpu(A, validate=2, **C1)
     b = run_gpu(A, validate=1, **C1)
     assert np.array_equal(a["rowidx"], b["rowidx"]) and np.array_equal(a["val"], b["val"])
+
+
+def test_stats_field_selection():
+    """Exporting a subset of the per-column statistics gives the same arrays as the
+    full export; unknown names are refused."""
+    import torch
+    import paper_1503_04500_amd.rsai as rsai
+    A = rsai.Matrix.from_host(gen.c1(), "cuda:0")
+    plan = rsai.build(A, **C1)
+    full = plan.stats()
+    part = plan.stats(fields=("resnorm", "nJ"))
+    assert set(part) == {"resnorm", "nJ"}
+    assert torch.equal(part["resnorm"], full["resnorm"]) and torch.equal(part["nJ"], full["nJ"])
+    with pytest.raises(ValueError):
+        plan.stats(fields=("bogus",))
+    plan.close()
