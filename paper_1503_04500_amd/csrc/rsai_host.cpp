@@ -861,30 +861,34 @@ rsai_status rsai_spmv(const rsai_csc *A, const double *x, double *y, int32_t tra
         HIPCHK(hipGetLastError());
         return RSAI_OK;
     }
-    // y = A x through the rows of A (deterministic summation order)
+    // y = A x through the rows of A (deterministic summation order); the work buffers
+    // come from one allocation (each allocator call may cross into the host runtime
+    // that owns the memory)
     rsai_status st = RSAI_OK;
     const int64_t n = A->n, nnz = A->nnz;
-    std::vector<void *> tmp;
-    auto al = [&](size_t bytes) -> void * {
-        void *p = dev_alloc(bytes, s);
-        if (!p) st = fail(RSAI_E_NOMEM, "allocation failed");
-        tmp.push_back(p);
-        return p;
+    int32_t *cnt = nullptr, *fill = nullptr, *ci = nullptr, *zerr = nullptr;
+    int64_t *rp = nullptr, *stmp = nullptr;
+    double *vv = nullptr;
+    auto layout = [&](Layout &L) {
+        cnt = L.take<int32_t>(n);
+        fill = L.take<int32_t>(n);
+        rp = L.take<int64_t>(n + 1);
+        ci = L.take<int32_t>(nnz);
+        vv = L.take<double>(nnz);
+        stmp = L.take<int64_t>(scan_tmp_elems(n + 1));
+        zerr = L.take<int32_t>(4);
     };
-    int32_t *cnt = (int32_t *)al(4 * n);
-    int32_t *fill = (int32_t *)al(4 * n);
-    int64_t *rp = (int64_t *)al(8 * (n + 1));
-    int32_t *ci = (int32_t *)al(4 * nnz);
-    double *vv = (double *)al(8 * nnz);
-    int64_t *stmp = (int64_t *)al(8 * scan_tmp_elems(n + 1));
-    int32_t *zerr = (int32_t *)al(16);
-    if (st == RSAI_OK) {
-        enqueue_rows(A, rp, ci, vv, cnt, fill, stmp, zerr, s);
-        launch_csr_spmv(n, rp, ci, vv, x, y, s);
-        if (hipGetLastError() != hipSuccess) st = fail(RSAI_E_HIP, "spmv launch failed");
-    }
-    // stream-ordered release: the work queued on s above still uses these blocks
-    for (void *p : tmp) dev_free(p, s);
+    Layout L0;
+    layout(L0);
+    Layout L1;
+    L1.base = (char *)dev_alloc(L0.off, s);
+    if (!L1.base) return fail(RSAI_E_NOMEM, "spmv work buffers (%zu bytes)", L0.off);
+    layout(L1);
+    enqueue_rows(A, rp, ci, vv, cnt, fill, stmp, zerr, s);
+    launch_csr_spmv(n, rp, ci, vv, x, y, s);
+    if (hipGetLastError() != hipSuccess) st = fail(RSAI_E_HIP, "spmv launch failed");
+    // stream-ordered release: the work queued on s above still uses the block
+    dev_free(L1.base, s);
     return st;
 }
 
