@@ -473,14 +473,24 @@ __global__ __launch_bounds__(64) void backward_factored_kernel(BwdArgs a) {
     LT &S = lds[grp];
     const MatDev A = a.mats[a.mat];
     const int64_t n = a.n;
-    const int64_t gstride = (int64_t)gridDim.x * FGPW;
-    const int64_t iters = (n + gstride - 1) / gstride;
+    // each XCD takes a contiguous eighth of the columns (block b runs on XCD b % 8):
+    // neighbouring columns add into the same entries of A, and their atomics then
+    // meet in one L2. The trip count is uniform within a block.
+    int64_t hi = n, k = (int64_t)blockIdx.x * FGPW + grp, gstride = (int64_t)gridDim.x * FGPW, lo = 0;
+    if (gridDim.x >= 8) {
+        const int x = blockIdx.x % 8, w = blockIdx.x / 8, nwx = (gridDim.x - x + 7) / 8;
+        const int64_t chunk = (n + 7) / 8;
+        lo = (int64_t)x * chunk;
+        hi = lo + chunk < n ? lo + chunk : n;
+        k = lo + (int64_t)w * FGPW + grp;
+        gstride = (int64_t)nwx * FGPW;
+    }
+    const int64_t iters = hi > lo ? (hi - lo + gstride - 1) / gstride : 0;
     uint64_t gmask = ~0ull;
     if constexpr (G < 64) gmask = (1ull << G) - 1;
     // the header of the group's first column; each iteration loads the next one's
-    int64_t k = (int64_t)blockIdx.x * FGPW + grp;
     int64_t nfo = -1, nmb = 0, nme = 0;
-    if (k < n) {
+    if (k < hi) {
         nfo = a.foff[k];
         nmb = a.Mcolptr[k];
         nme = a.Mcolptr[k + 1];
@@ -488,12 +498,12 @@ __global__ __launch_bounds__(64) void backward_factored_kernel(BwdArgs a) {
     for (int64_t itk = 0; itk < iters; ++itk, k += gstride) {
         const int64_t fo = nfo, mb = nmb;
         const int q = (int)(nme - nmb);
-        bool act = k < n && fo >= 0 && q >= QLO && q <= FQ;
+        bool act = k < hi && fo >= 0 && q >= QLO && q <= FQ;
         {
             const int64_t kn = k + gstride;
             nfo = -1;
             nmb = nme = 0;
-            if (kn < n) {
+            if (kn < hi) {
                 nfo = a.foff[kn];
                 nmb = a.Mcolptr[kn];
                 nme = a.Mcolptr[kn + 1];
