@@ -412,17 +412,23 @@ void launch_csc_spmv_t(int64_t n, const int64_t *colptr, const int32_t *rowidx, 
     hipLaunchKernelGGL(k_csc_spmv_t, dim3(nblocks(n, 256)), dim3(256), 0, s, n, colptr, rowidx, val, x, y);
 }
 
-// dval[e] += dy[row(e)] * x[col(e)]: one thread per column
+// dval[e] += dy[row(e)] * x[col(e)]: a group of VG lanes per column walks its entries
+// side by side (contiguous loads); every entry is updated by exactly one lane
+constexpr int VG = 8;
 __global__ void k_spmv_vjp(int64_t n, const int64_t *colptr, const int32_t *rowidx, const double *dy,
                            const double *x, double *dval) {
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    const int gl = threadIdx.x % VG;
+    const int64_t g0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / VG;
+    const int64_t gs = (int64_t)gridDim.x * blockDim.x / VG;
+    for (int64_t j = g0; j < n; j += gs) {
         const double xj = x[j];
-        for (int64_t e = colptr[j]; e < colptr[j + 1]; ++e) dval[e] += dy[rowidx[e]] * xj;
+        const int64_t e1 = colptr[j + 1];
+        for (int64_t e = colptr[j] + gl; e < e1; e += VG) dval[e] += dy[rowidx[e]] * xj;
     }
 }
 void launch_spmv_vjp(int64_t n, const int64_t *colptr, const int32_t *rowidx, const double *dy, const double *x,
                      double *dval, hipStream_t s) {
-    hipLaunchKernelGGL(k_spmv_vjp, dim3(nblocks(n, 256)), dim3(256), 0, s, n, colptr, rowidx, dy, x, dval);
+    hipLaunchKernelGGL(k_spmv_vjp, dim3(nblocks(n * VG, 256)), dim3(256), 0, s, n, colptr, rowidx, dy, x, dval);
 }
 
 // FP64 FMA throughput probe: every lane runs FMA_CHAINS independent dependency chains
