@@ -339,50 +339,110 @@ void launch_csc_transpose_fill(int64_t n, const int64_t *colptr, const int32_t *
                        fillpos, colidxT, valT);
 }
 
-// sort each row's (col, value) pairs by column so that row sums have a fixed order.
-// Rows of up to 32 entries are sorted in registers (each entry's place is the number
-// of smaller column indices in the row, which are distinct), longer ones in place.
-__global__ void k_sort_rows(int64_t n, const int64_t *rowptr, int32_t *colidx, double *val) {
+// one row by one thread: up to 32 entries in registers (each entry's place is the
+// number of smaller column indices in the row, which are distinct), longer in place
+__device__ __forceinline__ void sort_row_thread(int64_t s, int64_t e, int32_t *colidx, double *val) {
     constexpr int RS = 32;
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int len = (int)(e - s);
+    if (len <= RS) {
+        int key[RS];
+        double v[RS];
+#pragma unroll
+        for (int t = 0; t < RS; ++t) {
+            key[t] = (t < len) ? colidx[s + t] : INT_MAX;
+            v[t] = (t < len && val) ? val[s + t] : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < RS; ++t) {
+            if (t < len) {
+                int rank = 0;
+#pragma unroll
+                for (int u = 0; u < RS; ++u) rank += (key[u] < key[t]) ? 1 : 0;
+                colidx[s + rank] = key[t];
+                if (val) val[s + rank] = v[t];
+            }
+        }
+        return;
+    }
+    for (int64_t a = s + 1; a < e; ++a) {
+        int key = colidx[a];
+        double v = val ? val[a] : 0.0;
+        int64_t b = a - 1;
+        while (b >= s && colidx[b] > key) {
+            colidx[b + 1] = colidx[b];
+            if (val) val[b + 1] = val[b];
+            --b;
+        }
+        colidx[b + 1] = key;
+        if (val) val[b + 1] = v;
+    }
+}
+
+// number of keys in this lane's 16-lane row smaller than its own: the row rotated by
+// D = 1..15 lanes (DPP row_ror), one comparison per rotation
+template <int D>
+__device__ __forceinline__ int row16_rank(int key, int acc) {
+    if constexpr (D == 16) {
+        return acc;
+    } else {
+        const int other = __builtin_amdgcn_mov_dpp(key, 0x120 + D, 0xF, 0xF, true);
+        return row16_rank<D + 1>(key, acc + (other < key ? 1 : 0));
+    }
+}
+
+// Two keys per lane (entries gl and gl + 16 of a row of up to 32): the ranks of both
+// among all 32, counted over the rotations of both halves.
+template <int D>
+__device__ __forceinline__ void row32_rank(int ka, int kb, int &ca, int &cb) {
+    if constexpr (D < 16) {
+        const int ra = __builtin_amdgcn_mov_dpp(ka, 0x120 + D, 0xF, 0xF, true);
+        const int rb = __builtin_amdgcn_mov_dpp(kb, 0x120 + D, 0xF, 0xF, true);
+        ca += (ra < ka ? 1 : 0) + (rb < ka ? 1 : 0);
+        cb += (ra < kb ? 1 : 0) + (rb < kb ? 1 : 0);
+        row32_rank<D + 1>(ka, kb, ca, cb);
+    }
+}
+
+// sort each row's (col, value) pairs by column so that row sums have a fixed order.
+// Rows of up to 32 entries: a 16-lane row of the wave per matrix row, one or two
+// entries per lane (contiguous loads), each entry's place its rank; longer rows by
+// one lane.
+constexpr int SORT_G = 16;
+__global__ void k_sort_rows(int64_t n, const int64_t *rowptr, int32_t *colidx, double *val) {
+    const int gl = threadIdx.x % SORT_G;
+    const int64_t g0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / SORT_G;
+    const int64_t gs = (int64_t)gridDim.x * blockDim.x / SORT_G;
+    for (int64_t i = g0; i < n; i += gs) {
         const int64_t s = rowptr[i], e = rowptr[i + 1];
         const int len = (int)(e - s);
-        if (len <= RS) {
-            int key[RS];
-            double v[RS];
-#pragma unroll
-            for (int t = 0; t < RS; ++t) {
-                key[t] = (t < len) ? colidx[s + t] : INT_MAX;
-                v[t] = (t < len && val) ? val[s + t] : 0.0;
+        if (len <= SORT_G) {
+            const int key = gl < len ? colidx[s + gl] : INT_MAX;
+            const double v = (gl < len && val) ? val[s + gl] : 0.0;
+            const int rank = row16_rank<1>(key, 0);
+            if (gl < len) {
+                colidx[s + rank] = key;
+                if (val) val[s + rank] = v;
             }
-#pragma unroll
-            for (int t = 0; t < RS; ++t) {
-                if (t < len) {
-                    int rank = 0;
-#pragma unroll
-                    for (int u = 0; u < RS; ++u) rank += (key[u] < key[t]) ? 1 : 0;
-                    colidx[s + rank] = key[t];
-                    if (val) val[s + rank] = v[t];
-                }
+        } else if (len <= 2 * SORT_G) {
+            const int ka = colidx[s + gl];  // gl < 16 < len
+            const int kb = gl + SORT_G < len ? colidx[s + gl + SORT_G] : INT_MAX;
+            const double va = val ? val[s + gl] : 0.0;
+            const double vb = (gl + SORT_G < len && val) ? val[s + gl + SORT_G] : 0.0;
+            int ca = kb < ka ? 1 : 0, cb = ka < kb ? 1 : 0;
+            row32_rank<1>(ka, kb, ca, cb);
+            colidx[s + ca] = ka;
+            if (val) val[s + ca] = va;
+            if (gl + SORT_G < len) {
+                colidx[s + cb] = kb;
+                if (val) val[s + cb] = vb;
             }
-            continue;
-        }
-        for (int64_t a = s + 1; a < e; ++a) {
-            int key = colidx[a];
-            double v = val ? val[a] : 0.0;
-            int64_t b = a - 1;
-            while (b >= s && colidx[b] > key) {
-                colidx[b + 1] = colidx[b];
-                if (val) val[b + 1] = val[b];
-                --b;
-            }
-            colidx[b + 1] = key;
-            if (val) val[b + 1] = v;
+        } else if (gl == 0) {
+            sort_row_thread(s, e, colidx, val);
         }
     }
 }
 void launch_sort_rows(int64_t n, const int64_t *rowptr, int32_t *colidx, double *val, hipStream_t s) {
-    hipLaunchKernelGGL(k_sort_rows, dim3(nblocks(n, 256)), dim3(256), 0, s, n, rowptr, colidx, val);
+    hipLaunchKernelGGL(k_sort_rows, dim3(nblocks(n * SORT_G, 256)), dim3(256), 0, s, n, rowptr, colidx, val);
 }
 
 __global__ void k_csr_spmv(int64_t n, const int64_t *rowptr, const int32_t *colidx, const double *val,
