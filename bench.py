@@ -455,7 +455,7 @@ def main():
                    "n": n, "nnz": nnz, "nnzM": int(nnzM), "schedule": "batched"},
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / FP64_PEAK_TFLOPS, "traffic": measured_traffic(),
-                     "kernel": "tier_kernel<8,3,12,4>", "kernel_ms": t0_ms, "alg_flops": flops,
+                     "kernel": "tier_kernel<8,3,12,6>", "kernel_ms": t0_ms, "alg_flops": flops,
                      "hbm_alg_bytes": bytes_alg, "hbm_achieved_GBs": hbm_gbs, "hbm_frac": hbm_gbs / HBM_PEAK_GBS,
                      "measured_peaks": measured},
         "plain": plain,

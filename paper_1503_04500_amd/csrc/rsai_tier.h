@@ -125,7 +125,7 @@ struct GLds {
 //     registers
 // t2: up to 128 x 32 blocks, 4 columns per wave
 #ifndef RSAI_T0_STAGE
-#define RSAI_T0_STAGE 4
+#define RSAI_T0_STAGE 6
 #endif
 #ifndef RSAI_T0_HSF
 #define RSAI_T0_HSF 2
