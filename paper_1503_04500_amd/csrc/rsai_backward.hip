@@ -54,14 +54,35 @@ __global__ __launch_bounds__(256) void k_max2(int64_t n, const int32_t *a, const
                                               int32_t *out5) {
     __shared__ int red[5][4];
     int v[5] = {0, 0, 0, 0, 0};  // max a, max b, count, max a (no factor), count large
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        v[0] = max(v[0], a[i]);
-        if (!mask || mask[i] < 0) {
-            v[1] = max(v[1], b[i]);
-            v[3] = max(v[3], a[i]);
-            ++v[2];
-        } else if (a[i] > 32) {
-            ++v[4];
+    // U columns per thread with their loads in flight together
+    constexpr int U = 4;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i0 < n; i0 += U * stride) {
+        int av[U], bv[U];
+        bool nf[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + u * stride;
+            av[u] = -1;
+            bv[u] = 0;
+            nf[u] = false;
+            if (i < n) {
+                av[u] = a[i];
+                bv[u] = b[i];
+                nf[u] = !mask || mask[i] < 0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (av[u] < 0) continue;
+            v[0] = max(v[0], av[u]);
+            if (nf[u]) {
+                v[1] = max(v[1], bv[u]);
+                v[3] = max(v[3], av[u]);
+                ++v[2];
+            } else if (av[u] > 32) {
+                ++v[4];
+            }
         }
     }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -92,8 +113,8 @@ __global__ __launch_bounds__(256) void k_max2(int64_t n, const int32_t *a, const
     }
 }
 void launch_max2(int64_t n, const int32_t *a, const int32_t *b, const int64_t *mask, int32_t *out5, hipStream_t s) {
-    // one column per thread (the loads of a thread are then independent of each other)
-    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
+    // few blocks: each ends with five atomics on the same five words
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 256));
     hipLaunchKernelGGL(k_max2, dim3((unsigned)blocks), dim3(256), 0, s, n, a, b, mask, out5);
 }
 
