@@ -46,12 +46,14 @@ struct BLds {
 int backward_max_cols() { return BQMAX; }
 int backward_max_rows() { return BMMAX; }
 
-// out5: largest |J_k|; over the columns without a kept factor (mask[k] < 0, or all
-// columns without a mask) the largest |I_k|, their count and their largest |J_k|;
-// the number of columns with a factor and |J_k| > 32. Reduced per workgroup first,
-// then one atomic per workgroup and value.
+// Five values: largest |J_k|; over the columns without a kept factor (mask[k] < 0,
+// or all columns without a mask) the largest |I_k|, their count and their largest
+// |J_k|; the number of columns with a factor and |J_k| > 32. Reduced per workgroup
+// first, then one atomic per workgroup and value into one of MAX2_COPIES copies of
+// the five words (out[copy * 5 + value], copy = workgroup % MAX2_COPIES), so that
+// fewer workgroups meet on one address; max2_combine folds the copies on the host.
 __global__ __launch_bounds__(256) void k_max2(int64_t n, const int32_t *a, const int32_t *b, const int64_t *mask,
-                                              int32_t *out5) {
+                                              int32_t *outc) {
     __shared__ int red[5][4];
     int v[5] = {0, 0, 0, 0, 0};  // max a, max b, count, max a (no factor), count large
     // U columns per thread with their loads in flight together
@@ -105,6 +107,7 @@ __global__ __launch_bounds__(256) void k_max2(int64_t n, const int32_t *a, const
             v[3] = max(v[3], red[3][q]);
             v[4] += red[4][q];
         }
+        int32_t *out5 = outc + (blockIdx.x % MAX2_COPIES) * 5;
         atomicMax(&out5[0], v[0]);
         atomicMax(&out5[1], v[1]);
         atomicAdd(&out5[2], v[2]);
@@ -112,10 +115,22 @@ __global__ __launch_bounds__(256) void k_max2(int64_t n, const int32_t *a, const
         atomicAdd(&out5[4], v[4]);
     }
 }
-void launch_max2(int64_t n, const int32_t *a, const int32_t *b, const int64_t *mask, int32_t *out5, hipStream_t s) {
+void max2_combine(const int32_t *h, int32_t *out5) {
+    for (int t = 0; t < 5; ++t) out5[t] = h[t];
+    for (int c = 1; c < MAX2_COPIES; ++c) {
+        const int32_t *q = h + c * 5;
+        out5[0] = std::max(out5[0], q[0]);
+        out5[1] = std::max(out5[1], q[1]);
+        out5[2] += q[2];
+        out5[3] = std::max(out5[3], q[3]);
+        out5[4] += q[4];
+    }
+}
+
+void launch_max2(int64_t n, const int32_t *a, const int32_t *b, const int64_t *mask, int32_t *outc, hipStream_t s) {
     // few blocks: each ends with five atomics on the same five words
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 256));
-    hipLaunchKernelGGL(k_max2, dim3((unsigned)blocks), dim3(256), 0, s, n, a, b, mask, out5);
+    hipLaunchKernelGGL(k_max2, dim3((unsigned)blocks), dim3(256), 0, s, n, a, b, mask, outc);
 }
 
 __global__ __launch_bounds__(64) void backward_kernel(BwdArgs a) {

@@ -67,8 +67,8 @@ struct MatPlan {
     double *valM = nullptr;
     int64_t capM = 0;
     int64_t nnzM = -1;
-    int64_t *summary = nullptr;  // device: nnz(M), error flags, failed-column counts; [8..10] the
-                                 // adjoint's size maxima (five int32) when the factors are kept
+    int64_t *summary = nullptr;  // device: nnz(M), error flags, failed-column counts; from [8] the
+                                 // copies of the adjoint's size maxima (int32) when factors are kept
     int32_t maxq = -1, maxm = -1;  // largest final |J_k| and |I_k| (first backward)
     int32_t nofac = -1;            // columns without a kept factor
     int32_t maxq_nofac = -1;       // their largest |J_k|
@@ -353,7 +353,7 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
             // entries of M: at most qmid per column, and up to qlast for the columns the
             // dense class finishes (no more than its record capacity)
             M.capM = n * qmid + std::min<int64_t>(n, big_cap) * (qlast - qmid);
-            M.summary = L.take<int64_t>(12);
+            M.summary = L.take<int64_t>(8 + 5 * MAX2_COPIES / 2);
             M.colptrM = L.take<int64_t>(n + 1);
             M.rowidxM = L.take<int32_t>(M.capM);
             M.valM = L.take<double>(M.capM);
@@ -732,8 +732,8 @@ rsai_status rsai_plan_nnz(const rsai_plan *Pc, int32_t mat, int64_t *nnzM) {
     MatPlan &M = P->mats[mat];
     if (M.nnzM < 0) {
         const int64_t n = M.A.n;
-        int64_t h[12] = {};
-        launch_fill_i64(M.summary, 0, 12, P->stream);
+        int64_t h[8 + 5 * MAX2_COPIES / 2] = {};
+        launch_fill_i64(M.summary, 0, 8 + 5 * MAX2_COPIES / 2, P->stream);
         launch_summary(n, M.colptrM, P->out.status + M.col_base, P->err, M.summary, P->stream);
         // with kept factors the adjoint's size maxima come back in the same copy
         const bool sizes = P->out.foff != nullptr && M.maxq < 0;
@@ -743,8 +743,9 @@ rsai_status rsai_plan_nnz(const rsai_plan *Pc, int32_t mat, int64_t *nnzM) {
         HIPCHK(hipMemcpyAsync(h, M.summary, sizeof(h), hipMemcpyDeviceToHost, P->stream));
         HIPCHK(hipStreamSynchronize(P->stream));
         if (sizes) {
-            int32_t h2[5];
-            std::memcpy(h2, h + 8, sizeof(h2));
+            int32_t hc[5 * MAX2_COPIES], h2[5];
+            std::memcpy(hc, h + 8, sizeof(hc));
+            max2_combine(hc, h2);
             M.maxq = h2[0];
             M.maxm = h2[1];
             M.nofac = h2[2];
@@ -1116,13 +1117,14 @@ rsai_status rsai_backward(rsai_plan *P, int32_t mat, const double *dM_val, doubl
     if (M.maxq < 0) {
         // largest |J_k|; for the columns without a kept factor their largest |I_k|,
         // count and largest |J_k|; columns with a factor and |J_k| > 32
-        int32_t *d2 = P->alloc<int32_t>(5, st);
+        int32_t *d2 = P->alloc<int32_t>(5 * MAX2_COPIES, st);
         if (st != RSAI_OK) return st;
-        int32_t h2[5] = {0, 0, 0, 0, 0};
-        launch_fill_i32(d2, 0, 5, P->stream);
+        int32_t hc[5 * MAX2_COPIES] = {}, h2[5];
+        launch_fill_i32(d2, 0, 5 * MAX2_COPIES, P->stream);
         launch_max2(M.A.n, P->out.nJ + M.col_base, P->out.nI + M.col_base, foff, d2, P->stream);
-        HIPCHK(hipMemcpyAsync(h2, d2, sizeof(h2), hipMemcpyDeviceToHost, P->stream));
+        HIPCHK(hipMemcpyAsync(hc, d2, sizeof(hc), hipMemcpyDeviceToHost, P->stream));
         HIPCHK(hipStreamSynchronize(P->stream));
+        max2_combine(hc, h2);
         M.maxq = h2[0];
         M.maxm = h2[1];
         M.nofac = h2[2];

@@ -177,7 +177,11 @@ int backward_max_rows();
 int backward_factored_max_cols();
 // out2[0] = max a; out2[1] = max b over the entries with mask < 0 (all if mask is null);
 // out2[2] = number of those entries
-void launch_max2(int64_t n, const int32_t *a, const int32_t *b, const int64_t *mask, int32_t *out5, hipStream_t s);
+// the adjoint's size maxima: outc holds MAX2_COPIES copies of five int32 (zeroed by the
+// caller); max2_combine folds a host copy of them into the five values
+constexpr int MAX2_COPIES = 32;
+void launch_max2(int64_t n, const int32_t *a, const int32_t *b, const int64_t *mask, int32_t *outc, hipStream_t s);
+void max2_combine(const int32_t *h, int32_t *out5);
 // FP64 FMA throughput probe (256-thread blocks, fma_probe_chains() chains per lane)
 int fma_probe_chains();
 void launch_fma_probe(int blocks, int64_t iters, double *out, hipStream_t s);
