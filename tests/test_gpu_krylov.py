@@ -216,3 +216,29 @@ def test_left_rejects_mismatched_matrix():
     other = rsai.Matrix.from_host(gen.cd2d(20, seed=1), "cuda:0")
     with pytest.raises(rsai.RSAIError):
         rsai.bicgstab_left(other, plan, torch.ones(other.n, dtype=torch.float64, device="cuda:0"))
+
+
+def test_transpose_row_length_boundaries():
+    """Rows of 1, 15, 16, 17, 31, 32, 33 and 64 entries (the row sort's one-entry-per-
+    lane, two-entries-per-lane and single-lane paths and their boundaries) come out
+    sorted and complete; y = A x through those rows agrees with the host product."""
+    import torch
+    import paper_1503_04500_amd.rsai as rsai
+    n = 96
+    rng = np.random.default_rng(17)
+    rows, cols, vals = list(range(n)), list(range(n)), list(4.0 + rng.random(n))
+    for i, L in zip(range(8), (1, 15, 16, 17, 31, 32, 33, 64)):
+        extra = rng.choice(np.setdiff1d(np.arange(n), [i]), L - 1, replace=False)
+        rows += [i] * (L - 1)
+        cols += list(extra)
+        vals += list(rng.standard_normal(L - 1))
+    A = gen.from_coo(n, np.array(rows), np.array(cols), np.array(vals))
+    T = rsai.Matrix.from_host(A, "cuda:0").transpose()
+    H = _host_transpose(A)
+    assert np.array_equal(T.colptr.cpu().numpy(), H.colptr)
+    assert np.array_equal(T.rowidx.cpu().numpy(), H.rowidx)
+    assert np.array_equal(T.val.cpu().numpy(), H.val)
+    x = rng.standard_normal(n)
+    y = rsai.spmv(rsai.Matrix.from_host(A, "cuda:0"), torch.from_numpy(x).cuda()).cpu().numpy()
+    want = A.matvec(x)
+    assert np.abs(y - want).max() <= 1e-13 * np.abs(want).max()
