@@ -445,17 +445,41 @@ void launch_sort_rows(int64_t n, const int64_t *rowptr, int32_t *colidx, double 
     hipLaunchKernelGGL(k_sort_rows, dim3(nblocks(n * SORT_G, 256)), dim3(256), 0, s, n, rowptr, colidx, val);
 }
 
-__global__ void k_csr_spmv(int64_t n, const int64_t *rowptr, const int32_t *colidx, const double *val,
-                           const double *x, double *y) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        double s = 0.0;
-        for (int64_t e = rowptr[i]; e < rowptr[i + 1]; ++e) s += val[e] * x[colidx[e]];
-        y[i] = s;
+// y = A x by rows, each row summed in ascending column order by one thread. A block's
+// 256 rows occupy one contiguous range of entries: when it fits, the range's values
+// and gathered x are staged in LDS with contiguous loads first, and the rows summed
+// from there (the same products and additions in the same order).
+constexpr int SPMV_ROWS = 256, SPMV_STAGE = 3072;
+__global__ __launch_bounds__(SPMV_ROWS) void k_csr_spmv(int64_t n, const int64_t *rowptr, const int32_t *colidx,
+                                                       const double *val, const double *x, double *y) {
+    __shared__ double sv[SPMV_STAGE], sx[SPMV_STAGE];
+    for (int64_t r0 = blockIdx.x * (int64_t)SPMV_ROWS; r0 < n; r0 += (int64_t)gridDim.x * SPMV_ROWS) {
+        const int64_t r1 = r0 + SPMV_ROWS < n ? r0 + SPMV_ROWS : n;
+        const int64_t e0 = rowptr[r0], ne = rowptr[r1] - e0;
+        const bool staged = ne <= SPMV_STAGE;  // uniform over the block
+        if (staged)
+            for (int64_t t = threadIdx.x; t < ne; t += SPMV_ROWS) {
+                sv[t] = val[e0 + t];
+                sx[t] = x[colidx[e0 + t]];
+            }
+        __syncthreads();
+        const int64_t i = r0 + threadIdx.x;
+        if (i < r1) {
+            double s = 0.0;
+            const int64_t b = rowptr[i], e = rowptr[i + 1];
+            if (staged) {
+                for (int64_t k = b - e0; k < e - e0; ++k) s += sv[k] * sx[k];
+            } else {
+                for (int64_t k = b; k < e; ++k) s += val[k] * x[colidx[k]];
+            }
+            y[i] = s;
+        }
+        __syncthreads();  // the next range reuses the staging arrays
     }
 }
 void launch_csr_spmv(int64_t n, const int64_t *rowptr, const int32_t *colidx, const double *val, const double *x,
                      double *y, hipStream_t s) {
-    hipLaunchKernelGGL(k_csr_spmv, dim3(nblocks(n, 256)), dim3(256), 0, s, n, rowptr, colidx, val, x, y);
+    hipLaunchKernelGGL(k_csr_spmv, dim3(nblocks(n, SPMV_ROWS)), dim3(SPMV_ROWS), 0, s, n, rowptr, colidx, val, x, y);
 }
 
 // y = A^T x for CSC A: y_j = sum_i a_ij x_i (a column dot product)
