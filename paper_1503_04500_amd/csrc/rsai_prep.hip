@@ -482,19 +482,15 @@ void launch_csr_spmv(int64_t n, const int64_t *rowptr, const int32_t *colidx, co
     hipLaunchKernelGGL(k_csr_spmv, dim3(nblocks(n, SPMV_ROWS)), dim3(SPMV_ROWS), 0, s, n, rowptr, colidx, val, x, y);
 }
 
-// y = A^T x for CSC A: y_j = sum_i a_ij x_i (a column dot product)
-__global__ void k_csc_spmv_t(int64_t n, const int64_t *colptr, const int32_t *rowidx, const double *val,
-                             const double *x, double *y) {
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-        double s = 0.0;
-        for (int64_t e = colptr[j]; e < colptr[j + 1]; ++e) s += val[e] * x[rowidx[e]];
-        y[j] = s;
-    }
-}
+// y = A^T x for CSC A: y_j = sum_i a_ij x_i, a column dot product in ascending row
+// order; the columns of A in CSC are the rows of A^T in CSR, so the staged row kernel
+// serves unchanged
 void launch_csc_spmv_t(int64_t n, const int64_t *colptr, const int32_t *rowidx, const double *val, const double *x,
                        double *y, hipStream_t s) {
-    hipLaunchKernelGGL(k_csc_spmv_t, dim3(nblocks(n, 256)), dim3(256), 0, s, n, colptr, rowidx, val, x, y);
+    launch_csr_spmv(n, colptr, rowidx, val, x, y, s);
 }
+
+
 
 // dval[e] += dy[row(e)] * x[col(e)]: a group of VG lanes per column walks its entries
 // side by side (contiguous loads); every entry is updated by exactly one lane
