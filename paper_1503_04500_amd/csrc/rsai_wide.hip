@@ -20,6 +20,7 @@
 // Columns arrive as spill records of the previous class. A column whose |I_k| or
 // compressed block outgrows this class moves on to the next one.
 #include <climits>
+#include <type_traits>
 
 #include "rsai_kernels.h"
 
@@ -448,11 +449,14 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
                 if (wid == 0) {
                     bool singular = false;
                     constexpr int SU = 8;
-                    if (nsh <= SU) {
-                        // Few shared rows: lane c keeps the shared-row entries of column c in
-                        // registers; the reflector of step j is read from lane j. Row j of
-                        // column c > j is zero before step j, except the right-hand side of
-                        // the collapsed row of the column where k is private.
+                    // Few shared rows: lane c keeps the shared-row entries of column c in
+                    // registers; the reflector of step j is read from lane j. Row j of
+                    // column c > j is zero before step j, except the right-hand side of
+                    // the collapsed row of the column where k is private. SU slots: 4 when
+                    // the column set has at most 4 shared rows (the common case), else 8;
+                    // the slots past nsh hold zeros, so both give the same numbers.
+                    auto qr_regs = [&](auto ns) {
+                        constexpr int SU = decltype(ns)::value;
                         double b[SU];
 #pragma unroll
                         for (int t = 0; t < SU; ++t) b[t] = (lane <= q && t < nsh) ? S.blk[(q + t) * ld + lane] : 0.0;
@@ -496,6 +500,11 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
                         for (int t = 0; t < SU; ++t) r2 += b[t] * b[t];
                         r2 = readlane_f64(r2, q);
                         if (lane == 0) S.rn = sqrt(r2 + kconst);
+                    };
+                    if (nsh <= 4) {
+                        qr_regs(std::integral_constant<int, 4>{});
+                    } else if (nsh <= SU) {
+                        qr_regs(std::integral_constant<int, SU>{});
                     } else {
                     for (int j = 0; j < q; ++j) {
                         // the reflector's entries (row j and the first shared rows) and this
