@@ -62,6 +62,8 @@ def _load():
     lib.oracle_bicgstab.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _D, _I32, _P, _P]
     lib.oracle_bicgstab_left.restype = _I32
     lib.oracle_bicgstab_left.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _D, _I32, _P, _P]
+    lib.oracle_model_solve_flops.restype = _D
+    lib.oracle_model_solve_flops.argtypes = [_I32, _I32, _I32, _I32]
     _lib = lib
     return lib
 
@@ -123,6 +125,12 @@ def rsai(A, c: int = 3, lmax: int = 8, eps: float = 0.4, drop: int = DROP_FIXED,
         return out
     finally:
         lib.oracle_free(h)
+
+
+def model_solve_flops(m0: int, m: int, qlo: int, qn: int) -> float:
+    """The QR-update work model of one LS solve: a factor of qlo columns formed on m0
+    rows is kept and the block grows to m rows and qn columns (qlo = 0: from scratch)."""
+    return float(_load().oracle_model_solve_flops(int(m0), int(m), int(qlo), int(qn)))
 
 
 def fixed_pattern(A, Mcolptr, Mrowidx, threads: int = 0):

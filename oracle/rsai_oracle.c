@@ -254,17 +254,21 @@ typedef struct {
 } oparams;
 
 /*
- * Flop count of one LS solve done as a Householder QR *update*: the factor of the
- * first qlo columns (m rows) is kept, the qn - qlo new columns are brought in by
- * applying the qlo stored reflectors, then reflectors qlo..qn-1 are formed and
- * applied to the trailing columns and to Q^T e; then back substitution and the
- * residual norm ||(Q^T e)(qn:m)||. qlo = 0 is a from-scratch QR. This is the
- * algorithmic work model of the method (Algorithm 1, step 7), not the oracle's own
- * from-scratch arithmetic.
+ * Flop count of one LS solve done as a Householder QR *update* (Algorithm 1, step 7,
+ * with the column/row append of (3.1)): the factor of the first qlo columns was made
+ * on m0 rows and is kept; the augmented block has m rows and qn columns. The rows
+ * added since (I-hat) are zero in the old columns, so each stored reflector j < qlo
+ * acts on rows j..m0-1 of the qn - qlo new columns only (a dot product and an update,
+ * 4 (m0 - j) flops per column). Reflectors qlo..qn-1 are then formed on rows j..m-1
+ * (norm 2 (m - j)) and applied to the qn - j - 1 later columns and to Q^T e
+ * (4 (m - j) each); back substitution costs qn^2 and the residual norm
+ * ||(Q^T e)(qn:m)|| 2 (m - qn). qlo = 0 is a from-scratch QR (m0 unused). This is
+ * the algorithmic work model of the method, not the oracle's own from-scratch
+ * arithmetic.
  */
-static double model_solve_flops(int m, int qlo, int qn) {
+static double model_solve_flops(int m0, int m, int qlo, int qn) {
     double f = 0.0;
-    for (int j = 0; j < qlo; ++j) f += 4.0 * (double)(m - j) * (double)(qn - qlo);
+    for (int j = 0; j < qlo; ++j) f += 4.0 * (double)(m0 - j) * (double)(qn - qlo);
     for (int j = qlo; j < qn; ++j)
         f += 2.0 * (double)(m - j) + 4.0 * (double)(m - j) * (double)(qn - j - 1) + 4.0 * (double)(m - j);
     f += (double)qn * (double)qn + 2.0 * (double)(m - qn);
@@ -292,7 +296,7 @@ static int drop_step(const omat *A, int32_t k, const oparams *p, work *w, double
     memcpy(w->J.a, w->keep.a, sizeof(int32_t) * (size_t)w->keep.n);
     w->J.n = w->keep.n;
     *ndrop += 1;
-    *mflops += model_solve_flops(w->I.n, 0, w->J.n);
+    *mflops += model_solve_flops(0, w->I.n, 0, w->J.n);
     return ls_solve(A, k, w, resnorm, flops);
 }
 
@@ -321,7 +325,7 @@ static void rsai_column(const omat *A, int32_t k, const oparams *p, work *w, col
     int l = 0;
     int32_t nImax = w->I.n, nJmax = w->J.n;
     status = ls_solve(A, k, w, &rn, &flops);
-    mflops += model_solve_flops(w->I.n, 0, 1);
+    mflops += model_solve_flops(0, w->I.n, 0, 1);
     if (status == OR_OK) status = drop_step(A, k, p, w, &rn, &flops, &drop_margin, &ndrop, &mflops);
     if (hist && nsolve < hist_len) hist[nsolve] = rn;
     ++nsolve;
@@ -394,7 +398,7 @@ static void rsai_column(const omat *A, int32_t k, const oparams *p, work *w, col
         }
         iv_sort_unique(&w->tmp);
         set_minus(&w->tmp, &w->I, &w->Ihat);
-        int qprev = w->J.n;
+        int qprev = w->J.n, mprev = w->I.n;
         {
             ivec scratch = {0, 0, 0};
             set_union_into(&w->J, &w->Jhat, &scratch);
@@ -405,7 +409,7 @@ static void rsai_column(const omat *A, int32_t k, const oparams *p, work *w, col
         if (w->J.n > nJmax) nJmax = w->J.n;
         /* step 7: new LS solution and residual on the augmented pattern */
         status = ls_solve(A, k, w, &rn, &flops);
-        mflops += model_solve_flops(w->I.n, qprev, w->J.n);
+        mflops += model_solve_flops(mprev, w->I.n, qprev, w->J.n);
         if (status == OR_OK) status = drop_step(A, k, p, w, &rn, &flops, &drop_margin, &ndrop, &mflops);
         if (hist && nsolve < hist_len) hist[nsolve] = rn;
         ++nsolve;
@@ -518,6 +522,11 @@ void *oracle_rsai(int64_t n, const int64_t *colptr, const int32_t *rowidx, const
     free(A.rowptr);
     free(A.colidx);
     return R;
+}
+
+/* The QR-update work model of one LS solve (see model_solve_flops), for tests. */
+double oracle_model_solve_flops(int32_t m0, int32_t m, int32_t qlo, int32_t qn) {
+    return model_solve_flops(m0, m, qlo, qn);
 }
 
 int64_t oracle_nnz(void *h) { return ((oresult *)h)->nnz; }

@@ -41,19 +41,25 @@ def test_params_route_field():
 
 def test_bench_traffic_requires_matching_kernel_sources(tmp_path, monkeypatch):
     """bench.py reports the counter-derived HBM traffic only while the tier kernel's
-    sources hash to the value recorded beside the counters."""
+    sources hash to the value recorded beside the counters (a profile written for the
+    current sources is read; a change to a source invalidates it)."""
+    import hashlib
     import shutil
     import bench
     root = tmp_path
     (root / "profiles").mkdir()
     (root / "paper_1503_04500_amd" / "csrc").mkdir(parents=True)
     src = os.path.join(bench.ROOT, "paper_1503_04500_amd", "csrc")
+    h = hashlib.sha256()
     for f in ("rsai_tier.hip", "rsai_tier_kernel.h", "rsai_tier.h", "rsai_dev.h"):
         shutil.copy(os.path.join(src, f), root / "paper_1503_04500_amd" / "csrc" / f)
-    shutil.copy(os.path.join(bench.ROOT, "profiles", "tier_kernel_cd2d512_pmc.md"), root / "profiles")
+        with open(os.path.join(src, f), "rb") as fh:
+            h.update(fh.read())
+    with open(root / "profiles" / "tier_kernel_cd2d512_pmc.md", "w") as f:
+        f.write("# counters\n\n    kernel: tier_kernel\n    kernel_source_sha256: %s\n"
+                "    traffic_bytes_per_launch: 12345\n" % h.hexdigest())
     monkeypatch.setattr(bench, "ROOT", str(root))
-    got = bench.measured_traffic()
-    assert got is not None and got > 0
+    assert bench.measured_traffic() == 12345.0
     with open(root / "paper_1503_04500_amd" / "csrc" / "rsai_tier.hip", "a") as f:
         f.write("\n// changed\n")
     assert bench.measured_traffic() is None
