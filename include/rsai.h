@@ -126,9 +126,13 @@ typedef struct {
 rsai_status rsai_autotune(const rsai_csc *A, const rsai_params *p, int32_t reps, void *stream,
                           rsai_tune_choice *out, int32_t cap, int32_t *count, int32_t *best);
 
-/* Build M for one matrix. Queues all work on stream; with p->validate = 1 it first
-   synchronises once to check the CSC contract (RSAI_E_CSC on violation); with
-   p->validate = 0 or 2 it does not synchronise at all. */
+/* Build M for one matrix: every column m_k minimises ||A m_k - e_k||_2 (eqs. (2.1)-(2.2))
+   over its pattern J_k, solved as the reduced LS problem (2.3) on the rows I_k, with J_k
+   grown by Algorithm 1 (Section 3) and pruned by the dropping of Section 4 (fixed tol, or
+   the adaptive tolerance of eq. (4.3)). Queues all work on stream; with p->validate = 1
+   it first synchronises once to check the CSC contract (RSAI_E_CSC on violation); with
+   p->validate = 0 or 2 it does not synchronise at all. On success *out owns every
+   device buffer of the build (released by rsai_destroy); A stays borrowed. */
 rsai_status rsai_build(const rsai_csc *A, const rsai_params *p, void *stream, rsai_plan **out);
 
 /* Build M for count matrices in one pass: the columns of all matrices share the
@@ -150,12 +154,16 @@ rsai_status rsai_rebuild(rsai_plan *P, int32_t use_graph, void *stream);
 /* Number of matrices in a plan. */
 rsai_status rsai_plan_count(const rsai_plan *P, int32_t *count);
 
-/* nnz(M) of matrix mat (host output). Synchronises the build stream. Returns
-   RSAI_E_SINGULAR / RSAI_E_CAP if any column of the plan failed. */
+/* nnz(M) = sum_k |J_k| of matrix mat (host output; M = (m_1, ..., m_n), eq. (2.2)).
+   Synchronises the build stream. Returns RSAI_E_SINGULAR (a column's LS problem (2.3)
+   is rank deficient) / RSAI_E_CAP (a column outgrew the supported LS sizes) if any
+   column of the plan failed, RSAI_E_CSC with validate = 2 on a malformed input. */
 rsai_status rsai_plan_nnz(const rsai_plan *P, int32_t mat, int64_t *nnzM);
 
-/* Write M of matrix mat as CSC (rows ascending per column) into caller buffers:
-   colptr[n+1], rowidx[nnzM], val[nnzM]. */
+/* Write M = (m_1, ..., m_n) of matrix mat (eq. (2.2)) as CSC into caller device
+   buffers: int64 colptr[n+1], int32 rowidx[nnzM] (row indices of column k = J_k,
+   ascending), float64 val[nnzM] (the LS solution of (2.3) on that pattern). nnzM comes
+   from rsai_plan_nnz; the same errors. Stream-ordered copies on stream. */
 rsai_status rsai_export_M(const rsai_plan *P, int32_t mat, int64_t *colptr, int32_t *rowidx, double *val,
                           void *stream);
 
@@ -166,7 +174,11 @@ rsai_status rsai_export_M(const rsai_plan *P, int32_t mat, int64_t *colptr, int3
 rsai_status rsai_export_stats(const rsai_plan *P, int32_t mat, int32_t *loops, double *resnorm, int32_t *nI,
                               int32_t *nJ, double *flops, int32_t *status, void *stream);
 
-/* y = M x for matrix mat (x, y device arrays of n doubles). */
+/* y = M x for matrix mat: the application of the right preconditioner of eq. (1.2)
+   (A M y = b, x = M y). x, y: device arrays of n doubles, distinct. The rows of M are
+   formed once per build (one host synchronisation on the first call after a build);
+   each row is summed in ascending column order. Errors of rsai_plan_nnz,
+   RSAI_E_ARG on NULL vectors, RSAI_E_NOMEM. */
 rsai_status rsai_apply(const rsai_plan *P, int32_t mat, const double *x, double *y, void *stream);
 
 /* Adjoint of the fixed-pattern LS map A -> M (pattern of M fixed, values from (2.3)):
@@ -174,9 +186,9 @@ rsai_status rsai_apply(const rsai_plan *P, int32_t mat, const double *x, double 
    the structural nonzeros of A. dM_val (nnzM entries, CSC order of rsai_export_M)
    may be NULL. dA_val has nnz(A) entries and is accumulated into. Columns whose R
    factor the build kept (keep_factors) are solved on it; the others re-gather and
-   refactorise A(I_k, J_k). Columns with |J_k| > 32, or without a kept factor and
-   |I_k| > 64, are not supported: RSAI_E_CAP (checked before any accumulation, one
-   host synchronisation on the first call of a plan). */
+   refactorise A(I_k, J_k). Limits: |J_k| <= 128 on a kept factor; |J_k| <= 32 and
+   |I_k| <= 64 for a column that is refactorised; beyond them RSAI_E_CAP (checked
+   before any accumulation, one host synchronisation on the first call of a plan). */
 rsai_status rsai_backward(rsai_plan *P, int32_t mat, const double *dM_val, double w_frob, double *dA_val,
                           void *stream);
 

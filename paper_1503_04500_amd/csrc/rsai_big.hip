@@ -316,12 +316,13 @@ __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
         bool first = true;       // the stored pattern has no factor here yet
         bool need_solve = true;
         bool dropok = false;
-        int qmod = -1;
+        int qmod = -1, mmod = 0;
         int p_fresh = 0;
         if (rec[10] & 2) {
             // augmented pattern handed over before its solve
             dropok = (rec[10] & 4) != 0;
             qmod = rec[11];
+            mmod = rec[12];
         }
         if (status == ST_OK && q == 0 && nRh == 0) {
             // a column whose own rows exceed the register tiers: J = {k}, loop 0
@@ -374,6 +375,7 @@ __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
                 else need_solve = true;
                 dropok = (p > 0);
                 qmod = (p > 0) ? q : (first ? -1 : q);
+                mmod = m;
             }
             // ================= I-hat: rows of the new columns (step 5)
             if (need_solve && p > 0) {
@@ -556,7 +558,7 @@ __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
                 for (int i = qn + tid; i < m; i += NT) s += y[i] * y[i];
                 s = bsum(s, S);
                 rn = sqrt(s + (kidx < 0 ? 1.0 : 0.0));
-                if (qmod >= 0) fl += solve_flops(m, qmod, qn);
+                if (qmod >= 0) fl += solve_flops(mmod, m, qmod, qn);
                 // ---- dropping (Section 4), after the augment solve only
                 if (pass_drop == 0 && dropok && P.drop != DROP_NONE) {
                     const double t = (P.drop == DROP_FIXED)

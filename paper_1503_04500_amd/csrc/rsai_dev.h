@@ -277,15 +277,18 @@ constexpr int ilog2ceil(int x) {
     return l;
 }
 
-// Algorithmic flops of one Householder-update LS solve: qlo kept columns, qn - qlo
-// new ones, m rows (update of the new columns by the stored reflectors, new
-// reflectors applied to the trailing columns and to Q^T e, back substitution and
-// the residual norm ||(Q^T e)(qn:m)||).
-__host__ __device__ inline double solve_flops(int m, int qlo, int qn) {
+// Algorithmic flops of one Householder-update LS solve (Algorithm 1, step 7): the
+// factor of the first qlo columns was formed on m0 rows and is kept; the block now
+// has m rows and qn columns. The rows added since are zero in the old columns, so
+// stored reflector j < qlo updates the qn - qlo new columns over rows j..m0-1 only
+// (4 (m0 - j) per column); reflectors qlo..qn-1 cost their norm 2 (m - j) and
+// 4 (m - j) for each later column and for Q^T e; then back substitution (qn^2) and
+// the residual norm ||(Q^T e)(qn:m)|| (2 (m - qn)). qlo = 0: from scratch.
+__host__ __device__ inline double solve_flops(int m0, int m, int qlo, int qn) {
     double f = 0.0;
     double p = (double)(qn - qlo);
-    // sum_{j<qlo} 4 (m-j) p
-    f += 4.0 * p * ((double)qlo * m - 0.5 * (double)qlo * (qlo - 1));
+    // sum_{j<qlo} 4 (m0-j) p
+    f += 4.0 * p * ((double)qlo * m0 - 0.5 * (double)qlo * (qlo - 1));
     for (int j = qlo; j < qn; ++j) {
         double mj = (double)(m - j);
         f += mj * (2.0 + 4.0 * (double)(qn - j - 1) + 4.0);

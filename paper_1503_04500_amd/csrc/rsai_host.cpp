@@ -56,6 +56,16 @@ void dev_free(void *p, hipStream_t s) {
 
 }  // namespace
 
+rsai_status rsai::report(rsai_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
 struct MatPlan {
     rsai_csc A{};
     int64_t col_base = 0;
@@ -169,6 +179,22 @@ struct Layout {
         return base ? reinterpret_cast<T *>(base + a) : nullptr;
     }
 };
+
+// rows of a CSC matrix with values, each row sorted by column so that row sums have a
+// fixed order
+namespace rsai {
+void enqueue_rows(int64_t n, int64_t nnz, const int64_t *colptr, const int32_t *rowidx, const double *val,
+                  int64_t *rp, int32_t *ci, double *vv, int32_t *cnt, int32_t *fill, int64_t *stmp, int32_t *zerr,
+                  hipStream_t s) {
+    launch_fill_i32(zerr, 0, 4, s);
+    launch_fill_i32(cnt, 0, n, s);
+    launch_fill_i32(fill, 0, n, s);
+    launch_row_counts(nnz, rowidx, cnt, zerr, s);
+    launch_scan_i32(cnt, n, rp, stmp, s);
+    launch_csc_transpose_fill(n, colptr, rowidx, val, rp, fill, ci, vv, s);
+    launch_sort_rows(n, rp, ci, vv, s);
+}
+}  // namespace rsai
 
 extern "C" {
 
@@ -542,7 +568,10 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
                     a.q_qmax[i] = c <= tlast ? kTiers[c].QMAX : WIDE_QMAX;
                 }
                 const int gpw = 64 / kTiers[t].G;
-                int64_t want = (t == t0) ? (ncols + gpw - 1) / gpw : (int64_t)cus * 2;
+                // a later tier gets as many persistent waves as its register budget lets
+                // every SIMD hold (4 SIMDs per CU): when most columns outgrow the first
+                // tier (small eps), the later tier carries the build
+                int64_t want = (t == t0) ? (ncols + gpw - 1) / gpw : (int64_t)cus * 4 * kTiers[t].WPS;
                 int waves = (int)std::max<int64_t>(8, std::min<int64_t>(want, (int64_t)cus * 16));
                 waves = (waves + 7) / 8 * 8;
                 launch_tier_kernel(t, a, waves, s);
@@ -840,18 +869,10 @@ rsai_status rsai_apply(const rsai_plan *Pc, int32_t mat, const double *x, double
     return RSAI_OK;
 }
 
-// rows of a CSC matrix with values, each row sorted by column so that row sums have a
-// fixed order. Work buffers: cnt, fill (n each), stmp (scan_tmp_elems(n + 1)), zerr (4).
+
 static void enqueue_rows(const rsai_csc *A, int64_t *rp, int32_t *ci, double *vv, int32_t *cnt, int32_t *fill,
                          int64_t *stmp, int32_t *zerr, hipStream_t s) {
-    const int64_t n = A->n, nnz = A->nnz;
-    launch_fill_i32(zerr, 0, 4, s);
-    launch_fill_i32(cnt, 0, n, s);
-    launch_fill_i32(fill, 0, n, s);
-    launch_row_counts(nnz, A->rowidx, cnt, zerr, s);
-    launch_scan_i32(cnt, n, rp, stmp, s);
-    launch_csc_transpose_fill(n, A->colptr, A->rowidx, A->val, rp, fill, ci, vv, s);
-    launch_sort_rows(n, rp, ci, vv, s);
+    rsai::enqueue_rows(A->n, A->nnz, A->colptr, A->rowidx, A->val, rp, ci, vv, cnt, fill, stmp, zerr, s);
 }
 
 rsai_status rsai_spmv(const rsai_csc *A, const double *x, double *y, int32_t transpose, void *stream) {

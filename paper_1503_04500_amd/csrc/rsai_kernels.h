@@ -4,12 +4,17 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/rsai.h"
 #include "rsai_tier.h"
 
 namespace rsai {
 
+// Set the thread-local message rsai_last_error() returns and return st.
+rsai_status report(rsai_status st, const char *fmt, ...);
+
 struct TierInfo {
     int G, MMAX, QMAX, REC;
+    int WPS;  // waves per SIMD the tier's register budget allows
 };
 extern const TierInfo kTiers[];
 extern const int kNumTiers;
@@ -97,6 +102,12 @@ void launch_csc_transpose_fill(int64_t n, const int64_t *colptr, const int32_t *
                                const int64_t *rowptr, int32_t *fillpos, int32_t *colidxT, double *valT,
                                hipStream_t s);
 void launch_sort_rows(int64_t n, const int64_t *rowptr, int32_t *colidx, double *val, hipStream_t s);
+// rows of a CSC matrix (n, nnz, colptr, rowidx, val) with values, each row sorted by
+// column so that row sums have a fixed order. Work buffers: cnt, fill (n each), stmp
+// (scan_tmp_elems(n + 1)), zerr (4); every one is cleared by a kernel first.
+void enqueue_rows(int64_t n, int64_t nnz, const int64_t *colptr, const int32_t *rowidx, const double *val,
+                  int64_t *rp, int32_t *ci, double *vv, int32_t *cnt, int32_t *fill, int64_t *stmp, int32_t *zerr,
+                  hipStream_t s);
 // ---- right-preconditioned BiCGStab (rsai_krylov.hip)
 struct BicgState {
     double rho, rho1, rho1n, alpha, omega, rel, nb, tol;

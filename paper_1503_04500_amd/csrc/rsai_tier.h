@@ -25,8 +25,9 @@ namespace rsai {
 // [3] l, [4] q, [5] m, [6] nR, [7] nRh, [8..9] flop count (double bits), [10] flags:
 // bit 0 l is still to be advanced when the pending rows form J-hat, bit 1 the stored
 // pattern is augmented but not yet solved, bit 2 dropping applies to that solve;
-// [11] kept columns of the flop model of that solve.
-constexpr int RHDR = 12;
+// [11] kept columns of the flop model of that solve, [12] the rows its kept factor
+// was formed on.
+constexpr int RHDR = 13;
 
 template <int G_, int RPL_, int QMAX_, int STAGE_, int HSF_ = 2, int WPS_ = 2>
 struct TierCfg {

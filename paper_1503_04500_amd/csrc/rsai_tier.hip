@@ -4,9 +4,9 @@
 namespace rsai {
 
 const TierInfo kTiers[] = {
-    {Tier0::G, Tier0::MMAX, Tier0::QMAX, Tier0::REC},
-    {Tier1::G, Tier1::MMAX, Tier1::QMAX, Tier1::REC},
-    {Tier2::G, Tier2::MMAX, Tier2::QMAX, Tier2::REC},
+    {Tier0::G, Tier0::MMAX, Tier0::QMAX, Tier0::REC, Tier0::WPS},
+    {Tier1::G, Tier1::MMAX, Tier1::QMAX, Tier1::REC, Tier1::WPS},
+    {Tier2::G, Tier2::MMAX, Tier2::QMAX, Tier2::REC, Tier2::WPS},
 };
 const int kNumTiers = 3;
 const int kPlainTier = 1;

@@ -50,6 +50,7 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
     int mat = 0, k = 0;
     int q = 0, m = 0, l = 0, p = 0, qlo = 0;
     int qmod = 0;             // kept columns for the flop model of the next solve
+    int mmod = 0;             // rows the kept factor of that model was formed on
     int kidx = -1;            // local row of k in I, or -1
     bool kR = false;          // k used as a dominant row while k is not in I
     int nRh = 0;
@@ -274,6 +275,7 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
                         solve = (p > 0);
                         qlo = q;
                         qmod = q;
+                        mmod = m;
                         dropok = true;
                     } else if (linc) {
                         // resumed by the plain schedule: the factor is rebuilt from the
@@ -282,6 +284,7 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
                         qlo = 0;
                         dropok = (p > 0);
                         qmod = (p > 0) ? q : -1;
+                        mmod = m;
                     } else {
                         // resumed column: its block is refactored from scratch here, but
                         // the method's work is the update from the stored pattern
@@ -289,6 +292,7 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
                         qlo = 0;
                         dropok = (p > 0);
                         qmod = (p > 0) ? q : -1;
+                        mmod = m;
                     }
                 }
             }
@@ -645,7 +649,7 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
                 s = gsum<G>(s);
                 if (act) {
                     rn = sqrt(s + (kidx < 0 ? 1.0 : 0.0));
-                    if (qmod >= 0) fl += solve_flops(m, qmod, qn);
+                    if (qmod >= 0) fl += solve_flops(mmod, m, qmod, qn);
                     q = qn;
                     p = 0;
                     if (singular) status = ST_SINGULAR;

@@ -171,7 +171,7 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
         const int32_t *RJ = rec + RHDR, *RI = RJ + q, *RR = RI + m, *RHp = RR + nR0;
         int status = ST_OK;
         bool spill = false, pend = false, pend_drop = false;
-        int pend_qmod = -1;
+        int pend_qmod = -1, pend_mmod = 0;
         bool lookup_fail = false;
         double rn = 0.0;
 
@@ -219,12 +219,13 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
         __syncthreads();
 
         bool first = true, need_solve = true, dropok = false;
-        int qmod = -1;
+        int qmod = -1, mmod = 0;
         int p = 0;
         if (rec[10] & 2) {
             // augmented pattern handed over before its solve
             dropok = (rec[10] & 4) != 0;
             qmod = rec[11];
+            mmod = rec[12];
         }
         if (status == ST_OK && q == 0 && nRh == 0) {
             // a column whose own rows exceed the register tiers: J = {k}, loop 0
@@ -291,6 +292,7 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
                 need_solve = !(p == 0 && !first);  // empty J-hat: the loop ends without a solve
                 dropok = (p > 0);
                 qmod = (p > 0) ? q : (first ? -1 : q);
+                mmod = m;
                 __syncthreads();
             }
             // ================= I-hat: rows of the new columns not in I (step 5)
@@ -348,6 +350,7 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
                     pend = true;
                     pend_drop = dropok && pass == 0;
                     pend_qmod = qmod;
+                    pend_mmod = mmod;
                     break;
                 }
                 if (tid < nsh) {
@@ -453,8 +456,10 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
                     // registers; the reflector of step j is read from lane j. Row j of
                     // column c > j is zero before step j, except the right-hand side of
                     // the collapsed row of the column where k is private. SU slots: 4 when
-                    // the column set has at most 4 shared rows (the common case), else 8;
-                    // the slots past nsh hold zeros, so both give the same numbers.
+                    // the column set has at most 4 shared rows (the common case), else 8.
+                    // The slots past nsh hold zeros, but the two instances fuse their
+                    // sums of products differently, so their results agree only to
+                    // rounding level, not bit for bit.
                     auto qr_regs = [&](auto ns) {
                         constexpr int SU = decltype(ns)::value;
                         double b[SU];
@@ -585,7 +590,7 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
                 __syncthreads();
                 if (S.flag) { status = ST_SINGULAR; break; }
                 rn = S.rn;
-                if (qmod >= 0) fl += solve_flops(m, qmod, q);
+                if (qmod >= 0) fl += solve_flops(mmod, m, qmod, q);
                 // ---- dropping (Section 4), after the augment solve only
                 if (pass == 0 && dropok && P.drop != DROP_NONE) {
                     const double th = (P.drop == DROP_FIXED)
@@ -804,6 +809,7 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
                     R[9] = (int32_t)(fb >> 32);
                     R[10] = (linc ? 1 : 0) | (pend ? 2 : 0) | (pend_drop ? 4 : 0);
                     R[11] = pend_qmod;
+                    R[12] = pend_mmod;
                 }
                 __syncthreads();
                 continue;
