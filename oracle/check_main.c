@@ -27,7 +27,7 @@ int64_t oracle_fixed_pattern(int64_t n, const int64_t *colptr, const int32_t *ro
                              int32_t nthreads);
 int64_t oracle_backward(int64_t n, const int64_t *colptr, const int32_t *rowidx, const double *val,
                         const int64_t *Mcolptr, const int32_t *Mrowidx, const double *Mval, const double *gM,
-                        double w_frob, double *dA);
+                        double w_frob, double *dA, double *dA_scale);
 int32_t oracle_bicgstab(int64_t n, const int64_t *colptr, const int32_t *rowidx, const double *val,
                         const int64_t *Mcolptr, const int32_t *Mrowidx, const double *Mval, const double *b,
                         double tol, int32_t maxit, double *x, double *relres);
@@ -92,8 +92,9 @@ int main(int argc, char **argv) {
 
     double *gM = malloc(sizeof(double) * (size_t)(nzm ? nzm : 1));
     double *dA = calloc((size_t)nnz, sizeof(double));
+    double *dAs = calloc((size_t)nnz, sizeof(double));
     for (int64_t e = 0; e < nzm; ++e) gM[e] = 1.0 / (1.0 + (double)(e % 7));
-    const int64_t badb = oracle_backward(n, colptr, rowidx, val, mcp, mri, mv, gM, 0.5, dA);
+    const int64_t badb = oracle_backward(n, colptr, rowidx, val, mcp, mri, mv, gM, 0.5, dA, dAs);
     double sd = 0.0;
     for (int64_t e = 0; e < nnz; ++e) sd += dA[e];
     printf("backward bad %lld sum %.17g\n", (long long)badb, sd);
@@ -107,6 +108,6 @@ int main(int argc, char **argv) {
     printf("bicgstab right %d none %d left %d\n", it, it0, itl);
 
     free(colptr); free(rowidx); free(val); free(mcp); free(mri); free(mv); free(rn); free(nJmax); free(hist);
-    free(mv2); free(rn2); free(gM); free(dA); free(b); free(x);
+    free(mv2); free(rn2); free(gM); free(dA); free(dAs); free(b); free(x);
     return 0;
 }

@@ -57,7 +57,7 @@ def _load():
     lib.oracle_fixed_pattern.restype = _I64
     lib.oracle_fixed_pattern.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _I32]
     lib.oracle_backward.restype = _I64
-    lib.oracle_backward.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _D, _P]
+    lib.oracle_backward.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _D, _P, _P]
     lib.oracle_bicgstab.restype = _I32
     lib.oracle_bicgstab.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _D, _I32, _P, _P]
     lib.oracle_bicgstab_left.restype = _I32
@@ -148,8 +148,10 @@ def fixed_pattern(A, Mcolptr, Mrowidx, threads: int = 0):
     return mval, rn
 
 
-def backward(A, Mcolptr, Mrowidx, Mval, gM=None, w_frob: float = 0.0):
-    """Adjoint of the fixed-pattern LS map: returns dL/d(values of A) (length nnz(A))."""
+def backward(A, Mcolptr, Mrowidx, Mval, gM=None, w_frob: float = 0.0, scale: bool = False):
+    """Adjoint of the fixed-pattern LS map: returns dL/d(values of A) (length nnz(A));
+    with scale=True also, per entry, the sum of the magnitudes of the terms added into
+    it (the yardstick of a per-entry rounding tolerance)."""
     lib = _load()
     cp, ri, va = _csc(A.colptr, A.rowidx, A.val)
     mcp = np.ascontiguousarray(Mcolptr, np.int64)
@@ -157,11 +159,12 @@ def backward(A, Mcolptr, Mrowidx, Mval, gM=None, w_frob: float = 0.0):
     mv = np.ascontiguousarray(Mval, np.float64)
     g = None if gM is None else np.ascontiguousarray(gM, np.float64)
     dA = np.zeros(va.size)
+    sc = np.zeros(va.size) if scale else None
     bad = lib.oracle_backward(int(A.n), _ptr(cp), _ptr(ri), _ptr(va), _ptr(mcp), _ptr(mri), _ptr(mv), _ptr(g),
-                              float(w_frob), _ptr(dA))
+                              float(w_frob), _ptr(dA), _ptr(sc))
     if bad:
         raise ArithmeticError(f"{bad} singular columns")
-    return dA
+    return (dA, sc) if scale else dA
 
 
 def bicgstab(A, b, M=None, tol: float = 1e-8, maxit: int = 1000, left: bool = False):

@@ -629,10 +629,13 @@ int64_t oracle_fixed_pattern(int64_t n, const int64_t *colptr, const int32_t *ro
  * (+=) into dA (length nnz(A)). gM may be NULL (treated as zero).
  * The normal-equation system is solved here by forming A_k^T A_k and using a
  * Cholesky factorisation (an independent route from the QR of the forward solve).
+ * dA_scale (nullable) accumulates, per entry, the magnitudes of the terms summed into
+ * it, sum over contributions of |r_i z_j| + |(A_k z)_i m_j| + 2 w_frob |r_i m_j|: the
+ * size of a rounding error of that entry does not depend on cancellation between them.
  */
 int64_t oracle_backward(int64_t n, const int64_t *colptr, const int32_t *rowidx, const double *val,
                         const int64_t *Mcolptr, const int32_t *Mrowidx, const double *Mval,
-                        const double *gM, double w_frob, double *dA) {
+                        const double *gM, double w_frob, double *dA, double *dA_scale) {
     omat A = {n, colptr, rowidx, val, NULL, NULL, 0.0};
     int64_t bad = 0;
     work w;
@@ -718,6 +721,9 @@ int64_t oracle_backward(int64_t n, const int64_t *colptr, const int32_t *rowidx,
                 int ii = find_sorted(w.I.a, m, A.rowidx[e]);
                 double gr = -(rr.a[ii] * z.a[jj] + Az.a[ii] * mt[jj]) + 2.0 * w_frob * rr.a[ii] * mt[jj];
                 dA[e] += gr;
+                if (dA_scale)
+                    dA_scale[e] += fabs(rr.a[ii] * z.a[jj]) + fabs(Az.a[ii] * mt[jj]) +
+                                   2.0 * fabs(w_frob * rr.a[ii] * mt[jj]);
             }
         }
     }

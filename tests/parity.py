@@ -112,3 +112,30 @@ def compare(A, gpu, ref, check_flops=True, label="", margin_tol=None):
         assert fd.size == 0, (f"{label}: flop model differs at {fd[:5].tolist()}: "
                               f"{gpu['flops'][fd[:5]]} vs {ref['mflops'][fd[:5]]}")
     return dict(max_rel=float(rel.max(initial=0.0)), nnz=int(rcp[-1]))
+
+
+GRAD_RTOL = 1e-10
+
+
+def compare_grad(got, want, scale, label="", rtol=GRAD_RTOL):
+    """Entry-by-entry bar for an adjoint: |got_e - want_e| <= rtol * scale_e, where
+    scale_e is the sum of the magnitudes of the terms the oracle added into entry e
+    (``oracle.backward(..., scale=True)``). The two sides add the same terms in a
+    different order (FP64 atomics on the GPU) and solve for z by different routes (R
+    of a Householder QR vs a Cholesky factor of A_k^T A_k), so an entry's rounding
+    error is a multiple of eps times its own terms, whatever cancellation leaves of
+    them; a small entry is held to its own scale, not to the largest entry's.
+    Returns the largest ratio |got - want| / scale."""
+    got = np.asarray(got)
+    want = np.asarray(want)
+    scale = np.asarray(scale)
+    assert got.shape == want.shape == scale.shape
+    err = np.abs(got - want)
+    zero = scale == 0.0
+    assert np.all(err[zero] == 0.0), f"{label}: nonzero gradient on {int((err[zero] != 0).sum())} untouched entries"
+    ratio = np.zeros_like(err)
+    ratio[~zero] = err[~zero] / scale[~zero]
+    worst = int(np.argmax(ratio)) if ratio.size else 0
+    assert ratio.max(initial=0.0) <= rtol, (f"{label}: entry {worst}: gpu {got[worst]!r} oracle {want[worst]!r} "
+                                            f"scale {scale[worst]:.3e} ratio {ratio[worst]:.3e}")
+    return float(ratio.max(initial=0.0))

@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 from paper_1503_04500_amd import gen
-from tests.parity import run_gpu
+from tests.parity import compare_grad, run_gpu
 
 pytestmark = pytest.mark.gpu
 C1 = dict(c=3, lmax=8, eps=0.4, tol=1e-3)
@@ -48,12 +48,10 @@ def test_backward_kernel_vs_oracle(name, keep):
     # the adjoint part alone, through the C ABI, vs the oracle's adjoint on the GPU's M
     dA = torch.zeros(A.nnz, dtype=torch.float64, device="cuda:0")
     gpu["plan"].backward(torch.from_numpy(gM).cuda(), 1.0, dA)
-    only = oracle.backward(A, gpu["colptr"], gpu["rowidx"], gpu["val"], gM, w_frob=1.0)
+    only, scale = oracle.backward(A, gpu["colptr"], gpu["rowidx"], gpu["val"], gM, w_frob=1.0, scale=True)
     got = dA.cpu().numpy()
-    # normwise: the adjoint sums many contributions per entry (atomics on the GPU,
-    # a different order and a normal-equation solve in the oracle)
-    err = np.abs(got - only).max() / np.abs(only).max()
-    assert err <= 1e-10, err
+    r = compare_grad(got, only, scale, label=f"{name}/{keep}")
+    print(f"{name}/{keep}: max |gpu - oracle| / scale = {r:.2e}")
 
 
 def test_backward_large_columns_need_kept_factors():
@@ -224,7 +222,33 @@ def test_backward_edge_cases_vs_oracle(name):
     gM = 1.0 / (1.0 + (np.arange(gpu["val"].size) % 7))
     dA = torch.zeros(A.nnz, dtype=torch.float64, device="cuda:0")
     gpu["plan"].backward(torch.from_numpy(gM).cuda(), 0.5, dA)
-    want = oracle.backward(A, gpu["colptr"], gpu["rowidx"], gpu["val"], gM, w_frob=0.5)
-    got = dA.cpu().numpy()
-    err = np.abs(got - want).max() / max(np.abs(want).max(), 1e-300)
-    assert err <= 1e-10, err
+    want, scale = oracle.backward(A, gpu["colptr"], gpu["rowidx"], gpu["val"], gM, w_frob=0.5, scale=True)
+    compare_grad(dA.cpu().numpy(), want, scale, label=name)
+
+
+@pytest.mark.parametrize("keep", [True, False])
+def test_backward_c4_full_size_entrywise(keep):
+    """The 3D 64^3 configuration (n = 262144, nnz = 1,810,432) at its own size: the
+    adjoint of the GPU's build (on kept factors, and refactorised), entry by entry
+    against the oracle's adjoint on the same M, with w_frob = 1 and an upstream
+    gradient on every entry of M."""
+    import torch
+    A = gen.c4()
+    assert A.n == 262144 and A.nnz == 1810432
+    fk = dict(keep_factors=True) if keep else dict(keep_factors=False)
+    gpu = run_gpu(A, **C1, **fk)
+    assert gpu["status"].max() == 0
+    gM = np.cos(np.arange(gpu["val"].size, dtype=np.float64))
+    dA = torch.zeros(A.nnz, dtype=torch.float64, device="cuda:0")
+    try:
+        gpu["plan"].backward(torch.from_numpy(gM).cuda(), 1.0, dA)
+    except Exception as e:
+        if keep:
+            raise
+        # without kept factors, corner columns beyond the refactorising caps are reported
+        import paper_1503_04500_amd.rsai as rsai
+        assert isinstance(e, rsai.RSAIError) and e.code == -6 and not dA.any()
+        pytest.skip("refactorising adjoint caps reached on 64^3: " + str(e))
+    want, scale = oracle.backward(A, gpu["colptr"], gpu["rowidx"], gpu["val"], gM, w_frob=1.0, scale=True)
+    r = compare_grad(dA.cpu().numpy(), want, scale, label="cd3d64")
+    print(f"cd3d64 keep={keep}: max |gpu - oracle| / scale = {r:.2e}")
