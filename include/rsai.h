@@ -235,6 +235,23 @@ rsai_status rsai_transpose(const rsai_csc *A, int64_t *colptrT, int32_t *rowidxT
    ascending column order (the rows are formed in allocator work buffers per call). */
 rsai_status rsai_spmv(const rsai_csc *A, const double *x, double *y, int32_t transpose, void *stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving loops,
+   harnesses that forbid allocation): rsai_spmv without any allocation. Same kernels,
+   results and summation order as rsai_spmv. The work buffers of the row formation
+   (transpose = 0) live in one static device array of RSAI_SPMV_NOALLOC_MAX_BYTES
+   (64 MiB) that every device the library runs on holds until the process ends; a
+   matrix that needs more (8n + 8(n + 1) + 12 nnz bytes plus the scan's partial sums,
+   each part rounded up to 256 bytes; the 512 x 512 and 64^3 stencils fit, n = 10^6
+   with 7 nnz per column does not) is rejected with RSAI_E_ARG before any work is
+   queued. transpose = 1 needs no work buffers. All calls on one device share the
+   array: calls that overlap on a device (different streams or threads) race and must
+   be serialised by the caller; calls on one stream are ordered. Stream-ordered, no host
+   synchronisation. The first call on a device looks up the array's device address
+   (a host-side runtime query): make it once outside any graph capture.
+   Errors: RSAI_E_ARG (NULL pointer, bad sizes, matrix too large), RSAI_E_HIP. */
+#define RSAI_SPMV_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+rsai_status rsai_spmv_noalloc(const rsai_csc *A, const double *x, double *y, int32_t transpose, void *stream);
+
 /* Gradient of y = A x with respect to the values of A: dval[e] += dy[i] * x[j] for
    every stored entry e = (i, j) of A (dval has nnz entries). */
 rsai_status rsai_spmv_vjp(const rsai_csc *A, const double *dy, const double *x, double *dval, void *stream);

@@ -90,6 +90,7 @@ def load():
         "rsai_bicgstab_left": [P, P, I32, P, P, D, I32, I32, P, P, P],
         "rsai_transpose": [P, P, P, P, P],
         "rsai_spmv": [P, P, P, I32, P],
+        "rsai_spmv_noalloc": [P, P, P, I32, P],
         "rsai_spmv_vjp": [P, P, P, P, P],
         "rsai_plan_timing": [P, P, I32],
         "rsai_peak_fp64": [I64, P, P],
@@ -351,6 +352,17 @@ def spmv(A: Matrix, x, transpose=False, val=None):
     y = torch.empty(A.n, dtype=torch.float64, device=x.device)
     v = A.view(val)
     _check(load().rsai_spmv(ctypes.byref(v), x.data_ptr(), y.data_ptr(), 1 if transpose else 0, _stream()))
+    return y
+
+
+def spmv_noalloc(A: Matrix, x, y, transpose=False, val=None):
+    """y = A x or A^T x into the caller's y without any allocation (rsai_spmv_noalloc)."""
+    x = _dev(x, torch.float64, "x")
+    if not (isinstance(y, torch.Tensor) and y.is_cuda and y.dtype == torch.float64 and y.is_contiguous()
+            and y.numel() == A.n):
+        raise ValueError("y must be a contiguous float64 GPU tensor of n entries")
+    v = A.view(val)
+    _check(load().rsai_spmv_noalloc(ctypes.byref(v), x.data_ptr(), y.data_ptr(), 1 if transpose else 0, _stream()))
     return y
 
 

@@ -81,6 +81,11 @@ def test_argument_errors_without_gpu():
     assert lib.rsai_peak_fp64(15, ctypes.byref(tf), None) == -1
     cnt, best = ctypes.c_int32(), ctypes.c_int32()
     assert lib.rsai_autotune(None, ctypes.byref(p), 1, None, None, 0, ctypes.byref(cnt), ctypes.byref(best)) == -1
+    # the allocation-free SpMV checks its arguments and its work-area limit on the host
+    assert lib.rsai_spmv_noalloc(None, None, None, 0, None) == -1
+    huge = rsai.CSCView(10_000_000, 70_000_000, 8, 8, 8)
+    assert lib.rsai_spmv_noalloc(ctypes.byref(huge), ctypes.c_void_p(8), ctypes.c_void_p(8), 0, None) == -1
+    assert b"work area" in lib.rsai_last_error()
     bad = rsai.params()
     bad.route = 3
     assert lib.rsai_build(ctypes.byref(rsai.CSCView(4, 4, 8, 8, 8)), ctypes.byref(bad), None, ctypes.byref(out)) == -1
