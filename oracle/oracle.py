@@ -62,6 +62,8 @@ def _load():
     lib.oracle_bicgstab.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _D, _I32, _P, _P]
     lib.oracle_bicgstab_left.restype = _I32
     lib.oracle_bicgstab_left.argtypes = [_I64, _P, _P, _P, _P, _P, _P, _P, _D, _I32, _P, _P]
+    lib.oracle_transversal.restype = _I64
+    lib.oracle_transversal.argtypes = [_I64, _P, _P, _P]
     lib.oracle_model_solve_flops.restype = _D
     lib.oracle_model_solve_flops.argtypes = [_I32, _I32, _I32, _I32]
     _lib = lib
@@ -131,6 +133,36 @@ def model_solve_flops(m0: int, m: int, qlo: int, qn: int) -> float:
     """The QR-update work model of one LS solve: a factor of qlo columns formed on m0
     rows is kept and the block grows to m rows and qn columns (qlo = 0: from scratch)."""
     return float(_load().oracle_model_solve_flops(int(m0), int(m), int(qlo), int(qn)))
+
+
+def transversal(A):
+    """Maximum transversal of the pattern of A by augmenting paths. Returns (size,
+    match) with match[k] the row matched to column k (-1 if unmatched); size == n
+    gives a row permutation p = match with A(p[k], k) != 0 for every k."""
+    lib = _load()
+    cp, ri, _ = _csc(A.colptr, A.rowidx, A.val)
+    match = np.full(int(A.n), -1, np.int32)
+    size = lib.oracle_transversal(int(A.n), _ptr(cp), _ptr(ri), _ptr(match))
+    if size < 0:
+        raise MemoryError("oracle_transversal failed")
+    return int(size), match
+
+
+def permute_rows(A, p):
+    """The rows of A renumbered by the permutation p: row p[k] of A becomes row k
+    (B(k, j) = A(p[k], j)). Returns B as CSC arrays (colptr, rowidx, val), rows
+    ascending in every column."""
+    p = np.asarray(p, np.int64)
+    n = int(A.n)
+    if p.shape != (n,) or not np.array_equal(np.sort(p), np.arange(n)):
+        raise ValueError("p must be a permutation of 0..n-1")
+    inv = np.empty(n, np.int64)
+    inv[p] = np.arange(n)
+    cp, ri, va = _csc(A.colptr, A.rowidx, A.val)
+    rows = inv[ri]
+    col = np.repeat(np.arange(n), np.diff(cp))
+    order = np.lexsort((rows, col))
+    return cp.copy(), rows[order].astype(np.int32), va[order].copy()
 
 
 def fixed_pattern(A, Mcolptr, Mrowidx, threads: int = 0):

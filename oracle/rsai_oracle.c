@@ -733,6 +733,64 @@ int64_t oracle_backward(int64_t n, const int64_t *colptr, const int32_t *rowidx,
 }
 
 /* ====================================================================== */
+/*  Maximum transversal (row permutation to a zero-free diagonal)          */
+/* ====================================================================== */
+
+/*
+ * Section 5 first permutes the rows of its test matrices that have zero diagonal
+ * entries so that the diagonal becomes zero-free. Such a permutation is a
+ * transversal: n structural nonzeros, no two in one row or one column, i.e. a
+ * perfect matching of columns to rows in the bipartite graph of the pattern. A
+ * matching of the largest size is found here from the definition by augmenting
+ * paths (a matching is of maximum size exactly when no alternating path joins an
+ * unmatched column to an unmatched row): each column in turn, in ascending order,
+ * searches depth-first along alternating paths, its rows in ascending order,
+ * visiting each row at most once per search, and flips the first path it finds.
+ * match_col[k] receives the row matched to column k, or -1. Returns the size of
+ * the matching (the structural rank of A).
+ */
+int64_t oracle_transversal(int64_t n, const int64_t *colptr, const int32_t *rowidx, int32_t *match_col) {
+    int32_t *match_row = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    int64_t *visit = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    int32_t *scol = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)); /* columns on the path */
+    int64_t *sedge = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1)); /* next entry of each */
+    int32_t *srow = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)); /* row taken from each */
+    if (!match_row || !visit || !scol || !sedge || !srow) {
+        free(match_row); free(visit); free(scol); free(sedge); free(srow);
+        return -1;
+    }
+    for (int64_t i = 0; i < n; ++i) { match_row[i] = -1; match_col[i] = -1; visit[i] = -1; }
+    int64_t size = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        int top = 0;
+        scol[0] = (int32_t)k;
+        sedge[0] = colptr[k];
+        int found = 0;
+        while (top >= 0 && !found) {
+            const int32_t c = scol[top];
+            if (sedge[top] >= colptr[c + 1]) { --top; continue; }  /* dead end: back up */
+            const int32_t r = rowidx[sedge[top]++];
+            if (visit[r] == k) continue;
+            visit[r] = k;
+            srow[top] = r;
+            if (match_row[r] < 0) { found = 1; break; }
+            ++top; /* continue through the column matched to r */
+            scol[top] = match_row[r];
+            sedge[top] = colptr[match_row[r]];
+        }
+        if (!found) continue;
+        /* flip the path: column scol[d] takes row srow[d] */
+        for (int d = top; d >= 0; --d) {
+            match_col[scol[d]] = srow[d];
+            match_row[srow[d]] = scol[d];
+        }
+        ++size;
+    }
+    free(match_row); free(visit); free(scol); free(sedge); free(srow);
+    return size;
+}
+
+/* ====================================================================== */
 /*  Right-preconditioned BiCGStab (Section 5 protocol, textbook algorithm) */
 /* ====================================================================== */
 
