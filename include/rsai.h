@@ -230,6 +230,31 @@ rsai_status rsai_bicgstab_left(const rsai_csc *A, rsai_plan *PT, int32_t mat, co
    n < 1 or nnz < n), RSAI_E_NOMEM, RSAI_E_HIP. */
 rsai_status rsai_transpose(const rsai_csc *A, int64_t *colptrT, int32_t *rowidxT, double *valT, void *stream);
 
+/* Maximum transversal of the pattern of A: the preprocessing Section 5 applies to its
+   matrices with zero diagonal entries, a row permutation to a zero-free diagonal.
+   Writes p[k] = the row matched to column k (A(p[k], k) is a stored entry), -1 for a
+   column left unmatched, into the caller's device array p[n], and the size of the
+   matching (the structural rank of A) to *size (host). *size == n means p is a
+   permutation with a zero-free diagonal; a smaller size means A is structurally
+   singular (no row permutation makes the diagonal zero-free). Any maximum matching
+   may be returned (the device search is not ordered), its size is unique. Greedy
+   claims, then phases of breadth-first searches along alternating paths from all
+   unmatched columns. Host-synchronising (a few reads per phase); work buffers
+   (9 n int32) come from the allocator. The CSC contract is checked first.
+   Errors: RSAI_E_ARG (NULL pointer, bad sizes), RSAI_E_CSC, RSAI_E_NOMEM, RSAI_E_HIP. */
+rsai_status rsai_transversal(const rsai_csc *A, int32_t *p, int64_t *size, void *stream);
+
+/* B = P A for the row permutation p (device int32[n], a permutation of 0..n-1, e.g.
+   from rsai_transversal): row p[k] of A becomes row k of B, B(k, j) = A(p[k], j).
+   Written as CSC into caller device buffers colptrB[n+1], rowidxB[nnz] (rows
+   ascending in every column), valB[nnz]. With p from rsai_transversal, B has a
+   zero-free diagonal; RSAI of B gives the right preconditioner of (P A) x = P b.
+   Host-synchronising (p is checked to be a permutation: RSAI_E_ARG if not; the CSC
+   contract of A is checked too). Errors: RSAI_E_ARG, RSAI_E_CSC, RSAI_E_NOMEM,
+   RSAI_E_HIP. */
+rsai_status rsai_permute_rows(const rsai_csc *A, const int32_t *p, int64_t *colptrB, int32_t *rowidxB, double *valB,
+                              void *stream);
+
 /* y = A x (transpose = 0) or y = A^T x (transpose = 1) for a CSC matrix; x, y device
    arrays of n doubles. Stream-ordered, no host synchronisation. A x sums each row in
    ascending column order (the rows are formed in allocator work buffers per call). */

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librsai.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["rsai_tier.hip", "rsai_tier2.hip", "rsai_wide.hip", "rsai_big.hip", "rsai_prep.hip", "rsai_backward.hip", "rsai_krylov.hip", "rsai_noalloc.hip", "rsai_host.cpp"]
+SOURCES = ["rsai_tier.hip", "rsai_tier2.hip", "rsai_wide.hip", "rsai_big.hip", "rsai_prep.hip", "rsai_backward.hip", "rsai_krylov.hip", "rsai_noalloc.hip", "rsai_match.hip", "rsai_host.cpp"]
 ARCH = os.environ.get("RSAI_ARCH", "gfx950")
 
 

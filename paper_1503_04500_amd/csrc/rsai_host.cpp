@@ -1126,6 +1126,120 @@ rsai_status rsai_transpose(const rsai_csc *A, int64_t *colptrT, int32_t *rowidxT
     return st;
 }
 
+rsai_status rsai_transversal(const rsai_csc *A, int32_t *p, int64_t *size, void *stream) {
+    if (!A || !A->colptr || !A->rowidx || !p || !size) return fail(RSAI_E_ARG, "NULL argument");
+    if (A->n < 1 || A->n > INT32_MAX - 1 || A->nnz < 0 || A->nnz > INT32_MAX) return fail(RSAI_E_ARG, "bad sizes");
+    *size = 0;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = A->n;
+    rsai_status st = RSAI_OK;
+    std::vector<void *> tmp;
+    auto al = [&](size_t bytes) -> void * {
+        void *q = dev_alloc(std::max<size_t>(bytes, 8), s);
+        if (!q) st = fail(RSAI_E_NOMEM, "allocation failed");
+        tmp.push_back(q);
+        return q;
+    };
+    auto done = [&](rsai_status r) {
+        (void)hipStreamSynchronize(s);
+        for (void *q : tmp) dev_free(q, s);
+        return r;
+    };
+    int32_t *match_row = (int32_t *)al(4 * n), *visited = (int32_t *)al(4 * n), *parent = (int32_t *)al(4 * n);
+    int32_t *root = (int32_t *)al(4 * n), *found = (int32_t *)al(4 * n), *roots = (int32_t *)al(4 * n);
+    int32_t *fa = (int32_t *)al(4 * n), *fb = (int32_t *)al(4 * n);
+    int32_t *cnt = (int32_t *)al(4 * 64);  // [0] roots, [1] augmented, [2 + l % 2] frontier sizes
+    if (st != RSAI_OK) return done(st);
+    // the CSC contract first: the search indexes rows by the stored row indices
+    {
+        int32_t herr = 0;
+        launch_fill_i32(cnt, 0, 64, s);
+        launch_validate(n, A->nnz, A->colptr, A->rowidx, cnt, s);
+        if (hipMemcpyAsync(&herr, cnt, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return done(fail(RSAI_E_HIP, "transversal: validation readback failed"));
+        if (herr) return done(fail(RSAI_E_CSC, "malformed CSC (flags %d: 1 colptr, 2 row indices, 4 empty column)", herr));
+    }
+    launch_fill_i32(p, -1, n, s);
+    launch_fill_i32(match_row, -1, n, s);
+    launch_fill_i32(visited, 0, n, s);
+    launch_match_greedy(n, A->colptr, A->rowidx, p, match_row, s);
+    // phases of augmentation; each flips at least one path or ends the search
+    for (int32_t phase = 1; phase <= n + 1; ++phase) {
+        launch_fill_i32(cnt, 0, 64, s);
+        launch_match_roots(n, p, root, found, roots, cnt, s);
+        int32_t h[2] = {0, 0};
+        if (hipMemcpyAsync(h, cnt, 4, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+            return done(fail(RSAI_E_HIP, "transversal: root count readback failed"));
+        const int64_t nroots = h[0];
+        if (nroots == 0) break;  // every column is matched
+        // level-synchronous search: level 0 is the list of roots
+        const int32_t *fin = roots;
+        const int32_t *nin = cnt;
+        int64_t nin_h = nroots;
+        for (int lev = 0; nin_h > 0; ++lev) {
+            int32_t *fout = (lev % 2 == 0) ? fa : fb;
+            int32_t *nout = cnt + 2 + (lev % 2);
+            launch_fill_i32(nout, 0, 1, s);
+            launch_match_expand(n, A->colptr, A->rowidx, phase, visited, parent, root, found, match_row, fin, nin,
+                                fout, nout, nin_h, s);
+            int32_t hn = 0;
+            if (hipMemcpyAsync(&hn, nout, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return done(fail(RSAI_E_HIP, "transversal: frontier readback failed"));
+            fin = fout;
+            nin = nout;
+            nin_h = hn;
+        }
+        launch_match_augment(roots, cnt, nroots, found, parent, p, match_row, cnt + 1, s);
+        if (hipMemcpyAsync(h, cnt, 8, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+            return done(fail(RSAI_E_HIP, "transversal: augmentation readback failed"));
+        if (h[1] == 0) break;  // no augmenting path left: the matching is maximum
+    }
+    unsigned long long *sz = (unsigned long long *)al(8);
+    if (st != RSAI_OK) return done(st);
+    launch_fill_i64((int64_t *)sz, 0, 1, s);
+    launch_match_count(n, p, sz, s);
+    unsigned long long hs = 0;
+    if (hipMemcpyAsync(&hs, sz, 8, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+        return done(fail(RSAI_E_HIP, "transversal: size readback failed"));
+    if (hipGetLastError() != hipSuccess) return done(fail(RSAI_E_HIP, "transversal: launch failed"));
+    *size = (int64_t)hs;
+    return done(RSAI_OK);
+}
+
+rsai_status rsai_permute_rows(const rsai_csc *A, const int32_t *p, int64_t *colptrB, int32_t *rowidxB, double *valB,
+                              void *stream) {
+    if (!A || !A->colptr || !A->rowidx || !A->val || !p || !colptrB || !rowidxB || !valB)
+        return fail(RSAI_E_ARG, "NULL argument");
+    if (A->n < 1 || A->n > INT32_MAX - 1 || A->nnz < 0 || A->nnz > INT32_MAX) return fail(RSAI_E_ARG, "bad sizes");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = A->n;
+    int32_t *inv = (int32_t *)dev_alloc(4 * (size_t)n + 256, s);
+    if (!inv) return fail(RSAI_E_NOMEM, "allocation failed");
+    int32_t *err = inv + ((n + 63) / 64) * 64;
+    int32_t herr[2] = {0, 0};
+    launch_fill_i32(inv, -1, n, s);
+    launch_fill_i32(err, 0, 2, s);
+    launch_validate(n, A->nnz, A->colptr, A->rowidx, err + 1, s);
+    launch_perm_invert(n, p, inv, err, s);
+    rsai_status st = RSAI_OK;
+    if (hipMemcpyAsync(herr, err, 8, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+        st = fail(RSAI_E_HIP, "permutation check readback failed");
+    else if (herr[1])
+        st = fail(RSAI_E_CSC, "malformed CSC (flags %d: 1 colptr, 2 row indices, 4 empty column)", herr[1]);
+    else if (herr[0])
+        st = fail(RSAI_E_ARG, "p is not a permutation of 0..n-1 (the transversal was not of full size?)");
+    if (st == RSAI_OK) {
+        launch_perm_rows(n, A->nnz, A->colptr, A->rowidx, A->val, inv, colptrB, rowidxB, valB, s);
+        // rows ascending in every column: the segment sort of the row formation
+        launch_sort_rows(n, colptrB, rowidxB, valB, s);
+        if (hipGetLastError() != hipSuccess) st = fail(RSAI_E_HIP, "permutation launch failed");
+    }
+    dev_free(inv, s);
+    return st;
+}
+
 rsai_status rsai_backward(rsai_plan *P, int32_t mat, const double *dM_val, double w_frob, double *dA_val,
                           void *stream) {
     int64_t nz = 0;

@@ -108,6 +108,21 @@ void launch_sort_rows(int64_t n, const int64_t *rowptr, int32_t *colidx, double 
 void enqueue_rows(int64_t n, int64_t nnz, const int64_t *colptr, const int32_t *rowidx, const double *val,
                   int64_t *rp, int32_t *ci, double *vv, int32_t *cnt, int32_t *fill, int64_t *stmp, int32_t *zerr,
                   hipStream_t s);
+// ---- maximum transversal and row permutation (rsai_match.hip)
+void launch_match_greedy(int64_t n, const int64_t *colptr, const int32_t *rowidx, int32_t *match_col,
+                         int32_t *match_row, hipStream_t s);
+void launch_match_roots(int64_t n, const int32_t *match_col, int32_t *root, int32_t *found, int32_t *roots,
+                        int32_t *nroots, hipStream_t s);
+void launch_match_expand(int64_t n, const int64_t *colptr, const int32_t *rowidx, int32_t stamp, int32_t *visited,
+                         int32_t *parent, int32_t *root, int32_t *found, const int32_t *match_row, const int32_t *fin,
+                         const int32_t *nin, int32_t *fout, int32_t *nout, int64_t nin_host, hipStream_t s);
+void launch_match_augment(const int32_t *roots, const int32_t *nroots, int64_t nroots_host, const int32_t *found,
+                          const int32_t *parent, int32_t *match_col, int32_t *match_row, int32_t *naug,
+                          hipStream_t s);
+void launch_match_count(int64_t n, const int32_t *match_col, unsigned long long *size, hipStream_t s);
+void launch_perm_invert(int64_t n, const int32_t *p, int32_t *inv, int32_t *err, hipStream_t s);
+void launch_perm_rows(int64_t n, int64_t nnz, const int64_t *colptr, const int32_t *rowidx, const double *val,
+                      const int32_t *inv, int64_t *colptrB, int32_t *rowidxB, double *valB, hipStream_t s);
 // ---- right-preconditioned BiCGStab (rsai_krylov.hip)
 struct BicgState {
     double rho, rho1, rho1n, alpha, omega, rel, nb, tol;

@@ -91,6 +91,8 @@ def load():
         "rsai_transpose": [P, P, P, P, P],
         "rsai_spmv": [P, P, P, I32, P],
         "rsai_spmv_noalloc": [P, P, P, I32, P],
+        "rsai_transversal": [P, P, P, P],
+        "rsai_permute_rows": [P, P, P, P, P, P],
         "rsai_spmv_vjp": [P, P, P, P, P],
         "rsai_plan_timing": [P, P, I32],
         "rsai_peak_fp64": [I64, P, P],
@@ -177,6 +179,31 @@ class Matrix:
         v = self.view()
         _check(load().rsai_transpose(ctypes.byref(v), cp.data_ptr(), ri.data_ptr(), va.data_ptr(), _stream()))
         return Matrix(cp, ri, va)
+
+
+def transversal(A: Matrix):
+    """Maximum transversal of A's pattern (rsai_transversal): returns (p, size), p an
+    int32 GPU tensor with p[k] the row matched to column k (-1 if none)."""
+    _use_torch_allocator()
+    p = torch.empty(A.n, dtype=torch.int32, device=A.colptr.device)
+    size = ctypes.c_int64(0)
+    v = A.view()
+    _check(load().rsai_transversal(ctypes.byref(v), p.data_ptr(), ctypes.byref(size), _stream()))
+    return p, size.value
+
+
+def permute_rows(A: Matrix, p) -> Matrix:
+    """P A: row p[k] of A becomes row k (rsai_permute_rows)."""
+    _use_torch_allocator()
+    p = _dev(p, torch.int32, "p")
+    dev = A.colptr.device
+    cp = torch.empty(A.n + 1, dtype=torch.int64, device=dev)
+    ri = torch.empty(max(A.nnz, 1), dtype=torch.int32, device=dev)
+    va = torch.empty(max(A.nnz, 1), dtype=torch.float64, device=dev)
+    v = A.view()
+    _check(load().rsai_permute_rows(ctypes.byref(v), p.data_ptr(), cp.data_ptr(), ri.data_ptr(), va.data_ptr(),
+                                    _stream()))
+    return Matrix(cp, ri[:A.nnz], va[:A.nnz])
 
 
 def params(c=3, lmax=10, eps=0.4, drop="fixed", tol=1e-3, sched="batched", validate=True, tier0=-1,
