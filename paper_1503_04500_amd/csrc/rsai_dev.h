@@ -92,13 +92,54 @@ __device__ __forceinline__ double dpp_f64(double x) {
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
+// Groups of 32 and 64 lanes add one and two cross-row steps: v_permlane16_swap
+// (gfx950) called with the same register as both operands leaves, in every lane of an
+// aligned pair of 16-lane rows, the value of the even row in the first result and the
+// value of the odd row in the second; v_permlane32_swap does the same for the two
+// 32-lane halves. Adding the two results in that order gives every lane of the group
+// the bitwise-identical sum.
+__device__ __forceinline__ void xrow16_i32(int x, int &a, int &b) {
+    const auto p = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+    a = (int)p[0];
+    b = (int)p[1];
+}
+__device__ __forceinline__ void xrow32_i32(int x, int &a, int &b) {
+    const auto p = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+    a = (int)p[0];
+    b = (int)p[1];
+}
+template <int W>
+__device__ __forceinline__ void xrow_f64(double x, double &a, double &b) {
+    const long long v = __double_as_longlong(x);
+    int alo, ahi, blo, bhi;
+    if constexpr (W == 16) {
+        xrow16_i32((int)(v & 0xffffffffLL), alo, blo);
+        xrow16_i32((int)(v >> 32), ahi, bhi);
+    } else {
+        xrow32_i32((int)(v & 0xffffffffLL), alo, blo);
+        xrow32_i32((int)(v >> 32), ahi, bhi);
+    }
+    a = __longlong_as_double(((long long)ahi << 32) | (long long)(unsigned)alo);
+    b = __longlong_as_double(((long long)bhi << 32) | (long long)(unsigned)blo);
+}
+
 template <int G>
 __device__ __forceinline__ double gsum(double x) {
-    static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16, "group size");
+    static_assert(G == 1 || G == 2 || G == 4 || G == 8 || G == 16 || G == 32 || G == 64, "group size");
     if constexpr (G >= 2) x = x + dpp_f64<0xB1>(x);
     if constexpr (G >= 4) x = x + dpp_f64<0x4E>(x);
     if constexpr (G >= 8) x = x + dpp_f64<0x141>(x);
     if constexpr (G >= 16) x = x + dpp_f64<0x140>(x);
+    if constexpr (G >= 32) {
+        double a, b;
+        xrow_f64<16>(x, a, b);
+        x = a + b;
+    }
+    if constexpr (G >= 64) {
+        double a, b;
+        xrow_f64<32>(x, a, b);
+        x = a + b;
+    }
     return x;
 }
 
@@ -108,6 +149,16 @@ __device__ __forceinline__ int gsum_i(int x) {
     if constexpr (G >= 4) x = x + dpp_i32<0x4E>(x);
     if constexpr (G >= 8) x = x + dpp_i32<0x141>(x);
     if constexpr (G >= 16) x = x + dpp_i32<0x140>(x);
+    if constexpr (G >= 32) {
+        int a, b;
+        xrow16_i32(x, a, b);
+        x = a + b;
+    }
+    if constexpr (G >= 64) {
+        int a, b;
+        xrow32_i32(x, a, b);
+        x = a + b;
+    }
     return x;
 }
 
@@ -117,6 +168,16 @@ __device__ __forceinline__ int gmax_i(int x) {
     if constexpr (G >= 4) x = max(x, dpp_i32<0x4E>(x));
     if constexpr (G >= 8) x = max(x, dpp_i32<0x141>(x));
     if constexpr (G >= 16) x = max(x, dpp_i32<0x140>(x));
+    if constexpr (G >= 32) {
+        int a, b;
+        xrow16_i32(x, a, b);
+        x = max(a, b);
+    }
+    if constexpr (G >= 64) {
+        int a, b;
+        xrow32_i32(x, a, b);
+        x = max(a, b);
+    }
     return x;
 }
 
@@ -128,6 +189,16 @@ __device__ __forceinline__ void amax_step(double &a, int &g) {
     a = take ? a2 : a;
     g = take ? g2 : g;
 }
+template <int W>
+__device__ __forceinline__ void amax_xrow(double &a, int &g) {
+    double a0, a1;
+    int g0, g1;
+    xrow_f64<W>(a, a0, a1);
+    if constexpr (W == 16) xrow16_i32(g, g0, g1); else xrow32_i32(g, g0, g1);
+    const bool take1 = (a1 > a0) || (a1 == a0 && g1 < g0);
+    a = take1 ? a1 : a0;
+    g = take1 ? g1 : g0;
+}
 
 // Group arg-max with key (a descending, g ascending): the dominant-row order with
 // ties going to the smaller global row index.
@@ -137,6 +208,8 @@ __device__ __forceinline__ void gargmax(double &a, int &g) {
     if constexpr (G >= 4) amax_step<0x4E>(a, g);
     if constexpr (G >= 8) amax_step<0x141>(a, g);
     if constexpr (G >= 16) amax_step<0x140>(a, g);
+    if constexpr (G >= 32) amax_xrow<16>(a, g);
+    if constexpr (G >= 64) amax_xrow<32>(a, g);
 }
 
 // Value of x held by group lane `src` (others contribute exact zeros).

@@ -334,9 +334,11 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
     // records out of each sparse-block instance: few columns need the next class;
     // more than this many end with RSAI_E_CAP
     int64_t wide_rec_cap[WIDE_LEVELS];
-    wide_rec_cap[0] = std::min<int64_t>(ncols, std::max<int64_t>(4096, ncols / 4));
-    wide_rec_cap[1] = std::min<int64_t>(ncols, std::max<int64_t>(4096, ncols / 64));
-    wide_rec_cap[2] = std::min<int64_t>(ncols, std::max<int64_t>(4096, ncols / 256));
+    // (every column of a build of up to 16384 columns fits every queue, so a small eps,
+    // which sends most columns of a grid to the workgroup classes, still completes)
+    wide_rec_cap[0] = std::min<int64_t>(ncols, std::max<int64_t>(16384, ncols / 4));
+    wide_rec_cap[1] = std::min<int64_t>(ncols, std::max<int64_t>(16384, ncols / 64));
+    wide_rec_cap[2] = std::min<int64_t>(ncols, std::max<int64_t>(16384, ncols / 256));
     // the batched schedule ends with two workgroup-per-column classes: the sparse-block
     // class (an arena slot of 64 per column) and the dense large class, whose columns
     // (at most its record capacity) get a slot of BQMAX_BIG per record

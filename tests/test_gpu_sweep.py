@@ -23,6 +23,19 @@ def test_parameter_parity(eps, c, drop):
     compare(A, gpu, ref, label=f"eps={eps} c={c} {drop}")
 
 
+@pytest.mark.parametrize("N", [48, 128])
+def test_eps01_parity(N):
+    """eps = 0.1, the smallest of the paper's eps settings: every column runs to lmax on
+    blocks of about 100 x 64 (on the 128x128 grid |J_k| reaches 68 before dropping,
+    |I_k| 101), so nearly all columns finish in the workgroup classes. Full parity."""
+    A = gen.cd2d(N, seed=3 if N == 48 else 0)
+    ref = oracle.rsai(A, c=3, lmax=8, eps=0.1, drop=oracle.DROP_FIXED, tol=1e-3)
+    gpu = run_gpu(A, c=3, lmax=8, eps=0.1, drop="fixed", tol=1e-3)
+    s = compare(A, gpu, ref, label=f"eps=0.1 {N}x{N}")
+    print(f"eps=0.1 {N}x{N}: nJ max {int(ref['nJ'].max())}, nJmax {int(ref['nJmax'].max())}, "
+          f"nI max {int(ref['nI'].max())}, parity {s}", flush=True)
+
+
 def test_smaller_eps_gives_denser_m_and_fewer_iterations():
     """The trend of the paper's eps experiments on a 128x128 grid: M gets denser as
     eps falls, and the device BiCGStab needs fewer iterations with it."""
