@@ -72,6 +72,17 @@ typedef enum {
     RSAI_SCHED_PLAIN = 1    /* one wave per column, one launch per loop, state in HBM */
 } rsai_sched;
 
+/* One entry of a tuning table (rsai_params.tune_table): for a matrix with n in
+   [n_lo, n_hi), mean column length nnz/n in [len_lo, len_hi) and longest column in
+   [maxlen_lo, maxlen_hi), the schedule choices below (as written by rsai_autotune;
+   the first matching entry wins). */
+typedef struct {
+    double len_lo, len_hi;
+    int64_t maxlen_lo, maxlen_hi;
+    int64_t n_lo, n_hi;
+    int32_t tier0, refill, route, t0_hash, last_tier, reserved;
+} rsai_tune_entry;
+
 typedef struct {
     int32_t c;        /* dominant rows taken per loop (Algorithm 1, step 4), 1..8 */
     int32_t lmax;     /* maximum number of loops, 0..64 */
@@ -94,6 +105,23 @@ typedef struct {
                                     rsai_backward (R^T R = A(I,J)^T A(I,J)) */
     int64_t factor_budget_bytes; /* size of the factor store (0: 256 MB); columns that do not
                                     fit are refactorised by rsai_backward */
+    int32_t deterministic;       /* 1: rsai_backward adds every entry's contributions in a
+                                    fixed order (sorted by column), so dA is bitwise
+                                    repeatable; 0: FP64 atomics (faster) */
+    int32_t tune_count;          /* entries of tune_table (0: none) */
+    const rsai_tune_entry *tune_table; /* host array, read during rsai_build*: the schedule
+                                    fields left at -1 (tier0, refill, route, t0_hash,
+                                    last_tier) take the first entry matching the matrix
+                                    (for a batch: the smallest tier0, the largest route
+                                    and last_tier, refill and t0_hash of the largest
+                                    matrix's entry); no match keeps the defaults. Reading
+                                    each matrix's longest column costs one host
+                                    synchronisation */
+    int32_t t0_hash;  /* hash tables of the first register tier: -1 default (2), 2 or 4 times
+                         its row and column capacity (a tile choice; results unchanged) */
+    int32_t last_tier; /* last register tier: -1 default (2), 1 sends the columns that
+                          outgrow tier 1 straight to the sparse-block class (a class edge;
+                          results unchanged) */
 } rsai_params;
 
 typedef struct rsai_plan rsai_plan; /* opaque host handle */
@@ -115,14 +143,17 @@ rsai_status rsai_set_allocator(rsai_alloc_fn alloc, rsai_free_fn dealloc, void *
 
 /* Result of one autotuning candidate. */
 typedef struct {
-    int32_t tier0, refill, route, reserved;
+    int32_t tier0, refill, route, t0_hash, last_tier, reserved;
     double ms; /* median build time over the repetitions (HIP events) */
 } rsai_tune_choice;
 
-/* Time the batched build of A for every combination of tier0 (each register tier),
-   refill (0, 1) and route (0, 1), reps builds each (p gives the method parameters).
-   Writes up to cap results to out (host array), their number to *count and the index
-   of the fastest to *best. Synchronises the stream. */
+/* Time the batched build of A for every combination of the schedule choices, which
+   change the speed and never the results: tier0 (each register tier), refill (0, 1),
+   route (0, 1), the first tier's hash tables t0_hash (2, 4; with tier0 = 0 only) and
+   the last register tier last_tier (1, 2; not below tier0): 28 combinations, reps
+   builds each after one warm-up build (p gives the method parameters). Writes up to
+   cap results to out (host array), their number to *count and the index of the
+   fastest to *best. Synchronises the stream. */
 rsai_status rsai_autotune(const rsai_csc *A, const rsai_params *p, int32_t reps, void *stream,
                           rsai_tune_choice *out, int32_t cap, int32_t *count, int32_t *best);
 
@@ -150,6 +181,12 @@ rsai_status rsai_build_batched(int32_t count, const rsai_csc *A, const rsai_para
    repeated, validate = 2 stays on the device). Returns RSAI_E_HIP if capture or
    launch fails. */
 rsai_status rsai_rebuild(rsai_plan *P, int32_t use_graph, void *stream);
+
+/* The schedule a plan was built with, after defaults and the tuning table (host
+   outputs, any may be NULL): first register tier, refill mode, routing, hash factor of
+   the first tier (2 or 4) and last register tier. */
+rsai_status rsai_plan_schedule(const rsai_plan *P, int32_t *tier0, int32_t *refill, int32_t *route, int32_t *t0_hash,
+                               int32_t *last_tier);
 
 /* Number of matrices in a plan. */
 rsai_status rsai_plan_count(const rsai_plan *P, int32_t *count);

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librsai.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["rsai_tier.hip", "rsai_tier2.hip", "rsai_wide.hip", "rsai_big.hip", "rsai_prep.hip", "rsai_backward.hip", "rsai_krylov.hip", "rsai_noalloc.hip", "rsai_match.hip", "rsai_host.cpp"]
+SOURCES = ["rsai_tier.hip", "rsai_tier0h.hip", "rsai_tier2.hip", "rsai_wide.hip", "rsai_big.hip", "rsai_prep.hip", "rsai_backward.hip", "rsai_krylov.hip", "rsai_noalloc.hip", "rsai_match.hip", "rsai_detsum.hip", "rsai_host.cpp"]
 ARCH = os.environ.get("RSAI_ARCH", "gfx950")
 
 
@@ -34,7 +34,8 @@ def flags() -> list[str]:
 
 # per-source flags: the tier kernel's QR loops must unroll completely (constant register
 # indices), which exceeds the default threshold for the larger tiers
-SOURCE_FLAGS = {"rsai_tier.hip": ["-mllvm", "-pragma-unroll-threshold=262144"]}
+SOURCE_FLAGS = {"rsai_tier.hip": ["-mllvm", "-pragma-unroll-threshold=262144"],
+                "rsai_tier0h.hip": ["-mllvm", "-pragma-unroll-threshold=262144"]}
 
 
 def build(verbose: bool = False, extra: list[str] | None = None, out: str | None = None) -> str:
@@ -54,7 +55,7 @@ def build(verbose: bool = False, extra: list[str] | None = None, out: str | None
             print(r.stderr, file=sys.stderr)
         return obj
 
-    with cf.ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     target = LIB if out is None else out
     tmp = target + f".tmp{os.getpid()}"

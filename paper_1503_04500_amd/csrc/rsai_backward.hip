@@ -40,6 +40,7 @@ struct BLds {
     int news[BMMAX];
     int cnt;
     int pad;
+    long long cbase;  // fixed-order mode: first slot of the column's contributions
 };
 }  // namespace
 
@@ -378,22 +379,41 @@ __global__ __launch_bounds__(64) void backward_kernel(BwdArgs a) {
             }
         }
         __syncthreads();
-        // ---- scatter onto the nonzeros of A(:, J_k)
+        // ---- scatter onto the nonzeros of A(:, J_k) (the fixed-order mode appends
+        // the contributions at the column's reserved slots instead)
+        const bool det = a.ckey != nullptr;
+        if (det && act && gl == 0) {
+            int tot = 0;
+            for (int c = 0; c < q; ++c) tot += (int)(A.colptr[S.Jl[c] + 1] - A.colptr[S.Jl[c]]);
+            S.cbase = (long long)atomicAdd(a.ccur, (unsigned long long)tot);
+        }
+        __syncthreads();
         if (act) {
             const double w2 = 2.0 * a.w_frob;
+            long long slot0 = det ? S.cbase : 0;
 #pragma unroll
             for (int c = 0; c < QMAX; ++c) {
                 if (c < q) {
                     const int j = S.Jl[c];
                     const double zc = S.zS[c], mc = a.Mval[mb + c];
-                    for (int64_t e = A.colptr[j] + gl; e < A.colptr[j + 1]; e += G) {
+                    const int64_t c0 = A.colptr[j], c1 = A.colptr[j + 1];
+                    for (int64_t e = c0 + gl; e < c1; e += G) {
                         const int sl = hfind<BLOGHSI>(S.hI, A.rowidx[e]);
                         const int li = sl >= 0 ? S.hIv[sl] : -1;
-                        if (li < 0) continue;
-                        const double ri = S.stage[li], azi = S.stage[MMAX + li];
-                        const double g = -(ri * zc + azi * mc) + w2 * ri * mc;
-                        atomicAdd(&a.dA[e], g);
+                        double g = 0.0;
+                        if (li >= 0) {
+                            const double ri = S.stage[li], azi = S.stage[MMAX + li];
+                            g = -(ri * zc + azi * mc) + w2 * ri * mc;
+                        }
+                        if (det) {
+                            const long long slot = slot0 + (e - c0);
+                            a.ckey[slot] = ((unsigned long long)e << 32) | (unsigned long long)(unsigned)k;
+                            a.cval[slot] = g;
+                        } else if (li >= 0) {
+                            atomicAdd(&a.dA[e], g);
+                        }
                     }
+                    slot0 += c1 - c0;
                 }
             }
         }
@@ -454,6 +474,7 @@ struct FLds {
     double z[FQ];  // g (ascending order) until the back substitution writes z over it
     int js[FQ];    // J ascending (the order of M's column)
     int cnt;
+    long long cbase;  // fixed-order mode: first slot of the column's contributions
     union {
         struct {             // the triangular solves
             double R[RSZ];   // R row by row
@@ -634,8 +655,12 @@ __global__ __launch_bounds__(64) void backward_factored_kernel(BwdArgs a) {
         }
         wave_sync();
         const int tot = act ? S.w.acc.pre[q] : 0;
-        // small I_k: r and A_k z accumulated once per row in LDS
-        bool small = act && tot <= FM;
+        const bool det = a.ckey != nullptr;
+        if (det && act && gl == 0) S.cbase = (long long)atomicAdd(a.ccur, (unsigned long long)tot);
+        wave_sync();
+        // small I_k: r and A_k z accumulated once per row in LDS (atomics: not in the
+        // fixed-order mode)
+        bool small = act && tot <= FM && !det;
         if (wave_any(small)) {
             // entries u = gl + t G of the flattened columns, loaded once (all loads in
             // flight together) and used by the three passes
@@ -712,30 +737,204 @@ __global__ __launch_bounds__(64) void backward_factored_kernel(BwdArgs a) {
             }
             wave_sync();
         }
-        // larger I_k: r_i and (A_k z)_i from row i's pattern, per entry
+        // larger I_k: r_i and (A_k z)_i from row i's pattern, per entry; in the
+        // fixed-order mode over J_k in ascending order (the row pattern's order is
+        // not fixed) and appended instead of added
         if (act && !small) {
             const double w2 = 2.0 * a.w_frob;
+            const long long cbase = det ? S.cbase : 0;
             for (int c = 0; c < q; ++c) {
                 const int j = S.js[c];
                 const double zc = S.z[c], mc = a.Mval[mb + c];
-                for (int64_t e = A.colptr[j] + gl; e < A.colptr[j + 1]; e += G) {
+                const int64_t c0 = A.colptr[j];
+                for (int64_t e = c0 + gl; e < A.colptr[j + 1]; e += G) {
                     const int i = A.rowidx[e];
                     double ri = (i == (int)k) ? -1.0 : 0.0, azi = 0.0;
-                    for (int64_t f = A.rowptr[i]; f < A.rowptr[i + 1]; ++f) {
-                        const int jj = A.colidx[f];
-                        const int t = jpos(S.js, q, jj);
-                        if (t < 0) continue;
-                        const double aij = (jj == j) ? A.val[e] : aval(A, jj, i);
-                        ri += aij * a.Mval[mb + t];
-                        azi += aij * S.z[t];
+                    if (det) {
+                        for (int t = 0; t < q; ++t) {
+                            const int jj = S.js[t];
+                            const double aij = (jj == j) ? A.val[e] : aval(A, jj, i);
+                            ri += aij * a.Mval[mb + t];
+                            azi += aij * S.z[t];
+                        }
+                    } else {
+                        for (int64_t f = A.rowptr[i]; f < A.rowptr[i + 1]; ++f) {
+                            const int jj = A.colidx[f];
+                            const int t = jpos(S.js, q, jj);
+                            if (t < 0) continue;
+                            const double aij = (jj == j) ? A.val[e] : aval(A, jj, i);
+                            ri += aij * a.Mval[mb + t];
+                            azi += aij * S.z[t];
+                        }
                     }
                     const double gv = -(ri * zc + azi * mc) + w2 * ri * mc;
-                    atomicAdd(&a.dA[e], gv);
+                    if (det) {
+                        const long long slot = cbase + S.w.acc.pre[c] + (e - c0);
+                        a.ckey[slot] = ((unsigned long long)e << 32) | (unsigned long long)(unsigned)k;
+                        a.cval[slot] = gv;
+                    } else {
+                        atomicAdd(&a.dA[e], gv);
+                    }
                 }
             }
         }
         wave_sync();
     }
+}
+
+// ---------------------------------------------------------------- recomputed factors
+// Columns without a kept factor that are larger than the refactorising kernel's
+// register block (|J_k| > 32 or |I_k| > 64) get a factor recomputed here, into a
+// temporary store, and are then differentiated by the factored kernel. The factor is
+// the Cholesky factor L of the normal-equation matrix A_k^T A_k (R = L^T satisfies
+// R^T R = A_k^T A_k, all the factored kernel needs), so the dense block A(I_k, J_k)
+// is never formed: entry (a, b) is the dot product of the sparse columns J_a and J_b,
+// merged along their ascending row lists, and |I_k| is not limited.
+namespace {
+constexpr int RNT = 256;
+constexpr int RQMAX = 128;
+constexpr int RPACK = RQMAX * (RQMAX + 1) / 2;
+struct RLds {
+    double G[RPACK];   // lower triangle of A_k^T A_k, then of L, row by row
+    int64_t cb[RQMAX];
+    int cl[RQMAX];
+    int js[RQMAX];
+    int flag;
+};
+__device__ __forceinline__ int tri(int a, int b) { return a * (a + 1) / 2 + b; }  // a >= b
+// (a, b) with a >= b of packed lower-triangle position p
+__device__ __forceinline__ void untri(int p, int &a, int &b) {
+    int x = (int)((sqrtf(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
+    while ((x + 1) * (x + 2) / 2 <= p) ++x;
+    while (x * (x + 1) / 2 > p) --x;
+    a = x;
+    b = p - x * (x + 1) / 2;
+}
+__device__ __forceinline__ bool needs_refactor(const RefArgs &r, int64_t k, int q) {
+    if (q < 1 || q > RQMAX) return false;
+    if (r.foff && r.foff[k] >= 0) return false;
+    return q > r.small_cols || r.nI[k] > r.small_rows;
+}
+}  // namespace
+
+int refactor_max_cols() { return RQMAX; }
+
+// doubles of the records to recompute (one atomic per workgroup)
+__global__ __launch_bounds__(256) void k_refactor_size(RefArgs r, unsigned long long *total) {
+    unsigned long long t = 0;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < r.n; k += (int64_t)gridDim.x * blockDim.x) {
+        const int q = (int)(r.Mcolptr[k + 1] - r.Mcolptr[k]);
+        if (needs_refactor(r, k, q)) t += (unsigned long long)(q + q * (q + 1) / 2);
+    }
+    for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off);
+    if ((threadIdx.x & 63) == 0 && t) atomicAdd(total, t);
+}
+
+__global__ __launch_bounds__(RNT) void k_refactor(RefArgs r) {
+    __shared__ RLds S;
+    const int tid = threadIdx.x;
+    const MatDev A = r.mats[r.mat];
+    for (int64_t k = blockIdx.x; k < r.n; k += gridDim.x) {
+        const int64_t mb = r.Mcolptr[k];
+        const int q = (int)(r.Mcolptr[k + 1] - mb);
+        if (!needs_refactor(r, k, q)) continue;  // uniform over the workgroup
+        if (tid < q) {
+            const int j = r.Mrowidx[mb + tid];
+            S.js[tid] = j;
+            S.cb[tid] = A.colptr[j];
+            S.cl[tid] = (int)(A.colptr[j + 1] - S.cb[tid]);
+        }
+        if (tid == 0) S.flag = 0;
+        __syncthreads();
+        // A_k^T A_k: sparse column dot products, rows merged in ascending order
+        const int np = q * (q + 1) / 2;
+        for (int p = tid; p < np; p += RNT) {
+            int a, b;
+            untri(p, a, b);
+            const int64_t ea = S.cb[a] + S.cl[a], eb = S.cb[b] + S.cl[b];
+            int64_t ia = S.cb[a], ib = S.cb[b];
+            double sum = 0.0;
+            while (ia < ea && ib < eb) {
+                const int ra = A.rowidx[ia], rb = A.rowidx[ib];
+                if (ra == rb) {
+                    sum += A.val[ia] * A.val[ib];
+                    ++ia;
+                    ++ib;
+                } else if (ra < rb) {
+                    ++ia;
+                } else {
+                    ++ib;
+                }
+            }
+            S.G[p] = sum;
+        }
+        __syncthreads();
+        // Cholesky A_k^T A_k = L L^T, right-looking, in place
+        for (int j = 0; j < q; ++j) {
+            if (tid == 0) {
+                const double d = S.G[tri(j, j)];
+                if (d > 0.0) S.G[tri(j, j)] = sqrt(d); else S.flag = 1;
+            }
+            __syncthreads();
+            if (S.flag) break;
+            const double dj = S.G[tri(j, j)];
+            for (int a = j + 1 + tid; a < q; a += RNT) S.G[tri(a, j)] /= dj;
+            __syncthreads();
+            const int w = q - j - 1;
+            for (int t = tid; t < w * (w + 1) / 2; t += RNT) {
+                int a, b;
+                untri(t, a, b);
+                a += j + 1;
+                b += j + 1;
+                S.G[tri(a, b)] -= S.G[tri(a, j)] * S.G[tri(b, j)];
+            }
+            __syncthreads();
+        }
+        if (S.flag) {
+            if (tid == 0) atomicOr(r.err, 32);  // rank-deficient A_k: no factor
+            __syncthreads();
+            continue;
+        }
+        // record: J (ascending: the solve order of L), then R = L^T row by row
+        if (tid == 0) {
+            const unsigned long long need = (unsigned long long)(q + np);
+            const unsigned long long at = atomicAdd(r.cur, need);
+            S.cb[0] = (at + need <= (unsigned long long)r.cap) ? (int64_t)at : -1;
+        }
+        __syncthreads();
+        const int64_t fo = S.cb[0];
+        if (fo >= 0) {
+            double *F = r.fac + fo;
+            for (int t = tid; t < q; t += RNT) F[t] = (double)S.js[t];
+            for (int p = tid; p < np; p += RNT) {
+                int c, i;
+                untri(p, c, i);  // L(c, i), c >= i, is R(i, c)
+                F[q + i * q - i * (i - 1) / 2 + (c - i)] = S.G[p];
+            }
+            if (tid == 0) r.tfoff[k] = fo;
+        } else if (tid == 0) {
+            atomicOr(r.err, 64);  // store too small (sized exactly: internal error)
+        }
+        __syncthreads();
+    }
+}
+
+// columns with a factor in either store (mask >= 0), for the refactorising kernel
+__global__ void k_merge_masks(int64_t n, const int64_t *a, const int64_t *b, int64_t *out) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        out[k] = ((a && a[k] >= 0) || b[k] >= 0) ? 0 : -1;
+}
+
+void launch_refactor_size(const RefArgs &r, unsigned long long *total, hipStream_t s) {
+    const int64_t nb = std::min<int64_t>(std::max<int64_t>((r.n + 255) / 256, 1), 4096);
+    hipLaunchKernelGGL(k_refactor_size, dim3(nb), dim3(256), 0, s, r, total);
+}
+void launch_refactor(const RefArgs &r, int cus, hipStream_t s) {
+    hipLaunchKernelGGL(k_refactor, dim3(cus * 2), dim3(RNT), 0, s, r);
+}
+void launch_merge_masks(int64_t n, const int64_t *a, const int64_t *b, int64_t *out, hipStream_t s) {
+    const int64_t nb = std::min<int64_t>(std::max<int64_t>((n + 255) / 256, 1), 4096);
+    hipLaunchKernelGGL(k_merge_masks, dim3(nb), dim3(256), 0, s, n, a, b, out);
 }
 
 // resident workgroups per CU of each instance (the grids are persistent: a wave

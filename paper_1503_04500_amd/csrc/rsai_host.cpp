@@ -117,6 +117,7 @@ struct rsai_plan {
         if (have_events && !capturing && hipEventRecord(ev[i], s) == hipSuccess) recorded[i] = true;
     }
     int ntiers_used = 0;
+    int sched_t0 = 0, sched_refill = 1, sched_route = 1, sched_hash = 2, sched_last = 2;  // as resolved
     // the build's kernel sequence (everything after allocation and table upload), kept
     // for rsai_rebuild; first = the initial build (may check the CSC contract on the host)
     std::function<rsai_status(hipStream_t, bool)> enqueue;
@@ -165,6 +166,13 @@ static rsai_status check_params(const rsai_params *p) {
     if (p->tier0 < -1 || p->tier0 >= kNumTiers) return fail(RSAI_E_ARG, "tier0 out of range");
     if (p->refill < -1 || p->refill > 1) return fail(RSAI_E_ARG, "refill must be -1, 0 or 1");
     if (p->route < -1 || p->route > 1) return fail(RSAI_E_ARG, "route must be -1, 0 or 1");
+    if (p->deterministic < 0 || p->deterministic > 1) return fail(RSAI_E_ARG, "deterministic must be 0 or 1");
+    if (p->tune_count < 0 || (p->tune_count > 0 && !p->tune_table))
+        return fail(RSAI_E_ARG, "tune_count must be >= 0, with a table when > 0");
+    if (p->t0_hash != -1 && p->t0_hash != 2 && p->t0_hash != 4) return fail(RSAI_E_ARG, "t0_hash must be -1, 2 or 4");
+    if (p->last_tier < -1 || p->last_tier == 0 || p->last_tier >= kNumTiers)
+        return fail(RSAI_E_ARG, "last_tier must be -1 or a register tier from 1 to %d", kNumTiers - 1);
+    if (p->last_tier > 0 && p->tier0 > p->last_tier) return fail(RSAI_E_ARG, "tier0 is past last_tier");
     return RSAI_OK;
 }
 
@@ -214,6 +222,11 @@ rsai_status rsai_params_default(rsai_params *p) {
     p->route = -1;
     p->keep_factors = 0;
     p->factor_budget_bytes = 0;
+    p->deterministic = 0;
+    p->tune_count = 0;
+    p->tune_table = nullptr;
+    p->t0_hash = -1;
+    p->last_tier = -1;
     return RSAI_OK;
 }
 
@@ -275,6 +288,50 @@ static int route_default(int requested) {
     return 1;
 }
 
+// Schedule fields left at -1 take the first tuning-table entry whose ranges hold the
+// matrix (n, mean column length, longest column); for a batch the smallest tier0, the
+// largest route and last_tier, and refill and t0_hash of the largest matrix's entry.
+static rsai_status apply_tune_table(int32_t count, const rsai_csc *As, rsai_params &p, hipStream_t s) {
+    if (p.tune_count <= 0 || p.sched == RSAI_SCHED_PLAIN) return RSAI_OK;
+    if (p.tier0 >= 0 && p.refill >= 0 && p.route >= 0 && p.t0_hash >= 0 && p.last_tier >= 0) return RSAI_OK;
+    std::vector<int32_t> maxlen(count, 0);
+    int32_t *d = (int32_t *)dev_alloc(4 * (size_t)count, s);
+    if (!d) return fail(RSAI_E_NOMEM, "tuning: longest-column buffer");
+    launch_fill_i32(d, 0, count, s);
+    for (int i = 0; i < count; ++i) launch_max_collen(As[i].n, As[i].colptr, d + i, s);
+    const bool ok = hipMemcpyAsync(maxlen.data(), d, 4 * (size_t)count, hipMemcpyDeviceToHost, s) == hipSuccess &&
+                    hipStreamSynchronize(s) == hipSuccess;
+    dev_free(d, s);
+    if (!ok) return fail(RSAI_E_HIP, "tuning: longest-column readback failed");
+    int big = 0;
+    for (int i = 1; i < count; ++i)
+        if (As[i].n > As[big].n) big = i;
+    int t0 = -1, rf = -1, rt = -1, hh = -1, lt = -1;
+    for (int i = 0; i < count; ++i) {
+        const double mean = (double)As[i].nnz / (double)As[i].n;
+        for (int e = 0; e < p.tune_count; ++e) {
+            const rsai_tune_entry &E = p.tune_table[e];
+            if (E.len_lo <= mean && mean < E.len_hi && E.maxlen_lo <= maxlen[i] && maxlen[i] < E.maxlen_hi &&
+                E.n_lo <= As[i].n && As[i].n < E.n_hi) {
+                t0 = (t0 < 0) ? E.tier0 : std::min(t0, E.tier0);
+                rt = std::max(rt, E.route);
+                lt = std::max(lt, E.last_tier);
+                if (i == big) {
+                    rf = E.refill;
+                    hh = E.t0_hash;
+                }
+                break;
+            }
+        }
+    }
+    if (p.tier0 < 0 && t0 >= 0 && t0 < kNumTiers) p.tier0 = t0;
+    if (p.refill < 0 && (rf == 0 || rf == 1)) p.refill = rf;
+    if (p.route < 0 && (rt == 0 || rt == 1)) p.route = rt;
+    if (p.t0_hash < 0 && (hh == 2 || hh == 4)) p.t0_hash = hh;
+    if (p.last_tier < 0 && lt >= 1 && lt < kNumTiers && lt >= p.tier0) p.last_tier = lt;
+    return RSAI_OK;
+}
+
 static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_params *prm, void *stream,
                               rsai_plan **out) {
     if (!out) return fail(RSAI_E_ARG, "out is NULL");
@@ -291,8 +348,11 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
     }
     if (ncols > INT32_MAX - 1) return fail(RSAI_E_ARG, "too many columns in one build");
     (void)hipGetLastError();  // clear an error left by an unrelated earlier call
+    rsai_params pp = *prm;
+    st = apply_tune_table(count, As, pp, (hipStream_t)stream);
+    if (st != RSAI_OK) return st;
     rsai_plan *P = new rsai_plan();
-    P->p = *prm;
+    P->p = pp;
 
     P->stream = (hipStream_t)stream;
     hipStream_t s = P->stream;
@@ -324,7 +384,14 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
     // for every size class that may finish it
     const bool plain = (P->p.sched == RSAI_SCHED_PLAIN);
     const int t0 = plain ? kPlainTier : ((P->p.tier0 >= 0) ? P->p.tier0 : 0);
-    const int tlast = plain ? kPlainTier : kNumTiers - 1;
+    const int tlast = plain ? kPlainTier : ((P->p.last_tier > 0) ? P->p.last_tier : kNumTiers - 1);
+    const int hash4 = (P->p.t0_hash == 4) ? 1 : 0;
+    if (t0 > tlast) return bail(fail(RSAI_E_ARG, "tier0 is past the last register tier"));
+    P->sched_t0 = t0;
+    P->sched_refill = sync_refill_default(P->p.refill);
+    P->sched_route = route_default(P->p.route);
+    P->sched_hash = hash4 ? 4 : 2;
+    P->sched_last = tlast;
     int64_t slot_base[8] = {};
     int64_t acap = 0;
     for (int t = t0; t <= tlast; ++t) {
@@ -538,7 +605,7 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
                 int64_t want = (L == 0) ? (ncols + gpw - 1) / gpw : (int64_t)cus * 8;
                 int waves = (int)std::max<int64_t>(8, std::min<int64_t>(want, (int64_t)cus * 16));
                 waves = (waves + 7) / 8 * 8;
-                launch_tier_kernel(t, a, waves, s);
+                launch_tier_kernel(t, 0, a, waves, s);
             }
             P->record(2, s);
         } else {
@@ -576,7 +643,7 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
                 int64_t want = (t == t0) ? (ncols + gpw - 1) / gpw : (int64_t)cus * 4 * kTiers[t].WPS;
                 int waves = (int)std::max<int64_t>(8, std::min<int64_t>(want, (int64_t)cus * 16));
                 waves = (waves + 7) / 8 * 8;
-                launch_tier_kernel(t, a, waves, s);
+                launch_tier_kernel(t, hash4, a, waves, s);
                 if (t == t0) P->record(2, s);
             }
             if (big) {
@@ -705,41 +772,61 @@ rsai_status rsai_autotune(const rsai_csc *A, const rsai_params *p, int32_t reps,
     if (st != RSAI_OK) return st;
     int32_t nout = 0, ib = -1;
     for (int t0 = 0; t0 < kNumTiers; ++t0)
-        for (int rf = 0; rf <= 1; ++rf)
-            for (int rt = 0; rt <= 1; ++rt) {
-                rsai_params q = *p;
-                q.sched = RSAI_SCHED_BATCHED;
-                q.tier0 = t0;
-                q.refill = rf;
-                q.route = rt;
-                q.timing = 1;
-                std::vector<double> ms;
-                for (int r = 0; r < reps + 1; ++r) {
-                    rsai_plan *P = nullptr;
-                    st = rsai_build(A, &q, stream, &P);
-                    if (st != RSAI_OK) return st;
-                    int64_t nz = 0;
-                    st = rsai_plan_nnz(P, 0, &nz);
-                    double tm[6] = {};
-                    if (st == RSAI_OK) st = rsai_plan_timing(P, tm, 6);
-                    rsai_destroy(P);
-                    if (st != RSAI_OK) return st;
-                    if (r > 0) ms.push_back(tm[4]);  // the first build warms the allocator
-                }
-                std::sort(ms.begin(), ms.end());
-                if (nout < cap) {
-                    rsai_tune_choice &c = out[nout];
-                    c.tier0 = t0;
-                    c.refill = rf;
-                    c.route = rt;
-                    c.reserved = 0;
-                    c.ms = ms[ms.size() / 2];
-                    if (ib < 0 || c.ms < out[ib].ms) ib = nout;
-                    ++nout;
-                }
-            }
+        for (int lt = 1; lt < kNumTiers; ++lt)
+            for (int hh = 2; hh <= 4; hh += 2)
+                for (int rf = 0; rf <= 1; ++rf)
+                    for (int rt = 0; rt <= 1; ++rt) {
+                        if (lt < t0 || (hh == 4 && t0 != 0)) continue;  // no such schedule
+                        rsai_params q = *p;
+                        q.sched = RSAI_SCHED_BATCHED;
+                        q.tier0 = t0;
+                        q.refill = rf;
+                        q.route = rt;
+                        q.t0_hash = hh;
+                        q.last_tier = lt;
+                        q.tune_count = 0;
+                        q.tune_table = nullptr;
+                        q.timing = 1;
+                        std::vector<double> ms;
+                        for (int r = 0; r < reps + 1; ++r) {
+                            rsai_plan *P = nullptr;
+                            st = rsai_build(A, &q, stream, &P);
+                            if (st != RSAI_OK) return st;
+                            int64_t nz = 0;
+                            st = rsai_plan_nnz(P, 0, &nz);
+                            double tm[6] = {};
+                            if (st == RSAI_OK) st = rsai_plan_timing(P, tm, 6);
+                            rsai_destroy(P);
+                            if (st != RSAI_OK) return st;
+                            if (r > 0) ms.push_back(tm[4]);  // the first build warms the allocator
+                        }
+                        std::sort(ms.begin(), ms.end());
+                        if (nout < cap) {
+                            rsai_tune_choice &c = out[nout];
+                            c.tier0 = t0;
+                            c.refill = rf;
+                            c.route = rt;
+                            c.t0_hash = hh;
+                            c.last_tier = lt;
+                            c.reserved = 0;
+                            c.ms = ms[ms.size() / 2];
+                            if (ib < 0 || c.ms < out[ib].ms) ib = nout;
+                            ++nout;
+                        }
+                    }
     *count = nout;
     *best = ib;
+    return RSAI_OK;
+}
+
+rsai_status rsai_plan_schedule(const rsai_plan *P, int32_t *tier0, int32_t *refill, int32_t *route, int32_t *t0_hash,
+                               int32_t *last_tier) {
+    if (!P) return fail(RSAI_E_ARG, "plan is NULL");
+    if (tier0) *tier0 = P->sched_t0;
+    if (refill) *refill = P->sched_refill;
+    if (route) *route = P->sched_route;
+    if (t0_hash) *t0_hash = P->sched_hash;
+    if (last_tier) *last_tier = P->sched_last;
     return RSAI_OK;
 }
 
@@ -1268,13 +1355,9 @@ rsai_status rsai_backward(rsai_plan *P, int32_t mat, const double *dM_val, doubl
         M.maxq_nofac = h2[3];
         M.nlarge = h2[4];
     }
-    // columns on a kept factor: |J_k| <= 128; refactorised columns: |J_k| <= 32, |I_k| <= 64
-    if (foff && M.maxq > backward_factored_max_cols())
+    // columns on a kept factor: |J_k| <= 128 (every column the build can produce)
+    if (M.maxq > backward_factored_max_cols())
         return fail(RSAI_E_CAP, "adjoint supports |J_k| <= %d; this M has %d", backward_factored_max_cols(), M.maxq);
-    if (M.nofac > 0 && (M.maxq_nofac > backward_max_cols() || M.maxm > backward_max_rows()))
-        return fail(RSAI_E_CAP, "adjoint without a kept factor supports |J_k| <= %d and |I_k| <= %d; "
-                    "%d such columns reach %d and %d (keep_factors lifts this)", backward_max_cols(),
-                    backward_max_rows(), M.nofac, M.maxq_nofac, M.maxm);
     BwdArgs a{};
     a.mats = P->d_mats;
     a.mat = mat;
@@ -1288,11 +1371,152 @@ rsai_status rsai_backward(rsai_plan *P, int32_t mat, const double *dM_val, doubl
     a.err = P->err;
     a.fac = P->out.fac;
     a.foff = foff;
+    // columns without a kept factor beyond the refactorising kernel's block: their
+    // factor is recomputed into a temporary store (one host read for its size)
+    const bool recompute = M.nofac > 0 && (M.maxq_nofac > backward_max_cols() || M.maxm > backward_max_rows());
+    std::vector<void *> tmp;
+    auto release = [&]() {
+        for (void *q : tmp) dev_free(q, s);
+        tmp.clear();
+    };
+    int64_t *tfoff = nullptr, *mask = nullptr;
+    double *tfac = nullptr;
+    if (recompute) {
+        const int64_t n = M.A.n;
+        auto al = [&](size_t bytes) -> void * {
+            void *q = dev_alloc(std::max<size_t>(bytes, 8), s);
+            if (q) tmp.push_back(q);
+            return q;
+        };
+        unsigned long long *cur = (unsigned long long *)al(32);  // cursor, size, error flags
+        tfoff = (int64_t *)al(8 * (size_t)n);
+        mask = (int64_t *)al(8 * (size_t)n);
+        if (!cur || !tfoff || !mask) {
+            release();
+            return fail(RSAI_E_NOMEM, "adjoint work buffers");
+        }
+        RefArgs r{};
+        r.mats = P->d_mats;
+        r.mat = mat;
+        r.n = n;
+        r.Mcolptr = M.colptrM;
+        r.Mrowidx = M.rowidxM;
+        r.nI = P->out.nI + M.col_base;
+        r.foff = foff;
+        r.small_cols = backward_max_cols();
+        r.small_rows = backward_max_rows();
+        r.cur = cur;
+        r.tfoff = tfoff;
+        r.err = (int32_t *)(cur + 2);
+        launch_fill_i64((int64_t *)cur, 0, 4, s);
+        launch_refactor_size(r, cur + 1, s);
+        unsigned long long need = 0;
+        if (hipMemcpyAsync(&need, cur + 1, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            release();
+            return fail(RSAI_E_HIP, "adjoint: size readback failed");
+        }
+        tfac = (double *)al(8 * (size_t)std::max<unsigned long long>(need, 1));
+        if (!tfac) {
+            release();
+            return fail(RSAI_E_NOMEM, "recomputed factor store (%llu doubles)", need);
+        }
+        r.fac = tfac;
+        r.cap = (int64_t)need;
+        launch_fill_i64(tfoff, -1, n, s);
+        launch_refactor(r, device_cus(), s);
+        launch_merge_masks(n, foff, tfoff, mask, s);
+        int32_t ferr = 0;
+        if (hipMemcpyAsync(&ferr, r.err, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            release();
+            return fail(RSAI_E_HIP, "adjoint: factor recomputation failed");
+        }
+        if (ferr) {
+            release();
+            return fail(ferr & 32 ? RSAI_E_SINGULAR : RSAI_E_STATE,
+                        "adjoint: recomputing a column's factor failed (flags %d: 32 A_k^T A_k not positive "
+                        "definite, 64 store too small); nothing was accumulated", ferr);
+        }
+    }
+    // fixed-order mode: a slot per contribution (one host read for their number)
+    unsigned long long *ccur = nullptr;
+    unsigned long long *ck2 = nullptr;
+    double *cv2 = nullptr;
+    void *ctemp = nullptr;
+    size_t ctemp_bytes = 0;
+    if (P->p.deterministic) {
+        auto al = [&](size_t bytes) -> void * {
+            void *q = dev_alloc(std::max<size_t>(bytes, 8), s);
+            if (q) tmp.push_back(q);
+            return q;
+        };
+        ccur = (unsigned long long *)al(16);
+        if (!ccur) {
+            release();
+            return fail(RSAI_E_NOMEM, "adjoint work buffers");
+        }
+        launch_fill_i64((int64_t *)ccur, 0, 2, s);
+        launch_contrib_count(P->d_mats, mat, M.A.n, M.colptrM, M.rowidxM, ccur + 1, s);
+        unsigned long long cnt = 0;
+        if (hipMemcpyAsync(&cnt, ccur + 1, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            release();
+            return fail(RSAI_E_HIP, "adjoint: contribution count readback failed");
+        }
+        if (cnt > (unsigned long long)INT32_MAX) {
+            release();
+            return fail(RSAI_E_CAP, "fixed-order adjoint: %llu contributions exceed 2^31", cnt);
+        }
+        ctemp_bytes = det_reduce_bytes((int64_t)cnt);
+        a.ckey = (unsigned long long *)al(8 * (size_t)cnt);
+        a.cval = (double *)al(8 * (size_t)cnt);
+        ck2 = (unsigned long long *)al(8 * (size_t)cnt);
+        cv2 = (double *)al(8 * (size_t)cnt);
+        ctemp = al(ctemp_bytes);
+        if (!a.ckey || !a.cval || !ck2 || !cv2 || !ctemp) {
+            release();
+            return fail(RSAI_E_NOMEM, "fixed-order adjoint buffers (%llu contributions)", cnt);
+        }
+        a.ccur = ccur;
+        a.ccap = (int64_t)cnt;
+    }
     P->record(5, s);
     if (foff) launch_backward_factored(a, device_cus(), M.nlarge > 0, s);
-    if (!foff || M.nofac > 0) launch_backward(a, device_cus() * 8, s);
+    if (recompute) {
+        BwdArgs b = a;
+        b.fac = tfac;
+        b.foff = tfoff;
+        launch_backward_factored(b, device_cus(), M.maxq_nofac > backward_max_cols(), s);
+        b.foff = mask;  // the rest of the columns without a kept factor
+        launch_backward(b, device_cus() * 8, s);
+    } else if (!foff || M.nofac > 0) {
+        launch_backward(a, device_cus() * 8, s);
+    }
+    if (P->p.deterministic) {
+        // the appended contributions, sorted by (entry, column), summed per entry
+        unsigned long long used = 0;
+        if (hipMemcpyAsync(&used, ccur, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            release();
+            return fail(RSAI_E_HIP, "adjoint: contribution readback failed");
+        }
+        if (used > (unsigned long long)a.ccap) {
+            release();
+            return fail(RSAI_E_STATE, "fixed-order adjoint: %llu contributions for %lld slots", used,
+                        (long long)a.ccap);
+        }
+        if (det_reduce(a.ckey, a.cval, ck2, cv2, (int64_t)used, ctemp, ctemp_bytes, dA_val, s) != hipSuccess) {
+            release();
+            return fail(RSAI_E_HIP, "fixed-order adjoint: sort or sum failed");
+        }
+    }
     P->record(6, s);
-    HIPCHK(hipGetLastError());
+    const hipError_t le = hipGetLastError();
+    // stream-ordered release: the kernels queued on s still read these buffers
+    for (void *q : tmp) dev_free(q, s);
+    tmp.clear();
+    if (le != hipSuccess) return fail(RSAI_E_HIP, "adjoint launch failed: %s", hipGetErrorString(le));
     return RSAI_OK;
 }
 

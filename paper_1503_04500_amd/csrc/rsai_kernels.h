@@ -20,7 +20,7 @@ extern const TierInfo kTiers[];
 extern const int kNumTiers;
 extern const int kPlainTier;  // the one size class of the plain schedule
 
-void launch_tier_kernel(int tier, const TierArgs &a, int waves, hipStream_t s);
+void launch_tier_kernel(int tier, int hash4, const TierArgs &a, int waves, hipStream_t s);
 
 // ---- sparse-block size class (rsai_wide.hip): one workgroup per column, LS solved
 // on the compressed block (shared rows + one row per column)
@@ -85,6 +85,8 @@ void launch_row_fill(int64_t n, const int64_t *colptr, const int32_t *rowidx, co
 void launch_mat_stats(int64_t n, const int64_t *colptr, const double *val, const int32_t *rowcnt,
                       unsigned long long *stats, const int32_t *err, hipStream_t s);
 void launch_fill_many(int32_t *const *p, const int64_t *count, const int32_t *v, int k, hipStream_t s);
+// longest column of a CSC matrix into *out (atomic max; *out zeroed by the caller)
+void launch_max_collen(int64_t n, const int64_t *colptr, int32_t *out, hipStream_t s);
 void launch_summary(int64_t n, const int64_t *colptrM, const int32_t *status, const int32_t *err, int64_t *out,
                     hipStream_t s);
 
@@ -197,7 +199,23 @@ struct BwdArgs {
     int32_t *err;
     const double *fac;      // kept R factors (nullable)
     const int64_t *foff;    // per column of this matrix: record offset or -1 (nullable)
+    // fixed-order mode (ckey != nullptr): every contribution to dA is appended as
+    // (key = entry << 32 | column, value) at a slot reserved per column instead of
+    // being added with an atomic, and r, A_k z are summed over J_k in ascending order
+    unsigned long long *ckey;
+    double *cval;
+    unsigned long long *ccur;  // slots handed out
+    int64_t ccap;
 };
+// contributions the adjoint of matrix mat would append: sum over the entries (j, k)
+// of M of the length of column j of A (into *total, one atomic per workgroup)
+void launch_contrib_count(const MatDev *mats, int mat, int64_t n, const int64_t *Mcolptr, const int32_t *Mrowidx,
+                          unsigned long long *total, hipStream_t s);
+// sort the appended contributions by (entry, column) and add each entry's sum, taken in
+// column order, into dA; temp: device bytes returned by det_reduce_bytes
+size_t det_reduce_bytes(int64_t count);
+hipError_t det_reduce(unsigned long long *key, double *val, unsigned long long *key2, double *val2, int64_t count,
+                      void *temp, size_t temp_bytes, double *dA, hipStream_t s);
 int backward_max_cols();
 int backward_max_rows();
 int backward_factored_max_cols();
@@ -212,6 +230,27 @@ void max2_combine(const int32_t *h, int32_t *out5);
 int fma_probe_chains();
 void launch_fma_probe(int blocks, int64_t iters, double *out, hipStream_t s);
 void launch_backward(const BwdArgs &a, int waves, hipStream_t s);
+// recomputed factors for the adjoint: columns without a kept factor and beyond the
+// refactorising kernel's block (|J_k| > small_cols or |I_k| > small_rows), |J_k| <= 128
+struct RefArgs {
+    const MatDev *mats;
+    int mat;
+    int64_t n;
+    const int64_t *Mcolptr;
+    const int32_t *Mrowidx;
+    const int32_t *nI;        // |I_k| of the matrix's columns
+    const int64_t *foff;      // kept factors (nullable)
+    int small_cols, small_rows;
+    double *fac;              // temporary store
+    int64_t cap;              // its size in doubles
+    unsigned long long *cur;  // doubles handed out
+    int64_t *tfoff;           // record offset per column in the temporary store, -1 none
+    int32_t *err;             // bit 32: rank-deficient A_k, bit 64: store too small
+};
+int refactor_max_cols();
+void launch_refactor_size(const RefArgs &r, unsigned long long *total, hipStream_t s);
+void launch_refactor(const RefArgs &r, int cus, hipStream_t s);
+void launch_merge_masks(int64_t n, const int64_t *a, const int64_t *b, int64_t *out, hipStream_t s);
 // 16 lanes per column for |J_k| <= 32; with large also a wavefront per column for
 // 32 < |J_k| <= 128. Persistent grids of as many workgroups as fit on cus CUs.
 void launch_backward_factored(const BwdArgs &a, int cus, bool large, hipStream_t s);

@@ -80,6 +80,17 @@ void launch_fill_many(int32_t *const *p, const int64_t *count, const int32_t *v,
 
 // summary for the host: out[0] = colptrM[n] (nnz of M), out[1] = error flags,
 // out[2..4] = columns with status singular / cap / anything else not ok
+__global__ void k_max_collen(int64_t n, const int64_t *colptr, int32_t *out) {
+    int m = 0;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, (int)(colptr[j + 1] - colptr[j]));
+    for (int off = 32; off >= 1; off >>= 1) m = max(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, m);
+}
+void launch_max_collen(int64_t n, const int64_t *colptr, int32_t *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_max_collen, dim3(std::min(nblocks(n, 256), 1024)), dim3(256), 0, s, n, colptr, out);
+}
+
 __global__ void k_summary(int64_t n, const int64_t *colptrM, const int32_t *status, const int32_t *err,
                           int64_t *out) {
     int64_t a = 0, b = 0, c = 0;

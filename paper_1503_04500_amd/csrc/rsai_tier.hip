@@ -11,9 +11,12 @@ const TierInfo kTiers[] = {
 const int kNumTiers = 3;
 const int kPlainTier = 1;
 
-void launch_tier_kernel(int tier, const TierArgs &a, int waves, hipStream_t s) {
+void launch_tier_kernel(int tier, int hash4, const TierArgs &a, int waves, hipStream_t s) {
     switch (tier) {
-        case 0: launch_tier<Tier0>(a, waves, s); break;
+        case 0:
+            if (hash4) launch_tier0_h4(a, waves, s);
+            else launch_tier<Tier0>(a, waves, s);
+            break;
         case 1: launch_tier<Tier1>(a, waves, s); break;
         case 2: launch_tier2(a, waves, s); break;
         default: break;

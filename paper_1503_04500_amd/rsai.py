@@ -33,7 +33,16 @@ class Params(ctypes.Structure):
                 ("drop", ctypes.c_int32), ("tol", ctypes.c_double), ("sched", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("tier0", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("refill", ctypes.c_int32), ("route", ctypes.c_int32),
-                ("keep_factors", ctypes.c_int32), ("factor_budget_bytes", ctypes.c_int64)]
+                ("keep_factors", ctypes.c_int32), ("factor_budget_bytes", ctypes.c_int64),
+                ("deterministic", ctypes.c_int32), ("tune_count", ctypes.c_int32),
+                ("tune_table", ctypes.c_void_p), ("t0_hash", ctypes.c_int32), ("last_tier", ctypes.c_int32)]
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("len_lo", ctypes.c_double), ("len_hi", ctypes.c_double), ("maxlen_lo", ctypes.c_int64),
+                ("maxlen_hi", ctypes.c_int64), ("n_lo", ctypes.c_int64), ("n_hi", ctypes.c_int64),
+                ("tier0", ctypes.c_int32), ("refill", ctypes.c_int32), ("route", ctypes.c_int32),
+                ("t0_hash", ctypes.c_int32), ("last_tier", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class CSCView(ctypes.Structure):
@@ -99,6 +108,7 @@ def load():
         "rsai_tier_info": [I32, P, P, P],
         "rsai_rebuild": [P, I32, P],
         "rsai_autotune": [P, P, I32, P, P, I32, P, P],
+        "rsai_plan_schedule": [P, P, P, P, P, P],
         "rsai_destroy": [P],
     }
     for name, args in sigs.items():
@@ -207,7 +217,8 @@ def permute_rows(A: Matrix, p) -> Matrix:
 
 
 def params(c=3, lmax=10, eps=0.4, drop="fixed", tol=1e-3, sched="batched", validate=True, tier0=-1,
-           timing=False, refill=-1, route=-1, keep_factors=False, factor_budget_bytes=0):
+           timing=False, refill=-1, route=-1, keep_factors=False, factor_budget_bytes=0, deterministic=False,
+           t0_hash=-1, last_tier=-1):
     p = Params()
     _check(load().rsai_params_default(ctypes.byref(p)))
     p.c, p.lmax, p.eps, p.tol = int(c), int(lmax), float(eps), float(tol)
@@ -220,6 +231,9 @@ def params(c=3, lmax=10, eps=0.4, drop="fixed", tol=1e-3, sched="batched", valid
     p.route = int(route)
     p.keep_factors = 1 if keep_factors else 0
     p.factor_budget_bytes = int(factor_budget_bytes)
+    p.deterministic = 1 if deterministic else 0
+    p.t0_hash = int(t0_hash)
+    p.last_tier = int(last_tier)
     return p
 
 
@@ -314,6 +328,12 @@ class Plan:
         (rsai_rebuild; graph=True replays a captured HIP graph)."""
         _check(load().rsai_rebuild(self._hv(), 1 if graph else 0, _stream(stream)))
 
+    def schedule(self):
+        """The schedule the build used (rsai_plan_schedule)."""
+        v = [ctypes.c_int32() for _ in range(5)]
+        _check(load().rsai_plan_schedule(self._hv(), *[ctypes.byref(x) for x in v]))
+        return dict(zip(("tier0", "refill", "route", "t0_hash", "last_tier"), (x.value for x in v)))
+
     def timing(self):
         ms = (ctypes.c_double * 6)()
         _check(load().rsai_plan_timing(self._hv(), ms, 6))
@@ -325,37 +345,36 @@ def build(A: Matrix, stream=None, **kw) -> Plan:
     return build_batched([A], stream=stream, **kw)
 
 
-def _tuned(mats, kw):
-    """Fill schedule choices left at their defaults from the tuning table."""
-    keys = ("tier0", "refill", "route")
-    if kw.get("sched", "batched") not in ("batched", 0) or all(kw.get(k, -1) != -1 for k in keys):
-        return kw
+def tune_entries(table=None):
+    """The tuning table (tune.load_table entries, or the given list of dicts) as the C
+    ABI's rsai_tune_entry array; fields an entry lacks are -1 (not applied)."""
     from . import tune
-    # one choice per matrix; a batch starts in the smallest tier any of its matrices
-    # wants (a column that outgrows it moves on; one that starts too large is slow)
-    chs = [c for c in (tune.choose(m.n, m.nnz / max(m.n, 1), m.max_col_len) for m in mats) if c]
-    if not chs:
-        return kw
-    big = max(range(len(mats)), key=lambda i: mats[i].n)
-    ch = {"tier0": min(c["tier0"] for c in chs), "refill": chs[min(big, len(chs) - 1)]["refill"],
-          "route": max(c["route"] for c in chs)}
-    kw = dict(kw)
-    for k in keys:
-        if kw.get(k, -1) == -1:
-            kw[k] = ch[k]
-    return kw
+    rows = tune.load_table() if table is None else table
+    arr = (TuneEntry * max(len(rows), 1))()
+    for i, e in enumerate(rows):
+        arr[i] = TuneEntry(float(e["len_lo"]), float(e["len_hi"]), int(e["maxlen_lo"]), int(e["maxlen_hi"]),
+                           int(e["n_lo"]), int(e["n_hi"]), int(e.get("tier0", -1)), int(e.get("refill", -1)),
+                           int(e.get("route", -1)), int(e.get("t0_hash", -1)), int(e.get("last_tier", -1)), 0)
+    return arr, len(rows)
 
 
-def build_batched(mats, stream=None, **kw) -> Plan:
-    """Build M for several matrices in one pass (rsai_build_batched). Schedule choices
-    left at -1 come from the tuning table (tune.choose) when it has a matching entry."""
+def build_batched(mats, stream=None, tune_table=None, **kw) -> Plan:
+    """Build M for several matrices in one pass (rsai_build_batched). The tuning table
+    (tuning.json, or tune_table: a list of entries; [] for none) goes to the library
+    through rsai_params, which applies it to the schedule fields left at -1."""
     lib = load()
     _use_torch_allocator()
-    prm = params(**_tuned(mats, kw))
+    prm = params(**kw)
+    entries, count = tune_entries(tune_table)
+    if count:
+        prm.tune_table = ctypes.cast(entries, ctypes.c_void_p)
+        prm.tune_count = count
     views = (CSCView * len(mats))(*[m.view() for m in mats])
     h = ctypes.c_void_p()
     st = _stream(stream)
     _check(lib.rsai_build_batched(len(mats), views, ctypes.byref(prm), st, ctypes.byref(h)))
+    prm.tune_table = None  # the table is read during the call only
+    prm.tune_count = 0
     return Plan(h, list(mats), prm, st)
 
 

@@ -1,12 +1,13 @@
 """Autotuner of the batched build and the tuning table it writes.
 
-The batched build has three schedule choices that do not change its results: the
+The batched build has schedule choices that do not change its results: the
 register tier the columns start in (tier0), how the first tier refills its waves
-(refill) and where spilled columns go (route). ``autotune`` times every combination
+(refill), where spilled columns go (route), the size of the first tier's hash
+tables (t0_hash, a tile choice) and the last register tier (last_tier, a class edge). ``autotune`` times every combination
 on a matrix (rsai_autotune: median build time over repetitions, HIP events);
 ``main`` tunes a set of synthetic workloads and writes ``tuning.json``; ``choose``
-looks a matrix up in it by mean column length, longest column and n, and
-``rsai.build`` applies the choice to every schedule field left at -1.
+looks a matrix up in it by mean column length, longest column and n (the same rule
+the library applies when ``rsai.build`` hands it the table through rsai_params).
 """
 from __future__ import annotations
 
@@ -21,7 +22,10 @@ TABLE = os.path.join(HERE, "tuning.json")
 
 class Choice(ctypes.Structure):
     _fields_ = [("tier0", ctypes.c_int32), ("refill", ctypes.c_int32), ("route", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("ms", ctypes.c_double)]
+                ("t0_hash", ctypes.c_int32), ("last_tier", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
+
+KEYS = ("tier0", "refill", "route", "t0_hash", "last_tier")
 
 
 def autotune(A, reps: int = 3, **kw) -> dict:
@@ -36,7 +40,8 @@ def autotune(A, reps: int = 3, **kw) -> dict:
     cnt, best = ctypes.c_int32(), ctypes.c_int32()
     rsai._check(lib.rsai_autotune(ctypes.byref(view), ctypes.byref(prm), int(reps), rsai._stream(), out, 64,
                                   ctypes.byref(cnt), ctypes.byref(best)))
-    ch = [dict(tier0=c.tier0, refill=c.refill, route=c.route, ms=c.ms) for c in out[:cnt.value]]
+    ch = [dict(tier0=c.tier0, refill=c.refill, route=c.route, t0_hash=c.t0_hash, last_tier=c.last_tier, ms=c.ms)
+          for c in out[:cnt.value]]
     return {"choices": ch, "best": ch[best.value]}
 
 
@@ -63,7 +68,7 @@ def choose(n: int, mean_len: float, max_len: int, table=None):
     for e in (load_table() if table is None else table):
         if (e["len_lo"] <= mean_len < e["len_hi"] and e["maxlen_lo"] <= max_len < e["maxlen_hi"]
                 and e["n_lo"] <= n < e["n_hi"]):
-            return {"tier0": e["tier0"], "refill": e["refill"], "route": e["route"]}
+            return {k: e.get(k, -1) for k in KEYS}
     return None
 
 
@@ -98,8 +103,8 @@ def main(argv=None) -> int:
         b = r["best"]
         entries.append(dict(len_lo=r["mean_col_len"] * 0.8, len_hi=r["mean_col_len"] * 1.25,
                             maxlen_lo=max(1, r["max_col_len"] // 2), maxlen_hi=r["max_col_len"] * 2 + 1,
-                            n_lo=r["n"] // 4, n_hi=r["n"] * 4, tier0=b["tier0"], refill=b["refill"],
-                            route=b["route"], workload=r["workload"]))
+                            n_lo=r["n"] // 4, n_hi=r["n"] * 4, workload=r["workload"],
+                            **{k: b[k] for k in KEYS}))
     with open(out_path, "w") as f:
         json.dump({"device": torch.cuda.get_device_name(0), "entries": entries, "results": results}, f, indent=1)
     print("wrote", out_path)

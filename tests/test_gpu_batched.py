@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 from paper_1503_04500_amd import gen
-from tests.parity import compare, subset
+from tests.parity import compare
 
 pytestmark = pytest.mark.gpu
 
@@ -50,16 +50,22 @@ def test_batched_equals_single_builds():
             assert np.array_equal(res[i][key], one[key]), f"matrix {i}: {key}"
 
 
-def test_c5_sampled_columns():
+def test_c5_full_parity():
     """The 64-matrix batch (2D/3D convection-diffusion and power-law, n log-uniform in
-    [4096, 262144], sum about 4e6) in one build; 40 seeded columns of every matrix
-    recomputed by the oracle."""
+    [4096, 262144], sum about 3.8e6) in one build, every column of every matrix against
+    the oracle. A differing pattern is accepted only where the oracle decided at a
+    margin below 1e-14 (reported); the rest meet the full bar."""
+    from tests.parity import divergence_report, divergent_columns, trajectory_divergences
     specs = gen.batch64_specs()
     mats = [gen.make(s) for s in specs]
     assert 3.0e6 < sum(A.n for A in mats) < 5.5e6
     res = _run_batched(mats, **KW)
-    rng = np.random.default_rng(3)
+    ndiv = 0
     for i, (A, g) in enumerate(zip(mats, res)):
-        cols = np.sort(rng.choice(A.n, 40, replace=False))
-        ref = oracle.rsai(A, drop=1, cols=cols, **KW)
-        compare(A, subset(g, cols), ref, label=f"C5[{i}] {specs[i][0]}")
+        ref = oracle.rsai(A, drop=1, **KW)
+        div = trajectory_divergences(g, ref)
+        ndiv += div.size
+        for line in divergence_report(g, ref, div):
+            print(f"C5[{i}] " + line, flush=True)
+        compare(A, g, ref, label=f"C5[{i}] {specs[i][0]}", margin_tol=1e-14)
+    print(f"C5: {ndiv} columns of {sum(A.n for A in mats)} with a rounding-level pattern divergence", flush=True)

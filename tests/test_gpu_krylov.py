@@ -98,19 +98,36 @@ def test_zero_rhs_and_loose_tolerance_return_at_once():
 
 
 def test_cd2d_512_converges_like_oracle():
-    """The 512x512 benchmark matrix: the GPU solve passes the stopping test (checked
-    here in FP64 on the host) and its count lies within rounding-level chaos of the
-    oracle's count on the same M (the count moves with perturbations of 1e-13)."""
+    """The 512x512 benchmark matrix, end to end (Section 5 protocol, b = A 1): the
+    BiCGStab count with the GPU's M against the count with the oracle's own M. The
+    count is chaotic in the last bits of M, so the bound is an ensemble: the oracle's
+    M perturbed at the size of the observed GPU/oracle difference, solved by the same
+    host solver; the GPU's M, solved by that solver, must fall inside the ensemble's
+    spread. The device solver (its own rounding) must pass the stopping test in FP64
+    and stay within that spread of the host solve on the same M."""
     A = gen.c2()
     prm = dict(C1, drop="fixed")
     gpu = run_gpu(A, **prm)
+    ref = oracle.rsai(A, **C1)
+    assert np.array_equal(gpu["rowidx"], ref["rowidx"])
     b = A.matvec(np.ones(A.n))
     x, it, rel = _solve(gpu, b)
     assert 0 < it <= 1000 and rel < 1e-8
     assert _true_rel(A, x, b) < 1e-8 * (1 + 1e-6)
-    it_o, rel_o, _ = oracle.bicgstab(A, b, (gpu["colptr"], gpu["rowidx"], gpu["val"]))
-    assert 0 < it_o <= 1000
-    assert abs(it - it_o) <= max(3, it_o // 5), (it, it_o)
+    it_g, rel_g, _ = oracle.bicgstab(A, b, (gpu["colptr"], gpu["rowidx"], gpu["val"]))
+    it_o, rel_o, _ = oracle.bicgstab(A, b, (ref["colptr"], ref["rowidx"], ref["val"]))
+    delta = max(float(np.max(np.abs(gpu["val"] - ref["val"]) / np.abs(ref["val"]))), 1e-15)
+    its = [it_o]
+    for s in range(6):
+        v = ref["val"] * (1 + delta * np.random.default_rng(s).standard_normal(ref["val"].size))
+        its.append(oracle.bicgstab(A, b, (ref["colptr"], ref["rowidx"], v))[0])
+    lo, hi = min(its), max(its)
+    slack = max(5, (hi - lo) // 2)
+    print(f"512x512 BiCGStab iterations: oracle M {it_o}, GPU M (host solver) {it_g}, GPU M (device solver) "
+          f"{it}; oracle M perturbed by {delta:.1e}: {its[1:]}", flush=True)
+    assert all(0 < i <= 1000 for i in its) and 0 < it_g <= 1000
+    assert lo - slack <= it_g <= hi + slack, (it_g, its)
+    assert abs(it - it_g) <= max(slack, hi - lo), (it, it_g, its)
 
 
 def test_bad_arguments():

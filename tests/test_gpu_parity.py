@@ -147,6 +147,25 @@ def test_c3_sampled_columns():
     print("C3 sample", s, "max |I|", int(ref["nI"].max()))
 
 
+def test_c3_full_size_with_divergence_report():
+    """C3 in full (n = 10^6 power-law columns, c = 3, lmax = 10): every column against
+    the oracle. A column whose pattern differs is accepted only where the oracle took
+    a decision at a margin below 1e-14 (a tie in all but rounding; both outcomes are
+    results of the method); each such column is reported with both patterns, loop
+    counts and the |r| gap at the cut. Every other column meets the full bar."""
+    from tests.parity import divergence_report, divergent_columns, trajectory_divergences
+    A = gen.c3()
+    gpu = run_gpu(A, c=3, lmax=10, eps=0.4, drop="fixed", tol=1e-3)
+    ref = oracle.rsai(A, c=3, lmax=10, eps=0.4, drop=1, tol=1e-3)
+    div = trajectory_divergences(gpu, ref)
+    lines = divergence_report(gpu, ref, div)
+    print(f"C3 full: {div.size} of {A.n} columns with a different pattern or trajectory", flush=True)
+    for line in lines:
+        print("  " + line, flush=True)
+    s = compare(A, gpu, ref, label="C3-full", margin_tol=1e-14)
+    print("C3 full", s, "max |I|", int(ref["nI"].max()), flush=True)
+
+
 def test_zero_diagonals_parity():
     """Rows of a 24x24 grid matrix permuted at random: 567 of 576 diagonal entries are
     zero, so k is not in I_k at the start and r(k) = -1 enters the selection."""

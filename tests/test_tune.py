@@ -11,11 +11,17 @@ TABLE = [
 ]
 
 
+def _sub(d):
+    return {k: d[k] for k in ("tier0", "refill", "route")}
+
+
 def test_choose_matches_ranges_in_order():
-    assert tune.choose(262144, 5.0, 5, TABLE) == dict(tier0=0, refill=1, route=0)
+    assert _sub(tune.choose(262144, 5.0, 5, TABLE)) == dict(tier0=0, refill=1, route=0)
     # same mean length, told apart by the longest column
-    assert tune.choose(10**6, 7.0, 200, TABLE) == dict(tier0=1, refill=1, route=1)
-    assert tune.choose(262144, 6.9, 7, TABLE) == dict(tier0=0, refill=0, route=1)
+    assert _sub(tune.choose(10**6, 7.0, 200, TABLE)) == dict(tier0=1, refill=1, route=1)
+    assert _sub(tune.choose(262144, 6.9, 7, TABLE)) == dict(tier0=0, refill=0, route=1)
+    # fields an entry lacks come back as -1 (not applied)
+    assert tune.choose(262144, 5.0, 5, TABLE)["t0_hash"] == -1
     # outside every range
     assert tune.choose(10, 5.0, 5, TABLE) is None
     assert tune.choose(262144, 20.0, 5, TABLE) is None
@@ -29,6 +35,31 @@ def test_committed_table_is_well_formed():
     for e in entries:
         assert e["len_lo"] < e["len_hi"] and e["maxlen_lo"] < e["maxlen_hi"] and e["n_lo"] < e["n_hi"]
         assert 0 <= e["tier0"] < 3 and e["refill"] in (0, 1) and e["route"] in (0, 1)
+        assert e.get("t0_hash", -1) in (-1, 2, 4) and e.get("last_tier", -1) in (-1, 1, 2)
+
+
+def test_tune_entries_layout_and_params_checks():
+    """The binding's rsai_tune_entry matches the C layout (2 doubles, 4 int64, 6 int32)
+    and the library rejects bad schedule fields on the host."""
+    import ctypes
+    assert ctypes.sizeof(rsai.TuneEntry) == 72
+    if not os.path.exists(rsai.LIB_PATH):
+        return
+    arr, n = rsai.tune_entries(TABLE)
+    assert n == 3 and arr[1].maxlen_lo == 100 and arr[1].tier0 == 1 and arr[0].t0_hash == -1
+    lib = rsai.load()
+    out = ctypes.c_void_p()
+    v = rsai.CSCView(4, 4, 8, 8, 8)
+    for field, val in (("t0_hash", 3), ("last_tier", 0), ("last_tier", 5), ("deterministic", 2), ("tune_count", -1)):
+        q = rsai.params()
+        setattr(q, field, val)
+        assert lib.rsai_build(ctypes.byref(v), ctypes.byref(q), None, ctypes.byref(out)) == -1, field
+    q = rsai.params(tier0=2)
+    q.last_tier = 1
+    assert lib.rsai_build(ctypes.byref(v), ctypes.byref(q), None, ctypes.byref(out)) == -1
+    q = rsai.params()
+    q.tune_count = 2   # a count without a table
+    assert lib.rsai_build(ctypes.byref(v), ctypes.byref(q), None, ctypes.byref(out)) == -1
 
 
 def test_params_route_field():
