@@ -74,10 +74,12 @@ typedef enum {
 
 /* One entry of a tuning table (rsai_params.tune_table): for a matrix with n in
    [n_lo, n_hi), mean column length nnz/n in [len_lo, len_hi) and longest column in
-   [maxlen_lo, maxlen_hi), the schedule choices below (as written by rsai_autotune;
-   the first matching entry wins). */
+   [maxlen_lo, maxlen_hi), built with eps in [eps_lo, eps_hi), the schedule choices
+   below (as timed by rsai_autotune; the first matching entry wins; -1 leaves a field
+   to the default). */
 typedef struct {
     double len_lo, len_hi;
+    double eps_lo, eps_hi;   /* the build's eps in [eps_lo, eps_hi) */
     int64_t maxlen_lo, maxlen_hi;
     int64_t n_lo, n_hi;
     int32_t tier0, refill, route, t0_hash, last_tier, reserved;
@@ -103,8 +105,8 @@ typedef struct {
                          first class that holds their estimated |I_k|, |J_k| */
     int32_t keep_factors;        /* 1: keep the R factor of every column's final solve for
                                     rsai_backward (R^T R = A(I,J)^T A(I,J)) */
-    int64_t factor_budget_bytes; /* size of the factor store (0: 256 MB); columns that do not
-                                    fit are refactorised by rsai_backward */
+    int64_t factor_budget_bytes; /* size of the factor store (0: 2 GB); columns that do not
+                                    fit get their factor recomputed by rsai_backward */
     int32_t deterministic;       /* 1: rsai_backward adds every entry's contributions in a
                                     fixed order (sorted by column), so dA is bitwise
                                     repeatable; 0: FP64 atomics (faster) */
@@ -112,16 +114,18 @@ typedef struct {
     const rsai_tune_entry *tune_table; /* host array, read during rsai_build*: the schedule
                                     fields left at -1 (tier0, refill, route, t0_hash,
                                     last_tier) take the first entry matching the matrix
-                                    (for a batch: the smallest tier0, the largest route
-                                    and last_tier, refill and t0_hash of the largest
-                                    matrix's entry); no match keeps the defaults. Reading
-                                    each matrix's longest column costs one host
-                                    synchronisation */
+                                    and eps (for a batch: the smallest tier0, the largest
+                                    route and last_tier, refill and t0_hash of the
+                                    largest matrix's entry); no match keeps the
+                                    defaults */
     int32_t t0_hash;  /* hash tables of the first register tier: -1 default (2), 2 or 4 times
                          its row and column capacity (a tile choice; results unchanged) */
     int32_t last_tier; /* last register tier: -1 default (2), 1 sends the columns that
                           outgrow tier 1 straight to the sparse-block class (a class edge;
-                          results unchanged) */
+                          results agree to rounding) */
+    const int64_t *col_len_max; /* host array, one per matrix: its longest column, for the
+                          tuning table (NULL: read on the device, one host
+                          synchronisation per build) */
 } rsai_params;
 
 typedef struct rsai_plan rsai_plan; /* opaque host handle */

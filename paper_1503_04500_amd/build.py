@@ -35,7 +35,8 @@ def flags() -> list[str]:
 # per-source flags: the tier kernel's QR loops must unroll completely (constant register
 # indices), which exceeds the default threshold for the larger tiers
 SOURCE_FLAGS = {"rsai_tier.hip": ["-mllvm", "-pragma-unroll-threshold=262144"],
-                "rsai_tier0h.hip": ["-mllvm", "-pragma-unroll-threshold=262144"]}
+                "rsai_tier0h.hip": ["-mllvm", "-pragma-unroll-threshold=262144"],
+                "rsai_tier2.hip": ["-mllvm", "-pragma-unroll-threshold=262144"]}
 
 
 def build(verbose: bool = False, extra: list[str] | None = None, out: str | None = None) -> str:

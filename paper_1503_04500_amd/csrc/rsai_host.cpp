@@ -227,6 +227,7 @@ rsai_status rsai_params_default(rsai_params *p) {
     p->tune_table = nullptr;
     p->t0_hash = -1;
     p->last_tier = -1;
+    p->col_len_max = nullptr;
     return RSAI_OK;
 }
 
@@ -294,15 +295,21 @@ static int route_default(int requested) {
 static rsai_status apply_tune_table(int32_t count, const rsai_csc *As, rsai_params &p, hipStream_t s) {
     if (p.tune_count <= 0 || p.sched == RSAI_SCHED_PLAIN) return RSAI_OK;
     if (p.tier0 >= 0 && p.refill >= 0 && p.route >= 0 && p.t0_hash >= 0 && p.last_tier >= 0) return RSAI_OK;
-    std::vector<int32_t> maxlen(count, 0);
-    int32_t *d = (int32_t *)dev_alloc(4 * (size_t)count, s);
-    if (!d) return fail(RSAI_E_NOMEM, "tuning: longest-column buffer");
-    launch_fill_i32(d, 0, count, s);
-    for (int i = 0; i < count; ++i) launch_max_collen(As[i].n, As[i].colptr, d + i, s);
-    const bool ok = hipMemcpyAsync(maxlen.data(), d, 4 * (size_t)count, hipMemcpyDeviceToHost, s) == hipSuccess &&
-                    hipStreamSynchronize(s) == hipSuccess;
-    dev_free(d, s);
-    if (!ok) return fail(RSAI_E_HIP, "tuning: longest-column readback failed");
+    std::vector<int64_t> maxlen(count, 0);
+    if (p.col_len_max) {
+        for (int i = 0; i < count; ++i) maxlen[i] = p.col_len_max[i];
+    } else {
+        std::vector<int32_t> ml(count, 0);
+        int32_t *d = (int32_t *)dev_alloc(4 * (size_t)count, s);
+        if (!d) return fail(RSAI_E_NOMEM, "tuning: longest-column buffer");
+        launch_fill_i32(d, 0, count, s);
+        for (int i = 0; i < count; ++i) launch_max_collen(As[i].n, As[i].colptr, d + i, s);
+        const bool ok = hipMemcpyAsync(ml.data(), d, 4 * (size_t)count, hipMemcpyDeviceToHost, s) == hipSuccess &&
+                        hipStreamSynchronize(s) == hipSuccess;
+        dev_free(d, s);
+        if (!ok) return fail(RSAI_E_HIP, "tuning: longest-column readback failed");
+        for (int i = 0; i < count; ++i) maxlen[i] = ml[i];
+    }
     int big = 0;
     for (int i = 1; i < count; ++i)
         if (As[i].n > As[big].n) big = i;
@@ -312,7 +319,7 @@ static rsai_status apply_tune_table(int32_t count, const rsai_csc *As, rsai_para
         for (int e = 0; e < p.tune_count; ++e) {
             const rsai_tune_entry &E = p.tune_table[e];
             if (E.len_lo <= mean && mean < E.len_hi && E.maxlen_lo <= maxlen[i] && maxlen[i] < E.maxlen_hi &&
-                E.n_lo <= As[i].n && As[i].n < E.n_hi) {
+                E.n_lo <= As[i].n && As[i].n < E.n_hi && E.eps_lo <= p.eps && p.eps < E.eps_hi) {
                 t0 = (t0 < 0) ? E.tier0 : std::min(t0, E.tier0);
                 rt = std::max(rt, E.route);
                 lt = std::max(lt, E.last_tier);
@@ -423,11 +430,12 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
     // slab rows of the dense class: no LS block has more rows than the matrix
     const int64_t big_ld = std::min<int64_t>(BMMAX_BIG, (maxn + 63) / 64 * 64);
 
-    // R factors kept for the adjoint: an arena of the requested size (default 256 MB);
-    // columns that do not fit are refactorised by the adjoint
+    // R factors kept for the adjoint: an arena of the requested size (default 2 GB,
+    // against 288 GB of HBM: the 64-matrix batch's factors fit); columns that do not fit
+    // get their factor recomputed by the adjoint
     const int64_t fac_cap = P->p.keep_factors
                                 ? std::max<int64_t>(1, (P->p.factor_budget_bytes > 0 ? P->p.factor_budget_bytes
-                                                                                     : (int64_t)256 << 20) / 8)
+                                                                                     : (int64_t)2 << 30) / 8)
                                 : 0;
 
     // ---- every device buffer of the build, from one allocation
@@ -786,6 +794,7 @@ rsai_status rsai_autotune(const rsai_csc *A, const rsai_params *p, int32_t reps,
                         q.last_tier = lt;
                         q.tune_count = 0;
                         q.tune_table = nullptr;
+                        q.col_len_max = nullptr;
                         q.timing = 1;
                         std::vector<double> ms;
                         for (int r = 0; r < reps + 1; ++r) {

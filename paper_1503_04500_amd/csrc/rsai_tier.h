@@ -124,7 +124,9 @@ struct GLds {
 // t1: up to 64 x 24 blocks (3D 7-point stencils), 4 columns per wave; one wave per
 //     SIMD so that the fully unrolled QR keeps its 96 block entries per lane in
 //     registers
-// t2: up to 128 x 32 blocks, 4 columns per wave
+// t2: up to 128 x 32 blocks, a whole wave per column (two rows per lane, the group
+//     reductions crossing the 16-lane rows by permlane swaps): fully unrolled, its 64
+//     block entries per lane stay in registers at one wave per SIMD
 #ifndef RSAI_T0_STAGE
 #define RSAI_T0_STAGE 6
 #endif
@@ -136,7 +138,7 @@ using Tier0 = TierCfg<8, 3, 12, RSAI_T0_STAGE, RSAI_T0_HSF>;
 // the autotuner: fewer probes per insertion, more slots cleared per column)
 using Tier0H4 = TierCfg<8, 3, 12, RSAI_T0_STAGE, 4>;
 using Tier1 = TierCfg<16, 4, 24, 4, 2, 1>;
-using Tier2 = TierCfg<16, 8, 32, 4, 2, 2>;
+using Tier2 = TierCfg<64, 2, 32, 4, 2, 1>;
 void launch_tier2(const TierArgs &a, int waves, hipStream_t s);
 void launch_tier0_h4(const TierArgs &a, int waves, hipStream_t s);
 

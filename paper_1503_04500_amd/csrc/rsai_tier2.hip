@@ -1,6 +1,5 @@
-// Size tier 2 of the fused RSAI(tol) kernel. Its block (8 rows x 32 columns per
-// lane) does not fit the register file even fully unrolled, so this file keeps the
-// compiler's default unrolling.
+// Size tier 2 of the fused RSAI(tol) kernel (a wave per column, 2 rows x 32 columns
+// per lane), compiled with the full unrolling of the register tiers.
 #include "rsai_tier_kernel.h"
 
 namespace rsai {

@@ -35,11 +35,13 @@ class Params(ctypes.Structure):
                 ("refill", ctypes.c_int32), ("route", ctypes.c_int32),
                 ("keep_factors", ctypes.c_int32), ("factor_budget_bytes", ctypes.c_int64),
                 ("deterministic", ctypes.c_int32), ("tune_count", ctypes.c_int32),
-                ("tune_table", ctypes.c_void_p), ("t0_hash", ctypes.c_int32), ("last_tier", ctypes.c_int32)]
+                ("tune_table", ctypes.c_void_p), ("t0_hash", ctypes.c_int32), ("last_tier", ctypes.c_int32),
+                ("col_len_max", ctypes.c_void_p)]
 
 
 class TuneEntry(ctypes.Structure):
-    _fields_ = [("len_lo", ctypes.c_double), ("len_hi", ctypes.c_double), ("maxlen_lo", ctypes.c_int64),
+    _fields_ = [("len_lo", ctypes.c_double), ("len_hi", ctypes.c_double), ("eps_lo", ctypes.c_double),
+                ("eps_hi", ctypes.c_double), ("maxlen_lo", ctypes.c_int64),
                 ("maxlen_hi", ctypes.c_int64), ("n_lo", ctypes.c_int64), ("n_hi", ctypes.c_int64),
                 ("tier0", ctypes.c_int32), ("refill", ctypes.c_int32), ("route", ctypes.c_int32),
                 ("t0_hash", ctypes.c_int32), ("last_tier", ctypes.c_int32), ("reserved", ctypes.c_int32)]
@@ -352,7 +354,8 @@ def tune_entries(table=None):
     rows = tune.load_table() if table is None else table
     arr = (TuneEntry * max(len(rows), 1))()
     for i, e in enumerate(rows):
-        arr[i] = TuneEntry(float(e["len_lo"]), float(e["len_hi"]), int(e["maxlen_lo"]), int(e["maxlen_hi"]),
+        arr[i] = TuneEntry(float(e["len_lo"]), float(e["len_hi"]), float(e.get("eps_lo", 0.0)),
+                           float(e.get("eps_hi", float("inf"))), int(e["maxlen_lo"]), int(e["maxlen_hi"]),
                            int(e["n_lo"]), int(e["n_hi"]), int(e.get("tier0", -1)), int(e.get("refill", -1)),
                            int(e.get("route", -1)), int(e.get("t0_hash", -1)), int(e.get("last_tier", -1)), 0)
     return arr, len(rows)
@@ -369,12 +372,19 @@ def build_batched(mats, stream=None, tune_table=None, **kw) -> Plan:
     if count:
         prm.tune_table = ctypes.cast(entries, ctypes.c_void_p)
         prm.tune_count = count
+    # the longest column of each matrix, when the host knows it (saves the library a
+    # device read and a synchronisation)
+    lens = None
+    if count and all(m._max_col_len is not None for m in mats):
+        lens = (ctypes.c_int64 * len(mats))(*[int(m._max_col_len) for m in mats])
+        prm.col_len_max = ctypes.cast(lens, ctypes.c_void_p)
     views = (CSCView * len(mats))(*[m.view() for m in mats])
     h = ctypes.c_void_p()
     st = _stream(stream)
     _check(lib.rsai_build_batched(len(mats), views, ctypes.byref(prm), st, ctypes.byref(h)))
-    prm.tune_table = None  # the table is read during the call only
+    prm.tune_table = None  # the table and the lengths are read during the call only
     prm.tune_count = 0
+    prm.col_len_max = None
     return Plan(h, list(mats), prm, st)
 
 

@@ -62,23 +62,32 @@ def load_table(path: str = TABLE) -> list:
     return _table
 
 
-def choose(n: int, mean_len: float, max_len: int, table=None):
+def choose(n: int, mean_len: float, max_len: int, table=None, eps: float = 0.4):
     """Schedule choices of the first table entry whose ranges hold (mean column
-    length, longest column, n); None if no entry matches."""
+    length, longest column, n, eps); None if no entry matches."""
     for e in (load_table() if table is None else table):
         if (e["len_lo"] <= mean_len < e["len_hi"] and e["maxlen_lo"] <= max_len < e["maxlen_hi"]
-                and e["n_lo"] <= n < e["n_hi"]):
+                and e["n_lo"] <= n < e["n_hi"] and e.get("eps_lo", 0.0) <= eps < e.get("eps_hi", float("inf"))):
             return {k: e.get(k, -1) for k in KEYS}
     return None
 
 
 def _workloads():
+    """(name, matrix, parameters, the eps values tuned): the schedule that wins depends
+    on eps as well as on the matrix (a smaller eps grows larger blocks)."""
     from . import gen
-    return [("cd2d 512x512 (n=262144)", lambda: gen.cd2d(512, seed=0), dict(lmax=8)),
-            ("cd3d 64^3 (n=262144)", lambda: gen.cd3d(64, seed=0), dict(lmax=8)),
-            ("power-law n=10^6", lambda: gen.powerlaw(1_000_000, seed=0), dict(lmax=10)),
-            ("cd2d 128x128", lambda: gen.cd2d(128, seed=1), dict(lmax=8)),
-            ("power-law n=10^5", lambda: gen.powerlaw(100_000, seed=1), dict(lmax=10))]
+    return [("cd2d 512x512 (n=262144)", lambda: gen.cd2d(512, seed=0), dict(lmax=8), (0.4, 0.2)),
+            ("cd3d 64^3 (n=262144)", lambda: gen.cd3d(64, seed=0), dict(lmax=8), (0.4,)),
+            ("power-law n=10^6", lambda: gen.powerlaw(1_000_000, seed=0), dict(lmax=10), (0.4,)),
+            ("cd2d 128x128", lambda: gen.cd2d(128, seed=1), dict(lmax=8), (0.4, 0.2)),
+            ("power-law n=10^5", lambda: gen.powerlaw(100_000, seed=1), dict(lmax=10), (0.4,))]
+
+
+def eps_ranges(eps_values):
+    """Adjacent eps ranges around the tuned values, split at the midpoints."""
+    ev = sorted(eps_values)
+    cuts = [0.0] + [(a + b) / 2 for a, b in zip(ev, ev[1:])] + [float("inf")]
+    return {e: (cuts[i], cuts[i + 1]) for i, e in enumerate(ev)}
 
 
 def main(argv=None) -> int:
@@ -87,14 +96,17 @@ def main(argv=None) -> int:
     from . import rsai
     out_path = TABLE if not argv else argv[0]
     results, entries = [], []
-    for name, make, kw in _workloads():
+    for name, make, kw, epss in _workloads():
         H = make()
         A = rsai.Matrix.from_host(H, "cuda:0")
-        r = autotune(A, reps=3, c=3, eps=0.4, drop="fixed", tol=1e-3, validate=2, **kw)
         mean_len = H.nnz / H.n
         maxlen = int((H.colptr[1:] - H.colptr[:-1]).max())
-        results.append(dict(workload=name, n=H.n, mean_col_len=mean_len, max_col_len=maxlen, **r))
-        print(name, "best", r["best"], flush=True)
+        rng = eps_ranges(epss)
+        for eps in epss:
+            r = autotune(A, reps=3, c=3, eps=eps, drop="fixed", tol=1e-3, validate=2, **kw)
+            results.append(dict(workload=name, eps=eps, eps_lo=rng[eps][0], eps_hi=rng[eps][1], n=H.n,
+                                mean_col_len=mean_len, max_col_len=maxlen, **r))
+            print(name, "eps", eps, "best", r["best"], flush=True)
         del A
         torch.cuda.synchronize()
     # table: one entry per workload, keyed by mean column length, longest column and
@@ -102,8 +114,9 @@ def main(argv=None) -> int:
     for r in results:
         b = r["best"]
         entries.append(dict(len_lo=r["mean_col_len"] * 0.8, len_hi=r["mean_col_len"] * 1.25,
+                            eps_lo=r["eps_lo"], eps_hi=r["eps_hi"] if r["eps_hi"] != float("inf") else 1e300,
                             maxlen_lo=max(1, r["max_col_len"] // 2), maxlen_hi=r["max_col_len"] * 2 + 1,
-                            n_lo=r["n"] // 4, n_hi=r["n"] * 4, workload=r["workload"],
+                            n_lo=r["n"] // 4, n_hi=r["n"] * 4, workload=r["workload"] + f" eps {r['eps']}",
                             **{k: b[k] for k in KEYS}))
     with open(out_path, "w") as f:
         json.dump({"device": torch.cuda.get_device_name(0), "entries": entries, "results": results}, f, indent=1)

@@ -55,6 +55,15 @@ def test_tune_table_through_the_c_abi():
     assert p2.schedule()["refill"] == 1 and p2.schedule()["t0_hash"] == 4
     p3 = rsai.build(A, tune_table=table[:1], **C1)
     assert p3.schedule() == dict(tier0=0, refill=1, route=1, t0_hash=2, last_tier=2)
+    # a matrix whose longest column the host does not know: the library reads it
+    Ad = rsai.Matrix(A.colptr, A.rowidx, A.val)
+    assert Ad._max_col_len is None
+    assert rsai.build(Ad, tune_table=table, **C1).schedule() == p.schedule()
+    # the eps ranges of an entry
+    te = [dict(table[2], eps_lo=0.3, eps_hi=1.0, tier0=0, last_tier=1),
+          dict(table[2], eps_lo=0.0, eps_hi=0.3, tier0=1, last_tier=2)]
+    assert rsai.build(A, tune_table=te, **C1).schedule()["last_tier"] == 1
+    assert rsai.build(A, tune_table=te, **dict(C1, eps=0.2)).schedule()["tier0"] == 1
     ref = oracle.rsai(H, **C1)
     cp, ri, va = (t.cpu().numpy() for t in p.export())
     st = {k: v.cpu().numpy() for k, v in p.stats().items()}

@@ -22,6 +22,11 @@ def test_choose_matches_ranges_in_order():
     assert _sub(tune.choose(262144, 6.9, 7, TABLE)) == dict(tier0=0, refill=0, route=1)
     # fields an entry lacks come back as -1 (not applied)
     assert tune.choose(262144, 5.0, 5, TABLE)["t0_hash"] == -1
+    # eps ranges: adjacent, split at the midpoints of the tuned values
+    assert tune.eps_ranges((0.4, 0.2)) == {0.2: (0.0, 0.30000000000000004), 0.4: (0.30000000000000004, float("inf"))}
+    t2 = [dict(TABLE[0], eps_lo=0.3, eps_hi=1.0, tier0=0), dict(TABLE[0], eps_lo=0.0, eps_hi=0.3, tier0=1)]
+    assert tune.choose(262144, 5.0, 5, t2, eps=0.4)["tier0"] == 0
+    assert tune.choose(262144, 5.0, 5, t2, eps=0.2)["tier0"] == 1
     # outside every range
     assert tune.choose(10, 5.0, 5, TABLE) is None
     assert tune.choose(262144, 20.0, 5, TABLE) is None
@@ -42,7 +47,7 @@ def test_tune_entries_layout_and_params_checks():
     """The binding's rsai_tune_entry matches the C layout (2 doubles, 4 int64, 6 int32)
     and the library rejects bad schedule fields on the host."""
     import ctypes
-    assert ctypes.sizeof(rsai.TuneEntry) == 72
+    assert ctypes.sizeof(rsai.TuneEntry) == 88
     if not os.path.exists(rsai.LIB_PATH):
         return
     arr, n = rsai.tune_entries(TABLE)
