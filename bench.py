@@ -42,10 +42,12 @@ def parse():
                     help="only copy 64 MiB device to device three times (calibrates the HBM byte counters)")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many batched builds (for rocprofv3), print nothing else")
-    ap.add_argument("--profile-workload", choices=("cd2d", "batch64", "bicgstab", "fwdbwd"), default="cd2d",
-                    help="workload of --profile-steps: builds of the cd2d matrix or of the 64-matrix "
-                         "batch, BiCGStab solves (100 iterations) with M of the cd2d matrix, or "
-                         "fwd + bwd steps of the loss on the cd2d matrix")
+    ap.add_argument("--profile-workload", choices=("cd2d", "batch64", "bicgstab", "fwdbwd", "eps02", "powerlaw"),
+                    default="cd2d",
+                    help="workload of --profile-steps: builds of the cd2d matrix (eps 0.4, or eps02: 0.2), "
+                         "of the power-law matrix (n = 10^6) or of the 64-matrix batch, BiCGStab solves "
+                         "(100 iterations) with M of the cd2d matrix, or fwd + bwd steps of the loss on the "
+                         "cd2d matrix")
     return ap.parse_args()
 
 
@@ -68,6 +70,62 @@ def measured_traffic():
     if kv.get("kernel_source_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in kv:
         return None
     return float(kv["traffic_bytes_per_launch"])
+
+
+def alg_bytes(n, nnz, nnzM):
+    """Compulsory HBM bytes of a build's size-class kernels: A (values, row indices,
+    column pointers) and its row pattern (column indices, row pointers) read once, the
+    results (row indices and values of M) and the per-column statistics written once."""
+    return (nnz * (8 + 4) + (n + 1) * 8) + (nnz * 4 + (n + 1) * 8) + nnzM * (4 + 8) + n * (8 + 4 * 4 + 8 * 3)
+
+
+def class_roofline(rsai, mats, prm, np):
+    """Roofline of the size-class kernels of one (batched) build: model flops of every
+    column and compulsory bytes over the HIP-event time of those kernels."""
+    p = rsai.build_batched(mats, timing=True, **prm)
+    nz = [p.nnz(i) for i in range(len(mats))]
+    t = p.timing()
+    fl = sum(float(p.stats(i, fields=("flops",))["flops"].sum().item()) for i in range(len(mats)))
+    by = sum(alg_bytes(m.n, m.nnz, z) for m, z in zip(mats, nz))
+    p.close()
+    ms = t["tier0"] + t["tiers"]
+    tf = fl / (ms * 1e-3) / 1e12
+    gbs = by / (ms * 1e-3) / 1e9
+    return {"bound": "alu", "achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": tf / FP64_PEAK_TFLOPS, "kernel": "the size-class kernels (tier 0, later tiers, sparse-block "
+                                                       "and dense classes)", "kernel_ms": ms, "alg_flops": fl,
+            "hbm_alg_bytes": by, "hbm_achieved_GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS, "traffic": None,
+            "note": "the flops are the dense Householder-update model; the sparse-block class solves an "
+                    "orthogonally compressed block with fewer operations, so its share is an upper bound"}
+
+
+def adjoint_roofline(rsai, A, H, torch, np, prm):
+    """Roofline of the adjoint kernels on kept factors: z = R^-1 R^-T g (two triangular
+    solves, 2 q^2), r and A_k z over the entries of the columns of J (4 each) and the
+    contribution per entry (6); compulsory bytes: the R records, M, g and A read once,
+    dA read and written once."""
+    p = rsai.build(A, timing=True, keep_factors=True, **prm)
+    cp, ri, va = p.export()
+    cpn, rin = cp.cpu().numpy(), ri.cpu().numpy()
+    g = torch.cos(torch.arange(va.numel(), dtype=torch.float64, device=va.device))
+    dA = torch.zeros(H.nnz, dtype=torch.float64, device=va.device)
+    ms = []
+    for _ in range(4):
+        p.backward(g, 1.0, dA)
+        ms.append(p.timing()["backward"])
+    p.close()
+    q = np.diff(cpn).astype(np.float64)
+    lens = np.diff(H.colptr).astype(np.float64)
+    ent = lens[rin]                                  # entries of column j of A, per entry of M
+    fl = float(np.sum(2.0 * q * q) + 10.0 * ent.sum())
+    by = float(8 * np.sum(q + q * (q + 1) / 2) + 12 * cpn[-1] + 8 * cpn[-1] + 12 * H.nnz + 8 * (H.n + 1)
+               + 16 * H.nnz)
+    t = float(np.median(ms[1:]))
+    tf = fl / (t * 1e-3) / 1e12
+    gbs = by / (t * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "kernel": "backward_factored_kernel<16,32,1>", "kernel_ms": t, "hbm_alg_bytes": by,
+            "alg_flops": fl, "fp64_TFLOPs": tf, "fp64_frac": tf / FP64_PEAK_TFLOPS, "traffic": None}
 
 
 def time_builds(rsai, A, sched, steps, warmup, torch, prm=None):
@@ -121,9 +179,28 @@ def main():
         print(json.dumps({"profile_steps": args.profile_steps, "workload": "batch64"}))
         return
 
+    if args.profile_steps and args.profile_workload == "powerlaw":
+        A3 = rsai.Matrix.from_host(gen.c3(), "cuda:0")
+        for _ in range(args.profile_steps):
+            p = rsai.build(A3, **dict(PARAMS, lmax=10))
+            p.nnz()
+            p.close()
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_steps": args.profile_steps, "workload": "powerlaw"}))
+        return
+
     H = gen.cd2d(args.grid, seed=0)
     A = rsai.Matrix.from_host(H, "cuda:0")
     torch.cuda.synchronize()
+
+    if args.profile_steps and args.profile_workload == "eps02":
+        for _ in range(args.profile_steps):
+            p = rsai.build(A, **dict(PARAMS, eps=0.2))
+            p.nnz()
+            p.close()
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_steps": args.profile_steps, "workload": "eps02"}))
+        return
 
     if args.profile_steps and args.profile_workload == "bicgstab":
         pb = rsai.build(A, sched="batched", **PARAMS)
@@ -158,7 +235,7 @@ def main():
     # ---- batched (the value)
     dt_b = time_builds(rsai, A, "batched", args.steps, args.warmup, torch)
     # ---- dominant kernel timing with HIP events on the build stream, plus stats
-    tier0_ms, build_ms = [], []
+    tier0_ms, kern_ms, build_ms = [], [], []
     last = None
     for _ in range(max(3, min(args.steps, 10))):
         if last is not None:
@@ -166,19 +243,20 @@ def main():
         last = rsai.build(A, sched="batched", timing=True, **PARAMS)
         t = last.timing()
         tier0_ms.append(t["tier0"])
+        kern_ms.append(t["tier0"] + t["tiers"])
         build_ms.append(t["build"])
     st = {k: v.cpu().numpy() for k, v in last.stats().items()}
     nnzM = last.nnz()
     last.close()
     flops = float(st["flops"].sum())
     t0_ms = float(np.median(tier0_ms))
-    achieved_tf = flops / (t0_ms * 1e-3) / 1e12
-    # algorithmic HBM bytes of the tier kernel: read A (val, rowidx, colptr), the row
-    # pattern (colidx, rowptr) once; write the per-column results (J, values) and the
-    # per-column statistics
+    k_ms = float(np.median(kern_ms))
+    # the model flops of every column over the time of every size-class kernel of the
+    # build (tier 0 and the later classes, which finish the columns that leave it)
+    achieved_tf = flops / (k_ms * 1e-3) / 1e12
     n, nnz = H.n, H.nnz
-    bytes_alg = (nnz * (8 + 4) + (n + 1) * 8) + (nnz * 4 + (n + 1) * 8) + nnzM * (4 + 8) + n * (8 + 4 * 4 + 8 * 3)
-    hbm_gbs = bytes_alg / (t0_ms * 1e-3) / 1e9
+    bytes_alg = alg_bytes(n, nnz, nnzM)
+    hbm_gbs = bytes_alg / (k_ms * 1e-3) / 1e9
 
     # ---- the same build replayed as a captured HIP graph on the plan's buffers
     # (rsai_rebuild: no allocation, no host-side setup)
@@ -216,6 +294,7 @@ def main():
         if it > 0:
             fb.append(time.perf_counter() - t0)
     fwd_bwd_ms = float(np.median(fb)) * 1e3
+    adj_roof = adjoint_roofline(rsai, A, H, torch, np, PARAMS)
 
     # ---- further workloads (reported beside the value): power-law n = 10^6, the
     # 64-matrix batch in one build, fwd+bwd on the 64^3 3D matrix
@@ -274,6 +353,21 @@ def main():
                           "bicgstab_ms": dts * 1e3})
             ps.close()
         extra["sweep_cd2d512"] = sweep
+        # eps = 0.1 (the paper's smallest setting): blocks of about 100 x 64, most columns
+        # end in the workgroup classes; on the 128x128 grid
+        H01 = gen.cd2d(128, seed=0)
+        A01 = rsai.Matrix.from_host(H01, "cuda:0")
+        prm01 = dict(PARAMS, eps=0.1)
+        dt01 = time_builds(rsai, A01, "batched", 3, 1, torch, prm=prm01)
+        p01 = rsai.build(A01, sched="batched", timing=True, **prm01)
+        nz01 = p01.nnz()
+        b01 = rsai.spmv(A01, torch.ones(H01.n, dtype=torch.float64, device="cuda:0"))
+        _, its01, _ = p01.bicgstab(b01)
+        extra["eps01_cd2d128"] = {"eps": 0.1, "c": 3, "build_ms": dt01 * 1e3, "spar": nz01 / H01.nnz,
+                                  "phase_ms": p01.timing(), "bicgstab_iterations": its01,
+                                  "workload": "cd2d 128x128 seed 0; c=3 lmax=8 eps=0.1 tol=1e-3"}
+        p01.close()
+        del A01, H01
         # relatively dense rows (Section 4): 512x512 grid plus 1024 rows of 32 entries
         Hd = gen.dense_rows(512, 1024, 32)
         Ad = rsai.Matrix.from_host(Hd, "cuda:0")
@@ -292,7 +386,8 @@ def main():
         dt3 = time_builds(rsai, A3, "batched", 3, 1, torch, prm=P3)
         extra["powerlaw_1e6"] = {"value": H3.n / dt3, "unit": "columns/s", "ms_per_step": dt3 * 1e3,
                                  "workload": "power-law columns (min 2, mean 7, max 200), n=10^6, seed 0; "
-                                             "c=3 lmax=10 eps=0.4 tol=1e-3"}
+                                             "c=3 lmax=10 eps=0.4 tol=1e-3",
+                                 "roofline": class_roofline(rsai, [A3], P3, np)}
         host_mats["c3"] = H3
         del A3, H3
         specs = gen.batch64_specs()
@@ -335,12 +430,14 @@ def main():
         dt5g = (time.perf_counter() - t0) / 3
         p5.close()
         extra["batch64"] = {"value": n5 / dt5, "unit": "columns/s", "ms_per_step": dt5 * 1e3,
+                            "roofline": class_roofline(rsai, A5, PARAMS, np),
                             "sequential_ms": dt5s * 1e3, "graph_replay_ms": dt5g * 1e3,
                             "sequential_per_matrix_ms": [round(v, 3) for v in per5],
                             "workload": f"64 matrices in one build (2D/3D convection-diffusion, power-law; "
                                         f"sum n = {n5})"}
         # fwd + bwd of the summed loss over the 64 matrices (one batched build keeping
-        # every R factor, one adjoint per matrix)
+        # R factors in the default 256 MB store, one adjoint per matrix; the columns
+        # past the store get their factor recomputed)
         b5 = [torch.from_numpy(np.random.default_rng(2000 + i).standard_normal(h.n)).to("cuda:0")
               for i, h in enumerate(H5)]
         fb5 = []
@@ -348,7 +445,7 @@ def main():
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             v5 = [a5.val.clone().requires_grad_(True) for a5 in A5]
-            L5 = ag.rsai_loss_batched(A5, v5, b5, factor_budget_bytes=8 << 30, **PARAMS)
+            L5 = ag.rsai_loss_batched(A5, v5, b5, **PARAMS)
             L5.backward()
             torch.cuda.synchronize()
             if it > 0:
@@ -386,6 +483,17 @@ def main():
             reps += 1
         cpu = {"value": reps * n / tot, "unit": "columns/s", "cores": int(thr), "kind": "oracle",
                "sample": f"the full {args.grid}x{args.grid} matrix ({n} columns) built {reps} times"}
+        # end to end (Section 5 protocol, b = A 1): the host BiCGStab with the oracle's M
+        # and with the GPU's M, beside the device solve with the GPU's M
+        pe = rsai.build(A, sched="batched", **PARAMS)
+        gM = tuple(t.cpu().numpy() for t in pe.export())
+        bh = H.matvec(np.ones(n))
+        _, it_dev, _ = pe.bicgstab(torch.from_numpy(bh).to("cuda:0"))
+        pe.close()
+        it_om, rel_om, _ = oracle.bicgstab(H, bh, (R["colptr"], R["rowidx"], R["val"]))
+        it_gm, rel_gm, _ = oracle.bicgstab(H, bh, gM)
+        cpu["e2e_bicgstab"] = {"oracle_M_host_solver": it_om, "gpu_M_host_solver": it_gm,
+                               "gpu_M_device_solver": it_dev, "same_pattern": bool(np.array_equal(gM[1], R["rowidx"]))}
         # one host thread, on a seeded sample of 32768 columns
         cols = np.sort(np.random.default_rng(0).choice(n, 32768, replace=False))
         R1 = oracle.rsai(H, c=3, lmax=8, eps=0.4, drop=oracle.DROP_FIXED, tol=1e-3, threads=1, cols=cols)
@@ -455,13 +563,16 @@ def main():
                    "n": n, "nnz": nnz, "nnzM": int(nnzM), "schedule": "batched"},
         "roofline": {"bound": "alu", "achieved": achieved_tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / FP64_PEAK_TFLOPS, "traffic": measured_traffic(),
-                     "kernel": "tier_kernel<8,3,12,6>", "kernel_ms": t0_ms, "alg_flops": flops,
-                     "hbm_alg_bytes": bytes_alg, "hbm_achieved_GBs": hbm_gbs, "hbm_frac": hbm_gbs / HBM_PEAK_GBS,
-                     "measured_peaks": measured},
+                     "kernel": "tier_kernel<8,3,12,6> (with the later size classes' launches)",
+                     "kernel_ms": k_ms, "tier0_ms": t0_ms,
+                     "basis": "model flops of every column / HIP-event time of all size-class kernels",
+                     "alg_flops": flops, "hbm_alg_bytes": bytes_alg, "hbm_achieved_GBs": hbm_gbs,
+                     "hbm_frac": hbm_gbs / HBM_PEAK_GBS, "measured_peaks": measured},
         "plain": plain,
         "speedup_vs_plain": (plain["ms_per_step"] / (dt_b * 1e3)) if plain else None,
         "graph_rebuild": graph,
         "fwd_bwd_ms": fwd_bwd_ms,
+        "adjoint_roofline": adj_roof,
         "extra": extra,
         "build_event_ms": float(np.median(build_ms)),
         "phase_ms": {k: float(v) for k, v in t.items()},
