@@ -137,8 +137,8 @@ using Tier0 = TierCfg<8, 3, 12, RSAI_T0_STAGE, RSAI_T0_HSF>;
 // tier 0 with hash tables of four times its row and column capacity (a tile choice of
 // the autotuner: fewer probes per insertion, more slots cleared per column)
 using Tier0H4 = TierCfg<8, 3, 12, RSAI_T0_STAGE, 4>;
-using Tier1 = TierCfg<16, 4, 24, 4, 2, 1>;
-using Tier2 = TierCfg<64, 2, 32, 4, 2, 1>;
+using Tier1 = TierCfg<16, 4, 24, 8, 2, 1>;
+using Tier2 = TierCfg<64, 2, 32, 8, 2, 1>;
 void launch_tier2(const TierArgs &a, int waves, hipStream_t s);
 void launch_tier0_h4(const TierArgs &a, int waves, hipStream_t s);
 

@@ -16,6 +16,7 @@ template <class C, bool MULTI>
 __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
     constexpr int G = C::G, RPL = C::RPL, QMAX = C::QMAX, MMAX = C::MMAX, GPW = C::GPW;
     constexpr int STAGE = C::STAGE;
+    constexpr int QCB = 4;                       // columns per chunk of the QR update
     constexpr int NRI = (C::RIN + G - 1) / G;   // per-lane candidates per I round
     constexpr int NRJ = (C::RJN + G - 1) / G;   // per-lane candidates per J round
     constexpr int NNEW = (C::NEWC + G - 1) / G;
@@ -543,7 +544,10 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
             if (lookup_fail) atomicOr(args.err, 16);
 
             // ---- Householder QR update: stored reflectors j < qlo act on the new
-            // columns only; reflectors qlo..qn-1 are formed and applied.
+            // columns only; reflectors qlo..qn-1 are formed and applied. Columns
+            // below the smallest qlo of the wave's solving groups are final for every
+            // group: no reflector is formed there and no stored one is applied to them.
+            const int qloww = -wave_max_i(act ? -qlo : -QMAX);
 #pragma unroll
             for (int j = 0; j < QMAX; ++j) {
                 if (j >= qmaxw) continue;
@@ -554,12 +558,15 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
                 // above it (the entries of R there), so that the products with the
                 // other columns need no per-row predicate
                 double vr[RPL];
-                {
+#pragma unroll
+                for (int r = 0; r < RPL; ++r) vr[r] = (r * G + gl >= j) ? b[r][j] : 0.0;
+                if (j < qloww) {
+                    bj = gsum<G>((gl == j % G) ? bt[j / G] : 0.0);
+                } else {
                     double s2 = 0.0, x0p = 0.0;
 #pragma unroll
                     for (int r = 0; r < RPL; ++r) {
                         const int i = r * G + gl;
-                        vr[r] = (i >= j) ? b[r][j] : 0.0;
                         s2 += vr[r] * vr[r];
                         if (i == j) x0p = b[r][j];
                     }
@@ -588,19 +595,36 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
                     if (wave_any(ja && !newr)) bold = gsum<G>((gl == j % G) ? bt[j / G] : 0.0);
                     bj = newr ? bnew : bold;
                 }
+                // the columns right of j in chunks of QCB: the chunk's products and
+                // group sums are independent chains the wave issues interleaved
 #pragma unroll
-                for (int c = 0; c < QMAX; ++c) {
-                    if (c <= j) continue;
-                    if (c >= qmaxw) continue;
-                    const bool ca = ja && c < qn && (newr || c >= qlo);
-                    double w = 0.0;
+                for (int c0 = 0; c0 < QMAX; c0 += QCB) {
+                    if (c0 + QCB - 1 <= j) continue;
+                    if (c0 >= qmaxw || c0 + QCB <= qloww) continue;
+                    double w[QCB];
 #pragma unroll
-                    for (int r = 0; r < RPL; ++r) w += vr[r] * b[r][c];
-                    w = gsum<G>(w);
-                    if (ca) {
-                        const double f = bj * w;
+                    for (int u = 0; u < QCB; ++u) {
+                        const int c = c0 + u;
+                        w[u] = 0.0;
+                        if (c > j && c < QMAX) {
 #pragma unroll
-                        for (int r = 0; r < RPL; ++r) b[r][c] -= f * vr[r];
+                            for (int r = 0; r < RPL; ++r) w[u] += vr[r] * b[r][c];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < QCB; ++u)
+                        if (c0 + u > j && c0 + u < QMAX) w[u] = gsum<G>(w[u]);
+#pragma unroll
+                    for (int u = 0; u < QCB; ++u) {
+                        const int c = c0 + u;
+                        if (c > j && c < QMAX) {
+                            const bool ca = ja && c < qn && (newr || c >= qlo);
+                            if (ca) {
+                                const double f = bj * w[u];
+#pragma unroll
+                                for (int r = 0; r < RPL; ++r) b[r][c] -= f * vr[r];
+                            }
+                        }
                     }
                 }
                 if (wave_any(ja && newr)) {
