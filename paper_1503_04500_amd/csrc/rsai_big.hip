@@ -7,9 +7,10 @@
 //   * index sets are LDS hash sets; new rows are numbered in ascending global order
 //     (bitonic sort in LDS), so results do not depend on thread timing;
 //   * the dense block lives in a per-workgroup slab of global memory (column-major,
-//     leading dimension BMMAX); every solve refactors it by Householder QR with
-//     block-wide reductions (the work counted for the method is still the update
-//     model of the solve, as in the register tiers);
+//     leading dimension BMMAX) and holds the Householder factor between loops: a
+//     solve applies the stored reflectors to the new columns and forms theirs
+//     (blocked, FP64 MFMA compact WY); the solve after a drop refactors the kept
+//     columns;
 //   * the residual for step 4 is A(I,J) m - e_k(I) accumulated from the sparse
 //     columns in ascending column order (eq. (2.4)), so exact ties reach the
 //     smaller-index rule.
@@ -312,6 +313,7 @@ __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
         kR = (kidx < 0) && S.cnt;
         __syncthreads();
 
+        int fq = 0, fm = 0;      // columns and rows of the factor held in the block
         bool linc = linc0;       // advance l when J-hat is formed
         bool first = true;       // the stored pattern has no factor here yet
         bool need_solve = true;
@@ -448,12 +450,22 @@ __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
             int pass_drop = 0;
             while (need_solve && status == ST_OK) {
                 const int qn = q;
-                // gather: zero the block, scatter the columns' entries, Q^T e = e_k
-                for (int c = 0; c < qn; ++c)
+                // The factor of the previous solve (columns 0..fq-1 on rows 0..fm-1) is
+                // updated in place (Algorithm 1, step 7): the old columns are zero in the
+                // new rows (every row of a column of J is already in I), so their
+                // reflectors are unchanged; they are applied to the new columns, whose
+                // own reflectors are then formed. The solve after a drop starts afresh.
+                const int q0 = (pass_drop == 0 && fq <= qn) ? fq : 0;
+                const int m0 = (q0 > 0) ? fm : 0;
+                // gather: zero the new part of the block, scatter the new columns'
+                // entries, Q^T e = e_k on the new rows
+                for (int c = 0; c < q0; ++c)
+                    for (int i = m0 + tid; i < m; i += NT) B[(int64_t)c * ld + i] = 0.0;
+                for (int c = q0; c < qn; ++c)
                     for (int i = tid; i < m; i += NT) B[(int64_t)c * ld + i] = 0.0;
-                for (int i = tid; i < m; i += NT) y[i] = (i == kidx) ? 1.0 : 0.0;
+                for (int i = m0 + tid; i < m; i += NT) y[i] = (i == kidx) ? 1.0 : 0.0;
                 __syncthreads();
-                for (int c = 0; c < qn; ++c) {
+                for (int c = q0; c < qn; ++c) {
                     const int j = S.Jlist[c];
                     for (int64_t e = A.colptr[j] + tid; e < A.colptr[j + 1]; e += NT) {
                         const int sl = hfind<BLOGH>(S.hI, A.rowidx[e]);
@@ -461,11 +473,16 @@ __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
                     }
                 }
                 __syncthreads();
+                // the stored reflectors, a panel of NB at a time, on the new columns
+                for (int p0 = 0; p0 < q0; p0 += NB)
+                    for (int c_lo = q0; c_lo < qn; c_lo += NCTMAX * 16)
+                        panel_update(B, ld, y, m, qn, p0, min(NB, q0 - p0), c_lo, min(NCTMAX * 16, qn - c_lo), S,
+                                     gred);
                 bool singular = false;
                 // Blocked Householder QR: panels of NB columns are factored column by
                 // column; the rest of the block (and Q^T e) is updated once per panel
                 // with the compact WY form Q_p = I - V T V^T (FP64 MFMA 16x16x4).
-                for (int p0 = 0; p0 < qn; p0 += NB) {
+                for (int p0 = q0; p0 < qn; p0 += NB) {
                     const int pw = min(NB, qn - p0);
                     for (int j = p0; j < p0 + pw; ++j) {
                         double *bj = B + (int64_t)j * ld;
@@ -535,6 +552,8 @@ __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
                     if (ntr > 0) panel_update(B, ld, y, m, qn, p0, pw, c_lo, ntr, S, gred);
                 }
                 if (singular) { status = ST_SINGULAR; break; }
+                fq = qn;
+                fm = m;
                 // back substitution by wave 0: lane c holds m_c
                 if (tid < 64) {
                     double mc_lane = 0.0;
