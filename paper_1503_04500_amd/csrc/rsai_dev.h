@@ -250,7 +250,8 @@ __device__ __forceinline__ bool wave_all(bool p) { return __ballot(!p) == 0; }
 // cannot hold them all is replaced by a fresh one, taken from the store with a single
 // atomic (the rest of the old one stays unused), so the finishing columns of a wave
 // do not each wait on a contended device-wide atomic. -1 when the store is full.
-__device__ __forceinline__ long long fac_take(const ColOut &o, FacChunk &W, int need) {
+template <class O>  // ColOut, in any address space
+__device__ __forceinline__ long long fac_take(const O &o, FacChunk &W, int need) {
     const int lane = (int)__lane_id();
     const unsigned long long lm = __ballot(need > 0);
     if (lm == 0ull) return -1LL;

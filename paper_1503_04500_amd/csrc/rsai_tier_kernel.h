@@ -11,6 +11,17 @@
 namespace rsai {
 
 
+// The kernel's argument block in the kernarg segment, read through a pointer whose
+// value the compiler cannot see: the fields the column loop needs only now and then
+// (refill, spill, output) are loaded where they are used instead of being held in
+// scalar registers across the loop.
+__device__ __forceinline__ const __attribute__((address_space(4))) TierArgs *kargs() {
+    const __attribute__((address_space(4))) TierArgs *p =
+        (const __attribute__((address_space(4))) TierArgs *)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
 // MULTI = false: one matrix, whose pointers stay in scalar registers.
 template <class C, bool MULTI>
 __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
@@ -79,7 +90,7 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
         bool start = false;
         // with sync_refill, groups of a wave start their columns together, so they
         // stay at the same loop and the wave's QR is only as wide as its work
-        const bool may_refill = args.sync_refill ? wave_all(!busy) : true;
+        const bool may_refill = kargs()->sync_refill ? wave_all(!busy) : true;
         if (!busy && !fin && may_refill) {
             if (u_next < qhi_range) {
                 pos = u_next;
@@ -96,24 +107,24 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
             if (first_tier) {
                 ucol = pos;
                 if constexpr (MULTI) {
-                    int lo = 0, hi = args.nmat - 1;  // matrix with col_base[mat] <= ucol
+                    int lo = 0, hi = kargs()->nmat - 1;  // matrix with col_base[mat] <= ucol
                     while (lo < hi) {
                         int mid = (lo + hi + 1) / 2;
-                        if (args.col_base[mid] <= ucol) lo = mid; else hi = mid - 1;
+                        if (kargs()->col_base[mid] <= ucol) lo = mid; else hi = mid - 1;
                     }
                     mat = lo;
-                    k = (int)(ucol - args.col_base[mat]);
+                    k = (int)(ucol - kargs()->col_base[mat]);
                 } else {
                     mat = 0;
                     k = (int)ucol;
                 }
             } else {
-                rec = args.rec_in + pos * (int64_t)args.rec_in_stride;
+                rec = kargs()->rec_in + pos * (int64_t)kargs()->rec_in_stride;
                 ucol = rec[0];
                 mat = rec[1];
                 k = rec[2];
             }
-            if constexpr (MULTI) A = args.mats[mat];
+            if constexpr (MULTI) A = kargs()->mats[mat];
             busy = true;
             status = ST_OK;
             fl = 0.0;
@@ -401,26 +412,26 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
         if (wave_any(spill)) {
             int ps = 0;
             // destination class: the first whose limits hold the estimate
-            int d = args.nq - 1;
+            int d = kargs()->nq - 1;
 #pragma unroll
             for (int i = TierArgs::MAXQ - 2; i >= 0; --i)
-                if (i < args.nq - 1 && est_m <= args.q_mmax[i] && est_q <= args.q_qmax[i]) d = i;
-            int32_t *qrec = args.q_rec[0];
-            int qstr = args.q_stride[0];
-            int64_t qcap = args.q_cap[0];
+                if (i < kargs()->nq - 1 && est_m <= kargs()->q_mmax[i] && est_q <= kargs()->q_qmax[i]) d = i;
+            int32_t *qrec = kargs()->q_rec[0];
+            int qstr = kargs()->q_stride[0];
+            int64_t qcap = kargs()->q_cap[0];
             if (spill && gl == 0) ps = INT_MAX;
 #pragma unroll
             for (int i = 0; i < TierArgs::MAXQ; ++i) {
-                if (i > 0 && d == i) { qrec = args.q_rec[i]; qstr = args.q_stride[i]; qcap = args.q_cap[i]; }
+                if (i > 0 && d == i) { qrec = kargs()->q_rec[i]; qstr = kargs()->q_stride[i]; qcap = kargs()->q_cap[i]; }
                 // one counter address per pass, so that the lanes' increments combine
-                const bool mine = spill && gl == 0 && d == i && i < args.nq;
-                if (wave_any(mine) && mine) ps = atomicAdd(args.q_count[i], 1);
+                const bool mine = spill && gl == 0 && d == i && i < kargs()->nq;
+                if (wave_any(mine) && mine) ps = atomicAdd(kargs()->q_count[i], 1);
             }
-            if (args.nq <= 0) qrec = nullptr;
+            if (kargs()->nq <= 0) qrec = nullptr;
             ps = gbcast_i<G>(ps, gl == 0);
             // the plain schedule has one size class: outgrowing it is a cap error
             const bool ok = spill && qrec != nullptr && (int64_t)ps < qcap &&
-                            (parked || !args.one_loop);
+                            (parked || !kargs()->one_loop);
             int nR = __popc(rflag);
             nR = gsum_i<G>(nR) + (kR ? 1 : 0);
             if (spill && gl == 0) S.cnt = 0;
@@ -541,7 +552,7 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
                 }
                 wave_sync();
             }
-            if (lookup_fail) atomicOr(args.err, 16);
+            if (lookup_fail) atomicOr(kargs()->err, 16);
 
             // ---- Householder QR update: stored reflectors j < qlo act on the new
             // columns only; reflectors qlo..qn-1 are formed and applied. Columns
@@ -831,7 +842,7 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
                 // the wave's in-order LDS execution
             }
             wave_sync();
-            if (lookup_fail2) atomicOr(args.err, 16);
+            if (lookup_fail2) atomicOr(kargs()->err, 16);
             double ra[RPL];
             int gi[RPL];
 #pragma unroll
@@ -878,13 +889,13 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
                 if (nsel == 0) finish = true;  // no candidate row left: r = 0 (Section 3)
                 linc = true;
                 dropok = true;
-                if (args.one_loop && nsel > 0) park = true;
+                if (kargs()->one_loop && nsel > 0) park = true;
             }
         }
 
         // ================================================== output of a column
         if (finish) {
-            const int64_t slot = args.arena_base + ucol * (int64_t)QMAX;
+            const int64_t slot = kargs()->arena_base + ucol * (int64_t)QMAX;
             const int qq = (status == ST_OK) ? q : 0;
             // m_k with its rows in ascending order (rank of each entry in the group)
 #pragma unroll
@@ -894,26 +905,26 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
                     const int jc = S.Jlist[c];
                     int rank = 0;
                     for (int t = 0; t < qq; ++t) rank += (S.Jlist[t] < jc) ? 1 : 0;
-                    args.out.arenaJ[slot + rank] = jc;
-                    args.out.arenaV[slot + rank] = S.mt[c];
+                    kargs()->out.arenaJ[slot + rank] = jc;
+                    kargs()->out.arenaV[slot + rank] = S.mt[c];
                 }
             }
             if (gl == 0) {
-                args.out.off[ucol] = slot;
-                args.out.nJ[ucol] = qq;
-                args.out.nI[ucol] = m;
-                args.out.loops[ucol] = l;
-                args.out.status[ucol] = status;
-                args.out.resnorm[ucol] = rn;
-                args.out.flops[ucol] = fl;
+                kargs()->out.off[ucol] = slot;
+                kargs()->out.nJ[ucol] = qq;
+                kargs()->out.nI[ucol] = m;
+                kargs()->out.loops[ucol] = l;
+                kargs()->out.status[ucol] = status;
+                kargs()->out.resnorm[ucol] = rn;
+                kargs()->out.flops[ucol] = fl;
             }
             // R of the final solve for the adjoint: row i of R is held by the owner lane
             // of row i (diagonal in rd, the rest in the block). Small tiers pack it in the
             // staging tile first, so the global stores need no per-entry addressing.
-            if (args.out.fac != nullptr) {
-                const long long fo = fac_take(args.out, fch, (gl == 0 && qq > 0) ? qq + qq * (qq + 1) / 2 : 0);
+            if (kargs()->out.fac != nullptr) {
+                const long long fo = fac_take(kargs()->out, fch, (gl == 0 && qq > 0) ? qq + qq * (qq + 1) / 2 : 0);
                 if (gl == 0) {
-                    args.out.foff[ucol] = fo;
+                    kargs()->out.foff[ucol] = fo;
                     S.fo_lo = (int)(fo & 0xffffffffLL);
                     S.fo_hi = (int)(fo >> 32);
                 }
@@ -932,7 +943,7 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
                     wave_sync();
                     const long long fo = ((long long)S.fo_hi << 32) | (long long)(unsigned)S.fo_lo;
                     if (fo >= 0) {
-                        double *F = args.out.fac + fo;
+                        double *F = kargs()->out.fac + fo;
                         const int tot = qq + qq * (qq + 1) / 2;
                         for (int t = gl; t < tot; t += G) F[t] = (t < qq) ? (double)S.Jlist[t] : S.stage[t - qq];
                     }
@@ -940,7 +951,7 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
                     wave_sync();
                     const long long fo = ((long long)S.fo_hi << 32) | (long long)(unsigned)S.fo_lo;
                     if (fo >= 0) {
-                        double *F = args.out.fac + fo;
+                        double *F = kargs()->out.fac + fo;
                         for (int c = gl; c < qq; c += G) F[c] = (double)S.Jlist[c];
 #pragma unroll
                         for (int r = 0; r < RPL; ++r) {
