@@ -54,13 +54,15 @@ struct WLds {
     int ord[64];            // slots in ascending column order
     int srow[SMAX];         // shared rows, ascending
     int stmp[SMAX];
+    int slist[SMAX];        // rows whose holder count reached 2 since the last scan, plus
+                            // the shared rows of that scan (slovf: the list overflowed)
     int newc[64];           // columns of J-hat
     int Rh[CMAX];           // pending dominant rows
     double cva[NW];
     int cvg[NW];
     double akv;             // a_kj when k is a private row of column slot kcol
     int kcol;
-    int cnt, nsh, flag;
+    int cnt, nsh, flag, nsl, slovf;
     double rn;
 };
 
@@ -68,8 +70,16 @@ template <class L>
 __device__ __forceinline__ unsigned hget(const L &S, int sl) {
     return (S.hv[sl >> 2] >> ((sl & 3) * 8)) & 0xFFu;
 }
+// one more column holds the row of slot sl; a row that becomes shared (two holders)
+// joins the candidate list of the next shared-row scan
 template <class L>
-__device__ __forceinline__ void hinc(L &S, int sl) { atomicAdd(&S.hv[sl >> 2], 1u << ((sl & 3) * 8)); }
+__device__ __forceinline__ void hinc(L &S, int sl, int row) {
+    const unsigned old = atomicAdd(&S.hv[sl >> 2], 1u << ((sl & 3) * 8));
+    if (((old >> ((sl & 3) * 8)) & 0x7Fu) == 1u) {
+        const int ps = atomicAdd(&S.nsl, 1);
+        if (ps < (int)(sizeof(S.slist) / sizeof(int))) S.slist[ps] = row; else S.slovf = 1;
+    }
+}
 template <class L>
 __device__ __forceinline__ void hdec(L &S, int sl) { atomicSub(&S.hv[sl >> 2], 1u << ((sl & 3) * 8)); }
 template <class L>
@@ -108,9 +118,10 @@ __device__ __forceinline__ int sfind(const int *srow, int nsh, int row) {
 // one wave, one column after another: f(c, row, val) for each entry, then done(c).
 // The first 64 entries of the next HB columns are loaded together ahead of use; the
 // loop over columns stays rolled to keep the code small.
-template <bool VAL, class L, class F, class D>
-__device__ __forceinline__ void wave_cols(const L &S, const MatDev &A, int c0, int c1, int wid, int lane, F &&f,
-                                          D &&done) {
+// Columns for which want(c) is false are skipped without loading their entries.
+template <bool VAL, class L, class F, class D, class W>
+__device__ __forceinline__ void wave_cols_if(const L &S, const MatDev &A, int c0, int c1, int wid, int lane, F &&f,
+                                             D &&done, W &&want) {
     constexpr int HB = 8;
     for (int cb0 = c0 + wid; cb0 < c1; cb0 += NW * HB) {
         int rr[HB];
@@ -120,7 +131,7 @@ __device__ __forceinline__ void wave_cols(const L &S, const MatDev &A, int c0, i
             const int c = cb0 + NW * s;
             rr[s] = -1;
             vv[s] = 0.0;
-            if (c < c1 && lane < S.clen[c]) {
+            if (c < c1 && lane < S.clen[c] && want(c)) {
                 const int64_t e = S.cb[c] + lane;
                 rr[s] = A.rowidx[e];
                 if (VAL) vv[s] = A.val[e];
@@ -139,13 +150,18 @@ __device__ __forceinline__ void wave_cols(const L &S, const MatDev &A, int c0, i
             }
             if (r0 >= 0) f(c, r0, v0);
             const int len = S.clen[c];
-            if (len > 64) {
+            if (len > 64 && want(c)) {
                 const int64_t e0 = S.cb[c];
                 for (int t = 64 + lane; t < len; t += 64) f(c, A.rowidx[e0 + t], VAL ? A.val[e0 + t] : 0.0);
             }
             done(c);
         }
     }
+}
+template <bool VAL, class L, class F, class D>
+__device__ __forceinline__ void wave_cols(const L &S, const MatDev &A, int c0, int c1, int wid, int lane, F &&f,
+                                          D &&done) {
+    wave_cols_if<VAL>(S, A, c0, c1, wid, lane, f, done, [](int) { return true; });
 }
 }  // namespace
 
@@ -179,7 +195,7 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
         for (int t = tid; t < HS; t += NT) S.hk[t] = HEMPTY;
         for (int t = tid; t < HS / 4; t += NT) S.hv[t] = 0u;
         for (int t = tid; t < HJ; t += NT) S.hJ[t] = HEMPTY;
-        if (tid == 0) S.flag = 0;
+        if (tid == 0) { S.flag = 0; S.nsl = 0; S.slovf = 0; }
         __syncthreads();
         if (q > QM || m > MM || nRh > CMAX) status = ST_CAP;  // larger than any register tier
         if (status == ST_OK) {
@@ -204,7 +220,7 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
                 S, A, 0, q, wid, lane,
                 [&](int, int row, double) {
                     const int sl = hfind<LOGH>(S.hk, row);
-                    if (sl >= 0) hinc(S, sl); else lookup_fail = true;
+                    if (sl >= 0) hinc(S, sl, row); else lookup_fail = true;
                 },
                 [](int) {});
             for (int t = tid; t < nR0; t += NT) {
@@ -308,7 +324,7 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
                     [&](int, int row, double) {
                         int sl;
                         if (hinsert<LOGH>(S.hk, row, sl)) ++added;
-                        if (sl >= 0) hinc(S, sl); else lookup_fail = true;
+                        if (sl >= 0) hinc(S, sl, row); else lookup_fail = true;
                     },
                     [](int) {});
                 if (added) atomicAdd(&S.cnt, added);
@@ -334,15 +350,35 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
                 // ---- shared rows (held by two or more columns of J), ascending
                 if (tid == 0) { S.nsh = 0; S.kcol = -1; S.akv = 0.0; S.flag = 0; }
                 __syncthreads();
-                for (int t = tid; t < HS; t += NT) {
-                    const int key = S.hk[t];
-                    if (key != HEMPTY && (hget(S, t) & 0x7Fu) >= 2u) {
-                        const int ps = atomicAdd(&S.nsh, 1);
-                        if (ps < SMAX) S.stmp[ps] = key;
+                const bool slovf = S.slovf != 0;
+                if (slovf) {
+                    for (int t = tid; t < HS; t += NT) {
+                        const int key = S.hk[t];
+                        if (key != HEMPTY && (hget(S, t) & 0x7Fu) >= 2u) {
+                            const int ps = atomicAdd(&S.nsh, 1);
+                            if (ps < SMAX) S.stmp[ps] = key;
+                        }
+                    }
+                } else {
+                    // every row with two or more holders is in the candidate list: it
+                    // was shared at the last scan or reached two holders since
+                    const int nl = S.nsl;
+                    for (int t = tid; t < nl; t += NT) {
+                        const int key = S.slist[t];
+                        const int sl = hfind<LOGH>(S.hk, key);
+                        if (sl >= 0 && (hget(S, sl) & 0x7Fu) >= 2u) {
+                            const int ps = atomicAdd(&S.nsh, 1);
+                            if (ps < SMAX) S.stmp[ps] = key;
+                        }
                     }
                 }
                 __syncthreads();
                 const int nsh = S.nsh;
+                if (!slovf && nsh <= SMAX) {
+                    // the list keeps the shared rows only (no row enters it twice)
+                    for (int t = tid; t < nsh; t += NT) S.slist[t] = S.stmp[t];
+                    if (tid == 0) S.nsl = nsh;
+                }
                 const int ld = q + 1, mp = nsh + q;
                 if (nsh > SMAX || nsh * q > SHV || mp * ld > BLK) {
                     // the compressed block does not fit: hand the unsolved pattern over
@@ -617,14 +653,13 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
                     }
                     if (nk < q) {
                         // rows of the dropped columns lose one holder
-                        wave_cols<false>(
+                        wave_cols_if<false>(
                             S, A, 0, q, wid, lane,
-                            [&](int c, int row, double) {
-                                if ((keepm >> c) & 1ull) return;
+                            [&](int, int row, double) {
                                 const int sl = hfind<LOGH>(S.hk, row);
                                 if (sl >= 0) hdec(S, sl); else lookup_fail = true;
                             },
-                            [](int) {});
+                            [](int) {}, [&](int c) { return ((keepm >> c) & 1ull) == 0ull; });
                         __syncthreads();
                         if (wid == 0) {
                             // compaction of the slots in order: lane c moves to the number of
