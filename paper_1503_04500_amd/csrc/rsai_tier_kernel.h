@@ -27,7 +27,10 @@ template <class C, bool MULTI>
 __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
     constexpr int G = C::G, RPL = C::RPL, QMAX = C::QMAX, MMAX = C::MMAX, GPW = C::GPW;
     constexpr int STAGE = C::STAGE;
-    constexpr int QCB = 4;                       // columns per chunk of the QR update
+    // columns per chunk of the QR update: the small first tier keeps one (a chunk may
+    // reach past the wave's last column, which costs more there than the interleaving
+    // saves)
+    constexpr int QCB = QMAX <= 12 ? 1 : 4;
     constexpr int NRI = (C::RIN + G - 1) / G;   // per-lane candidates per I round
     constexpr int NRJ = (C::RJN + G - 1) / G;   // per-lane candidates per J round
     constexpr int NNEW = (C::NEWC + G - 1) / G;
@@ -555,10 +558,12 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
             if (lookup_fail) atomicOr(kargs()->err, 16);
 
             // ---- Householder QR update: stored reflectors j < qlo act on the new
-            // columns only; reflectors qlo..qn-1 are formed and applied. Columns
-            // below the smallest qlo of the wave's solving groups are final for every
-            // group: no reflector is formed there and no stored one is applied to them.
-            const int qloww = -wave_max_i(act ? -qlo : -QMAX);
+            // columns only; reflectors qlo..qn-1 are formed and applied. In the larger
+            // tiers, columns below the smallest qlo of the wave's solving groups are
+            // final for every group: no reflector is formed there and no stored one is
+            // applied to them (the first tier's blocks are too narrow for the test to
+            // pay).
+            const int qloww = QMAX > 12 ? -wave_max_i(act ? -qlo : -QMAX) : 0;
 #pragma unroll
             for (int j = 0; j < QMAX; ++j) {
                 if (j >= qmaxw) continue;
