@@ -368,6 +368,18 @@ def main():
                                   "workload": "cd2d 128x128 seed 0; c=3 lmax=8 eps=0.1 tol=1e-3"}
         p01.close()
         del A01, H01
+        # eps = 0.1 on the benchmark's 512x512 grid: about 243000 columns pass the
+        # sparse-block class to the dense class, whose queues must then hold every column
+        # (spill_capacity = n); one timed build
+        prm01b = dict(PARAMS, eps=0.1, spill_capacity=H.n)
+        dt01b = time_builds(rsai, A, "batched", 1, 1, torch, prm=prm01b)
+        p01b = rsai.build(A, sched="batched", **prm01b)
+        nz01b = p01b.nnz()
+        _, its01b, _ = p01b.bicgstab(rsai.spmv(A, torch.ones(H.n, dtype=torch.float64, device="cuda:0")))
+        extra["eps01_cd2d512"] = {"eps": 0.1, "c": 3, "build_ms": dt01b * 1e3, "spar": nz01b / H.nnz,
+                                  "bicgstab_iterations": its01b, "spill_capacity": H.n,
+                                  "workload": "cd2d 512x512 seed 0; c=3 lmax=8 eps=0.1 tol=1e-3"}
+        p01b.close()
         # relatively dense rows (Section 4): 512x512 grid plus 1024 rows of 32 entries
         Hd = gen.dense_rows(512, 1024, 32)
         Ad = rsai.Matrix.from_host(Hd, "cuda:0")

@@ -46,7 +46,8 @@ typedef enum {
     RSAI_E_SINGULAR = -3, /* a column's LS problem (2.3) is rank deficient */
     RSAI_E_NOMEM = -4,    /* allocation failed */
     RSAI_E_HIP = -5,      /* HIP runtime error */
-    RSAI_E_CAP = -6,      /* a column outgrew the largest LS size the build supports */
+    RSAI_E_CAP = -6,      /* a column outgrew the largest LS size the build supports, or
+                             the spill queues (rsai_params.spill_capacity) were full */
     RSAI_E_STATE = -7     /* call not valid in the plan's state */
 } rsai_status;
 
@@ -126,6 +127,14 @@ typedef struct {
     const int64_t *col_len_max; /* host array, one per matrix: its longest column, for the
                           tuning table (NULL: read on the device, one host
                           synchronisation per build) */
+    int64_t spill_capacity; /* records each queue of the workgroup-per-column classes (the
+                          sparse-block levels and the dense class) can hold: 0 default
+                          (a quarter, 1/64 and 1/256 of the columns, at least 16384),
+                          else this many, at most the number of columns. A build whose
+                          spilled columns overflow a queue ends with RSAI_E_CAP and a
+                          message that names this field; the number of columns makes
+                          every column fit (small eps on large grids) at the cost of
+                          the queues' memory (up to about 55 KB per column) */
 } rsai_params;
 
 typedef struct rsai_plan rsai_plan; /* opaque host handle */

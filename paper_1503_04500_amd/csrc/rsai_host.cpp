@@ -173,6 +173,7 @@ static rsai_status check_params(const rsai_params *p) {
     if (p->last_tier < -1 || p->last_tier == 0 || p->last_tier >= kNumTiers)
         return fail(RSAI_E_ARG, "last_tier must be -1 or a register tier from 1 to %d", kNumTiers - 1);
     if (p->last_tier > 0 && p->tier0 > p->last_tier) return fail(RSAI_E_ARG, "tier0 is past last_tier");
+    if (p->spill_capacity < 0) return fail(RSAI_E_ARG, "spill_capacity must be >= 0");
     return RSAI_OK;
 }
 
@@ -228,6 +229,7 @@ rsai_status rsai_params_default(rsai_params *p) {
     p->t0_hash = -1;
     p->last_tier = -1;
     p->col_len_max = nullptr;
+    p->spill_capacity = 0;
     return RSAI_OK;
 }
 
@@ -413,6 +415,8 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
     wide_rec_cap[0] = std::min<int64_t>(ncols, std::max<int64_t>(16384, ncols / 4));
     wide_rec_cap[1] = std::min<int64_t>(ncols, std::max<int64_t>(16384, ncols / 64));
     wide_rec_cap[2] = std::min<int64_t>(ncols, std::max<int64_t>(16384, ncols / 256));
+    if (P->p.spill_capacity > 0)
+        for (int w = 0; w < WIDE_LEVELS; ++w) wide_rec_cap[w] = std::min<int64_t>(ncols, P->p.spill_capacity);
     // the batched schedule ends with two workgroup-per-column classes: the sparse-block
     // class (an arena slot of 64 per column) and the dense large class, whose columns
     // (at most its record capacity) get a slot of BQMAX_BIG per record
@@ -882,7 +886,12 @@ rsai_status rsai_plan_nnz(const rsai_plan *Pc, int32_t mat, int64_t *nnzM) {
         const int64_t herr = h[1];
         if (herr & 7) return fail(RSAI_E_CSC, "malformed CSC (flags %lld: 1 colptr, 2 row indices, 4 empty column)",
                                   (long long)herr);
-        if (herr) return fail(RSAI_E_STATE, "internal index error (flags %lld)", (long long)herr);
+        if (herr & ~32LL) return fail(RSAI_E_STATE, "internal index error (flags %lld)", (long long)herr);
+        if (herr & 32)
+            return fail(RSAI_E_CAP,
+                        "%lld columns did not fit the spill queues of the workgroup-per-column classes "
+                        "(rsai_params.spill_capacity: %lld; the number of columns makes every column fit)",
+                        (long long)h[3], (long long)P->p.spill_capacity);
         if (h[4]) return fail(RSAI_E_STATE, "%lld columns were not processed", (long long)h[4]);
         if (h[2]) return fail(RSAI_E_SINGULAR, "%lld columns have a rank-deficient LS problem", (long long)h[2]);
         if (h[3]) return fail(RSAI_E_CAP, "%lld columns outgrew the largest supported LS size", (long long)h[3]);

@@ -463,6 +463,7 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
             if (spill && !ok) {
                 // no larger tier can take the column
                 status = ST_CAP;
+                if (gl == 0 && qrec != nullptr && (int64_t)ps >= qcap) atomicOr(kargs()->err, 32);  // queue full
             }
             if (spill && ok) busy = false;
             wave_sync();

@@ -850,6 +850,7 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
                 continue;
             }
             status = ST_CAP;  // no room in the next class
+            if (tid == 0 && args.rec_out != nullptr) atomicOr(args.err, 32);  // queue full
         }
 
         // ---------------------------------------------------------- output (rows ascending)

@@ -36,7 +36,7 @@ class Params(ctypes.Structure):
                 ("keep_factors", ctypes.c_int32), ("factor_budget_bytes", ctypes.c_int64),
                 ("deterministic", ctypes.c_int32), ("tune_count", ctypes.c_int32),
                 ("tune_table", ctypes.c_void_p), ("t0_hash", ctypes.c_int32), ("last_tier", ctypes.c_int32),
-                ("col_len_max", ctypes.c_void_p)]
+                ("col_len_max", ctypes.c_void_p), ("spill_capacity", ctypes.c_int64)]
 
 
 class TuneEntry(ctypes.Structure):
@@ -220,7 +220,7 @@ def permute_rows(A: Matrix, p) -> Matrix:
 
 def params(c=3, lmax=10, eps=0.4, drop="fixed", tol=1e-3, sched="batched", validate=True, tier0=-1,
            timing=False, refill=-1, route=-1, keep_factors=False, factor_budget_bytes=0, deterministic=False,
-           t0_hash=-1, last_tier=-1):
+           t0_hash=-1, last_tier=-1, spill_capacity=0):
     p = Params()
     _check(load().rsai_params_default(ctypes.byref(p)))
     p.c, p.lmax, p.eps, p.tol = int(c), int(lmax), float(eps), float(tol)
@@ -236,6 +236,7 @@ def params(c=3, lmax=10, eps=0.4, drop="fixed", tol=1e-3, sched="batched", valid
     p.deterministic = 1 if deterministic else 0
     p.t0_hash = int(t0_hash)
     p.last_tier = int(last_tier)
+    p.spill_capacity = int(spill_capacity)
     return p
 
 

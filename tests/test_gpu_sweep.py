@@ -74,3 +74,23 @@ def test_dense_rows_512_full_parity():
     gpu = run_gpu(A, c=3, lmax=8, eps=0.4, drop="fixed", tol=1e-3)
     s = compare(A, gpu, ref, label="dense-rows-512")
     print("dense rows 512", s)
+
+
+def test_eps01_256_queue_capacity():
+    """eps = 0.1 on a 256x256 grid sends about 48000 of the 65536 columns past the
+    sparse-block class (their compressed blocks, with most rows shared, do not fit it)
+    to the dense class: with the default queue capacity the build ends with RSAI_E_CAP
+    and a message naming spill_capacity; with spill_capacity = n every column fits and a
+    seeded sample of 1500 columns matches the oracle."""
+    import paper_1503_04500_amd.rsai as rsai
+    from tests.parity import subset
+    A = gen.cd2d(256, seed=0)
+    dA = rsai.Matrix.from_host(A, "cuda:0")
+    with pytest.raises(rsai.RSAIError) as ei:
+        rsai.build(dA, c=3, lmax=8, eps=0.1, tol=1e-3).nnz()
+    assert ei.value.code == -6 and "spill_capacity" in str(ei.value)
+    gpu = run_gpu(A, c=3, lmax=8, eps=0.1, drop="fixed", tol=1e-3, spill_capacity=A.n)
+    cols = np.sort(np.random.default_rng(11).choice(A.n, 1500, replace=False))
+    ref = oracle.rsai(A, c=3, lmax=8, eps=0.1, drop=oracle.DROP_FIXED, tol=1e-3, cols=cols)
+    s = compare(A, subset(gpu, cols), ref, label="eps=0.1 256x256 sample", margin_tol=1e-14)
+    print(f"eps=0.1 256x256 with spill_capacity=n: sample parity {s}", flush=True)
