@@ -17,6 +17,7 @@
 // Columns arrive as spill records of the previous class; a column that outgrows this
 // class ends with status RSAI_E_CAP.
 #include <climits>
+#include <utility>
 
 #include "rsai_kernels.h"
 
@@ -44,6 +45,7 @@ struct BigLds {
     double rd[BQMAX_BIG];
     double bt[BQMAX_BIG];
     double red[NW * 8];
+    double redp[NW * (NB + 1)];    // per-wave partials of the register-panel reductions
     double Tm[16 * 16];            // T of the compact WY form of a panel
     double Wp[16 * NCTMAX * 16];   // T^T V^T C of a panel
     int ired[NW * 2];
@@ -221,6 +223,126 @@ __device__ void panel_update(double *B, int64_t ld, double *y, int m, int qn, in
         }
     }
     __syncthreads();
+}
+
+// Block-wide sums of x[LO..HI) (up to NB + 1 values): a wave-level tree per value,
+// then the four waves' partials through LDS. Every thread gets the totals.
+template <int LO, int HI>
+__device__ __forceinline__ void bsum_many(double (&x)[NB + 1], BigLds &S) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int u = LO; u < HI; ++u) {
+        x[u] = gsum<16>(x[u]);
+        x[u] += __shfl_xor(x[u], 16);
+        x[u] += __shfl_xor(x[u], 32);
+    }
+    if (lane == 0)
+#pragma unroll
+        for (int u = LO; u < HI; ++u) S.redp[w * (NB + 1) + u] = x[u];
+    __syncthreads();
+#pragma unroll
+    for (int u = LO; u < HI; ++u) {
+        double t = 0.0;
+#pragma unroll
+        for (int ww = 0; ww < NW; ++ww) t += S.redp[ww * (NB + 1) + u];
+        x[u] = t;
+    }
+    __syncthreads();
+}
+
+// One step of the register panel: the reflector of panel column UJ (block column
+// p0 + UJ) and its application to the panel's later columns.
+template <int RPT, int UJ>
+__device__ __forceinline__ void panel_step(double (&pv)[RPT][NB], int m, int p0, int pw, BigLds &S,
+                                           bool &singular) {
+    if (UJ >= pw) return;
+    const int tid = threadIdx.x;
+    const int j = p0 + UJ;
+    double x[NB + 1];
+    x[0] = 0.0;  // ||column j from its diagonal down||^2
+    x[1] = 0.0;  // its diagonal entry (held by one thread)
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int r = tid + NT * i;
+        if (r >= j && r < m) x[0] += pv[i][UJ] * pv[i][UJ];
+        if (r == j) x[1] = pv[i][UJ];
+    }
+    bsum_many<0, 2>(x, S);
+    const double x0 = x[1];
+    const double nx = sqrt(x[0]);
+    const double alpha = (x0 >= 0.0) ? -nx : nx;
+    const double vj = x0 - alpha;
+    const double be = (nx > 0.0) ? 1.0 / (nx * (nx + fabs(x0))) : 0.0;
+    if (!(nx > 0.0)) singular = true;
+    double v[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int r = tid + NT * i;
+        v[i] = (r > j && r < m) ? pv[i][UJ] : 0.0;
+        if (r == j) {
+            v[i] = vj;
+            pv[i][UJ] = vj;
+        }
+    }
+    if constexpr (UJ + 1 < NB) {
+        if (UJ + 1 < pw) {
+            double d[NB + 1];
+#pragma unroll
+            for (int u = UJ + 1; u < NB; ++u) {
+                d[u] = 0.0;
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) d[u] += v[i] * pv[i][u];
+            }
+            bsum_many<UJ + 1, NB>(d, S);
+#pragma unroll
+            for (int u = UJ + 1; u < NB; ++u) {
+                const double f = d[u] * be;
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) pv[i][u] -= f * v[i];
+            }
+        }
+    }
+    if (tid == 0) {
+        S.rd[j] = alpha;
+        S.bt[j] = be;
+    }
+}
+
+template <int RPT, int... UJ>
+__device__ __forceinline__ void panel_steps(double (&pv)[RPT][NB], int m, int p0, int pw, BigLds &S, bool &singular,
+                                            std::integer_sequence<int, UJ...>) {
+    (panel_step<RPT, UJ>(pv, m, p0, pw, S, singular), ...);
+}
+
+// Factor the panel columns p0 .. p0+pw-1 (pw <= NB) of an m-row block, m <= NT * RPT,
+// with the panel held in registers (thread t holds rows t + NT * i of every panel
+// column): each step takes the norm of column j from its diagonal down and the diagonal
+// entry in one block reduction, forms the reflector, and applies it to the panel's
+// later columns with one more reduction of all their products. The panel is written
+// back (reflector heads on the diagonal, R above it); alpha and beta go to S.rd, S.bt.
+// Returns true if a column has zero norm from its diagonal down (rank deficiency).
+template <int RPT>
+__device__ bool panel_factor_regs(double *B, int64_t ld, int m, int p0, int pw, BigLds &S) {
+    const int tid = threadIdx.x;
+    double pv[RPT][NB];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int r = tid + NT * i;
+#pragma unroll
+        for (int u = 0; u < NB; ++u) pv[i][u] = (r < m && u < pw) ? B[(int64_t)(p0 + u) * ld + r] : 0.0;
+    }
+    bool singular = false;
+    panel_steps<RPT>(pv, m, p0, pw, S, singular, std::make_integer_sequence<int, NB>{});
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int r = tid + NT * i;
+        if (r < m)
+#pragma unroll
+            for (int u = 0; u < NB; ++u)
+                if (u < pw) B[(int64_t)(p0 + u) * ld + r] = pv[i][u];
+    }
+    __syncthreads();
+    return singular;
 }
 
 __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
@@ -484,6 +606,12 @@ __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
                 // with the compact WY form Q_p = I - V T V^T (FP64 MFMA 16x16x4).
                 for (int p0 = q0; p0 < qn; p0 += NB) {
                     const int pw = min(NB, qn - p0);
+                    // blocks of up to 1024 rows: the panel in registers; taller: in the slab
+                    if (m <= NT * 2) {
+                        if (panel_factor_regs<2>(B, ld, m, p0, pw, S)) singular = true;
+                    } else if (m <= NT * 4) {
+                        if (panel_factor_regs<4>(B, ld, m, p0, pw, S)) singular = true;
+                    } else
                     for (int j = p0; j < p0 + pw; ++j) {
                         double *bj = B + (int64_t)j * ld;
                         double s2 = 0.0;
