@@ -675,6 +675,26 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
                     w.rec_out_stride = wide_rec_stride(lv);
                     w.rec_out_count = P->rec_count + (tlast - t0 + 1 + lv);
                     w.rec_out_cap = wide_rec_cap[lv];
+                    // blocks that do not fit: level 0's go past level 1 (the same block
+                    // limits) to level 2; mostly shared ones go to the dense class
+                    for (int a = 0; a < 2; ++a) {
+                        w.rec_alt[a] = nullptr;
+                        w.rec_alt_count[a] = nullptr;
+                        w.rec_alt_stride[a] = 0;
+                        w.rec_alt_cap[a] = 0;
+                    }
+                    if (lv == 0 && WIDE_LEVELS > 2) {
+                        w.rec_alt[0] = P->rec[tlast + 2];
+                        w.rec_alt_stride[0] = wide_rec_stride(1);
+                        w.rec_alt_count[0] = P->rec_count + (tlast - t0 + 2);
+                        w.rec_alt_cap[0] = wide_rec_cap[1];
+                    }
+                    if (lv < WIDE_LEVELS - 1) {
+                        w.rec_alt[1] = P->rec[tlast + WIDE_LEVELS];
+                        w.rec_alt_stride[1] = wide_rec_stride(WIDE_LEVELS - 1);
+                        w.rec_alt_count[1] = P->rec_count + (tlast - t0 + WIDE_LEVELS);
+                        w.rec_alt_cap[1] = wide_rec_cap[WIDE_LEVELS - 1];
+                    }
                     w.err = P->err;
                     launch_wide_kernel(lv, w, device_cus() * wide_blocks_per_cu(lv), s);
                 }

@@ -36,10 +36,18 @@ struct WideArgs {
     int rec_in_stride;
     const int32_t *rec_in_count;
     int64_t rec_in_cap;
-    int32_t *rec_out;         // records for the dense large class
+    int32_t *rec_out;         // records for the next class
     int rec_out_stride;
     int32_t *rec_out_count;
     int64_t rec_out_cap;
+    // Columns whose compressed block does not fit: [0] the first later level with a
+    // larger block (when the next level's block is no larger), [1] the dense class
+    // (when most of the block's rows are shared, so that compressing gains little);
+    // nullptr where absent (the next class then takes them).
+    int32_t *rec_alt[2];
+    int rec_alt_stride[2];
+    int32_t *rec_alt_count[2];
+    int64_t rec_alt_cap[2];
     int32_t *err;
 };
 int wide_max_rows(int level);

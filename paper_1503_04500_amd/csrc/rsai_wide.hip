@@ -188,6 +188,7 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
         int status = ST_OK;
         bool spill = false, pend = false, pend_drop = false;
         int pend_qmod = -1, pend_mmod = 0;
+        int blk_nsh = -1;         // shared rows when the compressed block did not fit
         bool lookup_fail = false;
         double rn = 0.0;
 
@@ -383,6 +384,7 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
                 if (nsh > SMAX || nsh * q > SHV || mp * ld > BLK) {
                     // the compressed block does not fit: hand the unsolved pattern over
                     spill = true;
+                    blk_nsh = nsh;
                     pend = true;
                     pend_drop = dropok && pass == 0;
                     pend_qmod = qmod;
@@ -805,18 +807,32 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
         if (lookup_fail) atomicOr(args.err, 16);
 
         if (spill) {
-            // ---- hand the column over to the dense large class
+            // ---- hand the column over to a later class: the next one, or for a block
+            // that did not fit, the first level with a larger block, or the dense class
+            // when most of its rows are shared
+            int32_t *qo = args.rec_out, *qc = args.rec_out_count;
+            int qs = args.rec_out_stride;
+            int64_t qcap = args.rec_out_cap;
+            if (blk_nsh >= 0) {
+                const int d = (args.rec_alt[1] != nullptr && 2 * blk_nsh >= m) ? 1 : (args.rec_alt[0] != nullptr ? 0 : -1);
+                if (d >= 0) {
+                    qo = args.rec_alt[d];
+                    qc = args.rec_alt_count[d];
+                    qs = args.rec_alt_stride[d];
+                    qcap = args.rec_alt_cap[d];
+                }
+            }
             if (tid == 0) {
                 int ps = INT_MAX;
-                if (args.rec_out) ps = atomicAdd(args.rec_out_count, 1);
+                if (qo) ps = atomicAdd(qc, 1);
                 S.cnt = ps;
                 S.nsh = 0;  // R rows written
                 S.flag = 0; // I rows written
             }
             __syncthreads();
             const int ps = S.cnt;
-            if (args.rec_out != nullptr && (int64_t)ps < args.rec_out_cap) {
-                int32_t *R = args.rec_out + (int64_t)ps * args.rec_out_stride;
+            if (qo != nullptr && (int64_t)ps < qcap) {
+                int32_t *R = qo + (int64_t)ps * qs;
                 int32_t *RJo = R + RHDR, *RIo = RJo + q, *RRo = RIo + m;
                 for (int t = tid; t < q; t += NT) RJo[t] = S.Jl[t];
                 // I (hash order; the receiver numbers its rows in ascending order) and R
@@ -850,7 +866,7 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
                 continue;
             }
             status = ST_CAP;  // no room in the next class
-            if (tid == 0 && args.rec_out != nullptr) atomicOr(args.err, 32);  // queue full
+            if (tid == 0 && qo != nullptr) atomicOr(args.err, 32);  // queue full
         }
 
         // ---------------------------------------------------------- output (rows ascending)
