@@ -407,14 +407,16 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
         slot_base[t] = acap;
         acap += ncols * (int64_t)kTiers[t].QMAX;
     }
-    // records out of each sparse-block instance: few columns need the next class;
-    // more than this many end with RSAI_E_CAP
+    // capacity of the record queues after the register tiers (queue w feeds level w + 1
+    // of the sparse-block class, queue WIDE_LEVELS - 1 the dense class): few columns
+    // need the later classes; more than this many end with RSAI_E_CAP
     int64_t wide_rec_cap[WIDE_LEVELS];
     // (every column of a build of up to 16384 columns fits every queue, so a small eps,
     // which sends most columns of a grid to the workgroup classes, still completes)
     wide_rec_cap[0] = std::min<int64_t>(ncols, std::max<int64_t>(16384, ncols / 4));
     wide_rec_cap[1] = std::min<int64_t>(ncols, std::max<int64_t>(16384, ncols / 64));
-    wide_rec_cap[2] = std::min<int64_t>(ncols, std::max<int64_t>(16384, ncols / 256));
+    wide_rec_cap[2] = std::min<int64_t>(ncols, std::max<int64_t>(16384, ncols / 64));
+    wide_rec_cap[3] = std::min<int64_t>(ncols, std::max<int64_t>(16384, ncols / 256));
     if (P->p.spill_capacity > 0)
         for (int w = 0; w < WIDE_LEVELS; ++w) wide_rec_cap[w] = std::min<int64_t>(ncols, P->p.spill_capacity);
     // the batched schedule ends with two workgroup-per-column classes: the sparse-block
@@ -500,7 +502,7 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
                 P->rec[t] = L.take<int32_t>(ncols * (int64_t)kTiers[t].REC);
             if (big)
                 for (int w = 0; w < WIDE_LEVELS; ++w)
-                    P->rec[tlast + 1 + w] = L.take<int32_t>(wide_rec_cap[w] * (int64_t)wide_rec_stride(w));
+                    P->rec[tlast + 1 + w] = L.take<int32_t>(wide_rec_cap[w] * (int64_t)wide_queue_stride(w));
         }
         P->big_scratch = big ? L.take<double>((int64_t)big_blocks * big_scratch_stride(big_ld)) : nullptr;
     };
@@ -642,7 +644,7 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
                 for (int c = t + 1; c <= tlast + (big ? 2 : 0) && a.nq < nq_max; ++c) {
                     const int i = a.nq++;
                     a.q_rec[i] = P->rec[c - 1];
-                    a.q_stride[i] = c <= tlast + 1 ? kTiers[c - 1].REC : wide_rec_stride(0);
+                    a.q_stride[i] = c <= tlast + 1 ? kTiers[c - 1].REC : wide_queue_stride(0);
                     a.q_count[i] = P->rec_count + (c - 1 - t0);
                     a.q_cap[i] = c <= tlast + 1 ? ncols : wide_rec_cap[0];
                     a.q_mmax[i] = c <= tlast ? kTiers[c].MMAX : wide_max_rows(c - tlast - 1);
@@ -661,40 +663,51 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
             if (big) {
                 // columns that outgrew the last register tier: one workgroup per column,
                 // first on the compressed block, then (rarely) on the dense block
+                // queue w (rec[tlast + 1 + w], counter tlast - t0 + 1 + w) feeds level
+                // w + 1; the last one the dense class
+                auto queue = [&](int w, int32_t *&buf, int &stride, int32_t *&count, int64_t &cap) {
+                    buf = P->rec[tlast + 1 + w];
+                    stride = wide_queue_stride(w);
+                    count = P->rec_count + (tlast - t0 + 1 + w);
+                    cap = wide_rec_cap[w];
+                };
+                // where each level sends its columns: rows over its cap (and, for levels
+                // 1 to 3, blocks that do not fit) to out_q; level 0's blocks that do not
+                // fit to level 2, which has a larger block; mostly shared blocks of levels
+                // 0 to 2 to the dense class
+                static const int out_q[WIDE_LEVELS] = {0, 2, 2, 3};
                 for (int lv = 0; lv < WIDE_LEVELS; ++lv) {
                     WideArgs w{};
                     w.mats = P->d_mats;
                     w.P = base.P;
                     w.out = P->out;
                     w.arena_base = wide_base;
-                    w.rec_in = P->rec[tlast + lv];
-                    w.rec_in_stride = lv == 0 ? kTiers[tlast].REC : wide_rec_stride(lv - 1);
-                    w.rec_in_count = P->rec_count + (tlast - t0 + lv);
-                    w.rec_in_cap = lv == 0 ? ncols : wide_rec_cap[lv - 1];
-                    w.rec_out = P->rec[tlast + 1 + lv];
-                    w.rec_out_stride = wide_rec_stride(lv);
-                    w.rec_out_count = P->rec_count + (tlast - t0 + 1 + lv);
-                    w.rec_out_cap = wide_rec_cap[lv];
-                    // blocks that do not fit: level 0's go past level 1 (the same block
-                    // limits) to level 2; mostly shared ones go to the dense class
+                    if (lv == 0) {
+                        w.rec_in = P->rec[tlast];
+                        w.rec_in_stride = kTiers[tlast].REC;
+                        w.rec_in_count = P->rec_count + (tlast - t0);
+                        w.rec_in_cap = ncols;
+                    } else {
+                        int32_t *buf, *cnt;
+                        int st;
+                        int64_t cap;
+                        queue(lv - 1, buf, st, cnt, cap);
+                        w.rec_in = buf;
+                        w.rec_in_stride = st;
+                        w.rec_in_count = cnt;
+                        w.rec_in_cap = cap;
+                    }
+                    queue(out_q[lv], w.rec_out, w.rec_out_stride, w.rec_out_count, w.rec_out_cap);
                     for (int a = 0; a < 2; ++a) {
                         w.rec_alt[a] = nullptr;
                         w.rec_alt_count[a] = nullptr;
                         w.rec_alt_stride[a] = 0;
                         w.rec_alt_cap[a] = 0;
                     }
-                    if (lv == 0 && WIDE_LEVELS > 2) {
-                        w.rec_alt[0] = P->rec[tlast + 2];
-                        w.rec_alt_stride[0] = wide_rec_stride(1);
-                        w.rec_alt_count[0] = P->rec_count + (tlast - t0 + 2);
-                        w.rec_alt_cap[0] = wide_rec_cap[1];
-                    }
-                    if (lv < WIDE_LEVELS - 1) {
-                        w.rec_alt[1] = P->rec[tlast + WIDE_LEVELS];
-                        w.rec_alt_stride[1] = wide_rec_stride(WIDE_LEVELS - 1);
-                        w.rec_alt_count[1] = P->rec_count + (tlast - t0 + WIDE_LEVELS);
-                        w.rec_alt_cap[1] = wide_rec_cap[WIDE_LEVELS - 1];
-                    }
+                    if (lv == 0) queue(1, w.rec_alt[0], w.rec_alt_stride[0], w.rec_alt_count[0], w.rec_alt_cap[0]);
+                    if (lv < WIDE_LEVELS - 1)
+                        queue(WIDE_LEVELS - 1, w.rec_alt[1], w.rec_alt_stride[1], w.rec_alt_count[1],
+                              w.rec_alt_cap[1]);
                     w.err = P->err;
                     launch_wide_kernel(lv, w, device_cus() * wide_blocks_per_cu(lv), s);
                 }
@@ -704,7 +717,7 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
                 b.out = P->out;
                 b.arena_base = big_base;
                 b.rec_in = P->rec[tlast + WIDE_LEVELS];
-                b.rec_in_stride = wide_rec_stride(WIDE_LEVELS - 1);
+                b.rec_in_stride = wide_queue_stride(WIDE_LEVELS - 1);
                 b.rec_in_count = P->rec_count + (tlast - t0 + WIDE_LEVELS);
                 b.rec_in_cap = wide_rec_cap[WIDE_LEVELS - 1];
                 b.scratch = P->big_scratch;

@@ -24,7 +24,7 @@ void launch_tier_kernel(int tier, int hash4, const TierArgs &a, int waves, hipSt
 
 // ---- sparse-block size class (rsai_wide.hip): one workgroup per column, LS solved
 // on the compressed block (shared rows + one row per column)
-constexpr int WIDE_LEVELS = 3;   // instances: |I| <= 1024, 2048, 8192
+constexpr int WIDE_LEVELS = 4;   // instances: |I| <= 1024, 2048, 1024 (a larger compressed block), 8192
 constexpr int WIDE_QMAX = 63;    // columns of J
 constexpr int WIDE_RCAP = 8 * 64 + 1;  // dominant rows in a record: c * lmax + 1
 struct WideArgs {
@@ -51,7 +51,11 @@ struct WideArgs {
     int32_t *err;
 };
 int wide_max_rows(int level);
-int wide_rec_stride(int level);  // ints per record written by that instance
+int wide_rec_stride(int level);  // ints per record of up to that instance's rows
+// Record queues after the register tiers, in launch order of their readers: queue 0
+// feeds level 1 (rows over level 0's cap), queue 1 level 2 (level 0's blocks that do
+// not fit), queue 2 level 3 (from levels 1 and 2), queue 3 the dense class.
+int wide_queue_stride(int queue);
 int wide_blocks_per_cu(int level);
 void launch_wide_kernel(int level, const WideArgs &a, int blocks, hipStream_t s);
 

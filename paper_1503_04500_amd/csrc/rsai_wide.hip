@@ -914,15 +914,24 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
 }
 
 namespace {
-constexpr int kWideLogH[WIDE_LEVELS] = {11, 12, 14};
-constexpr int kWidePerCU[WIDE_LEVELS] = {4, 3, 1};
+// Level 2 takes level 0's columns whose compressed block does not fit (many shared
+// rows, as in the columns that pick a relatively dense row) at two workgroups per CU
+// instead of sending them to the one-per-CU level 3.
+constexpr int kWideLogH[WIDE_LEVELS] = {11, 12, 11, 14};
+constexpr int kWidePerCU[WIDE_LEVELS] = {4, 3, 2, 1};
 #define RSAI_WIDE0 kWideLogH[0], 2048, 768, 128, kWidePerCU[0]
 #define RSAI_WIDE1 kWideLogH[1], 2048, 768, 128, kWidePerCU[1]
-#define RSAI_WIDE2 kWideLogH[2], 6144, 1536, 256, kWidePerCU[2]
+#define RSAI_WIDE2 kWideLogH[2], 4096, 1536, 128, kWidePerCU[2]
+#define RSAI_WIDE3 kWideLogH[3], 6144, 1536, 256, kWidePerCU[3]
 }  // namespace
 
 int wide_max_rows(int level) { return (1 << kWideLogH[level]) / 2; }
 int wide_rec_stride(int level) { return RHDR + 64 + wide_max_rows(level) + WIDE_RCAP + CMAX; }
+int wide_queue_stride(int queue) {
+    // rows of the largest record a writer of the queue can hand over
+    static const int writer_level[WIDE_LEVELS] = {0, 0, 1, 3};
+    return wide_rec_stride(writer_level[queue]);
+}
 int wide_blocks_per_cu(int level) { return kWidePerCU[level]; }
 
 void launch_wide_kernel(int level, const WideArgs &a, int blocks, hipStream_t s) {
@@ -930,8 +939,10 @@ void launch_wide_kernel(int level, const WideArgs &a, int blocks, hipStream_t s)
         hipLaunchKernelGGL((wide_kernel<RSAI_WIDE0>), dim3(blocks), dim3(NT), 0, s, a);
     else if (level == 1)
         hipLaunchKernelGGL((wide_kernel<RSAI_WIDE1>), dim3(blocks), dim3(NT), 0, s, a);
-    else
+    else if (level == 2)
         hipLaunchKernelGGL((wide_kernel<RSAI_WIDE2>), dim3(blocks), dim3(NT), 0, s, a);
+    else
+        hipLaunchKernelGGL((wide_kernel<RSAI_WIDE3>), dim3(blocks), dim3(NT), 0, s, a);
 }
 
 }  // namespace rsai
