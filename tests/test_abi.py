@@ -89,6 +89,10 @@ def test_argument_errors_without_gpu():
     bad = rsai.params()
     bad.route = 3
     assert lib.rsai_build(ctypes.byref(rsai.CSCView(4, 4, 8, 8, 8)), ctypes.byref(bad), None, ctypes.byref(out)) == -1
+    bad = rsai.params(spill_capacity=-1)
+    assert lib.rsai_build(ctypes.byref(rsai.CSCView(4, 4, 8, 8, 8)), ctypes.byref(bad), None, ctypes.byref(out)) == -1
+    assert b"spill_capacity" in lib.rsai_last_error()
+    assert rsai.params().spill_capacity == 0
 
 
 def test_no_cpu_fallback():
