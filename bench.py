@@ -400,6 +400,14 @@ def main():
                                  "workload": "power-law columns (min 2, mean 7, max 200), n=10^6, seed 0; "
                                              "c=3 lmax=10 eps=0.4 tol=1e-3",
                                  "roofline": class_roofline(rsai, [A3], P3, np)}
+        # the plain schedule (one launch per loop; its outgrown columns go on to the same
+        # workgroup classes) on the deeper workloads, beside the batched one
+        dt3p = time_builds(rsai, A3, "plain", 2, 1, torch, prm=P3)
+        dt02p = time_builds(rsai, A, "plain", 2, 1, torch, prm=dict(PARAMS, eps=0.2))
+        dt02b = time_builds(rsai, A, "batched", 2, 1, torch, prm=dict(PARAMS, eps=0.2))
+        extra["plain_vs_batched"] = {
+            "powerlaw_1e6": {"plain_ms": dt3p * 1e3, "batched_ms": dt3 * 1e3, "speedup": dt3p / dt3},
+            "cd2d512_eps0.2": {"plain_ms": dt02p * 1e3, "batched_ms": dt02b * 1e3, "speedup": dt02p / dt02b}}
         host_mats["c3"] = H3
         del A3, H3
         specs = gen.batch64_specs()

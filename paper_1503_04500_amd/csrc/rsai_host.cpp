@@ -419,17 +419,26 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
     wide_rec_cap[3] = std::min<int64_t>(ncols, std::max<int64_t>(16384, ncols / 256));
     if (P->p.spill_capacity > 0)
         for (int w = 0; w < WIDE_LEVELS; ++w) wide_rec_cap[w] = std::min<int64_t>(ncols, P->p.spill_capacity);
-    // the batched schedule ends with two workgroup-per-column classes: the sparse-block
-    // class (an arena slot of 64 per column) and the dense large class, whose columns
-    // (at most its record capacity) get a slot of BQMAX_BIG per record
-    const bool big = !plain;
+    // both schedules end with the workgroup-per-column classes (the plain schedule hands
+    // them the columns that outgrow its one register class): the sparse-block class (an
+    // arena slot of 64 per column) and the dense large class, whose columns (at most its
+    // record capacity) get a slot of BQMAX_BIG per record
+    const bool big = true;
     const int64_t big_cap = big ? wide_rec_cap[WIDE_LEVELS - 1] : 0;
     const int64_t wide_base = acap;
     if (big) acap += ncols * (int64_t)(WIDE_QMAX + 1);
     const int64_t big_base = acap;
     if (big) acap += big_cap * (int64_t)BQMAX_BIG;
     P->arena_cap = acap;
-    const int nlaunch = plain ? P->p.lmax + 1 : (tlast - t0 + 1 + (big ? 1 + WIDE_LEVELS : 0));
+    // record queues and their counters. Batched: the register tiers' queues (counter k
+    // feeds class t0 + 1 + k), then the workgroup classes' queues. Plain: two queues
+    // used in turn by the loop launches (counter L is written by launch L), the queue of
+    // the columns that outgrow the register class, then the workgroup classes' queues.
+    const int nlaunch = plain ? P->p.lmax + 2 + WIDE_LEVELS : (tlast - t0 + 1 + (big ? 1 + WIDE_LEVELS : 0));
+    const int q_in0 = plain ? 2 : tlast;                      // rec[] of sparse-block level 0's input
+    const int c_in0 = plain ? P->p.lmax + 1 : tlast - t0;     // its counter
+    const int q_wide = q_in0 + 1;                             // rec[] of the workgroup queue 0
+    const int c_wide = c_in0 + 1;                             // its counter
     const int64_t qlast = big ? std::max<int64_t>(kTiers[tlast].QMAX, BQMAX_BIG) : kTiers[tlast].QMAX;
     const int64_t qmid = big ? std::max<int64_t>(kTiers[tlast].QMAX, WIDE_QMAX + 1) : qlast;
     const int big_blocks = device_cus();
@@ -495,15 +504,14 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
         P->rec_count = L.take<int32_t>(nlaunch + 1);
         for (int t = 0; t < 8; ++t) P->rec[t] = nullptr;
         if (plain) {
-            P->rec[0] = L.take<int32_t>(ncols * (int64_t)kTiers[kPlainTier].REC);
-            P->rec[1] = L.take<int32_t>(ncols * (int64_t)kTiers[kPlainTier].REC);
+            for (int r = 0; r < 3; ++r) P->rec[r] = L.take<int32_t>(ncols * (int64_t)kTiers[kPlainTier].REC);
         } else {
             for (int t = t0; t < tlast + (big ? 1 : 0); ++t)
                 P->rec[t] = L.take<int32_t>(ncols * (int64_t)kTiers[t].REC);
-            if (big)
-                for (int w = 0; w < WIDE_LEVELS; ++w)
-                    P->rec[tlast + 1 + w] = L.take<int32_t>(wide_rec_cap[w] * (int64_t)wide_queue_stride(w));
         }
+        if (big)
+            for (int w = 0; w < WIDE_LEVELS; ++w)
+                P->rec[q_wide + w] = L.take<int32_t>(wide_rec_cap[w] * (int64_t)wide_queue_stride(w));
         P->big_scratch = big ? L.take<double>((int64_t)big_blocks * big_scratch_stride(big_ld)) : nullptr;
     };
     Layout L0;
@@ -598,7 +606,7 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
             // the state of every unfinished column goes through HBM between launches
             const int t = kPlainTier;
             const int gpw = 64 / kTiers[t].G;
-            for (int L = 0; L < nlaunch; ++L) {
+            for (int L = 0; L <= P->p.lmax; ++L) {
                 TierArgs a = base;
                 a.arena_base = slot_base[t];
                 a.one_loop = 1;
@@ -611,11 +619,21 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
                     a.rec_in_count = P->rec_count + (L - 1);
                     a.rec_in_cap = ncols;
                 }
-                a.nq = 1;
+                // queue 0: the columns parked after this loop; queue 1: those that
+                // outgrew the register class (to the workgroup classes)
+                a.nq = 2;
                 a.q_rec[0] = P->rec[L % 2];
                 a.q_stride[0] = kTiers[t].REC;
                 a.q_count[0] = P->rec_count + L;
                 a.q_cap[0] = ncols;
+                a.q_mmax[0] = kTiers[t].MMAX;
+                a.q_qmax[0] = kTiers[t].QMAX;
+                a.q_rec[1] = P->rec[q_in0];
+                a.q_stride[1] = kTiers[t].REC;
+                a.q_count[1] = P->rec_count + c_in0;
+                a.q_cap[1] = ncols;
+                a.q_mmax[1] = wide_max_rows(0);
+                a.q_qmax[1] = WIDE_QMAX;
                 int64_t want = (L == 0) ? (ncols + gpw - 1) / gpw : (int64_t)cus * 8;
                 int waves = (int)std::max<int64_t>(8, std::min<int64_t>(want, (int64_t)cus * 16));
                 waves = (waves + 7) / 8 * 8;
@@ -660,72 +678,72 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
                 launch_tier_kernel(t, hash4, a, waves, s);
                 if (t == t0) P->record(2, s);
             }
-            if (big) {
-                // columns that outgrew the last register tier: one workgroup per column,
-                // first on the compressed block, then (rarely) on the dense block
-                // queue w (rec[tlast + 1 + w], counter tlast - t0 + 1 + w) feeds level
-                // w + 1; the last one the dense class
-                auto queue = [&](int w, int32_t *&buf, int &stride, int32_t *&count, int64_t &cap) {
-                    buf = P->rec[tlast + 1 + w];
-                    stride = wide_queue_stride(w);
-                    count = P->rec_count + (tlast - t0 + 1 + w);
-                    cap = wide_rec_cap[w];
-                };
-                // where each level sends its columns: rows over its cap (and, for levels
-                // 1 to 3, blocks that do not fit) to out_q; level 0's blocks that do not
-                // fit to level 2, which has a larger block; mostly shared blocks of levels
-                // 0 to 2 to the dense class
-                static const int out_q[WIDE_LEVELS] = {0, 2, 2, 3};
-                for (int lv = 0; lv < WIDE_LEVELS; ++lv) {
-                    WideArgs w{};
-                    w.mats = P->d_mats;
-                    w.P = base.P;
-                    w.out = P->out;
-                    w.arena_base = wide_base;
-                    if (lv == 0) {
-                        w.rec_in = P->rec[tlast];
-                        w.rec_in_stride = kTiers[tlast].REC;
-                        w.rec_in_count = P->rec_count + (tlast - t0);
-                        w.rec_in_cap = ncols;
-                    } else {
-                        int32_t *buf, *cnt;
-                        int st;
-                        int64_t cap;
-                        queue(lv - 1, buf, st, cnt, cap);
-                        w.rec_in = buf;
-                        w.rec_in_stride = st;
-                        w.rec_in_count = cnt;
-                        w.rec_in_cap = cap;
-                    }
-                    queue(out_q[lv], w.rec_out, w.rec_out_stride, w.rec_out_count, w.rec_out_cap);
-                    for (int a = 0; a < 2; ++a) {
-                        w.rec_alt[a] = nullptr;
-                        w.rec_alt_count[a] = nullptr;
-                        w.rec_alt_stride[a] = 0;
-                        w.rec_alt_cap[a] = 0;
-                    }
-                    if (lv == 0) queue(1, w.rec_alt[0], w.rec_alt_stride[0], w.rec_alt_count[0], w.rec_alt_cap[0]);
-                    if (lv < WIDE_LEVELS - 1)
-                        queue(WIDE_LEVELS - 1, w.rec_alt[1], w.rec_alt_stride[1], w.rec_alt_count[1],
-                              w.rec_alt_cap[1]);
-                    w.err = P->err;
-                    launch_wide_kernel(lv, w, device_cus() * wide_blocks_per_cu(lv), s);
+        }
+        if (big) {
+            // columns that outgrew the register classes: one workgroup per column,
+            // first on the compressed block, then (rarely) on the dense block.
+            // Queue w (rec[q_wide + w], counter c_wide + w) feeds level w + 1; the
+            // last one the dense class
+            auto queue = [&](int w, int32_t *&buf, int &stride, int32_t *&count, int64_t &cap) {
+                buf = P->rec[q_wide + w];
+                stride = wide_queue_stride(w);
+                count = P->rec_count + (c_wide + w);
+                cap = wide_rec_cap[w];
+            };
+            // where each level sends its columns: rows over its cap (and, for levels
+            // 1 to 3, blocks that do not fit) to out_q; level 0's blocks that do not
+            // fit to level 2, which has a larger block; mostly shared blocks of levels
+            // 0 to 2 to the dense class
+            static const int out_q[WIDE_LEVELS] = {0, 2, 2, 3};
+            for (int lv = 0; lv < WIDE_LEVELS; ++lv) {
+                WideArgs w{};
+                w.mats = P->d_mats;
+                w.P = base.P;
+                w.out = P->out;
+                w.arena_base = wide_base;
+                if (lv == 0) {
+                    w.rec_in = P->rec[q_in0];
+                    w.rec_in_stride = kTiers[plain ? kPlainTier : tlast].REC;
+                    w.rec_in_count = P->rec_count + c_in0;
+                    w.rec_in_cap = ncols;
+                } else {
+                    int32_t *buf, *cnt;
+                    int st;
+                    int64_t cap;
+                    queue(lv - 1, buf, st, cnt, cap);
+                    w.rec_in = buf;
+                    w.rec_in_stride = st;
+                    w.rec_in_count = cnt;
+                    w.rec_in_cap = cap;
                 }
-                BigArgs b{};
-                b.mats = P->d_mats;
-                b.P = base.P;
-                b.out = P->out;
-                b.arena_base = big_base;
-                b.rec_in = P->rec[tlast + WIDE_LEVELS];
-                b.rec_in_stride = wide_queue_stride(WIDE_LEVELS - 1);
-                b.rec_in_count = P->rec_count + (tlast - t0 + WIDE_LEVELS);
-                b.rec_in_cap = wide_rec_cap[WIDE_LEVELS - 1];
-                b.scratch = P->big_scratch;
-                b.scratch_stride = big_scratch_stride(big_ld);
-                b.ld = big_ld;
-                b.err = P->err;
-                launch_big_kernel(b, big_blocks, s);
+                queue(out_q[lv], w.rec_out, w.rec_out_stride, w.rec_out_count, w.rec_out_cap);
+                for (int a = 0; a < 2; ++a) {
+                    w.rec_alt[a] = nullptr;
+                    w.rec_alt_count[a] = nullptr;
+                    w.rec_alt_stride[a] = 0;
+                    w.rec_alt_cap[a] = 0;
+                }
+                if (lv == 0) queue(1, w.rec_alt[0], w.rec_alt_stride[0], w.rec_alt_count[0], w.rec_alt_cap[0]);
+                if (lv < WIDE_LEVELS - 1)
+                    queue(WIDE_LEVELS - 1, w.rec_alt[1], w.rec_alt_stride[1], w.rec_alt_count[1],
+                          w.rec_alt_cap[1]);
+                w.err = P->err;
+                launch_wide_kernel(lv, w, device_cus() * wide_blocks_per_cu(lv), s);
             }
+            BigArgs b{};
+            b.mats = P->d_mats;
+            b.P = base.P;
+            b.out = P->out;
+            b.arena_base = big_base;
+            b.rec_in = P->rec[q_wide + WIDE_LEVELS - 1];
+            b.rec_in_stride = wide_queue_stride(WIDE_LEVELS - 1);
+            b.rec_in_count = P->rec_count + (c_wide + WIDE_LEVELS - 1);
+            b.rec_in_cap = wide_rec_cap[WIDE_LEVELS - 1];
+            b.scratch = P->big_scratch;
+            b.scratch_stride = big_scratch_stride(big_ld);
+            b.ld = big_ld;
+            b.err = P->err;
+            launch_big_kernel(b, big_blocks, s);
         }
         P->ntiers_used = tlast - t0 + 1 + (big ? 1 + WIDE_LEVELS : 0);
         P->record(3, s);

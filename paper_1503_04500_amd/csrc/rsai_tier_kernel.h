@@ -432,9 +432,10 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
             }
             if (kargs()->nq <= 0) qrec = nullptr;
             ps = gbcast_i<G>(ps, gl == 0);
-            // the plain schedule has one size class: outgrowing it is a cap error
+            // (the plain schedule parks every column that fits after each loop in queue
+            // 0; a column that outgrew the class goes on to a later one)
             const bool ok = spill && qrec != nullptr && (int64_t)ps < qcap &&
-                            (parked || !kargs()->one_loop);
+                            (parked || !kargs()->one_loop || d > 0);
             int nR = __popc(rflag);
             nR = gsum_i<G>(nR) + (kR ? 1 : 0);
             if (spill && gl == 0) S.cnt = 0;

@@ -258,6 +258,24 @@ def test_plain_schedule_parity(case):
     compare(A, gpu, ref, label=f"plain-{case}")
 
 
+@pytest.mark.parametrize("case", ["cd2d-eps0.2", "cd3d", "powerlaw"])
+def test_plain_schedule_hands_large_columns_on(case):
+    """Columns that outgrow the plain schedule's register class go on to the
+    workgroup classes (as in the batched schedule), so deep configurations complete:
+    full parity with the oracle on small cases that reach those classes."""
+    if case == "cd2d-eps0.2":
+        A, kw = gen.cd2d(32, seed=0), dict(c=3, lmax=8, eps=0.2, tol=1e-3)
+    elif case == "cd3d":
+        A, kw = gen.cd3d(10, seed=0), dict(c=3, lmax=8, eps=0.3, tol=1e-3)
+    else:
+        A, kw = gen.powerlaw(4000, seed=5), dict(c=3, lmax=10, eps=0.4, tol=1e-3)
+    ref = _ref(A, **kw)
+    assert ref["nImax"].max() > 64 or ref["nJmax"].max() > 24  # past the plain class
+    gpu = run_gpu(A, sched="plain", **kw)
+    s = compare(A, gpu, ref, label=f"plain-deep-{case}", margin_tol=1e-14)
+    print(f"plain schedule, {case}: {s}", flush=True)
+
+
 def test_plain_equals_batched_c2():
     A = gen.c2()
     a = run_gpu(A, sched="plain", **C1)
