@@ -70,7 +70,9 @@ typedef enum {
     RSAI_SCHED_BATCHED = 0, /* size-bucketed persistent kernels, whole loop fused; columns
                                that outgrow the register tiers finish in a large class (one
                                256-thread workgroup per column, |I_k| <= 8192, |J_k| <= 128) */
-    RSAI_SCHED_PLAIN = 1    /* one wave per column, one launch per loop, state in HBM */
+    RSAI_SCHED_PLAIN = 1    /* one register class (16 lanes per column), one launch per
+                               loop, state in HBM; columns that outgrow the class finish in
+                               the same workgroup classes as in the batched schedule */
 } rsai_sched;
 
 /* One entry of a tuning table (rsai_params.tune_table): for a matrix with n in
