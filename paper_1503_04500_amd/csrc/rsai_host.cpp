@@ -77,6 +77,7 @@ struct MatPlan {
     double *valM = nullptr;
     int64_t capM = 0;
     int64_t nnzM = -1;
+    bool summary_clear = false;  // the build's first launch zeroed the summary, not used since
     int64_t *summary = nullptr;  // device: nnz(M), error flags, failed-column counts; from [8] the
                                  // copies of the adjoint's size maxima (int32) when factors are kept
     int32_t maxq = -1, maxm = -1;  // largest final |J_k| and |I_k| (first backward)
@@ -535,9 +536,12 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
         D.norm1_bits = P->stats + 2 * i + 1;
         D.col_base = M.col_base;
     }
-    if (hipMemcpyAsync(P->d_mats, P->hmats.data(), sizeof(MatDev) * count, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(P->d_colbase, P->hcolbase.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice, s) !=
-            hipSuccess)
+    // (a table of up to FILL_TAB matrices travels in the arguments of the build's first
+    // fill launch instead)
+    if (count > FILL_TAB &&
+        (hipMemcpyAsync(P->d_mats, P->hmats.data(), sizeof(MatDev) * count, hipMemcpyHostToDevice, s) != hipSuccess ||
+         hipMemcpyAsync(P->d_colbase, P->hcolbase.data(), sizeof(int64_t) * (count + 1), hipMemcpyHostToDevice, s) !=
+             hipSuccess))
         return bail(fail(RSAI_E_HIP, "matrix table upload failed"));
 
     // ---- the kernel sequence: CSC contract, row pattern, ||A||_1, the size classes,
@@ -545,19 +549,42 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
     std::vector<rsai_csc> Av(As, As + count);
     P->enqueue = [=](hipStream_t s, bool first) -> rsai_status {
         const rsai_csc *As = Av.data();
-        // ---- preprocessing: CSC contract, row pattern, ||A||_1 (all on the stream)
+        // ---- preprocessing: CSC contract, row pattern, ||A||_1 (all on the stream).
+        // Every initial fill of the build (and the matrix table) in as few launches as
+        // their number allows: the host's launches, not the GPU, set the pace before
+        // the first size class starts
         {
-            int32_t *fp[6] = {P->err, (int32_t *)P->stats, P->rec_count, P->out.status, P->out.nJ, nullptr};
-            int64_t fc[6] = {4, 4 * (int64_t)count, nlaunch + 1, ncols, ncols, 0};
-            int32_t fv[6] = {0, 0, 0, ST_INTERNAL, 0, 0};  // every column's status must be written
-            launch_fill_many(fp, fc, fv, 5, s);
-        }
-        if (P->out.fac) {
-            // no factor record yet: foff = -1 (two int32 -1 words), cursor = 0
-            int32_t *fp[6] = {(int32_t *)P->out.foff, (int32_t *)P->out.fac_cur, nullptr, nullptr, nullptr, nullptr};
-            int64_t fc[6] = {2 * ncols, 2, 0, 0, 0, 0};
-            int32_t fv[6] = {-1, 0, 0, 0, 0, 0};
-            launch_fill_many(fp, fc, fv, 2, s);
+            std::vector<int32_t *> fp;
+            std::vector<int64_t> fc;
+            std::vector<int32_t> fv;
+            auto add = [&](void *p, int64_t words, int32_t v) {
+                fp.push_back((int32_t *)p);
+                fc.push_back(words);
+                fv.push_back(v);
+            };
+            add(P->err, 4, 0);
+            add(P->stats, 4 * (int64_t)count, 0);
+            add(P->rec_count, nlaunch + 1, 0);
+            add(P->out.status, ncols, ST_INTERNAL);  // every column's status must be written
+            add(P->out.nJ, ncols, 0);
+            if (P->out.fac) {
+                // no factor record yet: foff = -1 (two int32 -1 words), cursor = 0
+                add(P->out.foff, 2 * ncols, -1);
+                add(P->out.fac_cur, 2, 0);
+            }
+            for (int i = 0; i < count; ++i) {
+                MatPlan &M = P->mats[i];
+                add(M.rowcnt, As[i].n, 0);
+                add(fillpos[i], As[i].n, 0);
+                // the summary rsai_plan_nnz accumulates into
+                add(M.summary, 2 * (8 + 5 * MAX2_COPIES / 2), 0);
+            }
+            const int ntab = count <= FILL_TAB ? count : 0;
+            for (size_t a = 0; a < fp.size(); a += FILL_SLOTS) {
+                const int k = (int)std::min<size_t>(FILL_SLOTS, fp.size() - a);
+                launch_fill_many(fp.data() + a, fc.data() + a, fv.data() + a, k, P->hmats.data(),
+                                 P->hcolbase.data(), a == 0 ? ntab : 0, P->d_mats, P->d_colbase, s);
+            }
         }
         if (P->p.validate)
             for (int i = 0; i < count; ++i) launch_validate(As[i].n, As[i].nnz, As[i].colptr, As[i].rowidx, P->err, s);
@@ -573,12 +600,6 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
         for (int i = 0; i < count; ++i) {
             MatPlan &M = P->mats[i];
             const int64_t n = As[i].n, nnz = As[i].nnz;
-            {
-                int32_t *fp[6] = {M.rowcnt, fillpos[i], nullptr, nullptr, nullptr, nullptr};
-                int64_t fc[6] = {n, n, 0, 0, 0, 0};
-                int32_t fv[6] = {0, 0, 0, 0, 0, 0};
-                launch_fill_many(fp, fc, fv, 2, s);
-            }
             launch_row_counts(nnz, As[i].rowidx, M.rowcnt, P->err, s);
             launch_scan_i32(M.rowcnt, n, M.rowptr, P->scan_tmp, s);
             launch_row_fill(n, As[i].colptr, As[i].rowidx, M.rowptr, fillpos[i], M.colidx, P->err, s);
@@ -764,6 +785,7 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
     };
     st = P->enqueue(s, true);
     if (st != RSAI_OK) return bail(st);
+    for (MatPlan &M : P->mats) M.summary_clear = true;
     *out = P;
     return RSAI_OK;
 }
@@ -794,13 +816,20 @@ rsai_status rsai_rebuild(rsai_plan *P, int32_t use_graph, void *stream) {
     // results of the previous build are out of date
     for (MatPlan &M : P->mats) {
         M.nnzM = -1;
+        M.summary_clear = false;
         M.maxq = M.maxm = M.maxq_nofac = M.nlarge = -1;
         M.t_valid = false;
     }
     for (bool &r : P->recorded) r = false;
+    // the sequence starts by zeroing every matrix's summary
+    auto cleared = [P]() {
+        for (MatPlan &M : P->mats) M.summary_clear = true;
+    };
     if (!use_graph) {
         const rsai_status st = P->enqueue(s, false);
-        return st != RSAI_OK ? st : order_after(P, s);
+        if (st != RSAI_OK) return st;
+        cleared();
+        return order_after(P, s);
     }
     if (!P->gexec) {
         // capture the sequence once on a private stream, then replay it on any stream
@@ -825,6 +854,7 @@ rsai_status rsai_rebuild(rsai_plan *P, int32_t use_graph, void *stream) {
         }
     }
     if (hipGraphLaunch(P->gexec, s) != hipSuccess) return fail(RSAI_E_HIP, "graph launch failed");
+    cleared();
     return order_after(P, s);
 }
 
@@ -915,7 +945,8 @@ rsai_status rsai_plan_nnz(const rsai_plan *Pc, int32_t mat, int64_t *nnzM) {
     if (M.nnzM < 0) {
         const int64_t n = M.A.n;
         int64_t h[8 + 5 * MAX2_COPIES / 2] = {};
-        launch_fill_i64(M.summary, 0, 8 + 5 * MAX2_COPIES / 2, P->stream);
+        if (!M.summary_clear) launch_fill_i64(M.summary, 0, 8 + 5 * MAX2_COPIES / 2, P->stream);
+        M.summary_clear = false;
         launch_summary(n, M.colptrM, P->out.status + M.col_base, P->err, M.summary, P->stream);
         // with kept factors the adjoint's size maxima come back in the same copy
         const bool sizes = P->out.foff != nullptr && M.maxq < 0;

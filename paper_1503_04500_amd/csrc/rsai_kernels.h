@@ -96,7 +96,12 @@ void launch_row_fill(int64_t n, const int64_t *colptr, const int32_t *rowidx, co
                      int32_t *fillpos, int32_t *colidx, const int32_t *err, hipStream_t s);
 void launch_mat_stats(int64_t n, const int64_t *colptr, const double *val, const int32_t *rowcnt,
                       unsigned long long *stats, const int32_t *err, hipStream_t s);
-void launch_fill_many(int32_t *const *p, const int64_t *count, const int32_t *v, int k, hipStream_t s);
+// up to FILL_SLOTS int32 fills in one launch; with 0 < ntab <= FILL_TAB the same launch
+// writes the matrix table tab[0..ntab) to dtab and colbase[0..ntab] to dcolbase
+constexpr int FILL_SLOTS = 8;
+constexpr int FILL_TAB = 4;
+void launch_fill_many(int32_t *const *p, const int64_t *count, const int32_t *v, int k, const MatDev *tab,
+                      const int64_t *colbase, int ntab, MatDev *dtab, int64_t *dcolbase, hipStream_t s);
 // longest column of a CSC matrix into *out (atomic max; *out zeroed by the caller)
 void launch_max_collen(int64_t n, const int64_t *colptr, int32_t *out, hipStream_t s);
 void launch_summary(int64_t n, const int64_t *colptrM, const int32_t *status, const int32_t *err, int64_t *out,

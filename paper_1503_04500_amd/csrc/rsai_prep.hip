@@ -52,28 +52,51 @@ void launch_fill_f64(double *p, double v, int64_t count, hipStream_t s) {
     if (count > 0) hipLaunchKernelGGL(k_fill<double>, dim3(nblocks(count, 1024)), dim3(256), 0, s, p, v, count);
 }
 
-// one launch for several int32 fills: p[i][0..count[i]) = v[i]
-struct Fill4 {
-    int32_t *p[6];
-    int64_t count[6];
-    int32_t v[6];
+// One launch for several int32 fills, p[i][0..count[i]) = v[i], which also writes the
+// batch's matrix table from its arguments when ntab > 0 (no host-to-device copy).
+struct FillMany {
+    int32_t *p[FILL_SLOTS];
+    int64_t count[FILL_SLOTS];
+    int32_t v[FILL_SLOTS];
+    MatDev *dtab;
+    int64_t *dcolbase;
+    int ntab;
+    MatDev tab[FILL_TAB];
+    int64_t colbase[FILL_TAB + 1];
 };
-__global__ void k_fill_many(Fill4 f) {
-    for (int a = 0; a < 6; ++a) {
+__global__ void k_fill_many(FillMany f) {
+    if (f.ntab > 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < FILL_TAB; ++i)
+            if (i < f.ntab) f.dtab[i] = f.tab[i];
+#pragma unroll
+        for (int i = 0; i <= FILL_TAB; ++i)
+            if (i <= f.ntab) f.dcolbase[i] = f.colbase[i];
+    }
+#pragma unroll
+    for (int a = 0; a < FILL_SLOTS; ++a) {
         if (!f.p[a]) continue;
         for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < f.count[a];
              i += (int64_t)gridDim.x * blockDim.x)
             f.p[a][i] = f.v[a];
     }
 }
-void launch_fill_many(int32_t *const *p, const int64_t *count, const int32_t *v, int k, hipStream_t s) {
-    Fill4 f{};
+void launch_fill_many(int32_t *const *p, const int64_t *count, const int32_t *v, int k, const MatDev *tab,
+                      const int64_t *colbase, int ntab, MatDev *dtab, int64_t *dcolbase, hipStream_t s) {
+    FillMany f{};
     int64_t mx = 1;
-    for (int a = 0; a < k && a < 6; ++a) {
+    for (int a = 0; a < k && a < FILL_SLOTS; ++a) {
         f.p[a] = p[a];
         f.count[a] = count[a];
         f.v[a] = v[a];
         mx = std::max(mx, count[a]);
+    }
+    if (ntab > 0 && ntab <= FILL_TAB) {
+        f.ntab = ntab;
+        f.dtab = dtab;
+        f.dcolbase = dcolbase;
+        for (int i = 0; i < ntab; ++i) f.tab[i] = tab[i];
+        for (int i = 0; i <= ntab; ++i) f.colbase[i] = colbase[i];
     }
     hipLaunchKernelGGL(k_fill_many, dim3(nblocks(mx, 1024)), dim3(256), 0, s, f);
 }

@@ -218,9 +218,33 @@ def permute_rows(A: Matrix, p) -> Matrix:
     return Matrix(cp, ri[:A.nnz], va[:A.nnz])
 
 
+_params_memo = {}
+
+
 def params(c=3, lmax=10, eps=0.4, drop="fixed", tol=1e-3, sched="batched", validate=True, tier0=-1,
            timing=False, refill=-1, route=-1, keep_factors=False, factor_budget_bytes=0, deterministic=False,
            t0_hash=-1, last_tier=-1, spill_capacity=0):
+    # a fresh copy of the struct made earlier for the same arguments (the build is often
+    # called in a loop with one parameter set)
+    key = (c, lmax, eps, drop, tol, sched, validate, tier0, timing, refill, route, keep_factors,
+           factor_budget_bytes, deterministic, t0_hash, last_tier, spill_capacity)
+    try:
+        made = _params_memo.get(key)
+    except TypeError:  # unhashable argument: no memo
+        key, made = None, None
+    if made is not None:
+        return Params.from_buffer_copy(made)
+    p = _make_params(c, lmax, eps, drop, tol, sched, validate, tier0, timing, refill, route, keep_factors,
+                     factor_budget_bytes, deterministic, t0_hash, last_tier, spill_capacity)
+    if key is not None:
+        if len(_params_memo) >= 256:
+            _params_memo.clear()
+        _params_memo[key] = bytes(p)
+    return p
+
+
+def _make_params(c, lmax, eps, drop, tol, sched, validate, tier0, timing, refill, route, keep_factors,
+                 factor_budget_bytes, deterministic, t0_hash, last_tier, spill_capacity):
     p = Params()
     _check(load().rsai_params_default(ctypes.byref(p)))
     p.c, p.lmax, p.eps, p.tol = int(c), int(lmax), float(eps), float(tol)
@@ -348,17 +372,24 @@ def build(A: Matrix, stream=None, **kw) -> Plan:
     return build_batched([A], stream=stream, **kw)
 
 
+_tune_memo = [None, None, 0]  # entries list converted last, its array, count
+
+
 def tune_entries(table=None):
     """The tuning table (tune.load_table entries, or the given list of dicts) as the C
     ABI's rsai_tune_entry array; fields an entry lacks are -1 (not applied)."""
     from . import tune
     rows = tune.load_table() if table is None else table
+    if table is None and _tune_memo[0] is rows:
+        return _tune_memo[1], _tune_memo[2]
     arr = (TuneEntry * max(len(rows), 1))()
     for i, e in enumerate(rows):
         arr[i] = TuneEntry(float(e["len_lo"]), float(e["len_hi"]), float(e.get("eps_lo", 0.0)),
                            float(e.get("eps_hi", float("inf"))), int(e["maxlen_lo"]), int(e["maxlen_hi"]),
                            int(e["n_lo"]), int(e["n_hi"]), int(e.get("tier0", -1)), int(e.get("refill", -1)),
                            int(e.get("route", -1)), int(e.get("t0_hash", -1)), int(e.get("last_tier", -1)), 0)
+    if table is None:
+        _tune_memo[:] = [rows, arr, len(rows)]
     return arr, len(rows)
 
 
