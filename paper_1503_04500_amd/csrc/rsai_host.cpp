@@ -54,6 +54,43 @@ void dev_free(void *p, hipStream_t s) {
     else (void)hipFree(p);
 }
 
+// The synchronous CSC check of a build: its flags are copied to a pinned host word
+// (one per thread, with one event per device, both kept until the process ends) right
+// after the check's kernel, and the host waits for them only once the rest of the
+// sequence is queued, so that the queue never runs dry on the host's wait.
+struct ValCheck {
+    bool active = false;
+    int32_t *host = nullptr;
+    hipEvent_t ev = nullptr;
+};
+bool val_check_start(const int32_t *err, hipStream_t s, ValCheck &vc) {
+    constexpr int kMaxDev = 64;
+    thread_local int32_t *word = nullptr;
+    thread_local hipEvent_t evs[kMaxDev] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return false;
+    if (!word && hipHostMalloc((void **)&word, 64, hipHostMallocPortable) != hipSuccess) {
+        word = nullptr;
+        return false;
+    }
+    if (!evs[dev] && hipEventCreateWithFlags(&evs[dev], hipEventDisableTiming) != hipSuccess) {
+        evs[dev] = nullptr;
+        return false;
+    }
+    if (hipMemcpyAsync(word, err, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipEventRecord(evs[dev], s) != hipSuccess)
+        return false;
+    vc.active = true;
+    vc.host = word;
+    vc.ev = evs[dev];
+    return true;
+}
+bool val_check_finish(const ValCheck &vc, int32_t &herr) {
+    if (hipEventSynchronize(vc.ev) != hipSuccess) return false;
+    herr = *(volatile int32_t *)vc.host;
+    return true;
+}
+
 }  // namespace
 
 rsai_status rsai::report(rsai_status st, const char *fmt, ...) {
@@ -77,7 +114,7 @@ struct MatPlan {
     double *valM = nullptr;
     int64_t capM = 0;
     int64_t nnzM = -1;
-    bool summary_clear = false;  // the build's first launch zeroed the summary, not used since
+    bool sizes_clear = false;  // the build's first launch zeroed the size maxima, not used since
     int64_t *summary = nullptr;  // device: nnz(M), error flags, failed-column counts; from [8] the
                                  // copies of the adjoint's size maxima (int32) when factors are kept
     int32_t maxq = -1, maxm = -1;  // largest final |J_k| and |I_k| (first backward)
@@ -588,15 +625,12 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
         }
         if (P->p.validate)
             for (int i = 0; i < count; ++i) launch_validate(As[i].n, As[i].nnz, As[i].colptr, As[i].rowidx, P->err, s);
-        if (P->p.validate == 1 && first) {
-            // synchronous check: RSAI_E_CSC is returned here; with validate = 2 the later
-            // kernels skip their work and the error is reported by rsai_plan_nnz
-            int32_t herr = 0;
-            if (hipMemcpyAsync(&herr, P->err, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
-                hipStreamSynchronize(s) != hipSuccess)
-                return fail(RSAI_E_HIP, "validation readback failed");
-            if (herr) return fail(RSAI_E_CSC, "malformed CSC (flags %d: 1 colptr, 2 row indices, 4 empty column)", herr);
-        }
+        // synchronous check (validate = 1): RSAI_E_CSC is returned by this call, once
+        // the sequence is queued (its kernels skip their work on a malformed matrix);
+        // with validate = 2 the error is reported by rsai_plan_nnz
+        ValCheck vc;
+        if (P->p.validate == 1 && first && !val_check_start(P->err, s, vc))
+            return fail(RSAI_E_HIP, "validation readback failed");
         for (int i = 0; i < count; ++i) {
             MatPlan &M = P->mats[i];
             const int64_t n = As[i].n, nnz = As[i].nnz;
@@ -775,17 +809,25 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
             const int64_t n = As[i].n;
             launch_scan_i32(P->out.nJ + M.col_base, n, M.colptrM, P->scan_tmp, s);
             launch_assemble(n, (int)qlast, P->out.off + M.col_base, P->out.nJ + M.col_base, M.colptrM, P->out.arenaJ,
-                            P->out.arenaV, M.rowidxM, M.valM, s);
+                            P->out.arenaV, M.rowidxM, M.valM, P->out.status + M.col_base, P->err, M.summary, s);
         }
         P->record(4, s);
         hipError_t le = hipGetLastError();
         if (le != hipSuccess) return fail(RSAI_E_HIP, "launch failed: %s", hipGetErrorString(le));
+        if (vc.active) {
+            int32_t herr = 0;
+            if (!val_check_finish(vc, herr)) return fail(RSAI_E_HIP, "validation readback failed");
+            if (herr) {
+                (void)hipStreamSynchronize(s);
+                return fail(RSAI_E_CSC, "malformed CSC (flags %d: 1 colptr, 2 row indices, 4 empty column)", herr);
+            }
+        }
         return RSAI_OK;
 
     };
     st = P->enqueue(s, true);
     if (st != RSAI_OK) return bail(st);
-    for (MatPlan &M : P->mats) M.summary_clear = true;
+    for (MatPlan &M : P->mats) M.sizes_clear = true;
     *out = P;
     return RSAI_OK;
 }
@@ -816,14 +858,14 @@ rsai_status rsai_rebuild(rsai_plan *P, int32_t use_graph, void *stream) {
     // results of the previous build are out of date
     for (MatPlan &M : P->mats) {
         M.nnzM = -1;
-        M.summary_clear = false;
+        M.sizes_clear = false;
         M.maxq = M.maxm = M.maxq_nofac = M.nlarge = -1;
         M.t_valid = false;
     }
     for (bool &r : P->recorded) r = false;
     // the sequence starts by zeroing every matrix's summary
     auto cleared = [P]() {
-        for (MatPlan &M : P->mats) M.summary_clear = true;
+        for (MatPlan &M : P->mats) M.sizes_clear = true;
     };
     if (!use_graph) {
         const rsai_status st = P->enqueue(s, false);
@@ -945,11 +987,11 @@ rsai_status rsai_plan_nnz(const rsai_plan *Pc, int32_t mat, int64_t *nnzM) {
     if (M.nnzM < 0) {
         const int64_t n = M.A.n;
         int64_t h[8 + 5 * MAX2_COPIES / 2] = {};
-        if (!M.summary_clear) launch_fill_i64(M.summary, 0, 8 + 5 * MAX2_COPIES / 2, P->stream);
-        M.summary_clear = false;
-        launch_summary(n, M.colptrM, P->out.status + M.col_base, P->err, M.summary, P->stream);
-        // with kept factors the adjoint's size maxima come back in the same copy
+        // (the first words were written by the assembly at the end of the build); with
+        // kept factors the adjoint's size maxima come back in the same copy
         const bool sizes = P->out.foff != nullptr && M.maxq < 0;
+        if (sizes && !M.sizes_clear) launch_fill_i64(M.summary + 8, 0, 5 * MAX2_COPIES / 2, P->stream);
+        M.sizes_clear = false;
         if (sizes)
             launch_max2(n, P->out.nJ + M.col_base, P->out.nI + M.col_base, P->out.foff + M.col_base,
                         (int32_t *)(M.summary + 8), P->stream);

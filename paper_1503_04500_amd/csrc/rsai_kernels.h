@@ -104,8 +104,6 @@ void launch_fill_many(int32_t *const *p, const int64_t *count, const int32_t *v,
                       const int64_t *colbase, int ntab, MatDev *dtab, int64_t *dcolbase, hipStream_t s);
 // longest column of a CSC matrix into *out (atomic max; *out zeroed by the caller)
 void launch_max_collen(int64_t n, const int64_t *colptr, int32_t *out, hipStream_t s);
-void launch_summary(int64_t n, const int64_t *colptrM, const int32_t *status, const int32_t *err, int64_t *out,
-                    hipStream_t s);
 
 // exclusive scan of n int32 counts into out[0..n] (out[n] = total); tmp needs
 // scan_tmp_elems(n) int64 elements
@@ -114,7 +112,8 @@ void launch_scan_i32(const int32_t *in, int64_t n, int64_t *out, int64_t *tmp, h
 
 // ---- assembly: per-column results in the arena -> CSC (rows ascending)
 void launch_assemble(int64_t n, int qcap, const int64_t *off, const int32_t *nJ, const int64_t *colptrM,
-                     const int32_t *arenaJ, const double *arenaV, int32_t *rowidxM, double *valM, hipStream_t s);
+                     const int32_t *arenaJ, const double *arenaV, int32_t *rowidxM, double *valM,
+                     const int32_t *status, const int32_t *err, int64_t *summary, hipStream_t s);
 
 // ---- SpMV
 void launch_csc_transpose_fill(int64_t n, const int64_t *colptr, const int32_t *rowidx, const double *val,

@@ -101,8 +101,7 @@ void launch_fill_many(int32_t *const *p, const int64_t *count, const int32_t *v,
     hipLaunchKernelGGL(k_fill_many, dim3(nblocks(mx, 1024)), dim3(256), 0, s, f);
 }
 
-// summary for the host: out[0] = colptrM[n] (nnz of M), out[1] = error flags,
-// out[2..4] = columns with status singular / cap / anything else not ok
+// longest column of a CSC matrix: atomic max into *out
 __global__ void k_max_collen(int64_t n, const int64_t *colptr, int32_t *out) {
     int m = 0;
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
@@ -112,28 +111,6 @@ __global__ void k_max_collen(int64_t n, const int64_t *colptr, int32_t *out) {
 }
 void launch_max_collen(int64_t n, const int64_t *colptr, int32_t *out, hipStream_t s) {
     hipLaunchKernelGGL(k_max_collen, dim3(std::min(nblocks(n, 256), 1024)), dim3(256), 0, s, n, colptr, out);
-}
-
-__global__ void k_summary(int64_t n, const int64_t *colptrM, const int32_t *status, const int32_t *err,
-                          int64_t *out) {
-    int64_t a = 0, b = 0, c = 0;
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
-        const int st = status[k];
-        a += (st == 3);
-        b += (st == 6);
-        c += (st != 0 && st != 3 && st != 6);
-    }
-    if (a) atomicAdd((unsigned long long *)&out[2], (unsigned long long)a);
-    if (b) atomicAdd((unsigned long long *)&out[3], (unsigned long long)b);
-    if (c) atomicAdd((unsigned long long *)&out[4], (unsigned long long)c);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        out[0] = colptrM[n];
-        out[1] = *err;
-    }
-}
-void launch_summary(int64_t n, const int64_t *colptrM, const int32_t *status, const int32_t *err, int64_t *out,
-                    hipStream_t s) {
-    hipLaunchKernelGGL(k_summary, dim3(std::min(nblocks(n, 256), 256)), dim3(256), 0, s, n, colptrM, status, err, out);
 }
 
 // ---------------------------------------------------------------- CSC contract
@@ -313,9 +290,14 @@ void launch_scan_i32(const int32_t *in, int64_t n, int64_t *out, int64_t *tmp, h
 // over n x QCAP, reading the padded slots and writing M at colptrM[k] + t.
 
 // 16 lanes per column copy its nJ[k] <= qcap entries from the arena slot into M
+// The same pass fills the summary the host reads after the build (zeroed at its start):
+// out[0] = colptrM[n] (nnz of M), out[1] = error flags, out[2..4] = columns with status
+// singular / cap / anything else not ok.
 __global__ void k_assemble(int64_t n, int qcap, const int64_t *off, const int32_t *nJ, const int64_t *colptrM,
-                           const int32_t *aJ, const double *aV, int32_t *rowidxM, double *valM) {
+                           const int32_t *aJ, const double *aV, int32_t *rowidxM, double *valM,
+                           const int32_t *status, const int32_t *err, int64_t *out) {
     const int64_t total = n * 16;
+    int64_t a = 0, b = 0, c = 0;
     for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
         const int64_t k = idx >> 4;
@@ -325,12 +307,26 @@ __global__ void k_assemble(int64_t n, int qcap, const int64_t *off, const int32_
             rowidxM[dst0 + t] = aJ[src0 + t];
             valM[dst0 + t] = aV[src0 + t];
         }
+        if ((idx & 15) == 0) {
+            const int st = status[k];
+            a += (st == 3);
+            b += (st == 6);
+            c += (st != 0 && st != 3 && st != 6);
+        }
+    }
+    if (a) atomicAdd((unsigned long long *)&out[2], (unsigned long long)a);
+    if (b) atomicAdd((unsigned long long *)&out[3], (unsigned long long)b);
+    if (c) atomicAdd((unsigned long long *)&out[4], (unsigned long long)c);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        out[0] = colptrM[n];
+        out[1] = *err;
     }
 }
 void launch_assemble(int64_t n, int qcap, const int64_t *off, const int32_t *nJ, const int64_t *colptrM,
-                     const int32_t *arenaJ, const double *arenaV, int32_t *rowidxM, double *valM, hipStream_t s) {
+                     const int32_t *arenaJ, const double *arenaV, int32_t *rowidxM, double *valM,
+                     const int32_t *status, const int32_t *err, int64_t *summary, hipStream_t s) {
     hipLaunchKernelGGL(k_assemble, dim3(nblocks(n * 16, 1024)), dim3(256), 0, s, n, qcap, off, nJ, colptrM,
-                       arenaJ, arenaV, rowidxM, valM);
+                       arenaJ, arenaV, rowidxM, valM, status, err, summary);
 }
 
 // ---------------------------------------------------------------- SpMV
