@@ -348,7 +348,7 @@ __device__ bool panel_factor_regs(double *B, int64_t ld, int m, int p0, int pw, 
 __global__ __launch_bounds__(NT) void big_kernel(BigArgs args) {
     __shared__ BigLds S;
     const int tid = threadIdx.x;
-    if (*args.err & 7) return;
+    if (*args.err & ERR_SKIP) return;
     const BuildParams P = args.P;
     const int64_t Q = min((int64_t)(*args.rec_in_count), args.rec_in_cap);
     double *B = args.scratch + (int64_t)blockIdx.x * args.scratch_stride;  // [BQMAX][BMMAX]

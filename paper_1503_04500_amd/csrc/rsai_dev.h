@@ -26,6 +26,9 @@ struct BuildParams {
 
 enum : int { DROP_NONE = 0, DROP_FIXED = 1, DROP_ADAPTIVE = 2 };
 enum : int { ST_OK = 0, ST_SINGULAR = 3, ST_CAP = 6, ST_INTERNAL = 7 };
+// error flags on which the size-class kernels process nothing: the CSC contract failed
+// (1, 2, 4) or a single-pass scan found its state not zeroed (64)
+constexpr int ERR_SKIP = 7 | 64;
 
 constexpr int CMAX = 8;      // largest c supported (dominant rows per loop)
 

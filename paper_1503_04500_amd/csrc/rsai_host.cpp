@@ -54,40 +54,48 @@ void dev_free(void *p, hipStream_t s) {
     else (void)hipFree(p);
 }
 
-// The synchronous CSC check of a build: its flags are copied to a pinned host word
-// (one per thread, with one event per device, both kept until the process ends) right
-// after the check's kernel, and the host waits for them only once the rest of the
-// sequence is queued, so that the queue never runs dry on the host's wait.
+// The synchronous CSC check of a build: the kernel after the check copies the flags to
+// a pinned host word (one per thread, with one event per device, both kept until the
+// process ends), and the host waits for them only once the rest of the sequence is
+// queued, so that the queue never runs dry on the host's wait.
 struct ValCheck {
     bool active = false;
-    int32_t *host = nullptr;
+    int32_t *host = nullptr;   // the word (host address)
+    int32_t *dev = nullptr;    // its device address
     hipEvent_t ev = nullptr;
 };
-bool val_check_start(const int32_t *err, hipStream_t s, ValCheck &vc) {
+constexpr int32_t kValUnset = -1;
+bool val_check_prepare(ValCheck &vc) {
     constexpr int kMaxDev = 64;
     thread_local int32_t *word = nullptr;
     thread_local hipEvent_t evs[kMaxDev] = {};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return false;
-    if (!word && hipHostMalloc((void **)&word, 64, hipHostMallocPortable) != hipSuccess) {
+    if (!word && hipHostMalloc((void **)&word, 64, hipHostMallocPortable | hipHostMallocMapped) != hipSuccess) {
         word = nullptr;
         return false;
     }
+    void *dp = nullptr;
+    if (hipHostGetDevicePointer(&dp, word, 0) != hipSuccess || !dp) return false;
     if (!evs[dev] && hipEventCreateWithFlags(&evs[dev], hipEventDisableTiming) != hipSuccess) {
         evs[dev] = nullptr;
         return false;
     }
-    if (hipMemcpyAsync(word, err, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipEventRecord(evs[dev], s) != hipSuccess)
-        return false;
-    vc.active = true;
+    *(volatile int32_t *)word = kValUnset;
     vc.host = word;
+    vc.dev = (int32_t *)dp;
     vc.ev = evs[dev];
     return true;
 }
-bool val_check_finish(const ValCheck &vc, int32_t &herr) {
+bool val_check_finish(const ValCheck &vc, const int32_t *err, hipStream_t s, int32_t &herr) {
     if (hipEventSynchronize(vc.ev) != hipSuccess) return false;
     herr = *(volatile int32_t *)vc.host;
+    if (herr == kValUnset) {
+        // (not written: read the flags themselves)
+        if (hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return false;
+    }
     return true;
 }
 
@@ -115,6 +123,7 @@ struct MatPlan {
     int64_t capM = 0;
     int64_t nnzM = -1;
     bool sizes_clear = false;  // the build's first launch zeroed the size maxima, not used since
+    unsigned long long *scan_state = nullptr;  // the build's two single-pass scan states
     int64_t *summary = nullptr;  // device: nnz(M), error flags, failed-column counts; from [8] the
                                  // copies of the adjoint's size maxima (int32) when factors are kept
     int32_t maxq = -1, maxm = -1;  // largest final |J_k| and |I_k| (first backward)
@@ -494,7 +503,7 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
     // ---- every device buffer of the build, from one allocation
     std::vector<int32_t *> fillpos(count);
     auto layout = [&](Layout &L) {
-        P->err = L.take<int32_t>(4);
+        P->err = L.take<int32_t>(4);  // [0] error flags
         P->stats = L.take<unsigned long long>(2 * (int64_t)count);
         P->scan_tmp = L.take<int64_t>(scan_tmp_elems(maxn + 1));
         P->d_mats = L.take<MatDev>(count);
@@ -509,7 +518,10 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
             // entries of M: at most qmid per column, and up to qlast for the columns the
             // dense class finishes (no more than its record capacity)
             M.capM = n * qmid + std::min<int64_t>(n, big_cap) * (qlast - qmid);
-            M.summary = L.take<int64_t>(8 + 5 * MAX2_COPIES / 2);
+            // the summary, then the states of the build's two single-pass scans (row
+            // pattern, colptr of M), all zeroed by the first launch
+            M.summary = L.take<int64_t>(8 + 5 * MAX2_COPIES / 2 + 2 * scan1_state_elems(n));
+            M.scan_state = (unsigned long long *)(M.summary + 8 + 5 * MAX2_COPIES / 2);
             M.colptrM = L.take<int64_t>(n + 1);
             M.rowidxM = L.take<int32_t>(M.capM);
             M.valM = L.take<double>(M.capM);
@@ -614,7 +626,7 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
                 add(M.rowcnt, As[i].n, 0);
                 add(fillpos[i], As[i].n, 0);
                 // the summary rsai_plan_nnz accumulates into
-                add(M.summary, 2 * (8 + 5 * MAX2_COPIES / 2), 0);
+                add(M.summary, 2 * (8 + 5 * MAX2_COPIES / 2 + 2 * scan1_state_elems(As[i].n)), 0);
             }
             const int ntab = count <= FILL_TAB ? count : 0;
             for (size_t a = 0; a < fp.size(); a += FILL_SLOTS) {
@@ -623,19 +635,26 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
                                  P->hcolbase.data(), a == 0 ? ntab : 0, P->d_mats, P->d_colbase, s);
             }
         }
-        if (P->p.validate)
-            for (int i = 0; i < count; ++i) launch_validate(As[i].n, As[i].nnz, As[i].colptr, As[i].rowidx, P->err, s);
-        // synchronous check (validate = 1): RSAI_E_CSC is returned by this call, once
-        // the sequence is queued (its kernels skip their work on a malformed matrix);
-        // with validate = 2 the error is reported by rsai_plan_nnz
+        // the CSC check and the row counts of the row pattern in one pass. Synchronous
+        // check (validate = 1): RSAI_E_CSC is returned by this call, once the sequence
+        // is queued (its kernels skip their work on a malformed matrix); the first scan
+        // after the checks leaves the flags in host memory. With validate = 2 the error
+        // is reported by rsai_plan_nnz.
         ValCheck vc;
-        if (P->p.validate == 1 && first && !val_check_start(P->err, s, vc))
+        if (P->p.validate == 1 && first && !val_check_prepare(vc))
             return fail(RSAI_E_HIP, "validation readback failed");
+        if (P->p.validate)
+            for (int i = 0; i < count; ++i)
+                launch_validate_counts(As[i].n, As[i].nnz, As[i].colptr, As[i].rowidx, P->mats[i].rowcnt, P->err, s);
         for (int i = 0; i < count; ++i) {
             MatPlan &M = P->mats[i];
             const int64_t n = As[i].n, nnz = As[i].nnz;
-            launch_row_counts(nnz, As[i].rowidx, M.rowcnt, P->err, s);
-            launch_scan_i32(M.rowcnt, n, M.rowptr, P->scan_tmp, s);
+            if (!P->p.validate) launch_row_counts(nnz, As[i].rowidx, M.rowcnt, P->err, s);
+            launch_scan1_i32(M.rowcnt, n, M.rowptr, M.scan_state, P->err, i == 0 ? vc.dev : nullptr, s);
+            if (i == 0 && vc.dev) {
+                if (hipEventRecord(vc.ev, s) != hipSuccess) return fail(RSAI_E_HIP, "validation readback failed");
+                vc.active = true;
+            }
             launch_row_fill(n, As[i].colptr, As[i].rowidx, M.rowptr, fillpos[i], M.colidx, P->err, s);
             if (P->p.drop == RSAI_DROP_ADAPTIVE)
                 launch_mat_stats(n, As[i].colptr, As[i].val, M.rowcnt, P->stats + 2 * i, P->err, s);
@@ -807,7 +826,8 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
         for (int i = 0; i < count; ++i) {
             MatPlan &M = P->mats[i];
             const int64_t n = As[i].n;
-            launch_scan_i32(P->out.nJ + M.col_base, n, M.colptrM, P->scan_tmp, s);
+            launch_scan1_i32(P->out.nJ + M.col_base, n, M.colptrM, M.scan_state + scan1_state_elems(n), P->err,
+                             nullptr, s);
             launch_assemble(n, (int)qlast, P->out.off + M.col_base, P->out.nJ + M.col_base, M.colptrM, P->out.arenaJ,
                             P->out.arenaV, M.rowidxM, M.valM, P->out.status + M.col_base, P->err, M.summary, s);
         }
@@ -816,7 +836,7 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
         if (le != hipSuccess) return fail(RSAI_E_HIP, "launch failed: %s", hipGetErrorString(le));
         if (vc.active) {
             int32_t herr = 0;
-            if (!val_check_finish(vc, herr)) return fail(RSAI_E_HIP, "validation readback failed");
+            if (!val_check_finish(vc, P->err, s, herr)) return fail(RSAI_E_HIP, "validation readback failed");
             if (herr) {
                 (void)hipStreamSynchronize(s);
                 return fail(RSAI_E_CSC, "malformed CSC (flags %d: 1 colptr, 2 row indices, 4 empty column)", herr);

@@ -86,6 +86,9 @@ void launch_big_kernel(const BigArgs &a, int blocks, hipStream_t s);
 // err bits: 1 colptr, 2 rows out of range / unsorted / duplicate, 4 empty column
 void launch_validate(int64_t n, int64_t nnz, const int64_t *colptr, const int32_t *rowidx, int32_t *err,
                      hipStream_t s);
+// the check fused with the row counts of the row pattern (cnt zeroed by the caller)
+void launch_validate_counts(int64_t n, int64_t nnz, const int64_t *colptr, const int32_t *rowidx, int32_t *cnt,
+                            int32_t *err, hipStream_t s);
 void launch_fill_i32(int32_t *p, int32_t v, int64_t count, hipStream_t s);
 void launch_fill_i64(int64_t *p, int64_t v, int64_t count, hipStream_t s);
 void launch_fill_f64(double *p, double v, int64_t count, hipStream_t s);
@@ -109,6 +112,13 @@ void launch_max_collen(int64_t n, const int64_t *colptr, int32_t *out, hipStream
 // scan_tmp_elems(n) int64 elements
 int64_t scan_tmp_elems(int64_t n);
 void launch_scan_i32(const int32_t *in, int64_t n, int64_t *out, int64_t *tmp, hipStream_t s);
+// the same in one launch (decoupled look-back): state holds scan1_state_elems(n) words,
+// zero before the launch; err bit 64 reports a state that was not. With host_flags
+// (device-visible host memory) the error flags as they stand at the launch are copied
+// there.
+int64_t scan1_state_elems(int64_t n);
+void launch_scan1_i32(const int32_t *in, int64_t n, int64_t *out, unsigned long long *state, int32_t *err,
+                      int32_t *host_flags, hipStream_t s);
 
 // ---- assembly: per-column results in the arena -> CSC (rows ascending)
 void launch_assemble(int64_t n, int qcap, const int64_t *off, const int32_t *nJ, const int64_t *colptrM,

@@ -142,6 +142,41 @@ void launch_validate(int64_t n, int64_t nnz, const int64_t *colptr, const int32_
     hipLaunchKernelGGL(k_validate, dim3(nblocks(n, 256)), dim3(256), 0, s, n, nnz, colptr, rowidx, err);
 }
 
+// The check above fused with the row counts of the row pattern: every entry of a column
+// whose extent is valid and whose row is in range adds one to its row's count (the
+// counts of a malformed matrix are never used: the later kernels skip their work).
+__global__ void k_validate_counts(int64_t n, int64_t nnz, const int64_t *colptr, const int32_t *rowidx,
+                                  int32_t *cnt, int32_t *err) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t s = colptr[j], e = colptr[j + 1];
+        if ((j == 0 && s != 0) || (j == n - 1 && e != nnz) || s < 0 || e > nnz || s > e) {
+            atomicOr(err, 1);
+            continue;
+        }
+        if (e == s) {
+            atomicOr(err, 4);
+            continue;
+        }
+        int prev = -1;
+        bool bad = false;
+        for (int64_t t = s; t < e; ++t) {
+            const int r = rowidx[t];
+            if (r < 0 || r >= n) {
+                bad = true;
+                break;
+            }
+            if (r <= prev) bad = true;
+            atomicAdd(&cnt[r], 1);
+            prev = r;
+        }
+        if (bad) atomicOr(err, 2);
+    }
+}
+void launch_validate_counts(int64_t n, int64_t nnz, const int64_t *colptr, const int32_t *rowidx, int32_t *cnt,
+                            int32_t *err, hipStream_t s) {
+    hipLaunchKernelGGL(k_validate_counts, dim3(nblocks(n, 256)), dim3(256), 0, s, n, nnz, colptr, rowidx, cnt, err);
+}
+
 // ---------------------------------------------------------------- row pattern
 
 __global__ void k_row_counts(int64_t nnz, const int32_t *rowidx, int32_t *cnt, const int32_t *err) {
@@ -277,6 +312,108 @@ __global__ void k_scan_final(const int32_t *in, int64_t n, int64_t nb, const int
     if (blockIdx.x == nb - 1 && threadIdx.x == SCAN_T - 1) out[n] = boff + sh[SCAN_T - 1];
 }
 
+// Single-pass form (decoupled look-back). A tile takes a ticket, so tiles start in
+// ticket order and every tile one waits on is already running; it scans its items,
+// publishes its sum, reads back through its predecessors' words until one holds an
+// inclusive prefix, and publishes its own prefix. state[0] counts the tickets, state[1 + t]
+// is tile t's word (bits 62-63: 1 sum, 2 prefix; bits 0-61 the value); all of it is zero
+// before the launch. A ticket past the last tile or a wait past its bound (neither
+// happens when the state was zeroed) sets err bit 64. With host_flags, the first tile
+// copies the error flags as they stand at the launch to that host word.
+constexpr unsigned long long SC_SUM = 1ull << 62, SC_PRE = 2ull << 62, SC_VAL = (1ull << 62) - 1;
+int64_t scan1_state_elems(int64_t n) { return 1 + (n + SCAN_B - 1) / SCAN_B; }
+
+__global__ void k_scan1(const int32_t *in, int64_t n, int64_t *out, unsigned long long *state, int32_t *err,
+                        int32_t *host_flags) {
+    __shared__ int64_t sh[SCAN_T];
+    __shared__ int64_t toff;
+    __shared__ unsigned long long tk;
+    if (threadIdx.x == 0) {
+        tk = atomicAdd(&state[0], 1ull);
+        if (host_flags && tk == 0)
+            __hip_atomic_store(host_flags, __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    __syncthreads();
+    const int64_t nb = (n + SCAN_B - 1) / SCAN_B;
+    const int64_t tile = (int64_t)tk;
+    if (tile >= nb) {
+        if (threadIdx.x == 0) atomicOr(err, 64);
+        return;
+    }
+    const int64_t base = tile * SCAN_B + (int64_t)threadIdx.x * SCAN_PER;
+    int64_t loc[SCAN_PER];
+    int64_t s = 0;
+#pragma unroll
+    for (int t = 0; t < SCAN_PER; ++t) {
+        const int64_t i = base + t;
+        loc[t] = s;
+        s += (i < n) ? in[i] : 0;
+    }
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < SCAN_T; off <<= 1) {
+        const int64_t t = (threadIdx.x >= off) ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    const int64_t tsum = sh[SCAN_T - 1];
+    if (threadIdx.x < 64) {
+        // the first wave reads 64 predecessors' words at a time (lane i: tile hi - i; a
+        // tile before the first counts as a prefix of 0) and sums those up to the
+        // nearest prefix; a window with a word not yet written is read again
+        const int lane = threadIdx.x;
+        unsigned long long *w = state + 1;
+        if (lane == 0 && tile > 0)
+            __hip_atomic_store(&w[tile], SC_SUM | (unsigned long long)tsum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int64_t acc = 0;
+        int64_t hi = tile - 1;
+        unsigned spins = 0;
+        while (hi >= 0) {
+            const int64_t p = hi - lane;
+            const unsigned long long v =
+                p >= 0 ? __hip_atomic_load(&w[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : SC_PRE;
+            const unsigned long long f = v >> 62;
+            const unsigned long long pre = __ballot(f == 2);
+            const int lim = pre ? __ffsll((long long)pre) - 1 : 63;  // lanes 0..lim are needed
+            const unsigned long long need = lim == 63 ? ~0ull : ((2ull << lim) - 1);
+            if (__ballot(f == 0) & need) {
+                if (++spins > (1u << 22)) {
+                    if (lane == 0) atomicOr(err, 64);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+                continue;
+            }
+            int64_t x = lane <= lim ? (int64_t)(v & SC_VAL) : 0;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off);
+            acc += x;
+            if (pre) break;
+            hi -= 64;
+        }
+        if (lane == 0) {
+            __hip_atomic_store(&w[tile], SC_PRE | (unsigned long long)(acc + tsum), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+            toff = acc;
+        }
+    }
+    __syncthreads();
+    const int64_t pre = toff + sh[threadIdx.x] - s;
+#pragma unroll
+    for (int t = 0; t < SCAN_PER; ++t) {
+        const int64_t i = base + t;
+        if (i < n) out[i] = pre + loc[t];
+    }
+    if (tile == nb - 1 && threadIdx.x == SCAN_T - 1) out[n] = toff + tsum;
+}
+void launch_scan1_i32(const int32_t *in, int64_t n, int64_t *out, unsigned long long *state, int32_t *err,
+                      int32_t *host_flags, hipStream_t s) {
+    const int64_t nb = (n + SCAN_B - 1) / SCAN_B;
+    hipLaunchKernelGGL(k_scan1, dim3((unsigned)nb), dim3(SCAN_T), 0, s, in, n, out, state, err, host_flags);
+}
+
 // exclusive scan with out[n] = total (n >= 1)
 void launch_scan_i32(const int32_t *in, int64_t n, int64_t *out, int64_t *tmp, hipStream_t s) {
     const int64_t nb = (n + SCAN_B - 1) / SCAN_B;
@@ -297,11 +434,12 @@ __global__ void k_assemble(int64_t n, int qcap, const int64_t *off, const int32_
                            const int32_t *aJ, const double *aV, int32_t *rowidxM, double *valM,
                            const int32_t *status, const int32_t *err, int64_t *out) {
     const int64_t total = n * 16;
+    const bool copy = (*err & 64) == 0;  // (no colptr from a scan whose state was not zeroed)
     int64_t a = 0, b = 0, c = 0;
     for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
         const int64_t k = idx >> 4;
-        const int cnt = min(nJ[k], qcap);
+        const int cnt = copy ? min(nJ[k], qcap) : 0;
         const int64_t src0 = off[k], dst0 = colptrM[k];
         for (int t = (int)(idx & 15); t < cnt; t += 16) {
             rowidxM[dst0 + t] = aJ[src0 + t];

@@ -42,7 +42,7 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
     const int grp = lane / G;
     GLds<C> &S = lds[grp];
     const BuildParams P = args.P;
-    if (*args.err & 7) return;  // the CSC contract failed: process nothing
+    if (*args.err & ERR_SKIP) return;  // the CSC contract failed: process nothing
     fac_chunk_init(fch);
 
     // ---- static, XCD-aware schedule: each of the 8 XCDs takes a contiguous range

@@ -171,7 +171,7 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
     constexpr int MM = HS / 2;  // row hash load at most one half
     __shared__ WLds<LOGH, BLK, SHV, SMAX> S;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    if (*args.err & 7) return;
+    if (*args.err & ERR_SKIP) return;
     const BuildParams P = args.P;
     const int64_t Q = min((int64_t)(*args.rec_in_count), args.rec_in_cap);
 
