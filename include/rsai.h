@@ -95,8 +95,9 @@ typedef struct {
     int32_t drop;     /* rsai_drop_mode */
     double tol;       /* fixed drop tolerance (RSAI_DROP_FIXED) */
     int32_t sched;    /* rsai_sched */
-    int32_t validate; /* CSC contract check: 0 none (input trusted), 1 checked before the
-                         build with one host synchronisation (RSAI_E_CSC from rsai_build),
+    int32_t validate; /* CSC contract check: 0 none (input trusted), 1 checked with one
+                         host wait, after the build's kernels are queued (RSAI_E_CSC from
+                         rsai_build; the queued kernels do nothing on a malformed input),
                          2 checked on the device without synchronising (the build's kernels
                          then do nothing and rsai_plan_nnz reports RSAI_E_CSC) */
     int32_t tier0;    /* first size tier for the batched schedule: -1 default (0), else a
@@ -176,9 +177,10 @@ rsai_status rsai_autotune(const rsai_csc *A, const rsai_params *p, int32_t reps,
    over its pattern J_k, solved as the reduced LS problem (2.3) on the rows I_k, with J_k
    grown by Algorithm 1 (Section 3) and pruned by the dropping of Section 4 (fixed tol, or
    the adaptive tolerance of eq. (4.3)). Queues all work on stream; with p->validate = 1
-   it first synchronises once to check the CSC contract (RSAI_E_CSC on violation); with
-   p->validate = 0 or 2 it does not synchronise at all. On success *out owns every
-   device buffer of the build (released by rsai_destroy); A stays borrowed. */
+   it then waits for the CSC contract check, which runs first on the stream (RSAI_E_CSC
+   on violation); with p->validate = 0 or 2 it does not synchronise at all. On success
+   *out owns every device buffer of the build (released by rsai_destroy); A stays
+   borrowed. */
 rsai_status rsai_build(const rsai_csc *A, const rsai_params *p, void *stream, rsai_plan **out);
 
 /* Build M for count matrices in one pass: the columns of all matrices share the
