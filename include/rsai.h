@@ -239,10 +239,12 @@ rsai_status rsai_apply(const rsai_plan *P, int32_t mat, const double *x, double 
    dA_val += d/dA [ <dM_val, M> + w_frob * sum_k ||A m_k - e_k||^2 ] restricted to
    the structural nonzeros of A. dM_val (nnzM entries, CSC order of rsai_export_M)
    may be NULL. dA_val has nnz(A) entries and is accumulated into. Columns whose R
-   factor the build kept (keep_factors) are solved on it; the others re-gather and
-   refactorise A(I_k, J_k). Limits: |J_k| <= 128 on a kept factor; |J_k| <= 32 and
-   |I_k| <= 64 for a column that is refactorised; beyond them RSAI_E_CAP (checked
-   before any accumulation, one host synchronisation on the first call of a plan). */
+   factor the build kept (keep_factors) are solved on it; the others have it
+   recomputed: A(I_k, J_k) re-gathered and refactorised in registers when |J_k| <= 32
+   and |I_k| <= 64, else R from A_k^T A_k (dot products of the sparse columns,
+   Cholesky) into a temporary store allocated for the call. Limit: |J_k| <= 128, the
+   build's own; beyond it RSAI_E_CAP (checked before any accumulation, one host
+   synchronisation on the first call of a plan). */
 rsai_status rsai_backward(rsai_plan *P, int32_t mat, const double *dM_val, double w_frob, double *dA_val,
                           void *stream);
 
