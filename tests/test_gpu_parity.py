@@ -316,6 +316,29 @@ def test_malformed_csc_reported(validate, kind):
     assert ei.value.code == -2
 
 
+@pytest.mark.parametrize("kind", ["unsorted", "range", "empty", "colptr"])
+def test_malformed_csc_in_a_batch_reported_by_the_build(kind):
+    """validate = 1 on a batch whose second matrix breaks the CSC contract: the build call
+    itself returns RSAI_E_CSC (the flags reach the host only after every matrix's check),
+    and the next builds on the same thread, of valid matrices, succeed with the result of
+    a build that never saw the error (no flags left over from the failed one)."""
+    import torch
+    import paper_1503_04500_amd.rsai as rsai
+    n, cp, ri, va = _malformed(kind)
+    good = rsai.Matrix.from_host(gen.c1(), "cuda:0")
+    bad = rsai.Matrix(torch.from_numpy(cp).cuda(), torch.from_numpy(ri).cuda(), torch.from_numpy(va).cuda())
+    with pytest.raises(rsai.RSAIError) as ei:
+        rsai.build_batched([good, bad], validate=1, **C1)
+    assert ei.value.code == -2
+    ref = run_gpu(gen.c1(), validate=1, **C1)
+    for _ in range(2):
+        plan = rsai.build_batched([good, good], validate=1, **C1)
+        for mat in (0, 1):
+            cpm, rim, vam = plan.export(mat)
+            assert np.array_equal(rim.cpu().numpy(), ref["rowidx"]) and np.array_equal(vam.cpu().numpy(), ref["val"])
+        plan.close()
+
+
 def test_async_validation_matches_sync_on_valid_input():
     A = gen.c1()
     a = run_gpu(A, validate=2, **C1)
