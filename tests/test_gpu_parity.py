@@ -339,6 +339,32 @@ def test_malformed_csc_in_a_batch_reported_by_the_build(kind):
         plan.close()
 
 
+def test_rsai_build_entry_point():
+    """rsai_build itself, called through the C ABI (the binding's builds go through
+    rsai_build_batched): M and the per-column statistics equal, bit for bit, those of
+    the binding's build with the same parameters and no tuning table, which the C1
+    parity test holds to the oracle."""
+    import ctypes
+    import paper_1503_04500_amd.rsai as rsai
+    A = gen.c1()
+    ref = run_gpu(A, tune_table=[], **C1)
+    dA = rsai.Matrix.from_host(A, "cuda:0")
+    lib = rsai.load()
+    rsai._use_torch_allocator()
+    prm = rsai.params(**C1)
+    v = dA.view()
+    st = rsai._stream()
+    h = ctypes.c_void_p()
+    assert lib.rsai_build(ctypes.byref(v), ctypes.byref(prm), st, ctypes.byref(h)) == 0
+    plan = rsai.Plan(h, [dA], prm, st)
+    cp, ri, va = (t.cpu().numpy() for t in plan.export())
+    assert np.array_equal(cp, ref["colptr"]) and np.array_equal(ri, ref["rowidx"]) and np.array_equal(va, ref["val"])
+    stats = {k: t.cpu().numpy() for k, t in plan.stats().items()}
+    for key in ("loops", "resnorm", "nI", "nJ", "status"):
+        assert np.array_equal(stats[key], ref[key]), key
+    plan.close()
+
+
 def test_async_validation_matches_sync_on_valid_input():
     A = gen.c1()
     a = run_gpu(A, validate=2, **C1)
