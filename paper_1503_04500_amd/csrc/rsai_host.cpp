@@ -625,7 +625,8 @@ static rsai_status build_impl(int32_t count, const rsai_csc *As, const rsai_para
                 MatPlan &M = P->mats[i];
                 add(M.rowcnt, As[i].n, 0);
                 add(fillpos[i], As[i].n, 0);
-                // the summary rsai_plan_nnz accumulates into
+                // the summary (counts the assembly adds up; the adjoint's size maxima,
+                // which rsai_plan_nnz gathers) and the two single-pass scan states
                 add(M.summary, 2 * (8 + 5 * MAX2_COPIES / 2 + 2 * scan1_state_elems(As[i].n)), 0);
             }
             const int ntab = count <= FILL_TAB ? count : 0;
@@ -883,7 +884,7 @@ rsai_status rsai_rebuild(rsai_plan *P, int32_t use_graph, void *stream) {
         M.t_valid = false;
     }
     for (bool &r : P->recorded) r = false;
-    // the sequence starts by zeroing every matrix's summary
+    // the sequence starts by zeroing every matrix's summary and scan states
     auto cleared = [P]() {
         for (MatPlan &M : P->mats) M.sizes_clear = true;
     };
