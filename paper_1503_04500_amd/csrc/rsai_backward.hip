@@ -519,8 +519,11 @@ __device__ __forceinline__ int rrow(int q, int i) { return i * q - i * (i - 1) /
 
 int backward_factored_max_cols() { return 128; }
 
+// (at least four waves per SIMD: the register budget is cut to 128 per lane, which the
+// small instance, R staged in LDS, needs to keep four waves; one register more cost it a
+// wave and a fifth of its speed)
 template <int FG, int FQ, int QLO>
-__global__ __launch_bounds__(64) void backward_factored_kernel(BwdArgs a) {
+__global__ __launch_bounds__(64, 4) void backward_factored_kernel(BwdArgs a) {
     constexpr int G = FG, FGPW = 64 / FG, CPL = FQ / G;
     using LT = FLds<FQ>;
     static_assert(FQ % G == 0 && FM % G == 0, "columns and entries split evenly over the lanes");
