@@ -185,7 +185,6 @@ __global__ __launch_bounds__(64, C::WPS) void tier_kernel(TierArgs args) {
                 }
                 kidx = gmax_i<G>(kidx);
                 nRh = rnRh;
-#pragma unroll
                 for (int t = gl; t < rnRh; t += G) S.Rh[t] = RI[rm + rnR + t];
             }
         }
