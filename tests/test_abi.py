@@ -95,6 +95,28 @@ def test_argument_errors_without_gpu():
     assert rsai.params().spill_capacity == 0
 
 
+def test_params_are_fresh_copies():
+    """rsai.params reuses the struct it made for the same arguments: each call still
+    returns a separate copy (changing one leaves the next call's alone), different
+    arguments give different structs, and a repeated call equals a first one."""
+    import paper_1503_04500_amd.rsai as rsai
+    a = rsai.params(c=3, lmax=8, eps=0.4, tol=1e-3)
+    a.c = 5
+    a.tune_count = 3
+    b = rsai.params(c=3, lmax=8, eps=0.4, tol=1e-3)
+    assert b.c == 3 and b.tune_count == 0 and b.lmax == 8
+    assert bytes(b) == bytes(rsai._make_params(3, 8, 0.4, "fixed", 1e-3, "batched", True, -1, False, -1, -1,
+                                               False, 0, False, -1, -1, 0))
+    assert rsai.params(c=4, lmax=8).c == 4 and rsai.params(c=3, lmax=8).c == 3
+    assert rsai.params(drop="adaptive").drop == rsai.DROP["adaptive"]
+    # the tuning array is converted once and reused while the table is the same
+    arr1, n1 = rsai.tune_entries()
+    arr2, n2 = rsai.tune_entries()
+    assert arr1 is arr2 and n1 == n2
+    arr3, n3 = rsai.tune_entries([])
+    assert n3 == 0
+
+
 def test_no_cpu_fallback():
     """The binding refuses host tensors instead of computing on the CPU."""
     import torch
