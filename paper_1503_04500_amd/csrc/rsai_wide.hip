@@ -53,6 +53,7 @@ struct WLds {
     int Jl[64];             // J, slot order
     int ord[64];            // slots in ascending column order
     int srow[SMAX];         // shared rows, ascending
+    unsigned long long shm[SMAX];  // columns (slots) of J holding each shared row
     int stmp[SMAX];
     int slist[SMAX];        // rows whose holder count reached 2 since the last scan, plus
                             // the shared rows of that scan (slovf: the list overflowed)
@@ -62,7 +63,7 @@ struct WLds {
     int cvg[NW];
     double akv;             // a_kj when k is a private row of column slot kcol
     int kcol;
-    int cnt, nsh, flag, nsl, slovf;
+    int cnt, nsh, flag, nsl, slovf, nsh2;
     double rn;
 };
 
@@ -347,12 +348,23 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
 
             // ================= LS solve(s) on (I, J) (2.3): pass 0 the augmented pattern,
             // pass 1 the pattern kept after dropping (Section 4)
+            // (after a drop, the drop step leaves the kept columns' compressed data in
+            // LDS: shared rows, their values, private sums and the row of k; the re-solve
+            // forms its block from them instead of gathering every column again)
+            bool reuse_next = false;
             for (int pass = 0; pass < 2 && need_solve && status == ST_OK; ++pass) {
+                const bool reuse = reuse_next;
+                reuse_next = false;
                 // ---- shared rows (held by two or more columns of J), ascending
-                if (tid == 0) { S.nsh = 0; S.kcol = -1; S.akv = 0.0; S.flag = 0; }
+                if (tid == 0) {
+                    if (!reuse) { S.nsh = 0; S.kcol = -1; S.akv = 0.0; }
+                    S.flag = 0;
+                }
                 __syncthreads();
                 const bool slovf = S.slovf != 0;
-                if (slovf) {
+                if (reuse) {
+                    // (shared rows already known)
+                } else if (slovf) {
                     for (int t = tid; t < HS; t += NT) {
                         const int key = S.hk[t];
                         if (key != HEMPTY && (hget(S, t) & 0x7Fu) >= 2u) {
@@ -375,7 +387,7 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
                 }
                 __syncthreads();
                 const int nsh = S.nsh;
-                if (!slovf && nsh <= SMAX) {
+                if (!reuse && !slovf && nsh <= SMAX) {
                     // the list keeps the shared rows only (no row enters it twice)
                     for (int t = tid; t < nsh; t += NT) S.slist[t] = S.stmp[t];
                     if (tid == 0) S.nsl = nsh;
@@ -391,15 +403,25 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
                     pend_mmod = mmod;
                     break;
                 }
-                if (tid < nsh) {
+                if (!reuse && tid < nsh) {
                     const int key = S.stmp[tid];
                     int rank = 0;
                     for (int t = 0; t < nsh; ++t) rank += (S.stmp[t] < key) ? 1 : 0;
                     S.srow[rank] = key;
                 }
                 for (int t = tid; t < mp * ld; t += NT) S.blk[t] = 0.0;
-                for (int t = tid; t < nsh * q; t += NT) S.shv[t] = 0.0;
+                if (!reuse) {
+                    for (int t = tid; t < nsh * q; t += NT) S.shv[t] = 0.0;
+                    for (int t = tid; t < nsh; t += NT) S.shm[t] = 0ull;
+                }
                 __syncthreads();
+                if (reuse) {
+                    // the kept shared values into the block
+                    for (int t = tid; t < nsh * q; t += NT) {
+                        const int si = t / q, c = t - si * q;
+                        S.blk[(q + si) * ld + c] = S.shv[t];
+                    }
+                } else
                 // ---- gather: shared entries into the block, private rows into column sums
                 {
                     auto visit = [&](int c, int row, double v, double &a2) {
@@ -413,6 +435,7 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
                             if (si >= 0) {
                                 S.blk[(q + si) * ld + c] = v;
                                 S.shv[si * q + c] = v;
+                                atomicOr(&S.shm[si], 1ull << c);
                             } else {
                                 lookup_fail = true;
                             }
@@ -663,6 +686,85 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
                             },
                             [](int) {}, [&](int c) { return ((keepm >> c) & 1ull) == 0ull; });
                         __syncthreads();
+                        // the kept columns' compressed data for the re-solve (old slots
+                        // here): a shared row keeps its place among the rows still held by
+                        // two or more kept columns; a row held by one kept column joins that
+                        // column's private sum (after the sum it had, rows ascending); the
+                        // row of k is private, shared or gone as its holders are
+                        {
+                            const int qo = q, nso = nsh;
+                            const int qn = __popcll(keepm);
+                            auto slot = [&](int c) { return __popcll(keepm & ((1ull << c) - 1ull)); };
+                            if (wid == 0) {
+                                int base = 0;
+                                for (int s0 = 0; s0 < nso; s0 += 64) {
+                                    const int si = s0 + lane;
+                                    const bool kr = si < nso && __popcll(S.shm[si] & keepm) >= 2;
+                                    const unsigned long long bal = __ballot(kr);
+                                    if (si < nso) S.stmp[si] = kr ? base + __popcll(bal & ((1ull << lane) - 1ull)) : -1;
+                                    base += __popcll(bal);
+                                }
+                                if (lane == 0) S.nsh2 = base;
+                            }
+                            int kc = -1;
+                            double ka = 0.0;
+                            if (tid == 0) {
+                                const int ksl2 = hfind<LOGH>(S.hk, k);
+                                const unsigned kcn2 = ksl2 >= 0 ? (hget(S, ksl2) & 0x7Fu) : 0u;
+                                if (kcn2 == 1u) {
+                                    if (S.kcol >= 0 && ((keepm >> S.kcol) & 1ull)) {
+                                        kc = slot(S.kcol);
+                                        ka = S.akv;
+                                    } else {
+                                        const int si = sfind(S.srow, nso, k);
+                                        if (si >= 0) {
+                                            const unsigned long long hm = S.shm[si] & keepm;
+                                            if (__popcll(hm) == 1) {
+                                                const int c = __ffsll((long long)hm) - 1;
+                                                kc = slot(c);
+                                                ka = S.shv[si * qo + c];
+                                            }
+                                        }
+                                    }
+                                }
+                            }
+                            __syncthreads();
+                            // kept shared values (staged in blk, free until the re-solve
+                            // forms its block) and the kept columns' private sums (in rd)
+                            for (int t = tid; t < nso * qo; t += NT) {
+                                const int si = t / qo, c = t - si * qo;
+                                const int ns = S.stmp[si];
+                                if (ns >= 0 && ((keepm >> c) & 1ull)) S.blk[ns * qn + slot(c)] = S.shv[t];
+                            }
+                            if (tid < qo && ((keepm >> tid) & 1ull)) {
+                                double acc = S.s2[tid];
+                                const unsigned long long me = 1ull << tid;
+                                for (int si = 0; si < nso; ++si)
+                                    if ((S.shm[si] & keepm) == me) {
+                                        const double v = S.shv[si * qo + tid];
+                                        acc += v * v;
+                                    }
+                                S.rd[slot(tid)] = acc;
+                            }
+                            const int myrow = tid < nso ? S.srow[tid] : 0;
+                            const int mynew = tid < nso ? S.stmp[tid] : -1;
+                            __syncthreads();
+                            const int nsn = S.nsh2;
+                            if (mynew >= 0) S.srow[mynew] = myrow;
+                            for (int t = tid; t < nsn * qn; t += NT) S.shv[t] = S.blk[t];
+                            if (tid < qn) S.s2[tid] = S.rd[tid];
+                            if (tid == 0) {
+                                S.kcol = kc;
+                                S.akv = ka;
+                                S.nsh = nsn;
+                            }
+                            __syncthreads();
+                            if (S.slovf == 0) {
+                                // the candidate list keeps the shared rows only
+                                for (int t = tid; t < nsn; t += NT) S.slist[t] = S.srow[t];
+                                if (tid == 0) S.nsl = nsn;
+                            }
+                        }
                         if (wid == 0) {
                             // compaction of the slots in order: lane c moves to the number of
                             // kept slots below it
@@ -691,6 +793,7 @@ __global__ __launch_bounds__(NT, WPC) void wide_kernel(WideArgs args) {
                             hinsert<LOGHJ>(S.hJ, S.Jl[c], sl);
                         }
                         qmod = 0;
+                        reuse_next = true;
                         __syncthreads();
                         continue;  // solve on the kept pattern
                     }
